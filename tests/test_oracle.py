@@ -1,0 +1,287 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: an
+independent exact-rational construction, a closed form, an invariant, a
+textbook special case (the patch test), or brute force on a tiny input.
+"""
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fem, solvers, post
+from paper_2203_15115_amd import workloads as wl
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def lame(E, nu):
+    return E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+
+
+# ----------------------------------------------------------------- element matrix
+@pytest.mark.parametrize("h", [(1, 1, 1), (1, 2, Fraction(1, 2)), (3, 1, 2)])
+def test_ke_gauss_equals_exact_rationals(h):
+    Kg = fem.ke_gauss(tuple(float(v) for v in h), 1.0, 0.3)
+    Kx = np.array([[float(v) for v in row] for row in fem.ke_exact(h, 1, Fraction(3, 10))])
+    assert np.max(np.abs(Kg - Kx)) <= 4e-16 * np.max(np.abs(Kx)) * 24
+
+
+def test_ke_unit_cube_closed_forms():
+    # Unit cube, E=1, nu=3/10: lambda=15/26, mu=5/13.  Every diagonal entry is
+    # (lambda+2mu)/9 + 2*mu/9 = (lambda+4mu)/9 = 55/234 and the trace is 24x that.
+    K = fem.ke_exact()
+    lam, mu = lame(Fraction(1), Fraction(3, 10))
+    assert (lam, mu) == (Fraction(15, 26), Fraction(5, 13))
+    for i in range(24):
+        assert K[i][i] == (lam + 4 * mu) / 9 == Fraction(55, 234)
+    assert sum(K[i][i] for i in range(24)) == Fraction(220, 39)
+    for i in range(24):
+        for j in range(24):
+            assert K[i][j] == K[j][i]
+
+
+def test_ke_box_diagonal_closed_form():
+    # Diagonal for displacement component i: (lam+2mu) int (dN/dx_i)^2
+    # + mu sum_{k != i} int (dN/dx_k)^2, with int (dN/dx)^2 = hy hz / (9 hx).
+    h = (1.0, 2.0, 0.5)
+    lam, mu = lame(1.0, 0.3)
+    g = [h[1] * h[2] / (9 * h[0]), h[0] * h[2] / (9 * h[1]), h[0] * h[1] / (9 * h[2])]
+    K = fem.ke_gauss(h, 1.0, 0.3)
+    for a in range(8):
+        for i in range(3):
+            want = (lam + 2 * mu) * g[i] + mu * (sum(g) - g[i])
+            assert abs(K[3 * a + i, 3 * a + i] - want) < 1e-15
+
+
+def test_ke_rigid_null_space_and_rank():
+    for h in [(1.0, 1.0, 1.0), (1.0, 2.0, 0.5)]:
+        K = fem.ke_gauss(h, 1.0, 0.3)
+        R = fem.rigid_modes_element(h)
+        assert np.max(np.abs(K @ R)) < 1e-14
+        ev = np.linalg.eigvalsh(K)
+        assert np.sum(ev < 1e-12) == 6 and np.all(ev > -1e-13)
+
+
+def test_ke_unit_cube_spectrum():
+    # Eigenvalues of the unit-cube matrix (E=1, nu=3/10), derived from the
+    # rational matrix: 0 (x6), 5/78 (x2), 55/468 (x3), 5/26 (x3), 10/39 (x1),
+    # 5/13 (x8), 5/4 (x1).  They sum to the trace 220/39.
+    spec = ([0] * 6 + [Fraction(5, 78)] * 2 + [Fraction(55, 468)] * 3 + [Fraction(5, 26)] * 3
+            + [Fraction(10, 39)] + [Fraction(5, 13)] * 8 + [Fraction(5, 4)])
+    assert sum(spec) == Fraction(220, 39)
+    ev = np.sort(np.linalg.eigvalsh(fem.ke_gauss()))
+    assert np.allclose(ev, np.sort([float(v) for v in spec]), atol=1e-14)
+
+
+def test_ke_uniform_strain_energy():
+    # A linear displacement u = eps x has the uniform strain eps, so its
+    # energy is exactly V * (lam tr(eps)^2 + 2 mu eps:eps) for any symmetric eps.
+    rng = np.random.default_rng(0)
+    for h in [(1.0, 1.0, 1.0), (2.0, 0.5, 1.5)]:
+        K = fem.ke_gauss(h, 2.5, 0.27)
+        lam, mu = lame(2.5, 0.27)
+        X = fem.LOCAL * np.asarray(h)
+        for _ in range(5):
+            A = rng.standard_normal((3, 3))
+            eps = (A + A.T) / 2
+            u = (X @ eps.T).ravel()   # antisymmetric part would be a rotation
+            want = np.prod(h) * (lam * np.trace(eps) ** 2 + 2 * mu * np.sum(eps * eps))
+            assert abs(u @ K @ u - want) < 1e-12 * abs(want)
+
+
+# ----------------------------------------------------------------- assembly
+def _rand_rho(dims, seed):
+    rng = np.random.default_rng(seed)
+    return np.where(rng.random(wl.n_elems(dims)) < 0.3, 1e-3, 1.0) * rng.uniform(0.5, 2.0, wl.n_elems(dims))
+
+
+def test_assembly_rigid_modes_and_jacobi_closed_form():
+    dims = (5, 3, 4)
+    rho = _rand_rho(dims, 1)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    X = fem.node_coords(dims)
+    x, y, z = X.T
+    o, zz = np.ones_like(x), np.zeros_like(x)
+    for m in [(o, zz, zz), (zz, o, zz), (zz, zz, o), (zz, -z, y), (z, zz, -x), (-y, x, zz)]:
+        r = np.stack(m, axis=1).ravel()
+        assert np.max(np.abs(K @ r)) < 1e-12
+    # diag(K)_(n,c) = 55/234 * sum of rho over the elements touching n
+    conn = fem.connectivity(dims)
+    rs = np.zeros(wl.n_nodes(dims))
+    np.add.at(rs, conn.ravel(), np.repeat(rho, 8))
+    assert np.allclose(K.diagonal(), np.repeat(rs, 3) * 55 / 234, rtol=1e-14, atol=0)
+    assert abs(K - K.T).max() < 1e-15
+
+
+def test_assembly_linear_field():
+    dims = (4, 5, 3)
+    rng = np.random.default_rng(2)
+    lam, mu = lame(1.0, 0.3)
+    A = rng.standard_normal((3, 3))
+    eps = (A + A.T) / 2
+    X = fem.node_coords(dims)
+    u = (X @ eps.T).ravel()
+    # uniform density: uniform stress is in equilibrium at interior nodes
+    K1 = fem.assemble(dims, np.ones(wl.n_elems(dims)), fem.ke_gauss())
+    y = (K1 @ u).reshape(-1, 3)
+    nx, ny, nz = dims
+    for k in range(1, nz):
+        for j in range(1, ny):
+            for i in range(1, nx):
+                assert np.max(np.abs(y[wl.node_id(dims, i, j, k)])) < 1e-12
+    # any density: energy of a uniform strain is sum_e rho_e V eps:C:eps
+    rho = _rand_rho(dims, 3)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    want = rho.sum() * (lam * np.trace(eps) ** 2 + 2 * mu * np.sum(eps * eps))
+    assert abs(u @ K @ u - want) < 1e-11 * want
+
+
+def test_ebe_apply_equals_assembled():
+    dims = (6, 4, 3)
+    rho = _rand_rho(dims, 4)
+    Ke = fem.ke_gauss()
+    K = fem.assemble(dims, rho, Ke)
+    u = np.random.default_rng(5).standard_normal(3 * wl.n_nodes(dims))
+    assert np.allclose(fem.apply_ebe(dims, rho, Ke, u), K @ u, rtol=0, atol=1e-13)
+
+
+# ----------------------------------------------------------------- solve
+def test_patch_test_uniaxial_stress():
+    # Rollers on x=0 (ux), y=0 (uy), z=0 (uz); traction sigma on x=Lx lumped
+    # consistently (sigma*hy*hz/4 per node per face quad).  The exact solution is
+    # linear: ux = sigma x/E, uy = -nu sigma y/E, uz = -nu sigma z/E.
+    dims = (4, 3, 2)
+    h = (1.5, 1.0, 2.0)
+    E, nu, sig = 3.0, 0.3, 0.7
+    nx, ny, nz = dims
+    K = fem.assemble(dims, np.ones(wl.n_elems(dims)), fem.ke_gauss(h, E, nu))
+    X = fem.node_coords(dims, h)
+    fixed = np.zeros(3 * wl.n_nodes(dims), dtype=np.uint8)
+    fixed[3 * np.flatnonzero(X[:, 0] == 0) + 0] = 1
+    fixed[3 * np.flatnonzero(X[:, 1] == 0) + 1] = 1
+    fixed[3 * np.flatnonzero(X[:, 2] == 0) + 2] = 1
+    f = np.zeros(3 * wl.n_nodes(dims))
+    for k in range(nz):
+        for j in range(ny):
+            for (dj, dk) in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+                f[3 * wl.node_id(dims, nx, j + dj, k + dk)] += sig * h[1] * h[2] / 4
+    u = solvers.solve_direct(K, fixed, f).reshape(-1, 3)
+    want = np.stack([sig * X[:, 0] / E, -nu * sig * X[:, 1] / E, -nu * sig * X[:, 2] / E], axis=1)
+    assert np.max(np.abs(u - want)) < 1e-12
+    vol = np.prod([d * hh for d, hh in zip(dims, h)])
+    assert abs(post.compliance(f, u.ravel()) - sig ** 2 * vol / E) < 1e-12
+
+
+def _tiny_problem(dims, seed, block):
+    rho = _rand_rho(dims, seed)
+    fixed = wl.clamp_x0(dims)
+    f = wl.edge_load(dims, "bottom") + 0.3 * wl.point_load(dims, wl.node_id(dims, dims[0] // 2 + 1, 1, dims[2]))
+    return rho, fixed, f
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (3, 2, 2), (6, 3, 3)])
+def test_direct_equals_dense_bruteforce(dims):
+    rho, fixed, f = _tiny_problem(dims, 7, (2, 2, 2))
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    u = solvers.solve_direct(K, fixed, f)
+    free = np.flatnonzero(fixed == 0)
+    ub = np.linalg.solve(K.toarray()[np.ix_(free, free)], f[free])
+    assert np.allclose(u[free], ub, rtol=1e-10, atol=0)
+    assert np.all(u[fixed == 1] == 0)
+
+
+@pytest.mark.parametrize("dims,block", [((8, 4, 4), (2, 2, 2)), ((12, 6, 6), (4, 4, 4)),
+                                        ((9, 5, 4), (4, 4, 4)), ((24, 12, 12), (4, 4, 4))])
+def test_cg_and_dcg_equal_direct(dims, block):
+    rho, fixed, f = _tiny_problem(dims, 11, block)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    ud = solvers.solve_direct(K, fixed, f)
+    uc, itc, rc = solvers.pcg(K, fixed, f, rtol=1e-12)
+    seen = []
+
+    def chk(r, W):
+        seen.append(np.max(np.abs(W.T @ r)) / np.max(np.abs(f)))
+
+    ux, itx, rx = solvers.dcg(K, fixed, f, dims, block, rtol=1e-12, check=chk)
+    nrm = np.linalg.norm(ud)
+    assert np.linalg.norm(uc - ud) / nrm < 1e-8
+    assert np.linalg.norm(ux - ud) / nrm < 1e-8
+    assert rc < 1e-11 and rx < 1e-11
+    assert max(seen) < 1e-9          # W^T r = 0 is an invariant of the deflated iteration
+    assert itx < itc
+
+
+def test_dcg_config0_workload():
+    p = wl.config(0)
+    K = fem.assemble(p.dims, p.rho, fem.ke_gauss())
+    ud = solvers.solve_direct(K, p.fixed, p.F[0])
+    ux, it, rr = solvers.dcg(K, p.fixed, p.F[0], p.dims, p.block, rtol=1e-8)
+    assert rr <= 1e-8
+    assert np.linalg.norm(ux - ud) / np.linalg.norm(ud) < 1e-3
+
+
+def test_linearity_and_mirror_symmetry():
+    dims = (6, 4, 3)
+    nx, ny, nz = dims
+    rng = np.random.default_rng(3)
+    r = np.where(rng.random((nz, ny, nx)) < 0.3, 1e-3, 1.0)
+    r = 0.5 * (r + r[:, ::-1, :])          # symmetric about the mid y-plane
+    rho = r.ravel()
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    fixed = wl.clamp_x0(dims)
+    f = wl.edge_load(dims, "top")           # uniform along y: symmetric
+    u = solvers.solve_direct(K, fixed, f).reshape(nz + 1, ny + 1, nx + 1, 3)
+    assert np.max(np.abs(u[:, :, :, 1] + u[:, ::-1, :, 1])) < 1e-12 * np.max(np.abs(u))
+    assert np.max(np.abs(u[:, :, :, 2] - u[:, ::-1, :, 2])) < 1e-12 * np.max(np.abs(u))
+    u2 = solvers.solve_direct(K, fixed, -2.5 * f).reshape(u.shape)
+    assert np.max(np.abs(u2 + 2.5 * u)) < 1e-12 * np.max(np.abs(u2))
+
+
+# ----------------------------------------------------------------- post-processing
+def test_energy_identity_and_reciprocity():
+    dims = (8, 4, 4)
+    rho, fixed, _ = _tiny_problem(dims, 13, (4, 4, 4))
+    Ke = fem.ke_gauss()
+    K = fem.assemble(dims, rho, Ke)
+    f1 = wl.edge_load(dims, "bottom")
+    f2 = wl.point_load(dims, wl.node_id(dims, 5, 2, 3))
+    u1 = solvers.solve_direct(K, fixed, f1)
+    u2 = solvers.solve_direct(K, fixed, f2)
+    s1 = post.element_energy(dims, rho, Ke, u1)
+    s12 = post.element_energy(dims, rho, Ke, u1, u2)
+    assert abs(s1.sum() - post.compliance(f1, u1)) < 1e-12 * abs(s1.sum())
+    # Maxwell-Betti: f1.u2 = f2.u1 = sum of the mutual energies
+    assert abs(post.compliance(f1, u2) - post.compliance(f2, u1)) < 1e-12 * abs(post.compliance(f2, u1))
+    assert abs(s12.sum() - post.compliance(f2, u1)) < 1e-12 * abs(s12.sum())
+    assert np.all(s1 >= 0)
+
+
+@pytest.mark.parametrize("n,vf", [(1, 0.5), (7, 0.5), (50, 0.3), (50, 1.0), (50, 0.0), (333, 0.475)])
+def test_threshold_bruteforce(n, vf):
+    rng = np.random.default_rng(n)
+    s = rng.integers(0, 6, n).astype(float) * 0.25      # many ties
+    solid, tau = post.threshold(s, vf)
+    ranked = sorted(range(n), key=lambda e: (-s[e], e))
+    keep = math.ceil(vf * n)
+    want = np.zeros(n, dtype=np.uint8)
+    want[ranked[:keep]] = 1
+    assert np.array_equal(solid, want)
+    if keep:
+        assert tau == s[ranked[keep - 1]]
+        assert np.all(s[solid == 1] >= tau) and np.all(s[solid == 0] <= tau)
+
+
+def test_coarse_matrix_structure():
+    dims = (8, 4, 4)
+    block = (4, 2, 2)
+    rho = _rand_rho(dims, 17)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    # unconstrained, one block: rigid modes have zero energy
+    E1, _ = solvers.coarse_matrix(K, np.zeros(K.shape[0], np.uint8), dims, (8, 4, 4))
+    assert np.max(np.abs(E1)) < 1e-12
+    E, nb = solvers.coarse_matrix(K, wl.clamp_x0(dims), dims, block)
+    assert nb == [2, 2, 2]
+    assert np.allclose(E, E.T, atol=1e-14)
+    assert np.linalg.eigvalsh(E).min() > 0       # clamped: positive definite
