@@ -1,0 +1,236 @@
+/*
+ * afdcg.h - C ABI of the MI355X assembly-free deflated voxel solver.
+ *
+ * The library solves the linear static problem K u = f of a finite element
+ * model (Eq. 1.1 of Deng & Suresh, "Multi-Constrained 3D Topology Optimization
+ * Via Augmented Topological Level-Set") on a box of nx*ny*nz voxels meshed by
+ * 8-node hexahedra (Sec. 3.8, step 1), with an assembly-free deflated
+ * conjugate gradient (Sec. 3.5), and returns the compliance J = f.u
+ * (Eq. 1.3-1.4), per-element strain-energy sensitivity fields (the element
+ * term u^T K^e u of Eq. 3.5, Sec. 3.1) and the topology extracted from such a
+ * field at a volume fraction (Eq. 3.6, Sec. 3.2).
+ *
+ * Conventions used by every call:
+ *   element e = ex + nx*(ey + ny*ez); node n = i + (nx+1)*(j + (ny+1)*k);
+ *   DOF 3*n + c (c = x, y, z): displacement-type vectors are interleaved per
+ *   node; a block of nrhs vectors is stored row-major [nrhs][ndof].
+ *   Element e has stiffness rho_e * Ke, Ke the 24x24 matrix of an isotropic
+ *   hx*hy*hz voxel (E, nu).  A DOF flagged fixed is a homogeneous Dirichlet
+ *   DOF: the solver works with the operator A = K_ff on free DOFs, extended by
+ *   the identity on fixed DOFs (so A is SPD on the whole DOF vector).
+ *
+ * Pointers: unless a call says otherwise, array arguments are DEVICE
+ * pointers on the context's device and kernels run asynchronously on the
+ * context's stream; calls named "host" take host pointers and return after
+ * the data has been copied.  The caller owns every buffer it passes.
+ *
+ * Errors: every call returns an int status (AFD_OK = 0, negative on error);
+ * afd_last_error() gives a thread-local message for the last failure on the
+ * calling thread.  No exception crosses this boundary.  Objects are not
+ * thread-safe, except the server.
+ */
+#ifndef AFDCG_H
+#define AFDCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define AFD_OK                 0
+#define AFD_PENDING            1   /* server: request not finished yet          */
+#define AFD_E_INVALID_ARG     -1   /* bad size, pointer, value or state          */
+#define AFD_E_NO_DEVICE       -2   /* no HIP device / bad device index           */
+#define AFD_E_OOM             -3   /* device allocation failed                   */
+#define AFD_E_OVER_BUDGET     -4   /* request larger than the server budget      */
+#define AFD_E_NOT_CONVERGED   -5   /* max_iter reached; outputs hold last iterate */
+#define AFD_E_BREAKDOWN       -6   /* p.Ap <= 0 or non-finite (singular K)       */
+#define AFD_E_COARSE_SINGULAR -7   /* every coarse pivot dropped                 */
+#define AFD_E_HIP             -8   /* a HIP runtime call failed                  */
+
+#define AFD_MEM_HOST   0
+#define AFD_MEM_DEVICE 1
+
+#define AFD_FP64  0   /* FP64 throughout                                         */
+#define AFD_MIXED 1   /* FP32 inner deflated PCG under FP64 iterative refinement */
+#define AFD_FP32  2   /* afd_apply_K only: FP32 vectors and FP32 arithmetic      */
+
+typedef struct afd_context afd_context;
+typedef struct afd_mesh afd_mesh;
+typedef struct afd_server afd_server;
+
+/* Geometry/material of a voxel mesh (Sec. 3.8 step 1: hexahedral elements;
+ * Sec. 4 states the material as E and nu).  bx,by,bz: edge (in elements) of
+ * the agglomerated element blocks whose six rigid-body motions span the
+ * deflation space of Sec. 3.5; 0 in any of them disables deflation. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double hx, hy, hz;
+    double E, nu;
+    int32_t bx, by, bz;
+} afd_mesh_desc;
+
+typedef struct {
+    double rtol;          /* stop when ||f - A u||_2 <= rtol * ||f||_2            */
+    int32_t max_iter;     /* CG iterations (FP64) or inner iterations per sweep   */
+    int32_t precision;    /* AFD_FP64 or AFD_MIXED                               */
+    double inner_rtol;    /* MIXED: relative residual reduction per inner solve  */
+    int32_t check_every;  /* iterations between host convergence checks (>=1)    */
+    int32_t mem_kind;     /* AFD_MEM_HOST or AFD_MEM_DEVICE for F, U, J, S       */
+    const int32_t* pairs; /* host array of 2*npairs RHS indices (a,b)            */
+    int32_t npairs;       /* mutual-energy fields requested                      */
+    int32_t max_refine;   /* MIXED: outer refinement sweeps (<=0: 30)            */
+} afd_solve_opts;
+
+typedef struct {
+    int32_t iterations;       /* total CG iterations (inner, for MIXED)           */
+    int32_t refinements;      /* MIXED: outer sweeps                              */
+    int32_t status;           /* AFD_OK or the failure of this right-hand side    */
+    int32_t coarse_dropped;   /* coarse columns dropped as rank-deficient         */
+    double rel_residual_true; /* ||f - A u|| / ||f|| recomputed in FP64 at exit    */
+    double t_setup, t_iter, t_post; /* seconds (host wall clock, stream-synced)   */
+} afd_solve_stats;
+
+/* ---- context ----------------------------------------------------------- */
+/* Opens device `device`.  `hip_stream` is a hipStream_t to run on (e.g.
+ * torch.cuda.current_stream().cuda_stream) or NULL for a library-owned stream.
+ * AFD_E_NO_DEVICE if the device does not exist. */
+int afd_context_create(int device, void* hip_stream, afd_context** out);
+void afd_context_destroy(afd_context* ctx);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* afd_last_error(void);
+/* Blocks until the context's stream is idle. */
+int afd_context_sync(afd_context* ctx);
+
+/* ---- mesh -------------------------------------------------------------- */
+/* Creates the device-resident state of a voxel mesh (no stiffness matrix is
+ * ever assembled: Sec. 3.5).  All rho start at 1 and no DOF is fixed.
+ * AFD_E_INVALID_ARG for n* < 1, h* <= 0, E <= 0, nu outside (-1, 0.5), b* < 0. */
+int afd_mesh_create(afd_context* ctx, const afd_mesh_desc* desc, afd_mesh** out);
+void afd_mesh_destroy(afd_mesh* mesh);
+/* Sizes: number of elements, nodes, DOFs, coarse unknowns (6 per block). */
+int afd_mesh_sizes(const afd_mesh* mesh, int64_t* n_elem, int64_t* n_node,
+                   int64_t* n_dof, int64_t* n_coarse);
+
+/* Per-element stiffness scale rho_e (> 0, finite), n_elem values, host or
+ * device per mem_kind; copied (stream-ordered).  Invalidates the Jacobi
+ * diagonal and the coarse factor (rebuilt at the next use).  Host input is
+ * validated (AFD_E_INVALID_ARG on a non-positive or non-finite value). */
+int afd_mesh_set_scale(afd_mesh* mesh, const double* rho, int64_t n_elem, int mem_kind);
+/* Fixity: one uint8 per DOF, nonzero = fixed (homogeneous Dirichlet). */
+int afd_mesh_set_fixed(afd_mesh* mesh, const uint8_t* dof_mask, int64_t n_dof, int mem_kind);
+/* Device bytes a solve of nrhs right-hand sides at `precision` will hold
+ * (mesh state + coarse factor + Krylov work space): used for admission. */
+int afd_mesh_footprint(const afd_mesh* mesh, int32_t nrhs, int32_t precision, uint64_t* bytes);
+
+/* ---- hot-path steps (device pointers, asynchronous on the context stream) */
+/* The element matrix Ke (24x24 row-major, local node order bottom face
+ * counter-clockwise then top face, DOF 3a+c) as the library uses it,
+ * written to a HOST buffer of 576 doubles.  (K^e of Eq. 3.5.) */
+int afd_mesh_ke(const afd_mesh* mesh, double* ke_host);
+
+/* Element-by-element operator apply (the assembly-free K.u of Sec. 3.5):
+ * Y[r] = A U[r] for r < nrhs, A = sum_e rho_e P_e^T Ke P_e restricted to free
+ * DOFs, identity on fixed DOFs.  precision AFD_FP64 (double U, Y) or
+ * AFD_FP32 (float U, Y).  U and Y must not overlap.  nrhs in 1..4. */
+int afd_apply_K(afd_mesh* mesh, int32_t precision, int32_t nrhs, const void* U, void* Y);
+/* Multi-RHS apply with the dense 24x24 Ke x [U_e...] contraction on the
+ * FP64 matrix cores (same result as afd_apply_K, FP64 only, nrhs 1..4). */
+int afd_apply_K_mfma(afd_mesh* mesh, int32_t nrhs, const double* U, double* Y);
+
+/* Jacobi diagonal of A (Sec. 3.5: preconditioner formed assembly-free):
+ * d[3n+c] = Ke_cc * sum of rho over the elements touching node n for a free
+ * DOF, 1 for a fixed DOF.  d: ndof doubles. */
+int afd_jacobi(afd_mesh* mesh, double* d);
+
+/* Deterministic FP64 dot product of two length-n device vectors; the result
+ * is written to *out_dev (device).  Fixed-order reduction: bitwise
+ * reproducible run to run. */
+int afd_dot(afd_context* ctx, int64_t n, const double* x, const double* y, double* out_dev);
+
+/* Deflation operators (W: six rigid motions per block, zero on fixed DOFs).
+ * Coarse vectors are [nrhs][n_coarse], entry 6*b + m for block
+ * b = bi + nbx*(bj + nby*bk) and motion m in (tx, ty, tz, rx, ry, rz); the
+ * motions are taken about the centre of the block's node range, in element
+ * units divided by max(bx,by,bz).  Node i (per axis) belongs to block
+ * min(i / b, nb - 1), nb = ceil(n_elem_axis / b). */
+int afd_restrict(afd_mesh* mesh, int32_t nrhs, const double* V, double* G);   /* G = W^T V */
+int afd_prolong(afd_mesh* mesh, int32_t nrhs, const double* MU, double* V);   /* V = W MU  */
+/* Builds E = W^T A W without assembling A and factors it by block Cholesky
+ * (done lazily by afd_solve; this call forces it).  Returns the number of
+ * coarse columns dropped as rank-deficient in *dropped (may be NULL). */
+int afd_coarse_setup(afd_mesh* mesh, int32_t* dropped);
+/* E as a dense HOST matrix n_coarse x n_coarse (row-major), for checking;
+ * only for n_coarse <= 8192. */
+int afd_coarse_matrix(afd_mesh* mesh, double* E_host);
+/* MU = E^-1 G (dropped columns give 0), nrhs in 1..4. */
+int afd_coarse_solve(afd_mesh* mesh, int32_t nrhs, const double* G, double* MU);
+
+/* Per-element energies: S[f][e] = rho_e u_e^T Ke v_e, f < nrhs + npairs:
+ * fields 0..nrhs-1 pair U[f] with itself (strain energy, sum_e = f.u = J);
+ * field nrhs+p pairs U[pairs[2p]] with U[pairs[2p+1]] (mutual energy).
+ * pairs is a HOST array.  (Element term of Eq. 3.5.) */
+int afd_sensitivity(afd_mesh* mesh, int32_t nrhs, const double* U,
+                    int32_t npairs, const int32_t* pairs, double* S);
+
+/* Topology at volume fraction vol_frac in [0,1] (Eq. 3.6, Sec. 3.2): the
+ * ceil(vol_frac*n) elements first in the order (s descending, index
+ * ascending) are solid (solid[e] = 1, else 0); *tau_host receives s of the
+ * last solid element (+inf if none).  order (optional, may be NULL) receives
+ * the full ranking as int32 element indices.  s, solid, order: device. */
+int afd_threshold(afd_context* ctx, const double* s, int64_t n, double vol_frac,
+                  uint8_t* solid, int32_t* order, double* tau_host);
+
+/* ---- the whole solve ---------------------------------------------------- */
+/* Solves A U[r] = F[r] for r < nrhs (1..4) by deflated Jacobi-PCG (Sec. 3.5),
+ * FP64 or FP32-inner/FP64-refined per opts->precision, then writes the
+ * compliances J[r] = F[r].U[r] (Eq. 1.3) and, if S != NULL, the energy fields
+ * of afd_sensitivity (opts->pairs).  F, U, J, S are host or device per
+ * opts->mem_kind.  F must be zero on fixed DOFs (AFD_E_INVALID_ARG
+ * otherwise when F is on the host).  stats (host, may be NULL) receives nrhs
+ * records.  Returns AFD_OK when every column converged, else the first
+ * failing column's status (U holds the last iterate). */
+int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
+              const double* F, double* U, double* J, double* S, afd_solve_stats* stats);
+
+/* ---- serving ------------------------------------------------------------ */
+typedef struct {
+    afd_mesh_desc desc;
+    const double* rho;        /* host, n_elem              */
+    const uint8_t* fixed;     /* host, n_dof               */
+    const double* F;          /* host, nrhs * n_dof        */
+    int32_t nrhs;
+    afd_solve_opts opts;      /* mem_kind ignored (host)   */
+} afd_request;
+
+typedef struct {
+    double* U;                /* host, nrhs * n_dof, caller-owned (may be NULL) */
+    double* J;                /* host, nrhs (may be NULL)                        */
+    afd_solve_stats* stats;   /* host, nrhs (may be NULL)                        */
+    int32_t status;           /* filled on completion                            */
+    double t_submit, t_start, t_done; /* seconds on the server's clock           */
+} afd_result;
+
+/* Continuous-batching solve server on one device: requests are admitted as
+ * slots and HBM budget free up, run concurrently on per-slot streams, and
+ * complete independently.  hbm_budget in bytes (0 = 90% of free memory). */
+int afd_server_create(afd_context* ctx, uint64_t hbm_budget, int32_t max_slots, afd_server** out);
+/* Copies the request (the caller may free it on return); `res` must stay
+ * valid until the ticket completes.  Thread-safe. */
+int afd_server_submit(afd_server* srv, const afd_request* req, afd_result* res, uint64_t* ticket);
+/* AFD_PENDING while running, else the request's final status. */
+int afd_server_poll(afd_server* srv, uint64_t ticket);
+/* Waits up to timeout_s (<0: forever); AFD_PENDING on timeout. */
+int afd_server_wait(afd_server* srv, uint64_t ticket, double timeout_s);
+/* Server clock now (seconds). */
+double afd_server_clock(afd_server* srv);
+/* Finishes queued work, then frees everything. */
+void afd_server_destroy(afd_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFDCG_H */

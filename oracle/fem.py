@@ -214,3 +214,34 @@ def apply_constrained(K, fixed, u):
     uf = np.where(fx, 0.0, u)
     y = K @ uf
     return np.where(fx, u, y)
+
+
+def apply_at_nodes(dims, rho, Ke, u, nodes, fixed=None):
+    """(A u) at the listed nodes only, one node at a time: the sum over the
+    (up to 8) elements touching each node of rho_e (Ke u_e) at that node's
+    local position; free/fixed handling as in ``apply_constrained``.
+    Returns an array (len(nodes), 3)."""
+    nx, ny, nz = dims
+    fx = None if fixed is None else (np.asarray(fixed) != 0)
+    out = np.zeros((len(nodes), 3))
+    for q, n in enumerate(nodes):
+        i = n % (nx + 1)
+        j = (n // (nx + 1)) % (ny + 1)
+        k = n // ((nx + 1) * (ny + 1))
+        acc = np.zeros(3)
+        for a, (dx, dy, dz) in enumerate(LOCAL):
+            ex, ey, ez = i - dx, j - dy, k - dz
+            if not (0 <= ex < nx and 0 <= ey < ny and 0 <= ez < nz):
+                continue
+            e = ex + nx * (ey + ny * ez)
+            ue = np.empty(24)
+            for b, (bx, by, bz) in enumerate(LOCAL):
+                m = (ex + bx) + (nx + 1) * ((ey + by) + (ny + 1) * (ez + bz))
+                ue[3 * b:3 * b + 3] = u[3 * m:3 * m + 3]
+                if fx is not None:
+                    ue[3 * b:3 * b + 3] *= ~fx[3 * m:3 * m + 3]
+            acc += rho[e] * (Ke[3 * a:3 * a + 3, :] @ ue)
+        if fx is not None:
+            acc = np.where(fx[3 * n:3 * n + 3], u[3 * n:3 * n + 3], acc)
+        out[q] = acc
+    return out

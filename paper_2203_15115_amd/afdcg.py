@@ -1,0 +1,273 @@
+"""Thin ctypes binding of the C ABI in ``include/afdcg.h``.
+
+Argument marshalling only: every step of the solve runs in the HIP library
+``libafdcg.so`` (built in-tree by ``build.py``).  Device arrays are passed as
+raw pointers (``tensor.data_ptr()`` of torch CUDA tensors); torch is used only
+for device memory and streams.  Loading fails loudly when the library is
+missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libafdcg.so")
+
+AFD_OK = 0
+AFD_PENDING = 1
+AFD_E_INVALID_ARG = -1
+AFD_E_NO_DEVICE = -2
+AFD_E_OOM = -3
+AFD_E_OVER_BUDGET = -4
+AFD_E_NOT_CONVERGED = -5
+AFD_E_BREAKDOWN = -6
+AFD_E_COARSE_SINGULAR = -7
+AFD_E_HIP = -8
+AFD_MEM_HOST = 0
+AFD_MEM_DEVICE = 1
+AFD_FP64 = 0
+AFD_MIXED = 1
+AFD_FP32 = 2
+
+STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVALID_ARG", -2: "E_NO_DEVICE", -3: "E_OOM",
+                -4: "E_OVER_BUDGET", -5: "E_NOT_CONVERGED", -6: "E_BREAKDOWN",
+                -7: "E_COARSE_SINGULAR", -8: "E_HIP"}
+
+EXPORTED = [
+    "afd_context_create", "afd_context_destroy", "afd_last_error", "afd_context_sync",
+    "afd_mesh_create", "afd_mesh_destroy", "afd_mesh_sizes", "afd_mesh_set_scale", "afd_mesh_set_fixed",
+    "afd_mesh_footprint", "afd_mesh_ke", "afd_apply_K", "afd_apply_K_mfma", "afd_jacobi", "afd_dot",
+    "afd_restrict", "afd_prolong", "afd_coarse_setup", "afd_coarse_matrix", "afd_coarse_solve",
+    "afd_sensitivity", "afd_threshold", "afd_solve", "afd_server_create", "afd_server_submit",
+    "afd_server_poll", "afd_server_wait", "afd_server_clock", "afd_server_destroy",
+]
+
+
+class afd_mesh_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double),
+                ("E", C.c_double), ("nu", C.c_double),
+                ("bx", C.c_int32), ("by", C.c_int32), ("bz", C.c_int32)]
+
+
+class afd_solve_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
+                ("inner_rtol", C.c_double), ("check_every", C.c_int32), ("mem_kind", C.c_int32),
+                ("pairs", C.POINTER(C.c_int32)), ("npairs", C.c_int32), ("max_refine", C.c_int32)]
+
+
+class afd_solve_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("refinements", C.c_int32), ("status", C.c_int32),
+                ("coarse_dropped", C.c_int32), ("rel_residual_true", C.c_double),
+                ("t_setup", C.c_double), ("t_iter", C.c_double), ("t_post", C.c_double)]
+
+
+class afd_request(C.Structure):
+    _fields_ = [("desc", afd_mesh_desc), ("rho", C.c_void_p), ("fixed", C.c_void_p), ("F", C.c_void_p),
+                ("nrhs", C.c_int32), ("opts", afd_solve_opts)]
+
+
+class afd_result(C.Structure):
+    _fields_ = [("U", C.c_void_p), ("J", C.c_void_p), ("stats", C.c_void_p), ("status", C.c_int32),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: run paper_2203_15115_amd/build.py (no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "afd_context_create": (C.c_int, [C.c_int, vp, C.POINTER(vp)]),
+            "afd_context_destroy": (None, [vp]),
+            "afd_last_error": (C.c_char_p, []),
+            "afd_context_sync": (C.c_int, [vp]),
+            "afd_mesh_create": (C.c_int, [vp, C.POINTER(afd_mesh_desc), C.POINTER(vp)]),
+            "afd_mesh_destroy": (None, [vp]),
+            "afd_mesh_sizes": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
+            "afd_mesh_set_scale": (C.c_int, [vp, vp, i64, C.c_int]),
+            "afd_mesh_set_fixed": (C.c_int, [vp, vp, i64, C.c_int]),
+            "afd_mesh_footprint": (C.c_int, [vp, i32, i32, C.POINTER(C.c_uint64)]),
+            "afd_mesh_ke": (C.c_int, [vp, vp]),
+            "afd_apply_K": (C.c_int, [vp, i32, i32, vp, vp]),
+            "afd_apply_K_mfma": (C.c_int, [vp, i32, vp, vp]),
+            "afd_jacobi": (C.c_int, [vp, vp]),
+            "afd_dot": (C.c_int, [vp, i64, vp, vp, vp]),
+            "afd_restrict": (C.c_int, [vp, i32, vp, vp]),
+            "afd_prolong": (C.c_int, [vp, i32, vp, vp]),
+            "afd_coarse_setup": (C.c_int, [vp, C.POINTER(i32)]),
+            "afd_coarse_matrix": (C.c_int, [vp, vp]),
+            "afd_coarse_solve": (C.c_int, [vp, i32, vp, vp]),
+            "afd_sensitivity": (C.c_int, [vp, i32, vp, i32, vp, vp]),
+            "afd_threshold": (C.c_int, [vp, vp, i64, dbl, vp, vp, C.POINTER(dbl)]),
+            "afd_solve": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, vp, vp, vp, vp, vp]),
+            "afd_server_create": (C.c_int, [vp, C.c_uint64, i32, C.POINTER(vp)]),
+            "afd_server_submit": (C.c_int, [vp, C.POINTER(afd_request), C.POINTER(afd_result),
+                                            C.POINTER(C.c_uint64)]),
+            "afd_server_poll": (C.c_int, [vp, C.c_uint64]),
+            "afd_server_wait": (C.c_int, [vp, C.c_uint64, dbl]),
+            "afd_server_clock": (dbl, [vp]),
+            "afd_server_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class AfdError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().afd_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, where):
+    if code not in (AFD_OK,):
+        raise AfdError(code, where)
+    return code
+
+
+def _ptr(x):
+    """Raw pointer of a torch tensor / numpy array / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+# ---- same-name wrappers (raise on error) ---------------------------------
+def afd_context_create(device=0, stream=None):
+    out = C.c_void_p()
+    check(lib().afd_context_create(device, stream, C.byref(out)), "afd_context_create")
+    return out.value
+
+
+def afd_context_destroy(ctx):
+    lib().afd_context_destroy(ctx)
+
+
+def afd_context_sync(ctx):
+    check(lib().afd_context_sync(ctx), "afd_context_sync")
+
+
+def afd_mesh_create(ctx, dims, h=(1.0, 1.0, 1.0), E=1.0, nu=0.3, block=(0, 0, 0)):
+    d = afd_mesh_desc(int(dims[0]), int(dims[1]), int(dims[2]), float(h[0]), float(h[1]), float(h[2]),
+                      float(E), float(nu), int(block[0]), int(block[1]), int(block[2]))
+    out = C.c_void_p()
+    check(lib().afd_mesh_create(ctx, C.byref(d), C.byref(out)), "afd_mesh_create")
+    return out.value
+
+
+def afd_mesh_destroy(mesh):
+    lib().afd_mesh_destroy(mesh)
+
+
+def afd_mesh_sizes(mesh):
+    v = [C.c_int64() for _ in range(4)]
+    check(lib().afd_mesh_sizes(mesh, *[C.byref(x) for x in v]), "afd_mesh_sizes")
+    return tuple(x.value for x in v)
+
+
+def afd_mesh_set_scale(mesh, rho, n, mem_kind):
+    check(lib().afd_mesh_set_scale(mesh, _ptr(rho), n, mem_kind), "afd_mesh_set_scale")
+
+
+def afd_mesh_set_fixed(mesh, mask, n, mem_kind):
+    check(lib().afd_mesh_set_fixed(mesh, _ptr(mask), n, mem_kind), "afd_mesh_set_fixed")
+
+
+def afd_mesh_footprint(mesh, nrhs, precision):
+    b = C.c_uint64()
+    check(lib().afd_mesh_footprint(mesh, nrhs, precision, C.byref(b)), "afd_mesh_footprint")
+    return b.value
+
+
+def afd_mesh_ke(mesh, ke_host):
+    check(lib().afd_mesh_ke(mesh, _ptr(ke_host)), "afd_mesh_ke")
+
+
+def afd_apply_K(mesh, precision, nrhs, U, Y):
+    check(lib().afd_apply_K(mesh, precision, nrhs, _ptr(U), _ptr(Y)), "afd_apply_K")
+
+
+def afd_apply_K_mfma(mesh, nrhs, U, Y):
+    check(lib().afd_apply_K_mfma(mesh, nrhs, _ptr(U), _ptr(Y)), "afd_apply_K_mfma")
+
+
+def afd_jacobi(mesh, d):
+    check(lib().afd_jacobi(mesh, _ptr(d)), "afd_jacobi")
+
+
+def afd_dot(ctx, n, x, y, out):
+    check(lib().afd_dot(ctx, n, _ptr(x), _ptr(y), _ptr(out)), "afd_dot")
+
+
+def afd_restrict(mesh, nrhs, V, G):
+    check(lib().afd_restrict(mesh, nrhs, _ptr(V), _ptr(G)), "afd_restrict")
+
+
+def afd_prolong(mesh, nrhs, MU, V):
+    check(lib().afd_prolong(mesh, nrhs, _ptr(MU), _ptr(V)), "afd_prolong")
+
+
+def afd_coarse_setup(mesh):
+    d = C.c_int32()
+    check(lib().afd_coarse_setup(mesh, C.byref(d)), "afd_coarse_setup")
+    return d.value
+
+
+def afd_coarse_matrix(mesh, E_host):
+    check(lib().afd_coarse_matrix(mesh, _ptr(E_host)), "afd_coarse_matrix")
+
+
+def afd_coarse_solve(mesh, nrhs, G, MU):
+    check(lib().afd_coarse_solve(mesh, nrhs, _ptr(G), _ptr(MU)), "afd_coarse_solve")
+
+
+def afd_sensitivity(mesh, nrhs, U, pairs, S):
+    npairs = len(pairs)
+    arr = (C.c_int32 * max(1, 2 * npairs))(*[int(v) for p in pairs for v in p])
+    check(lib().afd_sensitivity(mesh, nrhs, _ptr(U), npairs, C.cast(arr, C.c_void_p), _ptr(S)),
+          "afd_sensitivity")
+
+
+def afd_threshold(ctx, s, n, vol_frac, solid, order=None):
+    tau = C.c_double()
+    check(lib().afd_threshold(ctx, _ptr(s), n, float(vol_frac), _ptr(solid), _ptr(order), C.byref(tau)),
+          "afd_threshold")
+    return tau.value
+
+
+def make_opts(rtol=1e-8, max_iter=20000, precision=AFD_FP64, inner_rtol=1e-4, check_every=16,
+              mem_kind=AFD_MEM_HOST, pairs=(), max_refine=30):
+    npairs = len(pairs)
+    arr = (C.c_int32 * max(1, 2 * npairs))(*[int(v) for p in pairs for v in p])
+    o = afd_solve_opts(float(rtol), int(max_iter), int(precision), float(inner_rtol), int(check_every),
+                       int(mem_kind), C.cast(arr, C.POINTER(C.c_int32)), npairs, int(max_refine))
+    o._keep = arr  # keep the pair array alive with the struct
+    return o
+
+
+def afd_solve(mesh, opts, nrhs, F, U, J=None, S=None, raise_on_error=True):
+    """Returns (status, [afd_solve_stats] * nrhs)."""
+    st = (afd_solve_stats * nrhs)()
+    code = lib().afd_solve(mesh, C.byref(opts), nrhs, _ptr(F), _ptr(U), _ptr(J), _ptr(S),
+                           C.cast(st, C.c_void_p))
+    if raise_on_error:
+        check(code, "afd_solve")
+    return code, list(st)

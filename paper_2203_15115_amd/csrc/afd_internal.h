@@ -1,0 +1,185 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/afdcg.h"
+
+namespace afd {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+struct Status {
+    int code = AFD_OK;
+};
+#define AFD_HIP_TRY(expr)                                                          \
+    do {                                                                           \
+        hipError_t _e = (expr);                                                    \
+        if (_e != hipSuccess) {                                                    \
+            ::afd::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));   \
+            return AFD_E_HIP;                                                      \
+        }                                                                          \
+    } while (0)
+#define AFD_TRY(expr)                   \
+    do {                                \
+        int _s = (expr);                \
+        if (_s != AFD_OK) return _s;    \
+    } while (0)
+
+// ------------------------------------------------------------ element data
+// The element matrix in the tensor-product Haar basis.  Per axis, a node pair
+// (v0, v1) maps to (s, d) = (v0 + v1, v1 - v0); in that basis the isotropic
+// voxel matrix is block-sparse: a diagonal dg[i][alpha] (alpha = 3-bit Haar
+// index, bit k = difference along axis k) and, for i != j, a coupling of
+// (alpha, i) with (alpha ^ e_i ^ e_j, j) whose value depends only on the
+// third axis k and its bit: lam*Mk/4 when alpha_i = 1, mu*Mk/4 when
+// alpha_j = 1 (Mk = hk/4 for bit 0, hk/12 for bit 1).
+struct KeHaar {
+    double dg[3][8];      // dg[i][alpha]; dg[i][0] = 0 (translations)
+    double cl[3][2];      // lam * M_k(bit) / 4, indexed [k][bit_k]
+    double cm[3][2];      // mu  * M_k(bit) / 4
+    double kdiag[3];      // diagonal of Ke for component c
+};
+KeHaar make_ke_haar(const double h[3], double E, double nu);
+void make_ke_dense(const double h[3], double E, double nu, double* ke576);  // row-major, LOCAL order
+
+// -------------------------------------------------------------- geometry
+struct Grid {
+    int nx, ny, nz;          // elements per axis
+    int64_t nnode, nelem, ndof;
+};
+
+// Deflation block geometry
+struct Blocks {
+    int b[3];                // block edge (elements)
+    int nb[3];               // blocks per axis
+    int nblk;                // total blocks
+    int ncoarse;             // 6 * nblk
+    double inv_scale;        // 1 / max(b)
+    int perm[3];             // axis order of the coarse ordering (fastest first)
+    int P;                   // super-block size of the block-tridiagonal coarse matrix
+    int K;                   // number of super-blocks
+    int w;                   // half bandwidth in the permuted ordering
+};
+
+// Per-right-hand-side CG scalars, device resident.
+struct CgScalars {
+    double rz, rz_new, pq, alpha, beta, rr, bb, rr0;
+    double tol2;             // (rtol * ||b||)^2 threshold on r.r
+    int32_t done;            // 0 running, 1 converged, 2 breakdown, 3 max_iter
+    int32_t iters;
+    int32_t max_iter;
+    int32_t pad;
+};
+
+// --------------------------------------------------------------- launchers
+// matvec.hip
+struct MatvecArgs {
+    Grid g;
+    const double* rho;       // nelem
+    const float* rho32;      // nelem (FP32 path)
+    const uint8_t* nmask;    // nnode, bit c = DOF c fixed
+};
+struct DcgArgs {
+    const double* rinv;      // nnode: 1 / sum of rho over the node's elements
+    Blocks blk;
+    int deflate;
+    const double* mu;        // [nrhs][ncoarse] (null if !deflate)
+    CgScalars* sc;           // [nrhs]
+    double* partial;         // [(rhs*2 + which) * npart + i]
+    int npart;
+};
+int matvec_num_tiles(const Grid& g);
+int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,
+                 hipStream_t s);
+int launch_residual(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* F,
+                    const double* X, double* R, hipStream_t s);
+int launch_dir_apply(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* Pold,
+                     double* Pnew, const double* R, double* Q, hipStream_t s);
+int launch_residual_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
+                        const float* F, const float* X, float* R, hipStream_t s);
+int launch_dir_apply_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
+                         const float* Pold, float* Pnew, const float* R, float* Q, hipStream_t s);
+int launch_apply_mfma(const MatvecArgs& a, const double* ke576_dev, int nrhs, const double* U, double* Y,
+                      hipStream_t s);
+
+// vec.hip
+constexpr int VEC_NPART = 1024;
+int launch_pack_mask(const Grid& g, const uint8_t* dofmask, uint8_t* nmask, hipStream_t s);
+int launch_node_rsum(const Grid& g, const double* rho, double* rinv, float* rinv32, hipStream_t s);
+int launch_jacobi_full(const Grid& g, const double* rinv, const uint8_t* nmask, const KeHaar& kh, double* d,
+                       hipStream_t s);
+int launch_dot(int64_t n, const double* x, const double* y, double* partial, int npart, double* out,
+               hipStream_t s);
+int launch_dot_rhs(int64_t ndof, int nrhs, const double* F, double* partial, int npart, hipStream_t s);
+int launch_dot_rhs_f32(int64_t ndof, int nrhs, const float* F, double* partial, int npart, hipStream_t s);
+int launch_cg_init(CgScalars* sc, int nrhs, const double* part, int npart, double rtol, int max_iter,
+                   hipStream_t s);
+int launch_cg_start(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
+int launch_scalar_alpha(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
+int launch_scalar_beta(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
+int launch_cg_update(const Grid& g, const KeHaar& kh, const double* rinv, CgScalars* sc, int nrhs, double* X,
+                     const double* Pv, double* R, const double* Q, double* Z, double* partial, int npart,
+                     hipStream_t s);
+int launch_cg_update_f32(const Grid& g, const KeHaar& kh, const float* rinv32, CgScalars* sc, int nrhs, float* X,
+                         const float* Pv, float* R, const float* Q, float* Z, double* partial, int npart,
+                         hipStream_t s);
+int launch_precond(const Grid& g, const KeHaar& kh, const double* rinv, int nrhs, const double* R, double* Z,
+                   hipStream_t s);
+int launch_precond_f32(const Grid& g, const KeHaar& kh, const float* rinv32, int nrhs, const float* R, float* Z,
+                       hipStream_t s);
+int launch_restrict(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V, double* G,
+                    hipStream_t s);
+int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V, double* G,
+                        hipStream_t s);
+int launch_prolong(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, double* V,
+                   hipStream_t s);
+int launch_prolong_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, float* V,
+                       hipStream_t s);
+int launch_probe_vector(const Grid& g, const Blocks& b, const uint8_t* nmask, int color, int mode, double* V,
+                        hipStream_t s);
+int launch_copy_f64(int64_t n, const double* a, double* b, hipStream_t s);
+int launch_fill_f64(int64_t n, double v, double* a, hipStream_t s);
+int launch_fill_f32(int64_t n, float v, float* a, hipStream_t s);
+// mixed precision helpers
+int launch_to_f32_scaled(int64_t ndof, int nrhs, const double* R, const CgScalars* outer, float* Rf, hipStream_t s);
+int launch_axpy_refine(int64_t ndof, int nrhs, const CgScalars* outer, const float* D, double* X, hipStream_t s);
+int launch_outer_norm(CgScalars* outer, int nrhs, const double* part, int npart, hipStream_t s);
+
+// dense.hip : coarse matrix and its block Cholesky
+struct Coarse {
+    Blocks blk;
+    double* D = nullptr;     // K x P x P : diagonal blocks of E, then L_kk
+    double* B = nullptr;     // K x P x P : sub-diagonal blocks E_{k+1,k}, then C_k = L_{k+1,k}
+    double* Linv = nullptr;  // K x P x P : L_kk^-1
+    double* T = nullptr;     // K x P x P : T_k = Linv_k C_{k-1}
+    double* U = nullptr;     // K x P x P : U_k = Linv_k^T C_k^T
+    double* Ediag = nullptr; // K*P original diagonal
+    double* work = nullptr;  // P x P
+    int32_t* dropped_dev = nullptr;
+    int32_t* perm = nullptr; // natural coarse index -> ordered index
+    double* gperm = nullptr; // [4][K*P]
+    double* xperm = nullptr; // [4][K*P]
+    double* cvec = nullptr;  // [4][K*P]
+    int dropped = 0;
+    bool valid = false;
+};
+int coarse_alloc(Coarse& c);
+void coarse_free(Coarse& c);
+int coarse_begin(Coarse& c, hipStream_t s);
+int coarse_scatter_probe(Coarse& c, const double* G, int color, int mode, hipStream_t s);
+int coarse_factor(Coarse& c, hipStream_t s);
+int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s);
+int coarse_to_dense_host(Coarse& c, double* E_host, hipStream_t s);  // before factor only
+
+// post.hip
+int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int nfields, const double* const* Ua,
+                       const double* const* Ub, double* S, hipStream_t s);
+int threshold_gpu(const double* s, int64_t n, double vol_frac, uint8_t* solid, int32_t* order, double* tau_host,
+                  hipStream_t st);
+
+}  // namespace afd

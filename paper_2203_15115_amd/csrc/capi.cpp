@@ -1,0 +1,853 @@
+// C ABI and host runtime: context and mesh state, the deflated PCG driver
+// (Sec. 3.5), FP32-inner / FP64-refined mixed precision, compliance
+// (Eq. 1.3) and element energies (Eq. 3.5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "afd_internal.h"
+
+namespace afd {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace afd
+
+using namespace afd;
+
+struct afd_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double* scratch = nullptr;  // dot partials
+};
+
+struct Work {
+    int nrhs = 0;
+    int mixed = 0;
+    // FP64 Krylov state [nrhs][ndof]
+    double *X = nullptr, *R = nullptr, *P0 = nullptr, *P1 = nullptr, *Q = nullptr, *Z = nullptr, *AZ = nullptr;
+    double *F = nullptr;   // device copy of F (host input)
+    double *S = nullptr;   // energies (host output)
+    // FP32 inner state
+    float *Xf = nullptr, *Rf = nullptr, *P0f = nullptr, *P1f = nullptr, *Qf = nullptr, *Zf = nullptr,
+          *AZf = nullptr, *Bf = nullptr;
+    double *G = nullptr, *MU = nullptr;  // coarse vectors [4][ncoarse]
+    CgScalars* sc = nullptr;             // [4] inner / FP64
+    CgScalars* outer = nullptr;          // [4] refinement
+    double *partM = nullptr, *partV = nullptr;
+    double* Jdev = nullptr;
+};
+
+struct afd_mesh {
+    afd_context* ctx = nullptr;
+    afd_mesh_desc desc{};
+    Grid g{};
+    KeHaar kh{};
+    Blocks blk{};
+    int deflate = 0;
+    double* rho = nullptr;
+    float* rho32 = nullptr;
+    uint8_t* nmask = nullptr;
+    uint8_t* dofmask = nullptr;  // staging for set_fixed
+    double* rinv = nullptr;
+    float* rinv32 = nullptr;
+    double* ke_dev = nullptr;    // dense Ke (576) for the matrix-core path
+    bool jacobi_valid = false;
+    bool any_fixed = false;
+    Coarse coarse;
+    Work w;
+    int npartM = 0;
+};
+
+namespace {
+
+int check_ctx(afd_context* c) {
+    if (!c) {
+        set_error("null context");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_HIP_TRY(hipSetDevice(c->device));
+    return AFD_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+    if (*p) return AFD_OK;
+    if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        set_error("device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+        return AFD_E_OOM;
+    }
+    return AFD_OK;
+}
+template <typename T>
+void dfree(T** p) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+void free_work(Work& w) {
+    dfree(&w.X), dfree(&w.R), dfree(&w.P0), dfree(&w.P1), dfree(&w.Q), dfree(&w.Z), dfree(&w.AZ), dfree(&w.F),
+        dfree(&w.S);
+    dfree(&w.Xf), dfree(&w.Rf), dfree(&w.P0f), dfree(&w.P1f), dfree(&w.Qf), dfree(&w.Zf), dfree(&w.AZf),
+        dfree(&w.Bf);
+    dfree(&w.G), dfree(&w.MU), dfree(&w.sc), dfree(&w.outer), dfree(&w.partM), dfree(&w.partV), dfree(&w.Jdev);
+    w.nrhs = 0;
+    w.mixed = 0;
+}
+
+int ensure_work(afd_mesh* m, int nrhs, int mixed) {
+    Work& w = m->w;
+    if (w.nrhs >= nrhs && w.mixed >= mixed) return AFD_OK;
+    int nr = std::max(nrhs, w.nrhs);
+    int mx = std::max(mixed, w.mixed);
+    free_work(w);
+    const size_t n = (size_t)nr * m->g.ndof;
+    AFD_TRY(dalloc(&w.X, n));
+    AFD_TRY(dalloc(&w.R, n));
+    AFD_TRY(dalloc(&w.P0, n));
+    AFD_TRY(dalloc(&w.P1, n));
+    AFD_TRY(dalloc(&w.Q, n));
+    AFD_TRY(dalloc(&w.Z, n));
+    AFD_TRY(dalloc(&w.AZ, n));
+    AFD_TRY(dalloc(&w.F, n));
+    if (mx) {
+        AFD_TRY(dalloc(&w.Xf, n));
+        AFD_TRY(dalloc(&w.Rf, n));
+        AFD_TRY(dalloc(&w.P0f, n));
+        AFD_TRY(dalloc(&w.P1f, n));
+        AFD_TRY(dalloc(&w.Qf, n));
+        AFD_TRY(dalloc(&w.Zf, n));
+        AFD_TRY(dalloc(&w.AZf, n));
+        AFD_TRY(dalloc(&w.Bf, n));
+    }
+    AFD_TRY(dalloc(&w.G, (size_t)4 * std::max(1, m->blk.ncoarse)));
+    AFD_TRY(dalloc(&w.MU, (size_t)4 * std::max(1, m->blk.ncoarse)));
+    AFD_TRY(dalloc(&w.sc, 4));
+    AFD_TRY(dalloc(&w.outer, 4));
+    AFD_TRY(dalloc(&w.partM, (size_t)8 * m->npartM));
+    AFD_TRY(dalloc(&w.partV, (size_t)8 * VEC_NPART));
+    AFD_TRY(dalloc(&w.Jdev, 4));
+    w.nrhs = nr;
+    w.mixed = mx;
+    return AFD_OK;
+}
+
+MatvecArgs mv_args(afd_mesh* m) {
+    MatvecArgs a;
+    a.g = m->g;
+    a.rho = m->rho;
+    a.rho32 = m->rho32;
+    a.nmask = m->nmask;
+    return a;
+}
+
+int ensure_jacobi(afd_mesh* m) {
+    if (m->jacobi_valid) return AFD_OK;
+    AFD_TRY(launch_node_rsum(m->g, m->rho, m->rinv, m->rinv32, m->ctx->stream));
+    m->jacobi_valid = true;
+    return AFD_OK;
+}
+
+void setup_blocks(afd_mesh* m) {
+    Blocks& b = m->blk;
+    const int n[3] = {m->g.nx, m->g.ny, m->g.nz};
+    const int bb[3] = {m->desc.bx, m->desc.by, m->desc.bz};
+    m->deflate = (bb[0] > 0 && bb[1] > 0 && bb[2] > 0) ? 1 : 0;
+    b = Blocks{};
+    if (!m->deflate) return;
+    int mx = 0;
+    for (int a = 0; a < 3; ++a) {
+        b.b[a] = std::min(bb[a], n[a]);
+        b.nb[a] = (n[a] + b.b[a] - 1) / b.b[a];
+        mx = std::max(mx, b.b[a]);
+    }
+    b.inv_scale = 1.0 / mx;
+    b.nblk = b.nb[0] * b.nb[1] * b.nb[2];
+    b.ncoarse = 6 * b.nblk;
+    int ax[3] = {0, 1, 2};
+    std::stable_sort(ax, ax + 3, [&](int p, int q) { return b.nb[p] < b.nb[q]; });
+    for (int a = 0; a < 3; ++a) b.perm[a] = ax[a];
+    const int n0 = b.nb[ax[0]], n1 = b.nb[ax[1]];
+    b.w = 6 * (n0 * n1 + n0 + 1) + 5;
+    int P = ((b.w + 63) / 64) * 64;
+    const int nc64 = ((b.ncoarse + 63) / 64) * 64;
+    if (P > nc64) P = nc64;
+    b.P = P;
+    b.K = (b.ncoarse + P - 1) / P;
+}
+
+// E = W^T A W by probing: 27 colors of a 3x3x3 block pattern x 6 motions
+int ensure_coarse(afd_mesh* m) {
+    if (!m->deflate) return AFD_OK;
+    if (m->coarse.valid) return AFD_OK;
+    hipStream_t s = m->ctx->stream;
+    if (!m->coarse.D) {
+        m->coarse.blk = m->blk;
+        AFD_TRY(coarse_alloc(m->coarse));
+    }
+    AFD_TRY(ensure_work(m, 1, 0));
+    AFD_TRY(coarse_begin(m->coarse, s));
+    MatvecArgs a = mv_args(m);
+    for (int color = 0; color < 27; ++color) {
+        const int cc[3] = {color % 3, (color / 3) % 3, color / 9};
+        if (cc[0] >= m->blk.nb[0] || cc[1] >= m->blk.nb[1] || cc[2] >= m->blk.nb[2]) continue;
+        for (int mode = 0; mode < 6; ++mode) {
+            AFD_TRY(launch_probe_vector(m->g, m->blk, m->nmask, color, mode, m->w.Z, s));
+            AFD_TRY(launch_apply(a, m->kh, 0, 1, m->w.Z, m->w.AZ, s));
+            AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, 1, m->w.AZ, m->w.G, s));
+            AFD_TRY(coarse_scatter_probe(m->coarse, m->w.G, color, mode, s));
+        }
+    }
+    return coarse_factor(m->coarse, s);
+}
+
+int host_or_dev_to_dev(afd_mesh* m, const void* src, size_t bytes, int mem_kind, void* dst) {
+    AFD_HIP_TRY(hipMemcpyAsync(dst, src, bytes, mem_kind == AFD_MEM_HOST ? hipMemcpyHostToDevice
+                                                                         : hipMemcpyDeviceToDevice,
+                               m->ctx->stream));
+    if (mem_kind == AFD_MEM_HOST) AFD_HIP_TRY(hipStreamSynchronize(m->ctx->stream));
+    return AFD_OK;
+}
+
+DcgArgs dcg_args(afd_mesh* m, CgScalars* sc, double* part, int npart) {
+    DcgArgs d;
+    d.rinv = m->rinv;
+    d.blk = m->blk;
+    d.deflate = m->deflate;
+    d.mu = m->w.MU;
+    d.sc = sc;
+    d.partial = part;
+    d.npart = npart;
+    return d;
+}
+
+// Deflated Jacobi-PCG on A X = B (Saad et al.): x0 = W E^-1 W^T b, r0 = b - A x0,
+// then q = A p, alpha = r.z/p.q, x += alpha p, r -= alpha q, z = M^-1 r,
+// beta = r.z_new/r.z, mu = E^-1 W^T A z, p = beta p + z - W mu.
+// FP64 (T = double) or FP32 vectors (T = float, inner solve of the mixed form);
+// dot products and the coarse problem are always FP64.
+template <typename T>
+int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, T* Z, T* AZ, CgScalars* sc,
+            double rtol, int max_iter, int check_every, const CgScalars* outer_mask) {
+    hipStream_t s = m->ctx->stream;
+    Work& w = m->w;
+    MatvecArgs a = mv_args(m);
+    const bool f32 = sizeof(T) == 4;
+    const int64_t ndof = m->g.ndof;
+    // ||b||
+    if constexpr (sizeof(T) == 8) AFD_TRY(launch_dot_rhs(ndof, nrhs, (const double*)Bv, w.partV, VEC_NPART, s));
+    else AFD_TRY(launch_dot_rhs_f32(ndof, nrhs, (const float*)Bv, w.partV, VEC_NPART, s));
+    AFD_TRY(launch_cg_init(sc, nrhs, w.partV, VEC_NPART, rtol, max_iter, s));
+    (void)outer_mask;
+    // deflated start
+    if (m->deflate) {
+        if constexpr (sizeof(T) == 8) AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
+        else AFD_TRY(launch_restrict_f32(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
+        AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s));
+        if constexpr (sizeof(T) == 8) AFD_TRY(launch_prolong(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
+        else AFD_TRY(launch_prolong_f32(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
+    } else {
+        if constexpr (sizeof(T) == 8) AFD_TRY(launch_fill_f64(nrhs * ndof, 0.0, (double*)X, s));
+        else AFD_TRY(launch_fill_f32(nrhs * ndof, 0.0f, (float*)X, s));
+    }
+    DcgArgs dm = dcg_args(m, sc, w.partM, m->npartM);
+    if constexpr (sizeof(T) == 8) AFD_TRY(launch_residual(a, m->kh, dm, nrhs, Bv, X, R, s));
+    else AFD_TRY(launch_residual_f32(a, m->kh, dm, m->rinv32, nrhs, Bv, X, R, s));
+    AFD_TRY(launch_cg_start(sc, nrhs, w.partM, m->npartM, s));
+    auto coarse_of_z = [&]() -> int {
+        if (!m->deflate) return AFD_OK;
+        if constexpr (sizeof(T) == 8) {
+            AFD_TRY(launch_apply(a, m->kh, 0, nrhs, Z, AZ, s));
+            AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, nrhs, AZ, w.G, s));
+        } else {
+            AFD_TRY(launch_apply(a, m->kh, 1, nrhs, Z, AZ, s));
+            AFD_TRY(launch_restrict_f32(m->g, m->blk, m->nmask, nrhs, AZ, w.G, s));
+        }
+        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s);
+    };
+    if (m->deflate) {
+        if constexpr (sizeof(T) == 8) AFD_TRY(launch_precond(m->g, m->kh, m->rinv, nrhs, R, Z, s));
+        else AFD_TRY(launch_precond_f32(m->g, m->kh, m->rinv32, nrhs, R, Z, s));
+        AFD_TRY(coarse_of_z());
+    }
+    if constexpr (sizeof(T) == 8) AFD_TRY(launch_fill_f64(nrhs * ndof, 0.0, (double*)P0, s));
+    else AFD_TRY(launch_fill_f32(nrhs * ndof, 0.0f, (float*)P0, s));
+    if constexpr (sizeof(T) == 8) AFD_TRY(launch_dir_apply(a, m->kh, dm, nrhs, P0, P1, R, Q, s));
+    else AFD_TRY(launch_dir_apply_f32(a, m->kh, dm, m->rinv32, nrhs, P0, P1, R, Q, s));
+    std::swap(P0, P1);
+    std::vector<CgScalars> hsc(nrhs);
+    const int ce = std::max(1, check_every);
+    for (int it = 0; it < max_iter; ++it) {
+        AFD_TRY(launch_scalar_alpha(sc, nrhs, w.partM, m->npartM, s));
+        if constexpr (sizeof(T) == 8)
+            AFD_TRY(launch_cg_update(m->g, m->kh, m->rinv, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr, w.partV,
+                                     VEC_NPART, s));
+        else
+            AFD_TRY(launch_cg_update_f32(m->g, m->kh, m->rinv32, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr,
+                                         w.partV, VEC_NPART, s));
+        AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
+        AFD_TRY(coarse_of_z());
+        if constexpr (sizeof(T) == 8) AFD_TRY(launch_dir_apply(a, m->kh, dm, nrhs, P0, P1, R, Q, s));
+        else AFD_TRY(launch_dir_apply_f32(a, m->kh, dm, m->rinv32, nrhs, P0, P1, R, Q, s));
+        std::swap(P0, P1);
+        if ((it + 1) % ce == 0 || it + 1 == max_iter) {
+            AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+            AFD_HIP_TRY(hipStreamSynchronize(s));
+            bool all = true;
+            for (int r = 0; r < nrhs; ++r) all = all && hsc[r].done != 0;
+            if (all) break;
+        }
+    }
+    (void)f32;
+    return AFD_OK;
+}
+
+int status_of(int done) {
+    if (done == 1) return AFD_OK;
+    if (done == 2) return AFD_E_BREAKDOWN;
+    return AFD_E_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* afd_last_error(void) { return g_err.c_str(); }
+
+int afd_context_create(int device, void* hip_stream, afd_context** out) {
+    if (!out) {
+        set_error("null output pointer");
+        return AFD_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        set_error("no HIP device");
+        return AFD_E_NO_DEVICE;
+    }
+    if (device < 0 || device >= n) {
+        set_error("device index out of range");
+        return AFD_E_NO_DEVICE;
+    }
+    AFD_HIP_TRY(hipSetDevice(device));
+    afd_context* c = new afd_context();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            set_error("hipStreamCreate failed");
+            return AFD_E_HIP;
+        }
+        c->own_stream = true;
+    }
+    if (hipMalloc((void**)&c->scratch, VEC_NPART * sizeof(double)) != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        set_error("device allocation failed");
+        return AFD_E_OOM;
+    }
+    *out = c;
+    return AFD_OK;
+}
+
+void afd_context_destroy(afd_context* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->scratch) (void)hipFree(c->scratch);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int afd_context_sync(afd_context* c) {
+    AFD_TRY(check_ctx(c));
+    AFD_HIP_TRY(hipStreamSynchronize(c->stream));
+    return AFD_OK;
+}
+
+int afd_mesh_create(afd_context* ctx, const afd_mesh_desc* d, afd_mesh** out) {
+    AFD_TRY(check_ctx(ctx));
+    if (!d || !out) {
+        set_error("null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || !(d->hx > 0) || !(d->hy > 0) || !(d->hz > 0) || !(d->E > 0) ||
+        !(d->nu > -1.0 && d->nu < 0.5) || d->bx < 0 || d->by < 0 || d->bz < 0 || !std::isfinite(d->hx) ||
+        !std::isfinite(d->hy) || !std::isfinite(d->hz) || !std::isfinite(d->E)) {
+        set_error("invalid mesh description (need n >= 1, h > 0, E > 0, -1 < nu < 0.5, b >= 0)");
+        return AFD_E_INVALID_ARG;
+    }
+    const int64_t nnode = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+    if (3 * nnode >= ((int64_t)1 << 31)) {
+        set_error("mesh too large (3 * nodes must fit in int32)");
+        return AFD_E_INVALID_ARG;
+    }
+    afd_mesh* m = new afd_mesh();
+    m->ctx = ctx;
+    m->desc = *d;
+    m->g.nx = d->nx;
+    m->g.ny = d->ny;
+    m->g.nz = d->nz;
+    m->g.nnode = nnode;
+    m->g.nelem = (int64_t)d->nx * d->ny * d->nz;
+    m->g.ndof = 3 * nnode;
+    const double h[3] = {d->hx, d->hy, d->hz};
+    m->kh = make_ke_haar(h, d->E, d->nu);
+    setup_blocks(m);
+    m->npartM = matvec_num_tiles(m->g);
+    std::vector<double> ke(576);
+    make_ke_dense(h, d->E, d->nu, ke.data());
+    int rc = AFD_OK;
+    if ((rc = dalloc(&m->rho, m->g.nelem)) || (rc = dalloc(&m->rho32, m->g.nelem)) ||
+        (rc = dalloc(&m->nmask, m->g.nnode)) || (rc = dalloc(&m->dofmask, m->g.ndof)) ||
+        (rc = dalloc(&m->rinv, m->g.nnode)) || (rc = dalloc(&m->rinv32, m->g.nnode)) ||
+        (rc = dalloc(&m->ke_dev, 576))) {
+        afd_mesh_destroy(m);
+        return rc;
+    }
+    hipStream_t s = ctx->stream;
+    if (launch_fill_f64(m->g.nelem, 1.0, m->rho, s) || launch_fill_f32(m->g.nelem, 1.0f, m->rho32, s) ||
+        hipMemsetAsync(m->nmask, 0, m->g.nnode, s) != hipSuccess ||
+        hipMemcpyAsync(m->ke_dev, ke.data(), 576 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        afd_mesh_destroy(m);
+        set_error("mesh initialisation failed");
+        return AFD_E_HIP;
+    }
+    *out = m;
+    return AFD_OK;
+}
+
+void afd_mesh_destroy(afd_mesh* m) {
+    if (!m) return;
+    (void)hipSetDevice(m->ctx->device);
+    (void)hipStreamSynchronize(m->ctx->stream);
+    free_work(m->w);
+    coarse_free(m->coarse);
+    dfree(&m->rho), dfree(&m->rho32), dfree(&m->nmask), dfree(&m->dofmask), dfree(&m->rinv), dfree(&m->rinv32),
+        dfree(&m->ke_dev);
+    delete m;
+}
+
+int afd_mesh_sizes(const afd_mesh* m, int64_t* ne, int64_t* nn, int64_t* nd, int64_t* nc) {
+    if (!m) {
+        set_error("null mesh");
+        return AFD_E_INVALID_ARG;
+    }
+    if (ne) *ne = m->g.nelem;
+    if (nn) *nn = m->g.nnode;
+    if (nd) *nd = m->g.ndof;
+    if (nc) *nc = m->deflate ? m->blk.ncoarse : 0;
+    return AFD_OK;
+}
+
+__global__ void k_rho32(int64_t n, const double* a, float* b) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+int afd_mesh_set_scale(afd_mesh* m, const double* rho, int64_t n, int mem_kind) {
+    if (!m || !rho) {
+        set_error("null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    if (n != m->g.nelem || (mem_kind != AFD_MEM_HOST && mem_kind != AFD_MEM_DEVICE)) {
+        set_error("set_scale: n_elem mismatch or bad mem_kind");
+        return AFD_E_INVALID_ARG;
+    }
+    if (mem_kind == AFD_MEM_HOST)
+        for (int64_t i = 0; i < n; ++i)
+            if (!(rho[i] > 0.0) || !std::isfinite(rho[i])) {
+                set_error("set_scale: rho must be positive and finite (element " + std::to_string(i) + ")");
+                return AFD_E_INVALID_ARG;
+            }
+    AFD_TRY(host_or_dev_to_dev(m, rho, n * sizeof(double), mem_kind, m->rho));
+    hipLaunchKernelGGL(k_rho32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, m->ctx->stream, n, m->rho, m->rho32);
+    AFD_HIP_TRY(hipGetLastError());
+    m->jacobi_valid = false;
+    m->coarse.valid = false;
+    return AFD_OK;
+}
+
+int afd_mesh_set_fixed(afd_mesh* m, const uint8_t* mask, int64_t n, int mem_kind) {
+    if (!m || !mask) {
+        set_error("null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    if (n != m->g.ndof || (mem_kind != AFD_MEM_HOST && mem_kind != AFD_MEM_DEVICE)) {
+        set_error("set_fixed: n_dof mismatch or bad mem_kind");
+        return AFD_E_INVALID_ARG;
+    }
+    if (mem_kind == AFD_MEM_HOST) {
+        bool any = false;
+        for (int64_t i = 0; i < n && !any; ++i) any = mask[i] != 0;
+        m->any_fixed = any;
+    } else {
+        m->any_fixed = true;
+    }
+    AFD_TRY(host_or_dev_to_dev(m, mask, n, mem_kind, m->dofmask));
+    AFD_TRY(launch_pack_mask(m->g, m->dofmask, m->nmask, m->ctx->stream));
+    m->coarse.valid = false;
+    return AFD_OK;
+}
+
+int afd_mesh_footprint(const afd_mesh* m, int32_t nrhs, int32_t precision, uint64_t* bytes) {
+    if (!m || !bytes || nrhs < 1 || nrhs > 4) {
+        set_error("footprint: bad argument");
+        return AFD_E_INVALID_ARG;
+    }
+    const uint64_t nd = m->g.ndof, nn = m->g.nnode, ne = m->g.nelem;
+    uint64_t b = ne * 12 + nn * (1 + 12) + nd + 576 * 8;                 // rho, rho32, masks, rinv
+    b += (uint64_t)nrhs * nd * 8 * 8;                                    // FP64 work vectors
+    if (precision == AFD_MIXED) b += (uint64_t)nrhs * nd * 4 * 8;        // FP32 inner vectors
+    if (m->deflate) {
+        const uint64_t PP = (uint64_t)m->blk.P * m->blk.P;
+        b += PP * m->blk.K * 8 * 5 + PP * 8 + (uint64_t)m->blk.K * m->blk.P * 8 * 14;
+    }
+    b += (uint64_t)m->npartM * 64 + VEC_NPART * 64;
+    *bytes = b;
+    return AFD_OK;
+}
+
+int afd_mesh_ke(const afd_mesh* m, double* ke) {
+    if (!m || !ke) {
+        set_error("null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
+    make_ke_dense(h, m->desc.E, m->desc.nu, ke);
+    return AFD_OK;
+}
+
+int afd_apply_K(afd_mesh* m, int32_t precision, int32_t nrhs, const void* U, void* Y) {
+    if (!m || !U || !Y || nrhs < 1 || nrhs > 4 || (precision != AFD_FP64 && precision != AFD_FP32)) {
+        set_error("apply_K: bad argument (nrhs 1..4, precision FP64 or FP32)");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    return launch_apply(mv_args(m), m->kh, precision == AFD_FP32, nrhs, U, Y, m->ctx->stream);
+}
+
+int afd_apply_K_mfma(afd_mesh* m, int32_t nrhs, const double* U, double* Y) {
+    if (!m || !U || !Y || nrhs < 1 || nrhs > 4) {
+        set_error("apply_K_mfma: bad argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    return launch_apply_mfma(mv_args(m), m->ke_dev, nrhs, U, Y, m->ctx->stream);
+}
+
+int afd_jacobi(afd_mesh* m, double* d) {
+    if (!m || !d) {
+        set_error("null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    AFD_TRY(ensure_jacobi(m));
+    return launch_jacobi_full(m->g, m->rinv, m->nmask, m->kh, d, m->ctx->stream);
+}
+
+int afd_dot(afd_context* c, int64_t n, const double* x, const double* y, double* out) {
+    AFD_TRY(check_ctx(c));
+    if (n < 0 || !x || !y || !out) {
+        set_error("dot: bad argument");
+        return AFD_E_INVALID_ARG;
+    }
+    return launch_dot(n, x, y, c->scratch, VEC_NPART, out, c->stream);
+}
+
+static int need_deflate(afd_mesh* m) {
+    if (!m) {
+        set_error("null mesh");
+        return AFD_E_INVALID_ARG;
+    }
+    if (!m->deflate) {
+        set_error("deflation disabled for this mesh (block size 0)");
+        return AFD_E_INVALID_ARG;
+    }
+    return check_ctx(m->ctx);
+}
+
+int afd_restrict(afd_mesh* m, int32_t nrhs, const double* V, double* G) {
+    AFD_TRY(need_deflate(m));
+    if (nrhs < 1 || nrhs > 4 || !V || !G) {
+        set_error("restrict: bad argument");
+        return AFD_E_INVALID_ARG;
+    }
+    return launch_restrict(m->g, m->blk, m->nmask, nrhs, V, G, m->ctx->stream);
+}
+
+int afd_prolong(afd_mesh* m, int32_t nrhs, const double* MU, double* V) {
+    AFD_TRY(need_deflate(m));
+    if (nrhs < 1 || nrhs > 4 || !V || !MU) {
+        set_error("prolong: bad argument");
+        return AFD_E_INVALID_ARG;
+    }
+    return launch_prolong(m->g, m->blk, m->nmask, nrhs, MU, V, m->ctx->stream);
+}
+
+int afd_coarse_setup(afd_mesh* m, int32_t* dropped) {
+    AFD_TRY(need_deflate(m));
+    AFD_TRY(ensure_coarse(m));
+    if (dropped) *dropped = m->coarse.dropped;
+    return AFD_OK;
+}
+
+int afd_coarse_matrix(afd_mesh* m, double* E) {
+    AFD_TRY(need_deflate(m));
+    if (!E || m->blk.ncoarse > 8192) {
+        set_error("coarse_matrix: null output or n_coarse > 8192");
+        return AFD_E_INVALID_ARG;
+    }
+    // assemble (without factoring) into the coarse buffers, copy out, invalidate
+    hipStream_t s = m->ctx->stream;
+    if (!m->coarse.D) {
+        m->coarse.blk = m->blk;
+        AFD_TRY(coarse_alloc(m->coarse));
+    }
+    AFD_TRY(ensure_work(m, 1, 0));
+    AFD_TRY(coarse_begin(m->coarse, s));
+    MatvecArgs a = mv_args(m);
+    for (int color = 0; color < 27; ++color) {
+        const int cc[3] = {color % 3, (color / 3) % 3, color / 9};
+        if (cc[0] >= m->blk.nb[0] || cc[1] >= m->blk.nb[1] || cc[2] >= m->blk.nb[2]) continue;
+        for (int mode = 0; mode < 6; ++mode) {
+            AFD_TRY(launch_probe_vector(m->g, m->blk, m->nmask, color, mode, m->w.Z, s));
+            AFD_TRY(launch_apply(a, m->kh, 0, 1, m->w.Z, m->w.AZ, s));
+            AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, 1, m->w.AZ, m->w.G, s));
+            AFD_TRY(coarse_scatter_probe(m->coarse, m->w.G, color, mode, s));
+        }
+    }
+    int rc = coarse_to_dense_host(m->coarse, E, s);
+    m->coarse.valid = false;
+    return rc;
+}
+
+int afd_coarse_solve(afd_mesh* m, int32_t nrhs, const double* G, double* MU) {
+    AFD_TRY(need_deflate(m));
+    if (nrhs < 1 || nrhs > 4 || !G || !MU) {
+        set_error("coarse_solve: bad argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(ensure_coarse(m));
+    return coarse_solve(m->coarse, nrhs, G, MU, m->ctx->stream);
+}
+
+int afd_sensitivity(afd_mesh* m, int32_t nrhs, const double* U, int32_t npairs, const int32_t* pairs, double* S) {
+    if (!m || !U || !S || nrhs < 1 || nrhs > 4 || npairs < 0 || nrhs + npairs > 16 || (npairs > 0 && !pairs)) {
+        set_error("sensitivity: bad argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    const double* ua[16];
+    const double* ub[16];
+    for (int f = 0; f < nrhs; ++f) ua[f] = ub[f] = U + (int64_t)f * m->g.ndof;
+    for (int p = 0; p < npairs; ++p) {
+        const int a = pairs[2 * p], b = pairs[2 * p + 1];
+        if (a < 0 || a >= nrhs || b < 0 || b >= nrhs) {
+            set_error("sensitivity: pair index out of range");
+            return AFD_E_INVALID_ARG;
+        }
+        ua[nrhs + p] = U + (int64_t)a * m->g.ndof;
+        ub[nrhs + p] = U + (int64_t)b * m->g.ndof;
+    }
+    return launch_sensitivity(m->g, m->kh, m->rho, nrhs + npairs, ua, ub, S, m->ctx->stream);
+}
+
+int afd_threshold(afd_context* c, const double* s, int64_t n, double vol_frac, uint8_t* solid, int32_t* order,
+                  double* tau) {
+    AFD_TRY(check_ctx(c));
+    if (!s || !solid) {
+        set_error("threshold: null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    return threshold_gpu(s, n, vol_frac, solid, order, tau, c->stream);
+}
+
+int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* F, double* U, double* J, double* S,
+              afd_solve_stats* st) {
+    if (!m || !o || !F || !U || nrhs < 1 || nrhs > 4) {
+        set_error("solve: bad argument (nrhs 1..4, non-null F, U, opts)");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    if (!(o->rtol > 0) || o->max_iter < 1 || (o->precision != AFD_FP64 && o->precision != AFD_MIXED) ||
+        (o->mem_kind != AFD_MEM_HOST && o->mem_kind != AFD_MEM_DEVICE) || o->npairs < 0 ||
+        nrhs + o->npairs > 16 || (o->npairs > 0 && !o->pairs)) {
+        set_error("solve: bad options");
+        return AFD_E_INVALID_ARG;
+    }
+    for (int p = 0; p < o->npairs; ++p)
+        if (o->pairs[2 * p] < 0 || o->pairs[2 * p] >= nrhs || o->pairs[2 * p + 1] < 0 ||
+            o->pairs[2 * p + 1] >= nrhs) {
+            set_error("solve: pair index out of range");
+            return AFD_E_INVALID_ARG;
+        }
+    const int64_t ndof = m->g.ndof;
+    const bool host = o->mem_kind == AFD_MEM_HOST;
+    if (host) {
+        std::vector<uint8_t> mask(ndof);
+        AFD_HIP_TRY(hipMemcpy(mask.data(), m->dofmask, ndof, hipMemcpyDeviceToHost));
+        for (int r = 0; r < nrhs; ++r)
+            for (int64_t i = 0; i < ndof; ++i) {
+                const double f = F[r * ndof + i];
+                if (!std::isfinite(f) || (m->any_fixed && mask[i] && f != 0.0)) {
+                    set_error("solve: F must be finite and zero on fixed DOFs");
+                    return AFD_E_INVALID_ARG;
+                }
+            }
+    }
+    hipStream_t s = m->ctx->stream;
+    const bool mixed = o->precision == AFD_MIXED;
+    const double t0 = now_s();
+    AFD_TRY(ensure_work(m, nrhs, mixed ? 1 : 0));
+    AFD_TRY(ensure_jacobi(m));
+    AFD_TRY(ensure_coarse(m));
+    Work& w = m->w;
+    AFD_HIP_TRY(hipMemcpyAsync(w.F, F, nrhs * ndof * sizeof(double),
+                               host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    AFD_HIP_TRY(hipStreamSynchronize(s));
+    const double t1 = now_s();
+    const int ce = o->check_every > 0 ? o->check_every : 16;
+    std::vector<CgScalars> hsc(nrhs), hout(nrhs);
+    int refinements = 0;
+    if (!mixed) {
+        AFD_TRY(dcg_run<double>(m, nrhs, w.F, w.X, w.R, w.P0, w.P1, w.Q, w.Z, w.AZ, w.sc, o->rtol, o->max_iter, ce,
+                                nullptr));
+        AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), w.sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    } else {
+        // FP64 iterative refinement around an FP32 deflated PCG
+        MatvecArgs a = mv_args(m);
+        const int max_ref = o->max_refine > 0 ? o->max_refine : 30;
+        const double inner = (o->inner_rtol > 0 && o->inner_rtol < 1) ? o->inner_rtol : 1e-4;
+        AFD_TRY(launch_dot_rhs(ndof, nrhs, w.F, w.partV, VEC_NPART, s));
+        AFD_TRY(launch_cg_init(w.outer, nrhs, w.partV, VEC_NPART, o->rtol, max_ref, s));
+        AFD_TRY(launch_fill_f64(nrhs * ndof, 0.0, w.X, s));
+        int total_inner = 0;
+        std::vector<int> inner_iters(nrhs, 0);
+        for (int ref = 0; ref <= max_ref; ++ref) {
+            DcgArgs dm = dcg_args(m, w.outer, w.partM, m->npartM);
+            // residual r = f - A x in FP64 (partials: slot 1 = r.r); the outer
+            // scalars are not "done" yet for RESID unless converged
+            AFD_TRY(launch_residual(a, m->kh, dm, nrhs, w.F, w.X, w.R, s));
+            AFD_TRY(launch_outer_norm(w.outer, nrhs, w.partM, m->npartM, s));
+            AFD_HIP_TRY(hipMemcpyAsync(hout.data(), w.outer, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+            AFD_HIP_TRY(hipStreamSynchronize(s));
+            bool all = true;
+            for (int r = 0; r < nrhs; ++r) all = all && hout[r].done != 0;
+            if (all) break;
+            refinements = ref + 1;
+            AFD_TRY(launch_to_f32_scaled(ndof, nrhs, w.R, w.outer, w.Bf, s));
+            AFD_TRY(dcg_run<float>(m, nrhs, w.Bf, w.Xf, w.Rf, w.P0f, w.P1f, w.Qf, w.Zf, w.AZf, w.sc, inner,
+                                   o->max_iter, ce, w.outer));
+            AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), w.sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+            AFD_HIP_TRY(hipStreamSynchronize(s));
+            for (int r = 0; r < nrhs; ++r) {
+                inner_iters[r] += hsc[r].iters;
+                total_inner += hsc[r].iters;
+            }
+            AFD_TRY(launch_axpy_refine(ndof, nrhs, w.outer, w.Xf, w.X, s));
+        }
+        for (int r = 0; r < nrhs; ++r) {
+            hsc[r] = hout[r];
+            hsc[r].iters = inner_iters[r];
+        }
+        (void)total_inner;
+    }
+    AFD_HIP_TRY(hipStreamSynchronize(s));
+    const double t2 = now_s();
+    // true FP64 residual, compliance, energies
+    std::vector<double> rr(nrhs), bb(nrhs), Jh(nrhs);
+    {
+        AFD_TRY(launch_dot_rhs(ndof, nrhs, w.F, w.partV, VEC_NPART, s));
+        std::vector<double> part(2 * nrhs * VEC_NPART);
+        AFD_HIP_TRY(hipMemcpyAsync(part.data(), w.partV, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        // residual with a scalar set that is not done
+        std::vector<CgScalars> zero(nrhs);
+        memset(zero.data(), 0, nrhs * sizeof(CgScalars));
+        AFD_HIP_TRY(hipMemcpyAsync(w.outer, zero.data(), nrhs * sizeof(CgScalars), hipMemcpyHostToDevice, s));
+        DcgArgs dm = dcg_args(m, w.outer, w.partM, m->npartM);
+        AFD_TRY(launch_residual(mv_args(m), m->kh, dm, nrhs, w.F, w.X, w.Z, s));
+        std::vector<double> pm(2 * nrhs * (size_t)m->npartM);
+        AFD_HIP_TRY(hipMemcpyAsync(pm.data(), w.partM, pm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        for (int r = 0; r < nrhs; ++r) AFD_TRY(launch_dot(ndof, w.F + r * ndof, w.X + r * ndof, m->ctx->scratch,
+                                                           VEC_NPART, w.Jdev + r, s));
+        AFD_HIP_TRY(hipMemcpyAsync(Jh.data(), w.Jdev, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        AFD_HIP_TRY(hipStreamSynchronize(s));
+        for (int r = 0; r < nrhs; ++r) {
+            double b = 0, q = 0;
+            for (int i = 0; i < VEC_NPART; ++i) b += part[(size_t)(r * 2 + 1) * VEC_NPART + i];
+            for (int i = 0; i < m->npartM; ++i) q += pm[(size_t)(r * 2 + 1) * m->npartM + i];
+            bb[r] = b;
+            rr[r] = q;
+        }
+    }
+    if (host) {
+        AFD_HIP_TRY(hipMemcpyAsync(U, w.X, nrhs * ndof * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (J) memcpy(J, Jh.data(), nrhs * sizeof(double));
+    } else {
+        AFD_HIP_TRY(hipMemcpyAsync(U, w.X, nrhs * ndof * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (J) AFD_HIP_TRY(hipMemcpyAsync(J, w.Jdev, nrhs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (S) {
+        const int nf = nrhs + o->npairs;
+        double* Sd = S;
+        if (host) {
+            dfree(&w.S);
+            AFD_TRY(dalloc(&w.S, (size_t)nf * m->g.nelem));
+            Sd = w.S;
+        }
+        const double* ua[16];
+        const double* ub[16];
+        for (int f = 0; f < nrhs; ++f) ua[f] = ub[f] = w.X + (int64_t)f * ndof;
+        for (int p = 0; p < o->npairs; ++p) {
+            ua[nrhs + p] = w.X + (int64_t)o->pairs[2 * p] * ndof;
+            ub[nrhs + p] = w.X + (int64_t)o->pairs[2 * p + 1] * ndof;
+        }
+        AFD_TRY(launch_sensitivity(m->g, m->kh, m->rho, nf, ua, ub, Sd, s));
+        if (host)
+            AFD_HIP_TRY(hipMemcpyAsync(S, Sd, (size_t)nf * m->g.nelem * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    AFD_HIP_TRY(hipStreamSynchronize(s));
+    const double t3 = now_s();
+    int rc = AFD_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        int stt = status_of(hsc[r].done);
+        if (bb[r] == 0.0) stt = AFD_OK;
+        if (stt != AFD_OK && rc == AFD_OK) rc = stt;
+        if (st) {
+            st[r].iterations = hsc[r].iters;
+            st[r].refinements = refinements;
+            st[r].status = stt;
+            st[r].coarse_dropped = m->deflate ? m->coarse.dropped : 0;
+            st[r].rel_residual_true = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
+            st[r].t_setup = t1 - t0;
+            st[r].t_iter = t2 - t1;
+            st[r].t_post = t3 - t2;
+        }
+    }
+    if (rc != AFD_OK) set_error(rc == AFD_E_BREAKDOWN ? "solve: breakdown (p.Ap <= 0: singular or indefinite)"
+                                                      : "solve: not converged within max_iter");
+    return rc;
+}
+
+}  // extern "C"

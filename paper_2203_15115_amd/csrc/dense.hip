@@ -1,0 +1,517 @@
+// Coarse problem of the deflated CG (Sec. 3.5): E = W^T A W for W holding the
+// six rigid-body motions of every agglomerated block, its Cholesky factor,
+// and the solve mu = E^-1 g used once per iteration.
+//
+// Ordering: blocks are numbered with the two axes of fewest blocks fastest, so
+// E (27-neighbour 6x6 block stencil) has half bandwidth
+// w = 6 (n0 n1 + n0 + 1) + 5.  Cutting the ordered unknowns into super-blocks
+// of P >= w makes E block tridiagonal: diagonal blocks D_k, sub-diagonal blocks
+// B_k = E_{k+1,k}.  The block Cholesky E = L L^T gives
+//   L_kk L_kk^T = D_k - C_{k-1} C_{k-1}^T,   C_k = L_{k+1,k} = B_k L_kk^-T,
+// and the solve is then a chain of dense matrix-vector products with
+// precomputed matrices (no triangular solve on the critical path):
+//   forward  x_k = Linv_k g_k - T_k x_{k-1},        T_k = Linv_k C_{k-1}
+//   backward mu_k = Linv_k^T x_k - U_k mu_{k+1},    U_k = Linv_k^T C_k^T.
+// A pivot that falls below 1e-10 of the original diagonal marks a
+// rank-deficient coarse column (e.g. a block whose nodes are all fixed); it
+// is dropped: its row and column of Linv are zeroed, so its mu is 0.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "afd_internal.h"
+
+namespace afd {
+
+namespace {
+
+constexpr int NB = 64;  // tile of the blocked dense kernels
+constexpr double DROP_TOL = 1e-10;
+
+// ------------------------------------------------------------------ GEMM
+// C[M x N] = alpha * op(A) op(B) + beta * C, row-major, FP64.
+// op(A)(i,k) = ta ? A[k*lda + i] : A[i*lda + k]; op(B)(k,j) = tb ? B[j*ldb + k] : B[k*ldb + j]
+constexpr int GT = 64, GK = 16;
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha, const double* A, int lda, int ta,
+                                              const double* B, int ldb, int tb, double beta, double* C, int ldc) {
+    __shared__ double As[GK][GT + 1];
+    __shared__ double Bs[GK][GT + 1];
+    const int t = threadIdx.x;
+    const int tr = t / 16, tc = t % 16;  // 16x16 threads, 4x4 outputs each
+    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        for (int e = t; e < GT * GK; e += 256) {
+            // A tile: rows i0..i0+63, cols k0..k0+15
+            int ii, kk;
+            if (ta) {
+                ii = e % GT;
+                kk = e / GT;
+            } else {
+                kk = e % GK;
+                ii = e / GK;
+            }
+            const int gi = i0 + ii, gk = k0 + kk;
+            double av = 0.0;
+            if (gi < M && gk < K) av = ta ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk];
+            As[kk][ii] = av;
+            int jj, kb;
+            if (tb) {
+                kb = e % GK;
+                jj = e / GK;
+            } else {
+                jj = e % GT;
+                kb = e / GT;
+            }
+            const int gj = j0 + jj, gkb = k0 + kb;
+            double bv = 0.0;
+            if (gj < N && gkb < K) bv = tb ? B[(int64_t)gj * ldb + gkb] : B[(int64_t)gkb * ldb + gj];
+            Bs[kb][jj] = bv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[kk][tr + 16 * q];
+                b[q] = Bs[kk][tc + 16 * q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[q][u] = fma(a[q], b[u], acc[q][u]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int gi = i0 + tr + 16 * q, gj = j0 + tc + 16 * u;
+            if (gi < M && gj < N) {
+                double* c = C + (int64_t)gi * ldc + gj;
+                *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[q][u];
+            }
+        }
+}
+
+int gemm(int M, int N, int K, double alpha, const double* A, int lda, int ta, const double* B, int ldb, int tb,
+         double beta, double* C, int ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0) return AFD_OK;
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+// ---------------------------------------------------------- dense Cholesky
+// Factor the nb x nb diagonal tile at (j0, j0) of the row-major P x P matrix
+// A in place (lower), with dropping; write the tile inverse (rows/cols of
+// dropped pivots zeroed) to the same position of Linv.
+__global__ __launch_bounds__(256) void k_potrf_tile(double* A, double* Linv, int P, int j0, int nb,
+                                                    const double* ediag, int32_t* dropped) {
+    __shared__ double L[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    __shared__ int drop[NB];
+    const int t = threadIdx.x;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int r = e / NB, c = e % NB;
+        L[r][c] = (r < nb && c < nb && c <= r) ? A[(int64_t)(j0 + r) * P + j0 + c] : 0.0;
+        X[r][c] = 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < nb; ++c) {
+        if (t == 0) {
+            const double d = L[c][c];
+            const double e0 = ediag[j0 + c];
+            const bool dr = !(e0 > 0.0) || !(d > DROP_TOL * e0);
+            drop[c] = dr ? 1 : 0;
+            L[c][c] = dr ? 1.0 : sqrt(d);
+        }
+        __syncthreads();
+        const double piv = L[c][c];
+        const int dr = drop[c];
+        for (int r = c + 1 + t; r < nb; r += 256) L[r][c] = dr ? 0.0 : L[r][c] / piv;
+        __syncthreads();
+        // trailing update of the tile
+        for (int e = t; e < nb * nb; e += 256) {
+            const int r = e / nb, q = e % nb;
+            if (r > c && q > c && q <= r) L[r][q] -= L[r][c] * L[q][c];
+        }
+        __syncthreads();
+    }
+    // tile inverse by forward substitution, one column per thread
+    for (int col = t; col < nb; col += 256) {
+        for (int r = col; r < nb; ++r) {
+            double s = (r == col) ? 1.0 : 0.0;
+            for (int q = col; q < r; ++q) s -= L[r][q] * X[q][col];
+            X[r][col] = s / L[r][r];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < nb * nb; e += 256) {
+        const int r = e / nb, c = e % nb;
+        if (c <= r) {
+            A[(int64_t)(j0 + r) * P + j0 + c] = L[r][c];
+            const double x = (drop[r] || drop[c]) ? 0.0 : X[r][c];
+            Linv[(int64_t)(j0 + r) * P + j0 + c] = x;
+        }
+    }
+    if (t < nb) dropped[j0 + t] = drop[t];
+}
+
+// panel rows r >= j0+nb, cols j0..j0+nb-1:  A_rc <- sum_t A_rt Tinv_ct  (Tinv = diag tile of Linv)
+__global__ __launch_bounds__(256) void k_panel(double* A, const double* Linv, int P, int j0, int nb) {
+    __shared__ double Ti[NB][NB + 1];
+    __shared__ double Ar[64][NB + 1];
+    const int t = threadIdx.x;
+    const int r0 = j0 + nb + blockIdx.x * 64;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int r = e / NB, c = e % NB;
+        Ti[r][c] = (r < nb && c < nb) ? Linv[(int64_t)(j0 + r) * P + j0 + c] : 0.0;
+        const int gr = r0 + r;
+        Ar[r][c] = (gr < P && c < nb) ? A[(int64_t)gr * P + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * nb; e += 256) {
+        const int r = e / nb, c = e % nb;
+        const int gr = r0 + r;
+        if (gr >= P) continue;
+        double s = 0.0;
+        for (int q = 0; q <= c; ++q) s += Ar[r][q] * Ti[c][q];
+        A[(int64_t)gr * P + j0 + c] = s;
+    }
+}
+
+__global__ void k_zero_dropped(double* Linv, int P, const int32_t* dropped) {
+    const int r = blockIdx.y;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < P; c += gridDim.x * blockDim.x)
+        if (dropped[r] || dropped[c]) Linv[(int64_t)r * P + c] = 0.0;
+}
+
+__global__ void k_transpose(int P, const double* A, double* B) {
+    __shared__ double tile[32][33];
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    for (int q = threadIdx.y; q < 32; q += blockDim.y) {
+        const int r = y0 + q, c = x0 + threadIdx.x;
+        if (r < P && c < P) tile[q][threadIdx.x] = A[(int64_t)r * P + c];
+    }
+    __syncthreads();
+    for (int q = threadIdx.y; q < 32; q += blockDim.y) {
+        const int r = x0 + q, c = y0 + threadIdx.x;
+        if (r < P && c < P) B[(int64_t)r * P + c] = tile[threadIdx.x][q];
+    }
+}
+
+// -------------------------------------------------------------- assembly
+struct ScatP {
+    int nb[3];
+    int P, ncoarse;
+    const int32_t* perm;  // natural coarse index -> ordered index
+};
+
+// one thread per (block J, row mode m'): E[(J,m'),(I,m)] = G[6J+m'] with I the
+// block of `color` adjacent to J
+__global__ void k_scatter_probe(ScatP p, const double* G, int color, int mode, double* D, double* B) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nblk = p.nb[0] * p.nb[1] * p.nb[2];
+    if (q >= 6 * nblk) return;
+    const int J = q / 6, mr = q % 6;
+    const int jb[3] = {J % p.nb[0], (J / p.nb[0]) % p.nb[1], J / (p.nb[0] * p.nb[1])};
+    const int cc[3] = {color % 3, (color / 3) % 3, color / 9};
+    int ib[3];
+    for (int a = 0; a < 3; ++a) {
+        ib[a] = -1;
+        for (int d = -1; d <= 1; ++d) {
+            const int v = jb[a] + d;
+            if (v >= 0 && v < p.nb[a] && v % 3 == cc[a]) ib[a] = v;
+        }
+        if (ib[a] < 0) return;
+    }
+    const int I = ib[0] + p.nb[0] * (ib[1] + p.nb[1] * ib[2]);
+    const int row = p.perm[6 * J + mr], col = p.perm[6 * I + mode];
+    const int kr = row / p.P, kc = col / p.P;
+    const double v = G[6 * J + mr];
+    if (kr == kc) D[((int64_t)kr * p.P + row % p.P) * p.P + col % p.P] = v;
+    else if (kr == kc + 1) B[((int64_t)kc * p.P + row % p.P) * p.P + col % p.P] = v;
+}
+
+__global__ void k_init_coarse(int K, int P, int ncoarse, double* D) {
+    // identity on the padding unknowns of the last super-block
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = K * P;
+    if (i >= n || i < ncoarse) return;
+    const int k = i / P, r = i % P;
+    D[((int64_t)k * P + r) * P + r] = 1.0;
+}
+
+__global__ void k_extract_diag(int K, int P, const double* D, double* ed) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K * P) return;
+    const int k = i / P, r = i % P;
+    ed[i] = D[((int64_t)k * P + r) * P + r];
+}
+
+// ------------------------------------------------------------------ solve
+// y[r][i] = c[r][i] + alpha * sum_j M[i][j] x[r][j]   (one wave per row)
+__global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t mstride, const double* x,
+                                              int64_t xstride, const double* c, int64_t cstride, double alpha,
+                                              double* y, int64_t ystride, int nrhs, int64_t vstride) {
+    const int kb = blockIdx.y;
+    M += kb * mstride;
+    x += kb * xstride;
+    if (c) c += kb * cstride;
+    y += kb * ystride;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= P) return;
+    const double* m = M + (int64_t)row * P;
+    double acc[4] = {0, 0, 0, 0};
+    for (int j = lane; j < P; j += 64) {
+        const double mv = m[j];
+        for (int r = 0; r < nrhs; ++r) acc[r] = fma(mv, x[r * vstride + j], acc[r]);
+    }
+    for (int r = 0; r < nrhs; ++r) {
+        double v = acc[r];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) y[r * vstride + row] = (c ? c[r * vstride + row] : 0.0) + alpha * v;
+    }
+}
+
+// y[r][i] = sum_j M[j][i] x[r][j]   (one thread per output)
+__global__ void k_gemv_t(int P, const double* M, int64_t mstride, const double* x, double* y, int nrhs,
+                         int64_t vstride) {
+    const int kb = blockIdx.y;
+    M += kb * mstride;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    double acc[4] = {0, 0, 0, 0};
+    for (int j = 0; j < P; ++j) {
+        const double mv = M[(int64_t)j * P + i];
+        for (int r = 0; r < nrhs; ++r) acc[r] = fma(mv, x[r * vstride + (int64_t)kb * P + j], acc[r]);
+    }
+    for (int r = 0; r < nrhs; ++r) y[r * vstride + (int64_t)kb * P + i] = acc[r];
+}
+
+__global__ void k_perm_in(int ncoarse, int npad, const int32_t* perm, int nrhs, const double* G, double* gp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < npad && i >= ncoarse) gp[(int64_t)r * npad + i] = 0.0;
+    if (i >= ncoarse) return;
+    gp[(int64_t)r * npad + perm[i]] = G[(int64_t)r * ncoarse + i];
+}
+__global__ void k_perm_out(int ncoarse, int npad, const int32_t* perm, const double* xp, double* MU) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= ncoarse) return;
+    MU[(int64_t)r * ncoarse + i] = xp[(int64_t)r * npad + perm[i]];
+}
+
+__global__ void k_count(const int32_t* a, int n, int32_t* out) {
+    __shared__ int sh[256];
+    int s = 0;
+    for (int i = threadIdx.x; i < n; i += 256) s += a[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int i = 0; i < 256; ++i) tot += sh[i];
+        *out = tot;
+    }
+}
+
+inline double* blkptr(double* base, int k, int P) { return base + (int64_t)k * P * P; }
+
+}  // namespace
+
+int coarse_alloc(Coarse& c) {
+    const Blocks& b = c.blk;
+    const int64_t PP = (int64_t)b.P * b.P;
+    const int64_t npad = (int64_t)b.K * b.P;
+    size_t bytes = PP * b.K * sizeof(double);
+    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.T, &c.U};
+    for (double** a : arrs) {
+        if (hipMalloc((void**)a, bytes) != hipSuccess) {
+            coarse_free(c);
+            set_error("coarse: out of device memory");
+            return AFD_E_OOM;
+        }
+    }
+    AFD_HIP_TRY(hipMalloc((void**)&c.Ediag, npad * sizeof(double)));
+    AFD_HIP_TRY(hipMalloc((void**)&c.work, PP * sizeof(double)));
+    AFD_HIP_TRY(hipMalloc((void**)&c.dropped_dev, (npad + 1) * sizeof(int32_t)));
+    AFD_HIP_TRY(hipMalloc((void**)&c.gperm, 4 * npad * sizeof(double)));
+    AFD_HIP_TRY(hipMalloc((void**)&c.xperm, 4 * npad * sizeof(double)));
+    AFD_HIP_TRY(hipMalloc((void**)&c.cvec, 4 * npad * sizeof(double)));
+    AFD_HIP_TRY(hipMalloc((void**)&c.perm, b.ncoarse * sizeof(int32_t)));
+    // ordering: axes of fewest blocks fastest
+    std::vector<int32_t> perm(b.ncoarse);
+    const int a0 = b.perm[0], a1 = b.perm[1], a2 = b.perm[2];
+    for (int bk = 0; bk < b.nb[2]; ++bk)
+        for (int bj = 0; bj < b.nb[1]; ++bj)
+            for (int bi = 0; bi < b.nb[0]; ++bi) {
+                const int bb[3] = {bi, bj, bk};
+                const int nat = bi + b.nb[0] * (bj + b.nb[1] * bk);
+                const int ord = bb[a0] + b.nb[a0] * (bb[a1] + b.nb[a1] * bb[a2]);
+                for (int m = 0; m < 6; ++m) perm[6 * nat + m] = 6 * ord + m;
+            }
+    AFD_HIP_TRY(hipMemcpy(c.perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return AFD_OK;
+}
+
+void coarse_free(Coarse& c) {
+    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.T, &c.U, &c.Ediag, &c.work, &c.gperm, &c.xperm, &c.cvec};
+    for (double** a : arrs)
+        if (*a) {
+            (void)hipFree(*a);
+            *a = nullptr;
+        }
+    if (c.dropped_dev) (void)hipFree(c.dropped_dev);
+    if (c.perm) (void)hipFree(c.perm);
+    c.dropped_dev = nullptr;
+    c.perm = nullptr;
+    c.valid = false;
+}
+
+int coarse_begin(Coarse& c, hipStream_t s) {
+    const Blocks& b = c.blk;
+    const int64_t PP = (int64_t)b.P * b.P;
+    AFD_HIP_TRY(hipMemsetAsync(c.D, 0, PP * b.K * sizeof(double), s));
+    AFD_HIP_TRY(hipMemsetAsync(c.B, 0, PP * b.K * sizeof(double), s));
+    c.valid = false;
+    return AFD_OK;
+}
+
+int coarse_scatter_probe(Coarse& c, const double* G, int color, int mode, hipStream_t s) {
+    const Blocks& b = c.blk;
+    ScatP p;
+    for (int a = 0; a < 3; ++a) p.nb[a] = b.nb[a];
+    p.P = b.P;
+    p.ncoarse = b.ncoarse;
+    p.perm = c.perm;
+    hipLaunchKernelGGL(k_scatter_probe, dim3((b.ncoarse + 255) / 256), dim3(256), 0, s, p, G, color, mode, c.D, c.B);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int coarse_factor(Coarse& c, hipStream_t s) {
+    const Blocks& b = c.blk;
+    const int P = b.P, K = b.K;
+    const int64_t PP = (int64_t)P * P;
+    const int npad = K * P;
+    hipLaunchKernelGGL(k_init_coarse, dim3((npad + 255) / 256), dim3(256), 0, s, K, P, b.ncoarse, c.D);
+    hipLaunchKernelGGL(k_extract_diag, dim3((npad + 255) / 256), dim3(256), 0, s, K, P, c.D, c.Ediag);
+    AFD_HIP_TRY(hipMemsetAsync(c.Linv, 0, PP * K * sizeof(double), s));
+    AFD_HIP_TRY(hipMemsetAsync(c.T, 0, PP * K * sizeof(double), s));
+    AFD_HIP_TRY(hipMemsetAsync(c.U, 0, PP * K * sizeof(double), s));
+    for (int k = 0; k < K; ++k) {
+        double* Dk = blkptr(c.D, k, P);
+        double* Li = blkptr(c.Linv, k, P);
+        if (k > 0) {  // D_k -= C_{k-1} C_{k-1}^T  (C stored in B[k-1])
+            AFD_TRY(gemm(P, P, P, -1.0, blkptr(c.B, k - 1, P), P, 0, blkptr(c.B, k - 1, P), P, 1, 1.0, Dk, P, s));
+        }
+        // dense blocked Cholesky of D_k, tile inverses into Linv's diagonal tiles
+        for (int j0 = 0; j0 < P; j0 += NB) {
+            const int nb = std::min(NB, P - j0);
+            hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, Dk, Li, P, j0, nb, c.Ediag + (int64_t)k * P,
+                               c.dropped_dev + (int64_t)k * P);
+            const int rows = P - j0 - nb;
+            if (rows > 0) {
+                hipLaunchKernelGGL(k_panel, dim3((rows + 63) / 64), dim3(256), 0, s, Dk, Li, P, j0, nb);
+                AFD_TRY(gemm(rows, rows, nb, -1.0, Dk + (int64_t)(j0 + nb) * P + j0, P, 0,
+                             Dk + (int64_t)(j0 + nb) * P + j0, P, 1, 1.0, Dk + (int64_t)(j0 + nb) * P + j0 + nb, P,
+                             s));
+            }
+        }
+        AFD_HIP_TRY(hipGetLastError());
+        // Linv: row tile i: X[i, 0:i] = -X_ii (L[i, 0:i] X[0:i, 0:i])
+        for (int i0 = NB; i0 < P; i0 += NB) {
+            const int nb = std::min(NB, P - i0);
+            AFD_TRY(gemm(nb, i0, i0, 1.0, Dk + (int64_t)i0 * P, P, 0, Li, P, 0, 0.0, c.work, P, s));
+            AFD_TRY(gemm(nb, i0, nb, -1.0, Li + (int64_t)i0 * P + i0, P, 0, c.work, P, 0, 0.0, Li + (int64_t)i0 * P,
+                         P, s));
+        }
+        hipLaunchKernelGGL(k_zero_dropped, dim3((P + 255) / 256, P), dim3(256), 0, s, Li, P,
+                           c.dropped_dev + (int64_t)k * P);
+        if (k > 0) {  // T_k = Linv_k C_{k-1}
+            AFD_TRY(gemm(P, P, P, 1.0, Li, P, 0, blkptr(c.B, k - 1, P), P, 0, 0.0, blkptr(c.T, k, P), P, s));
+        }
+        if (k < K - 1) {  // C_k = B_k Linv_k^T (in work, then back into B[k]); U_k = Linv_k^T C_k^T
+            AFD_TRY(gemm(P, P, P, 1.0, blkptr(c.B, k, P), P, 0, Li, P, 1, 0.0, c.work, P, s));
+            AFD_HIP_TRY(hipMemcpyAsync(blkptr(c.B, k, P), c.work, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
+            AFD_TRY(gemm(P, P, P, 1.0, Li, P, 1, blkptr(c.B, k, P), P, 1, 0.0, blkptr(c.U, k, P), P, s));
+        }
+    }
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, c.dropped_dev, b.ncoarse, c.dropped_dev + npad);
+    AFD_HIP_TRY(hipGetLastError());
+    int32_t nd = 0;
+    AFD_HIP_TRY(hipMemcpyAsync(&nd, c.dropped_dev + npad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    AFD_HIP_TRY(hipStreamSynchronize(s));
+    c.dropped = nd;
+    c.valid = true;
+    if (nd >= b.ncoarse) {
+        set_error("coarse: every pivot dropped");
+        return AFD_E_COARSE_SINGULAR;
+    }
+    return AFD_OK;
+}
+
+int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s) {
+    const Blocks& b = c.blk;
+    const int P = b.P, K = b.K;
+    const int64_t PP = (int64_t)P * P;
+    const int npad = K * P;
+    dim3 gp((npad + 255) / 256, nrhs);
+    hipLaunchKernelGGL(k_perm_in, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, nrhs, G, c.gperm);
+    // c_k = Linv_k g_k, all k
+    hipLaunchKernelGGL(k_gemv, dim3((P + 3) / 4, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad);
+    // x_0 = c_0; x_k = c_k - T_k x_{k-1}
+    AFD_HIP_TRY(hipMemcpy2DAsync(c.xperm, npad * sizeof(double), c.cvec, npad * sizeof(double), P * sizeof(double),
+                                 nrhs, hipMemcpyDeviceToDevice, s));
+    for (int k = 1; k < K; ++k)
+        hipLaunchKernelGGL(k_gemv, dim3((P + 3) / 4, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
+                           c.xperm + (int64_t)(k - 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
+                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad);
+    // c'_k = Linv_k^T x_k, all k
+    hipLaunchKernelGGL(k_gemv_t, dim3((P + 255) / 256, K), dim3(256), 0, s, P, c.Linv, PP, c.xperm, c.cvec, nrhs,
+                       (int64_t)npad);
+    // mu_{K-1} = c'_{K-1}; mu_k = c'_k - U_k mu_{k+1}
+    AFD_HIP_TRY(hipMemcpy2DAsync(c.gperm + (int64_t)(K - 1) * P, npad * sizeof(double),
+                                 c.cvec + (int64_t)(K - 1) * P, npad * sizeof(double), P * sizeof(double), nrhs,
+                                 hipMemcpyDeviceToDevice, s));
+    for (int k = K - 2; k >= 0; --k)
+        hipLaunchKernelGGL(k_gemv, dim3((P + 3) / 4, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
+                           c.gperm + (int64_t)(k + 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
+                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad);
+    hipLaunchKernelGGL(k_perm_out, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, c.gperm, MU);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int coarse_to_dense_host(Coarse& c, double* E, hipStream_t s) {
+    const Blocks& b = c.blk;
+    const int P = b.P, K = b.K, n = b.ncoarse;
+    const int64_t PP = (int64_t)P * P;
+    std::vector<double> D(PP * K), B(PP * K);
+    std::vector<int32_t> perm(n);
+    AFD_HIP_TRY(hipMemcpyAsync(D.data(), c.D, PP * K * sizeof(double), hipMemcpyDeviceToHost, s));
+    AFD_HIP_TRY(hipMemcpyAsync(B.data(), c.B, PP * K * sizeof(double), hipMemcpyDeviceToHost, s));
+    AFD_HIP_TRY(hipMemcpyAsync(perm.data(), c.perm, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    AFD_HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int pi = perm[i], pj = perm[j];
+            const int ki = pi / P, kj = pj / P;
+            double v = 0.0;
+            if (ki == kj) v = D[((int64_t)ki * P + pi % P) * P + pj % P];
+            else if (ki == kj + 1) v = B[((int64_t)kj * P + pi % P) * P + pj % P];
+            else if (kj == ki + 1) v = B[((int64_t)ki * P + pj % P) * P + pi % P];
+            E[(int64_t)i * n + j] = v;
+        }
+    return AFD_OK;
+}
+
+}  // namespace afd

@@ -1,0 +1,284 @@
+// Post-processing of a solve: per-element energies (the element term
+// u^T K^e u of Eq. 3.5, the element-sensitivity route of Sec. 3.1) and the
+// topology extracted at a volume fraction by ranking a sensitivity field
+// (Eq. 3.6 with the cutting value set by the target volume, Sec. 3.2).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "afd_internal.h"
+
+namespace afd {
+
+namespace {
+
+constexpr int MAXF = 16;
+
+struct SensP {
+    int nx, ny, nz;
+    int nfields;
+    const double* ua[MAXF];
+    const double* ub[MAXF];
+    KeHaar kh;
+};
+
+__device__ __forceinline__ void haar_fwd(double v[8][3]) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int st = 1 << ax;
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            if (n & st) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double s = v[n][c] + v[n + st][c], d = v[n + st][c] - v[n][c];
+                v[n][c] = s;
+                v[n + st][c] = d;
+            }
+        }
+    }
+}
+
+// S[f][e] = rho_e * u_e^T Ke v_e = rho_e * (T u_e)^T Khat (T v_e)
+__global__ void k_sensitivity(SensP p, const double* rho, double* S) {
+    const int64_t nE = (int64_t)p.nx * p.ny * p.nz;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nE) return;
+    const int ex = (int)(e % p.nx), ey = (int)((e / p.nx) % p.ny), ez = (int)(e / ((int64_t)p.nx * p.ny));
+    const int64_t sy = p.nx + 1, sz = (int64_t)(p.nx + 1) * (p.ny + 1);
+    int64_t nd[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) nd[a] = (ex + (a & 1)) + sy * (ey + ((a >> 1) & 1)) + sz * (ez + (a >> 2));
+    const double r = rho[e];
+    for (int f = 0; f < p.nfields; ++f) {
+        double u[8][3], v[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                u[a][c] = p.ua[f][3 * nd[a] + c];
+                v[a][c] = p.ub[f][3 * nd[a] + c];
+            }
+        haar_fwd(u);
+        haar_fwd(v);
+        double s = 0.0;
+#pragma unroll
+        for (int al = 1; al < 8; ++al)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double acc = p.kh.dg[i][al] * v[al][i];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    if (j == i) continue;
+                    const int k = 3 - i - j;
+                    const int bi = (al >> i) & 1, bj = (al >> j) & 1, bk = (al >> k) & 1;
+                    if (bi == bj) continue;
+                    acc = fma(bi ? p.kh.cl[k][bk] : p.kh.cm[k][bk], v[al ^ (1 << i) ^ (1 << j)][j], acc);
+                }
+                s = fma(u[al][i], acc, s);
+            }
+        S[(int64_t)f * nE + e] = r * s;
+    }
+}
+
+// ------------------------------------------------------------ radix sort
+// Stable LSD radix sort (8-bit digits) of 64-bit keys with int32 payloads.
+constexpr int RS_T = 256;     // threads
+constexpr int RS_R = 8;       // rounds (keys per thread)
+constexpr int RS_TILE = RS_T * RS_R;
+
+// Orders doubles descending (NaN last among equal bit patterns is irrelevant
+// here), as an unsigned key ascending.
+__global__ void k_make_keys(int64_t n, const double* s, uint64_t* key, int32_t* idx) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t b = (uint64_t)__double_as_longlong(s[i]);
+    b = (b >> 63) ? ~b : (b | 0x8000000000000000ull);  // ascending order of the double
+    key[i] = ~b;                                       // descending
+    idx[i] = (int32_t)i;
+}
+
+__global__ void k_hist(int64_t n, const uint64_t* key, int shift, uint32_t* hist, int ntiles) {
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_R; ++r) {
+        const int64_t i = base + r * RS_T + t;
+        if (i < n) atomicAdd(&h[(key[i] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)t * ntiles + blockIdx.x] = h[t];
+}
+
+// per digit: exclusive prefix over tiles (in place) and the digit total
+__global__ void k_scan_tiles(uint32_t* hist, int ntiles, uint32_t* dtot) {
+    __shared__ uint32_t sh[256];
+    const int d = blockIdx.x, t = threadIdx.x;
+    uint32_t* h = hist + (int64_t)d * ntiles;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < ntiles; b0 += 256) {
+        const uint32_t v = (b0 + t < ntiles) ? h[b0 + t] : 0u;
+        sh[t] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele
+            uint32_t a = (t >= off) ? sh[t - off] : 0u;
+            __syncthreads();
+            sh[t] += a;
+            __syncthreads();
+        }
+        if (b0 + t < ntiles) h[b0 + t] = carry + sh[t] - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+    if (t == 0) dtot[d] = carry;
+}
+
+__global__ void k_scan_digits(uint32_t* dtot) {
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int d = 0; d < 256; ++d) {
+            const uint32_t v = dtot[d];
+            dtot[d] = run;
+            run += v;
+        }
+    }
+}
+
+__global__ void k_scatter(int64_t n, const uint64_t* kin, const int32_t* iin, uint64_t* kout, int32_t* iout,
+                          int shift, const uint32_t* hist, int ntiles, const uint32_t* dbase) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[RS_T / 64][256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    run[t] = dbase[t] + hist[(int64_t)t * ntiles + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_R; ++r) {
+        for (int q = 0; q < RS_T / 64; ++q) wc[q][t] = 0;
+        __syncthreads();
+        const int64_t i = base + r * RS_T + t;
+        const bool valid = i < n;
+        uint64_t k = valid ? kin[i] : 0;
+        const int d = (int)((k >> shift) & 255);
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bs = __ballot(valid && ((d >> b) & 1));
+            peers &= ((d >> b) & 1) ? bs : ~bs;
+        }
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const uint32_t rank = __popcll(peers & lt);
+        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[d] + rank;
+            for (int q = 0; q < w; ++q) off += wc[q][d];
+            kout[off] = k;
+            iout[off] = iin[i];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int q = 0; q < RS_T / 64; ++q) add += wc[q][t];
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* solid, int32_t* order_out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t e = order[i];
+    solid[e] = (i < keep) ? 1 : 0;
+    if (order_out) order_out[i] = e;
+}
+
+}  // namespace
+
+int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int nfields, const double* const* Ua,
+                       const double* const* Ub, double* S, hipStream_t s) {
+    if (nfields < 1 || nfields > MAXF) {
+        set_error("sensitivity: 1..16 fields");
+        return AFD_E_INVALID_ARG;
+    }
+    SensP p;
+    memset(&p, 0, sizeof(p));
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.nz = g.nz;
+    p.nfields = nfields;
+    for (int f = 0; f < nfields; ++f) {
+        p.ua[f] = Ua[f];
+        p.ub[f] = Ub[f];
+    }
+    p.kh = kh;
+    hipLaunchKernelGGL(k_sensitivity, dim3((unsigned)((g.nelem + 255) / 256)), dim3(256), 0, s, p, rho, S);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int threshold_gpu(const double* s, int64_t n, double vol_frac, uint8_t* solid, int32_t* order, double* tau_host,
+                  hipStream_t st) {
+    if (n <= 0 || n > 0x7fffffff || !(vol_frac >= 0.0 && vol_frac <= 1.0)) {
+        set_error("threshold: need 0 < n < 2^31 and 0 <= vol_frac <= 1");
+        return AFD_E_INVALID_ARG;
+    }
+    const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    int32_t *i0 = nullptr, *i1 = nullptr;
+    uint32_t *hist = nullptr, *dtot = nullptr;
+    int rc = AFD_OK;
+    if (hipMalloc((void**)&k0, n * 8) != hipSuccess || hipMalloc((void**)&k1, n * 8) != hipSuccess ||
+        hipMalloc((void**)&i0, n * 4) != hipSuccess || hipMalloc((void**)&i1, n * 4) != hipSuccess ||
+        hipMalloc((void**)&hist, (size_t)256 * ntiles * 4) != hipSuccess ||
+        hipMalloc((void**)&dtot, 256 * 4) != hipSuccess) {
+        set_error("threshold: out of device memory");
+        rc = AFD_E_OOM;
+    }
+    if (rc == AFD_OK) {
+        hipLaunchKernelGGL(k_make_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, k0, i0);
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 8 * pass;
+            hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(RS_T), 0, st, n, k0, shift, hist, ntiles);
+            hipLaunchKernelGGL(k_scan_tiles, dim3(256), dim3(256), 0, st, hist, ntiles, dtot);
+            hipLaunchKernelGGL(k_scan_digits, dim3(1), dim3(64), 0, st, dtot);
+            hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(RS_T), 0, st, n, k0, i0, k1, i1, shift, hist, ntiles,
+                               dtot);
+            std::swap(k0, k1);
+            std::swap(i0, i1);
+        }
+        int64_t keep = (int64_t)std::ceil(vol_frac * (double)n);
+        if (keep > n) keep = n;
+        if (keep < 0) keep = 0;
+        hipLaunchKernelGGL(k_mark, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, keep, i0, solid, order);
+        if (hipGetLastError() != hipSuccess) {
+            set_error("threshold: kernel launch failed");
+            rc = AFD_E_HIP;
+        }
+        if (rc == AFD_OK && tau_host) {
+            *tau_host = INFINITY;
+            if (keep > 0) {
+                int32_t e = 0;
+                if (hipMemcpyAsync(&e, i0 + keep - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess ||
+                    hipMemcpyAsync(tau_host, s + e, 8, hipMemcpyDeviceToHost, st) != hipSuccess) {
+                    set_error("threshold: copy failed");
+                    rc = AFD_E_HIP;
+                }
+            }
+        }
+        if (hipStreamSynchronize(st) != hipSuccess && rc == AFD_OK) {
+            set_error("threshold: stream sync failed");
+            rc = AFD_E_HIP;
+        }
+    }
+    (void)hipFree(k0);
+    (void)hipFree(k1);
+    (void)hipFree(i0);
+    (void)hipFree(i1);
+    (void)hipFree(hist);
+    (void)hipFree(dtot);
+    return rc;
+}
+
+}  // namespace afd

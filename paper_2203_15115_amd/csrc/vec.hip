@@ -1,0 +1,548 @@
+// Vector-level kernels of the deflated PCG (Sec. 3.5): Jacobi diagonal formed
+// assembly-free, deterministic dot products, CG scalar recurrences kept on the
+// device, the fused x/r update, and the deflation operators W^T v / W mu of
+// the six rigid-body motions per agglomerated block.
+//
+// Every reduction is two-stage with a fixed order (per-workgroup partials,
+// then one workgroup summing the partials in index order), so results are
+// bitwise reproducible; no floating-point atomics are used.
+#include <cmath>
+
+#include "afd_internal.h"
+
+namespace afd {
+
+namespace {
+
+constexpr int WG = 256;
+
+__device__ __forceinline__ double wg_reduce(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+    const int t = threadIdx.x;
+    __syncthreads();
+    if ((t & 63) == 0) sh[t >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (t == 0)
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += sh[w];
+    return s;  // valid in thread 0
+}
+
+// fixed-order sum of n partials by one workgroup (valid in thread 0)
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    return wg_reduce(v, sh);
+}
+
+__global__ void k_pack_mask(int64_t nnode, const uint8_t* dm, uint8_t* nm) {
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nnode) return;
+    nm[n] = (uint8_t)((dm[3 * n] ? 1 : 0) | (dm[3 * n + 1] ? 2 : 0) | (dm[3 * n + 2] ? 4 : 0));
+}
+
+__global__ void k_node_rsum(int nx, int ny, int nz, const double* rho, double* rinv, float* rinv32) {
+    const int64_t nnode = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nnode) return;
+    const int i = (int)(n % (nx + 1));
+    const int j = (int)((n / (nx + 1)) % (ny + 1));
+    const int k = (int)(n / ((int64_t)(nx + 1) * (ny + 1)));
+    double s = 0.0;
+    for (int dz = -1; dz <= 0; ++dz)
+        for (int dy = -1; dy <= 0; ++dy)
+            for (int dx = -1; dx <= 0; ++dx) {
+                const int ex = i + dx, ey = j + dy, ez = k + dz;
+                if (ex < 0 || ey < 0 || ez < 0 || ex >= nx || ey >= ny || ez >= nz) continue;
+                s += rho[ex + (int64_t)nx * (ey + (int64_t)ny * ez)];
+            }
+    const double r = 1.0 / s;
+    rinv[n] = r;
+    rinv32[n] = (float)r;
+}
+
+__global__ void k_jacobi_full(int64_t nnode, const double* rinv, const uint8_t* nm, double k0, double k1, double k2,
+                              double* d) {
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nnode) return;
+    const double kd[3] = {k0, k1, k2};
+    for (int c = 0; c < 3; ++c) d[3 * n + c] = ((nm[n] >> c) & 1) ? 1.0 : kd[c] / rinv[n];
+}
+
+__global__ void k_dot_partial(int64_t n, const double* x, const double* y, double* part) {
+    __shared__ double sh[WG / 64];
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) v += x[i] * y[i];
+    v = wg_reduce(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void k_sum(const double* part, int n, double* out) {
+    __shared__ double sh[WG / 64];
+    double s = sum_partials(part, n, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---- CG scalar recurrences (one workgroup, one rhs per blockIdx.x) -------
+// partial layout: [(rhs*2 + which) * npart + i]
+__global__ void k_cg_init(CgScalars* sc, const double* part, int npart, double rtol, int max_iter) {
+    __shared__ double sh[WG / 64];
+    const int r = blockIdx.x;
+    double bb = sum_partials(part + (int64_t)(r * 2 + 1) * npart, npart, sh);
+    if (threadIdx.x == 0) {
+        CgScalars s{};
+        s.bb = bb;
+        s.tol2 = rtol * rtol * bb;
+        s.max_iter = max_iter;
+        s.done = (bb == 0.0) ? 1 : 0;
+        sc[r] = s;
+    }
+}
+
+// after the residual of the deflated start: rz, rr
+__global__ void k_cg_start(CgScalars* sc, const double* part, int npart) {
+    __shared__ double sh[WG / 64];
+    const int r = blockIdx.x;
+    if (sc[r].done) return;
+    double rz = sum_partials(part + (int64_t)(r * 2 + 0) * npart, npart, sh);
+    double rr = sum_partials(part + (int64_t)(r * 2 + 1) * npart, npart, sh);
+    if (threadIdx.x == 0) {
+        sc[r].rz = rz;
+        sc[r].rr = rr;
+        sc[r].rr0 = rr;
+        sc[r].beta = 0.0;
+        if (rr <= sc[r].tol2) sc[r].done = 1;
+    }
+}
+
+__global__ void k_scalar_alpha(CgScalars* sc, const double* part, int npart) {
+    __shared__ double sh[WG / 64];
+    const int r = blockIdx.x;
+    if (sc[r].done) return;
+    double pq = sum_partials(part + (int64_t)(r * 2 + 0) * npart, npart, sh);
+    if (threadIdx.x == 0) {
+        sc[r].pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(sc[r].rz)) {
+            sc[r].done = 2;  // breakdown: A not SPD on the Krylov space (e.g. no fixed DOFs)
+            sc[r].alpha = 0.0;
+        } else {
+            sc[r].alpha = sc[r].rz / pq;
+        }
+    }
+}
+
+__global__ void k_scalar_beta(CgScalars* sc, const double* part, int npart) {
+    __shared__ double sh[WG / 64];
+    const int r = blockIdx.x;
+    if (sc[r].done) return;
+    double rz = sum_partials(part + (int64_t)(r * 2 + 0) * npart, npart, sh);
+    double rr = sum_partials(part + (int64_t)(r * 2 + 1) * npart, npart, sh);
+    if (threadIdx.x == 0) {
+        CgScalars s = sc[r];
+        s.iters += 1;
+        s.rz_new = rz;
+        s.rr = rr;
+        s.beta = rz / s.rz;
+        s.rz = rz;
+        if (!isfinite(rr)) s.done = 2;
+        else if (rr <= s.tol2) s.done = 1;
+        else if (s.iters >= s.max_iter) s.done = 3;
+        sc[r] = s;
+    }
+}
+
+// x += alpha p, r -= alpha q, z = M^-1 r (optional), partials of r.z and r.r
+template <typename T>
+__global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, const float* rinv32,
+                            double kd0, double kd1, double kd2, CgScalars* sc, T* X, const T* Pv, T* R,
+                            const T* Q, T* Z, double* part, int npart) {
+    __shared__ double sh[WG / 64];
+    const int r = blockIdx.y;
+    if (sc[r].done) return;
+    const double alpha = sc[r].alpha;
+    const T a = (T)alpha;
+    X += r * ndof;
+    Pv += r * ndof;
+    R += r * ndof;
+    Q += r * ndof;
+    if (Z) Z += r * ndof;
+    const double kd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
+    double rz = 0.0, rr = 0.0;
+    for (int64_t n = blockIdx.x * (int64_t)WG + threadIdx.x; n < nnode; n += (int64_t)gridDim.x * WG) {
+        const double ri = (sizeof(T) == 8) ? rinv[n] : (double)rinv32[n];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t i = 3 * n + c;
+            X[i] = X[i] + a * Pv[i];
+            const T rv = R[i] - a * Q[i];
+            R[i] = rv;
+            const double z = ri * kd[c] * (double)rv;
+            if (Z) Z[i] = (T)z;
+            rz += (double)rv * z;
+            rr += (double)rv * (double)rv;
+        }
+    }
+    double s0 = wg_reduce(rz, sh);
+    double s1 = wg_reduce(rr, sh);
+    if (threadIdx.x == 0) {
+        part[(int64_t)(r * 2 + 0) * npart + blockIdx.x] = s0;
+        part[(int64_t)(r * 2 + 1) * npart + blockIdx.x] = s1;
+    }
+}
+
+// ---- deflation operators ------------------------------------------------
+struct BlkP {
+    int nx, ny, nz;
+    int b[3], nb[3];
+    double inv_scale;
+    int ncoarse;
+};
+
+__device__ __forceinline__ void block_range(const BlkP& p, int ax, int bb, int& lo, int& hi) {
+    const int n = ax == 0 ? p.nx : (ax == 1 ? p.ny : p.nz);
+    lo = bb * p.b[ax];
+    hi = (bb == p.nb[ax] - 1) ? n : lo + p.b[ax] - 1;
+}
+
+// G[r][6*blk+m] = sum over free DOFs of block blk of w_m . V[r]  (one workgroup per block)
+template <typename T>
+__global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, const T* V, double* G) {
+    __shared__ double sh[WG / 64];
+    const int blk = blockIdx.x;
+    const int bi = blk % p.nb[0], bj = (blk / p.nb[0]) % p.nb[1], bk = blk / (p.nb[0] * p.nb[1]);
+    int lo[3], hi[3];
+    block_range(p, 0, bi, lo[0], hi[0]);
+    block_range(p, 1, bj, lo[1], hi[1]);
+    block_range(p, 2, bk, lo[2], hi[2]);
+    const double c0 = 0.5 * (lo[0] + hi[0]), c1 = 0.5 * (lo[1] + hi[1]), c2 = 0.5 * (lo[2] + hi[2]);
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    const int cnt = ex * ey * ez;
+    for (int r = 0; r < nrhs; ++r) {
+        const T* v = V + r * ndof;
+        double m[6] = {0, 0, 0, 0, 0, 0};
+        for (int q = threadIdx.x; q < cnt; q += WG) {
+            const int i = lo[0] + q % ex, j = lo[1] + (q / ex) % ey, k = lo[2] + q / (ex * ey);
+            const int64_t n = i + (int64_t)(p.nx + 1) * (j + (int64_t)(p.ny + 1) * k);
+            const uint8_t mk = nm[n];
+            const double x = (i - c0) * p.inv_scale, y = (j - c1) * p.inv_scale, z = (k - c2) * p.inv_scale;
+            const double u0 = (mk & 1) ? 0.0 : (double)v[3 * n];
+            const double u1 = (mk & 2) ? 0.0 : (double)v[3 * n + 1];
+            const double u2 = (mk & 4) ? 0.0 : (double)v[3 * n + 2];
+            m[0] += u0;
+            m[1] += u1;
+            m[2] += u2;
+            m[3] += -z * u1 + y * u2;
+            m[4] += z * u0 - x * u2;
+            m[5] += -y * u0 + x * u1;
+        }
+        for (int a = 0; a < 6; ++a) {
+            double s = wg_reduce(m[a], sh);
+            if (threadIdx.x == 0) G[(int64_t)r * p.ncoarse + 6 * blk + a] = s;
+        }
+    }
+}
+
+// V[r] = W MU[r] (zero on fixed DOFs); or, with color >= 0, the probe vector
+// sum over blocks of that 3x3x3 color of motion `mode`.
+template <typename T>
+__global__ void k_prolong(BlkP p, const uint8_t* nm, int nrhs, int64_t nnode, const double* MU, T* V,
+                          int color, int mode) {
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nnode) return;
+    const int r = blockIdx.y;
+    const int i = (int)(n % (p.nx + 1));
+    const int j = (int)((n / (p.nx + 1)) % (p.ny + 1));
+    const int k = (int)(n / ((int64_t)(p.nx + 1) * (p.ny + 1)));
+    const int pp[3] = {i, j, k};
+    int bb[3];
+    double x[3];
+    for (int a = 0; a < 3; ++a) {
+        int q = pp[a] / p.b[a];
+        if (q > p.nb[a] - 1) q = p.nb[a] - 1;
+        int lo, hi;
+        block_range(p, a, q, lo, hi);
+        bb[a] = q;
+        x[a] = (pp[a] - 0.5 * (lo + hi)) * p.inv_scale;
+    }
+    const uint8_t mk = nm[n];
+    double m[6];
+    if (color >= 0) {
+        const int col = (bb[0] % 3) + 3 * (bb[1] % 3) + 9 * (bb[2] % 3);
+        for (int a = 0; a < 6; ++a) m[a] = (col == color && a == mode) ? 1.0 : 0.0;
+    } else {
+        const double* mu = MU + (int64_t)r * p.ncoarse + 6 * (bb[0] + p.nb[0] * (bb[1] + p.nb[1] * bb[2]));
+        for (int a = 0; a < 6; ++a) m[a] = mu[a];
+    }
+    T* v = V + (int64_t)r * 3 * nnode + 3 * n;
+    v[0] = (mk & 1) ? T(0) : (T)(m[0] + m[4] * x[2] - m[5] * x[1]);
+    v[1] = (mk & 2) ? T(0) : (T)(m[1] - m[3] * x[2] + m[5] * x[0]);
+    v[2] = (mk & 4) ? T(0) : (T)(m[2] + m[3] * x[1] - m[4] * x[0]);
+}
+
+__global__ void k_copy(int64_t n, const double* a, double* b) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T* a) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+
+template <typename T>
+__global__ void k_dot_partial_t(int64_t n, const T* x, double* part) {
+    __shared__ double sh[WG / 64];
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG)
+        v += (double)x[i] * (double)x[i];
+    v = wg_reduce(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// z = M^-1 r (Jacobi), zero on fixed DOFs through r
+template <typename T>
+__global__ void k_precond(int64_t nnode, int64_t ndof, const double* rinv, const float* rinv32, double kd0,
+                          double kd1, double kd2, const T* R, T* Z) {
+    const int r = blockIdx.y;
+    const double kd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
+    for (int64_t n = blockIdx.x * (int64_t)WG + threadIdx.x; n < nnode; n += (int64_t)gridDim.x * WG) {
+        const double ri = rinv ? rinv[n] : (double)rinv32[n];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t i = r * ndof + 3 * n + c;
+            Z[i] = (T)(ri * kd[c] * (double)R[i]);
+        }
+    }
+}
+
+// outer refinement: rr from partials; converged or scale = ||r||
+__global__ void k_outer_norm(CgScalars* sc, const double* part, int npart) {
+    __shared__ double sh[WG / 64];
+    const int r = blockIdx.x;
+    if (sc[r].done) return;
+    double rr = sum_partials(part + (int64_t)(r * 2 + 1) * npart, npart, sh);
+    if (threadIdx.x == 0) {
+        sc[r].rr = rr;
+        if (!isfinite(rr)) sc[r].done = 2;
+        else if (rr <= sc[r].tol2) sc[r].done = 1;
+        else if (sc[r].iters >= sc[r].max_iter) sc[r].done = 3;
+        else {
+            sc[r].alpha = sqrt(rr);
+            sc[r].iters += 1;
+        }
+    }
+}
+
+__global__ void k_to_f32_scaled(int64_t ndof, const double* R, const CgScalars* sc, float* Rf) {
+    const int r = blockIdx.y;
+    const bool dn = sc[r].done != 0;
+    const double inv = dn ? 0.0 : 1.0 / sc[r].alpha;
+    for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < ndof; i += (int64_t)gridDim.x * WG)
+        Rf[r * ndof + i] = dn ? 0.0f : (float)(R[r * ndof + i] * inv);
+}
+
+__global__ void k_axpy_refine(int64_t ndof, const CgScalars* sc, const float* D, double* X) {
+    const int r = blockIdx.y;
+    if (sc[r].done) return;
+    const double a = sc[r].alpha;
+    for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < ndof; i += (int64_t)gridDim.x * WG)
+        X[r * ndof + i] += a * (double)D[r * ndof + i];
+}
+
+BlkP blkp(const Grid& g, const Blocks& b) {
+    BlkP p;
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.nz = g.nz;
+    for (int a = 0; a < 3; ++a) {
+        p.b[a] = b.b[a];
+        p.nb[a] = b.nb[a];
+    }
+    p.inv_scale = b.inv_scale;
+    p.ncoarse = b.ncoarse;
+    return p;
+}
+
+inline unsigned nblocks(int64_t n, int per = WG) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+int launch_pack_mask(const Grid& g, const uint8_t* dofmask, uint8_t* nmask, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_mask, dim3(nblocks(g.nnode)), dim3(WG), 0, s, g.nnode, dofmask, nmask);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_node_rsum(const Grid& g, const double* rho, double* rinv, float* rinv32, hipStream_t s) {
+    hipLaunchKernelGGL(k_node_rsum, dim3(nblocks(g.nnode)), dim3(WG), 0, s, g.nx, g.ny, g.nz, rho, rinv, rinv32);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_jacobi_full(const Grid& g, const double* rinv, const uint8_t* nmask, const KeHaar& kh, double* d,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_jacobi_full, dim3(nblocks(g.nnode)), dim3(WG), 0, s, g.nnode, rinv, nmask, kh.kdiag[0],
+                       kh.kdiag[1], kh.kdiag[2], d);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_dot(int64_t n, const double* x, const double* y, double* partial, int npart, double* out,
+               hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(npart), dim3(WG), 0, s, n, x, y, partial);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(WG), 0, s, partial, npart, out);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+// bb partials: slot 1 of each rhs holds f.f
+int launch_dot_rhs(int64_t ndof, int nrhs, const double* F, double* partial, int npart, hipStream_t s) {
+    for (int r = 0; r < nrhs; ++r)
+        hipLaunchKernelGGL(k_dot_partial, dim3(npart), dim3(WG), 0, s, ndof, F + r * ndof, F + r * ndof,
+                           partial + (int64_t)(r * 2 + 1) * npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_cg_init(CgScalars* sc, int nrhs, const double* part, int npart, double rtol, int max_iter,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_init, dim3(nrhs), dim3(WG), 0, s, sc, part, npart, rtol, max_iter);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+int launch_cg_start(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_start, dim3(nrhs), dim3(WG), 0, s, sc, part, npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+int launch_scalar_alpha(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_alpha, dim3(nrhs), dim3(WG), 0, s, sc, part, npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+int launch_scalar_beta(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_beta, dim3(nrhs), dim3(WG), 0, s, sc, part, npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_cg_update(const Grid& g, const KeHaar& kh, const double* rinv, CgScalars* sc, int nrhs, double* X,
+                     const double* Pv, double* R, const double* Q, double* Z, double* partial, int npart,
+                     hipStream_t s) {
+    hipLaunchKernelGGL((k_cg_update<double>), dim3(npart, nrhs), dim3(WG), 0, s, g.nnode, g.ndof, rinv,
+                       (const float*)nullptr, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], sc, X, Pv, R, Q, Z, partial,
+                       npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_cg_update_f32(const Grid& g, const KeHaar& kh, const float* rinv32, CgScalars* sc, int nrhs, float* X,
+                         const float* Pv, float* R, const float* Q, float* Z, double* partial, int npart,
+                         hipStream_t s) {
+    hipLaunchKernelGGL((k_cg_update<float>), dim3(npart, nrhs), dim3(WG), 0, s, g.nnode, g.ndof,
+                       (const double*)nullptr, rinv32, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], sc, X, Pv, R, Q, Z,
+                       partial, npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_restrict(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V, double* G,
+                    hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, G);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_prolong(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, double* V,
+                   hipStream_t s) {
+    hipLaunchKernelGGL((k_prolong<double>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, nrhs,
+                       g.nnode, MU, V, -1, 0);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_probe_vector(const Grid& g, const Blocks& b, const uint8_t* nmask, int color, int mode, double* V,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_prolong<double>), dim3(nblocks(g.nnode), 1), dim3(WG), 0, s, blkp(g, b), nmask, 1,
+                       g.nnode, (const double*)nullptr, V, color, mode);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_copy_f64(int64_t n, const double* a, double* b, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, dim3(1024), dim3(WG), 0, s, n, a, b);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+int launch_fill_f64(int64_t n, double v, double* a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill<double>), dim3(1024), dim3(WG), 0, s, n, v, a);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+int launch_fill_f32(int64_t n, float v, float* a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill<float>), dim3(1024), dim3(WG), 0, s, n, v, a);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V, double* G,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, G);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_prolong_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, float* V,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((k_prolong<float>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, nrhs,
+                       g.nnode, MU, V, -1, 0);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_dot_rhs_f32(int64_t ndof, int nrhs, const float* F, double* partial, int npart, hipStream_t s) {
+    for (int r = 0; r < nrhs; ++r)
+        hipLaunchKernelGGL((k_dot_partial_t<float>), dim3(npart), dim3(WG), 0, s, ndof, F + r * ndof,
+                           partial + (int64_t)(r * 2 + 1) * npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_precond(const Grid& g, const KeHaar& kh, const double* rinv, int nrhs, const double* R, double* Z,
+                   hipStream_t s) {
+    hipLaunchKernelGGL((k_precond<double>), dim3(VEC_NPART, nrhs), dim3(WG), 0, s, g.nnode, g.ndof, rinv,
+                       (const float*)nullptr, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], R, Z);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_precond_f32(const Grid& g, const KeHaar& kh, const float* rinv32, int nrhs, const float* R, float* Z,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((k_precond<float>), dim3(VEC_NPART, nrhs), dim3(WG), 0, s, g.nnode, g.ndof,
+                       (const double*)nullptr, rinv32, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], R, Z);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_outer_norm(CgScalars* outer, int nrhs, const double* part, int npart, hipStream_t s) {
+    hipLaunchKernelGGL(k_outer_norm, dim3(nrhs), dim3(WG), 0, s, outer, part, npart);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_to_f32_scaled(int64_t ndof, int nrhs, const double* R, const CgScalars* outer, float* Rf,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32_scaled, dim3(VEC_NPART, nrhs), dim3(WG), 0, s, ndof, R, outer, Rf);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_axpy_refine(int64_t ndof, int nrhs, const CgScalars* outer, const float* D, double* X, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_refine, dim3(VEC_NPART, nrhs), dim3(WG), 0, s, ndof, outer, D, X);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+}  // namespace afd
