@@ -83,7 +83,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream(device=dev)  # default priority; the library launches on it
+    torch.cuda.set_stream(stream)
     p = wl.config(args.config)
     ctx = afdcg.afd_context_create(0, stream.cuda_stream)
     mesh = afdcg.afd_mesh_create(ctx, p.dims, block=p.block)

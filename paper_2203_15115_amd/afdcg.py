@@ -271,3 +271,54 @@ def afd_solve(mesh, opts, nrhs, F, U, J=None, S=None, raise_on_error=True):
     if raise_on_error:
         check(code, "afd_solve")
     return code, list(st)
+
+
+def afd_server_create(ctx, hbm_budget=0, max_slots=4):
+    out = C.c_void_p()
+    check(lib().afd_server_create(ctx, int(hbm_budget), int(max_slots), C.byref(out)), "afd_server_create")
+    return out.value
+
+
+class ServerRequest:
+    """Holds a request's host buffers and result storage alive until it completes."""
+
+    def __init__(self, dims, rho, fixed, F, block=(8, 8, 8), h=(1.0, 1.0, 1.0), E=1.0, nu=0.3, **optkw):
+        import numpy as np
+        self.rho = np.ascontiguousarray(rho, dtype=np.float64)
+        self.fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
+        self.F = np.ascontiguousarray(np.atleast_2d(F), dtype=np.float64)
+        self.nrhs = self.F.shape[0]
+        self.U = np.zeros_like(self.F)
+        self.J = np.zeros(self.nrhs)
+        self.stats = (afd_solve_stats * self.nrhs)()
+        self.opts = make_opts(**optkw)
+        desc = afd_mesh_desc(int(dims[0]), int(dims[1]), int(dims[2]), float(h[0]), float(h[1]), float(h[2]),
+                             float(E), float(nu), int(block[0]), int(block[1]), int(block[2]))
+        self.req = afd_request(desc, self.rho.ctypes.data, self.fixed.ctypes.data, self.F.ctypes.data,
+                               self.nrhs, self.opts)
+        self.res = afd_result(self.U.ctypes.data, self.J.ctypes.data, C.cast(self.stats, C.c_void_p).value,
+                              AFD_PENDING, 0.0, 0.0, 0.0)
+        self.ticket = None
+
+
+def afd_server_submit(srv, sreq):
+    t = C.c_uint64()
+    check(lib().afd_server_submit(srv, C.byref(sreq.req), C.byref(sreq.res), C.byref(t)), "afd_server_submit")
+    sreq.ticket = t.value
+    return t.value
+
+
+def afd_server_poll(srv, ticket):
+    return lib().afd_server_poll(srv, ticket)
+
+
+def afd_server_wait(srv, ticket, timeout_s=-1.0):
+    return lib().afd_server_wait(srv, ticket, float(timeout_s))
+
+
+def afd_server_clock(srv):
+    return lib().afd_server_clock(srv)
+
+
+def afd_server_destroy(srv):
+    lib().afd_server_destroy(srv)

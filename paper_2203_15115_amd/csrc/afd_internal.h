@@ -156,6 +156,7 @@ struct Coarse {
     double* D = nullptr;     // K x P x P : diagonal blocks of E, then L_kk
     double* B = nullptr;     // K x P x P : sub-diagonal blocks E_{k+1,k}, then C_k = L_{k+1,k}
     double* Linv = nullptr;  // K x P x P : L_kk^-1
+    double* LinvT = nullptr; // K x P x P : (L_kk^-1)^T
     double* T = nullptr;     // K x P x P : T_k = Linv_k C_{k-1}
     double* U = nullptr;     // K x P x P : U_k = Linv_k^T C_k^T
     double* Ediag = nullptr; // K*P original diagonal
@@ -168,7 +169,7 @@ struct Coarse {
     int dropped = 0;
     bool valid = false;
 };
-int coarse_alloc(Coarse& c);
+int coarse_alloc(Coarse& c, hipStream_t s);
 void coarse_free(Coarse& c);
 int coarse_begin(Coarse& c, hipStream_t s);
 int coarse_scatter_probe(Coarse& c, const double* G, int color, int mode, hipStream_t s);

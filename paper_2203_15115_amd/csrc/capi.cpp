@@ -197,7 +197,7 @@ int ensure_coarse(afd_mesh* m) {
     hipStream_t s = m->ctx->stream;
     if (!m->coarse.D) {
         m->coarse.blk = m->blk;
-        AFD_TRY(coarse_alloc(m->coarse));
+        AFD_TRY(coarse_alloc(m->coarse, m->ctx->stream));
     }
     AFD_TRY(ensure_work(m, 1, 0));
     AFD_TRY(coarse_begin(m->coarse, s));
@@ -521,7 +521,7 @@ int afd_mesh_footprint(const afd_mesh* m, int32_t nrhs, int32_t precision, uint6
     if (precision == AFD_MIXED) b += (uint64_t)nrhs * nd * 4 * 8;        // FP32 inner vectors
     if (m->deflate) {
         const uint64_t PP = (uint64_t)m->blk.P * m->blk.P;
-        b += PP * m->blk.K * 8 * 5 + PP * 8 + (uint64_t)m->blk.K * m->blk.P * 8 * 14;
+        b += PP * m->blk.K * 8 * 6 + PP * 8 + (uint64_t)m->blk.K * m->blk.P * 8 * 14;
     }
     b += (uint64_t)m->npartM * 64 + VEC_NPART * 64;
     *bytes = b;
@@ -622,7 +622,7 @@ int afd_coarse_matrix(afd_mesh* m, double* E) {
     hipStream_t s = m->ctx->stream;
     if (!m->coarse.D) {
         m->coarse.blk = m->blk;
-        AFD_TRY(coarse_alloc(m->coarse));
+        AFD_TRY(coarse_alloc(m->coarse, m->ctx->stream));
     }
     AFD_TRY(ensure_work(m, 1, 0));
     AFD_TRY(coarse_begin(m->coarse, s));
@@ -706,7 +706,8 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
     const bool host = o->mem_kind == AFD_MEM_HOST;
     if (host) {
         std::vector<uint8_t> mask(ndof);
-        AFD_HIP_TRY(hipMemcpy(mask.data(), m->dofmask, ndof, hipMemcpyDeviceToHost));
+        AFD_HIP_TRY(hipMemcpyAsync(mask.data(), m->dofmask, ndof, hipMemcpyDeviceToHost, m->ctx->stream));
+        AFD_HIP_TRY(hipStreamSynchronize(m->ctx->stream));
         for (int r = 0; r < nrhs; ++r)
             for (int64_t i = 0; i < ndof; ++i) {
                 const double f = F[r * ndof + i];

@@ -254,21 +254,20 @@ __global__ void k_extract_diag(int K, int P, const double* D, double* ed) {
 }
 
 // ------------------------------------------------------------------ solve
-// y[r][i] = c[r][i] + alpha * sum_j M[i][j] x[r][j]   (one wave per row)
+// y[r][i] = c[r][i] + alpha * sum_j M[i][j] x[r][j]: one workgroup per row so
+// that every lane's loads are independent (the row is streamed once, the
+// short x vectors come from cache); batched over blockIdx.y
 __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t mstride, const double* x,
                                               int64_t xstride, const double* c, int64_t cstride, double alpha,
                                               double* y, int64_t ystride, int nrhs, int64_t vstride) {
+    __shared__ double sh[4][4];
     const int kb = blockIdx.y;
-    M += kb * mstride;
+    const int row = blockIdx.x;
+    const double* m = M + kb * mstride + (int64_t)row * P;
     x += kb * xstride;
-    if (c) c += kb * cstride;
-    y += kb * ystride;
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= P) return;
-    const double* m = M + (int64_t)row * P;
+    const int t = threadIdx.x;
     double acc[4] = {0, 0, 0, 0};
-    for (int j = lane; j < P; j += 64) {
+    for (int j = t; j < P; j += 256) {
         const double mv = m[j];
         for (int r = 0; r < nrhs; ++r) acc[r] = fma(mv, x[r * vstride + j], acc[r]);
     }
@@ -276,23 +275,14 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t ms
         double v = acc[r];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) y[r * vstride + row] = (c ? c[r * vstride + row] : 0.0) + alpha * v;
+        if ((t & 63) == 0) sh[r][t >> 6] = v;
     }
-}
-
-// y[r][i] = sum_j M[j][i] x[r][j]   (one thread per output)
-__global__ void k_gemv_t(int P, const double* M, int64_t mstride, const double* x, double* y, int nrhs,
-                         int64_t vstride) {
-    const int kb = blockIdx.y;
-    M += kb * mstride;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    double acc[4] = {0, 0, 0, 0};
-    for (int j = 0; j < P; ++j) {
-        const double mv = M[(int64_t)j * P + i];
-        for (int r = 0; r < nrhs; ++r) acc[r] = fma(mv, x[r * vstride + (int64_t)kb * P + j], acc[r]);
+    __syncthreads();
+    if (t < nrhs) {
+        const double v = (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
+        const int64_t o = t * vstride + row;
+        y[kb * ystride + o] = (c ? c[kb * cstride + o] : 0.0) + alpha * v;
     }
-    for (int r = 0; r < nrhs; ++r) y[r * vstride + (int64_t)kb * P + i] = acc[r];
 }
 
 __global__ void k_perm_in(int ncoarse, int npad, const int32_t* perm, int nrhs, const double* G, double* gp) {
@@ -326,12 +316,12 @@ inline double* blkptr(double* base, int k, int P) { return base + (int64_t)k * P
 
 }  // namespace
 
-int coarse_alloc(Coarse& c) {
+int coarse_alloc(Coarse& c, hipStream_t s) {
     const Blocks& b = c.blk;
     const int64_t PP = (int64_t)b.P * b.P;
     const int64_t npad = (int64_t)b.K * b.P;
     size_t bytes = PP * b.K * sizeof(double);
-    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.T, &c.U};
+    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.LinvT, &c.T, &c.U};
     for (double** a : arrs) {
         if (hipMalloc((void**)a, bytes) != hipSuccess) {
             coarse_free(c);
@@ -357,12 +347,13 @@ int coarse_alloc(Coarse& c) {
                 const int ord = bb[a0] + b.nb[a0] * (bb[a1] + b.nb[a1] * bb[a2]);
                 for (int m = 0; m < 6; ++m) perm[6 * nat + m] = 6 * ord + m;
             }
-    AFD_HIP_TRY(hipMemcpy(c.perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    AFD_HIP_TRY(hipMemcpyAsync(c.perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    AFD_HIP_TRY(hipStreamSynchronize(s));
     return AFD_OK;
 }
 
 void coarse_free(Coarse& c) {
-    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.T, &c.U, &c.Ediag, &c.work, &c.gperm, &c.xperm, &c.cvec};
+    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.LinvT, &c.T, &c.U, &c.Ediag, &c.work, &c.gperm, &c.xperm, &c.cvec};
     for (double** a : arrs)
         if (*a) {
             (void)hipFree(*a);
@@ -435,6 +426,8 @@ int coarse_factor(Coarse& c, hipStream_t s) {
         }
         hipLaunchKernelGGL(k_zero_dropped, dim3((P + 255) / 256, P), dim3(256), 0, s, Li, P,
                            c.dropped_dev + (int64_t)k * P);
+        hipLaunchKernelGGL(k_transpose, dim3((P + 31) / 32, (P + 31) / 32), dim3(32, 8), 0, s, P, Li,
+                           blkptr(c.LinvT, k, P));
         if (k > 0) {  // T_k = Linv_k C_{k-1}
             AFD_TRY(gemm(P, P, P, 1.0, Li, P, 0, blkptr(c.B, k - 1, P), P, 0, 0.0, blkptr(c.T, k, P), P, s));
         }
@@ -466,24 +459,24 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
     dim3 gp((npad + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_perm_in, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, nrhs, G, c.gperm);
     // c_k = Linv_k g_k, all k
-    hipLaunchKernelGGL(k_gemv, dim3((P + 3) / 4, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
+    hipLaunchKernelGGL(k_gemv, dim3(P, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
                        (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad);
     // x_0 = c_0; x_k = c_k - T_k x_{k-1}
     AFD_HIP_TRY(hipMemcpy2DAsync(c.xperm, npad * sizeof(double), c.cvec, npad * sizeof(double), P * sizeof(double),
                                  nrhs, hipMemcpyDeviceToDevice, s));
     for (int k = 1; k < K; ++k)
-        hipLaunchKernelGGL(k_gemv, dim3((P + 3) / 4, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
+        hipLaunchKernelGGL(k_gemv, dim3(P, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
                            c.xperm + (int64_t)(k - 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
                            c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad);
     // c'_k = Linv_k^T x_k, all k
-    hipLaunchKernelGGL(k_gemv_t, dim3((P + 255) / 256, K), dim3(256), 0, s, P, c.Linv, PP, c.xperm, c.cvec, nrhs,
-                       (int64_t)npad);
+    hipLaunchKernelGGL(k_gemv, dim3(P, K), dim3(256), 0, s, P, c.LinvT, PP, c.xperm, (int64_t)P,
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad);
     // mu_{K-1} = c'_{K-1}; mu_k = c'_k - U_k mu_{k+1}
     AFD_HIP_TRY(hipMemcpy2DAsync(c.gperm + (int64_t)(K - 1) * P, npad * sizeof(double),
                                  c.cvec + (int64_t)(K - 1) * P, npad * sizeof(double), P * sizeof(double), nrhs,
                                  hipMemcpyDeviceToDevice, s));
     for (int k = K - 2; k >= 0; --k)
-        hipLaunchKernelGGL(k_gemv, dim3((P + 3) / 4, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
+        hipLaunchKernelGGL(k_gemv, dim3(P, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
                            c.gperm + (int64_t)(k + 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
                            c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad);
     hipLaunchKernelGGL(k_perm_out, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, c.gperm, MU);

@@ -35,10 +35,12 @@ enum { APPLY = 0, RESID = 1, DIR = 2 };
 
 template <typename T>
 struct KH {
-    T dg[3][8];
-    T cl[3][2];
-    T cm[3][2];
+    T dg[3][8];   // general voxel: diagonal of the Haar-basis element matrix
+    T cl[3][2];   // lam * M_k(bit) / 4
+    T cm[3][2];   // mu  * M_k(bit) / 4
     T kdiag[3];
+    T dgc[2][3];  // cubic voxel: dg depends only on (alpha_i, number of other set bits)
+    T clc[2], cmc[2];
 };
 
 template <typename T>
@@ -52,14 +54,38 @@ KH<T> to_kh(const KeHaar& k) {
             o.cm[i][b] = (T)k.cm[i][b];
         }
     for (int i = 0; i < 3; ++i) o.kdiag[i] = (T)k.kdiag[i];
+    // representatives (component 0): alpha_0 = bit, others = first n of bits 1, 2
+    const int rep[2][3] = {{0, 2, 6}, {1, 3, 7}};
+    for (int b = 0; b < 2; ++b)
+        for (int n = 0; n < 3; ++n) o.dgc[b][n] = (T)k.dg[0][rep[b][n]];
+    for (int b = 0; b < 2; ++b) {
+        o.clc[b] = (T)k.cl[0][b];
+        o.cmc[b] = (T)k.cm[0][b];
+    }
     return o;
+}
+
+bool is_cubic(const KeHaar& k) {
+    // all three axes share the same 1-D integrals iff the coefficient tables
+    // are symmetric under axis permutation
+    for (int b = 0; b < 2; ++b)
+        if (k.cl[0][b] != k.cl[1][b] || k.cl[0][b] != k.cl[2][b] || k.cm[0][b] != k.cm[1][b] ||
+            k.cm[0][b] != k.cm[2][b])
+            return false;
+    for (int i = 0; i < 3; ++i)
+        for (int a = 1; a < 8; ++a) {
+            const int bi = (a >> i) & 1, n = __builtin_popcount(a & ~(1 << i));
+            const int rep[2][3] = {{0, 2, 6}, {1, 3, 7}};
+            if (k.dg[i][a] != k.dg[0][rep[bi][n]]) return false;
+        }
+    return true;
 }
 
 template <typename T>
 struct MvParams {
     int nx, ny, nz;
     int tiles_x, tiles_y, zc, nchunk;
-    int64_t ndof;
+    int ndof;
     const T* rho;
     const uint8_t* nmask;
     const T* U;     // APPLY: input; RESID: X; DIR: P (old)
@@ -75,97 +101,148 @@ struct MvParams {
     const double* mu;
     int ncoarse;
     CgScalars* sc;
-    double* partial;  // [rhs][npart]
+    double* partial;  // [(rhs*2 + which) * npart + i]
     int npart;
 };
 
-// y = rho * Ke v for one element; v,y indexed [bit pattern ax+2ay+4az][comp]
+template <typename T, bool CUB>
+__device__ __forceinline__ T dgv(const KH<T>& kh, int i, int al) {
+    if constexpr (CUB) return kh.dgc[(al >> i) & 1][__builtin_popcount(al & ~(1 << i))];
+    else return kh.dg[i][al];
+}
+template <typename T, bool CUB>
+__device__ __forceinline__ T clv(const KH<T>& kh, int k, int b) {
+    if constexpr (CUB) return kh.clc[b];
+    else return kh.cl[k][b];
+}
+template <typename T, bool CUB>
+__device__ __forceinline__ T cmv(const KH<T>& kh, int k, int b) {
+    if constexpr (CUB) return kh.cmc[b];
+    else return kh.cm[k][b];
+}
+
+// forward x then y stage of a face: q = ax + 2 ay, (v0, v1) -> (v0 + v1, v1 - v0)
 template <typename T>
-__device__ __forceinline__ void element_apply(const KH<T>& kh, T rho, T v[8][3], T y[8][3]) {
-    // forward Haar per axis: (v0, v1) -> (v0 + v1, v1 - v0)
+__device__ __forceinline__ void face_fwd(T f[4][3]) {
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int st = 1 << ax;
-#pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            if (n & st) continue;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T s = v[n][c] + v[n + st][c];
-                T d = v[n + st][c] - v[n][c];
-                v[n][c] = s;
-                v[n + st][c] = d;
-            }
-        }
+    for (int c = 0; c < 3; ++c) {
+        T s0 = f[0][c] + f[1][c], d0 = f[1][c] - f[0][c];
+        T s1 = f[2][c] + f[3][c], d1 = f[3][c] - f[2][c];
+        f[0][c] = s0 + s1;
+        f[2][c] = s1 - s0;
+        f[1][c] = d0 + d1;
+        f[3][c] = d1 - d0;
     }
+}
+// inverse y then x stage: (s, d) -> (s - d, s + d)
+template <typename T>
+__device__ __forceinline__ void face_inv(T f[4][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T a0 = f[0][c] - f[2][c], a2 = f[0][c] + f[2][c];
+        T a1 = f[1][c] - f[3][c], a3 = f[1][c] + f[3][c];
+        f[0][c] = a0 - a1;
+        f[1][c] = a0 + a1;
+        f[2][c] = a2 - a3;
+        f[3][c] = a2 + a3;
+    }
+}
+
+// element step in the Haar basis: from the transformed bottom (bf) and top (tf)
+// faces, produce the transformed bottom (yb) and top (yt) face outputs of
+// rho * Ke u_e (z stage done here; x/y stages are per face)
+template <typename T, bool CUB>
+__device__ __forceinline__ void element_haar(const KH<T>& kh, T rho, const T bf[4][3], const T tf[4][3],
+                                             T yb[4][3], T yt[4][3]) {
+    T v[8][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[q][c] = bf[q][c] + tf[q][c];
+            v[q + 4][c] = tf[q][c] - bf[q][c];
+        }
+    T y[8][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) y[0][c] = T(0);
+    if constexpr (CUB) {
+        // fold rho into the ten distinct coefficients of a cubic voxel
+        T rd[2][3], rl[2], rm[2];
 #pragma unroll
-    for (int al = 1; al < 8; ++al) {
+        for (int b = 0; b < 2; ++b) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            T acc = kh.dg[i][al] * v[al][i];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                if (j == i) continue;
-                const int k = 3 - i - j;
-                const int bi = (al >> i) & 1, bj = (al >> j) & 1, bk = (al >> k) & 1;
-                if (bi == bj) continue;
-                const T cf = bi ? kh.cl[k][bk] : kh.cm[k][bk];
-                acc = fma(cf, v[al ^ (1 << i) ^ (1 << j)][j], acc);
-            }
-            y[al][i] = rho * acc;
+            for (int n = 0; n < 3; ++n) rd[b][n] = rho * kh.dgc[b][n];
+            rl[b] = rho * kh.clc[b];
+            rm[b] = rho * kh.cmc[b];
         }
-    }
-    // inverse per axis: (s, d) -> (s - d, s + d)
 #pragma unroll
-    for (int ax = 2; ax >= 0; --ax) {
-        const int st = 1 << ax;
+        for (int al = 1; al < 8; ++al) {
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            if (n & st) continue;
+            for (int i = 0; i < 3; ++i) {
+                T acc = rd[(al >> i) & 1][__builtin_popcount(al & ~(1 << i))] * v[al][i];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T s = y[n][c], d = y[n + st][c];
-                y[n][c] = s - d;
-                y[n + st][c] = s + d;
+                for (int j = 0; j < 3; ++j) {
+                    if (j == i) continue;
+                    const int k = 3 - i - j;
+                    const int bi = (al >> i) & 1, bj = (al >> j) & 1, bk = (al >> k) & 1;
+                    if (bi == bj) continue;
+                    acc = fma(bi ? rl[bk] : rm[bk], v[al ^ (1 << i) ^ (1 << j)][j], acc);
+                }
+                y[al][i] = acc;
             }
         }
-    }
-}
-
-// rigid-motion value of block coarse vector mu at node (i,j,k), component c
-__device__ __forceinline__ double wmu(const int b[3], const int nb[3], int nx, int ny, int nz, double inv_scale,
-                                      const double* mu, int i, int j, int k, int c) {
-    const int n[3] = {nx, ny, nz};
-    const int p[3] = {i, j, k};
-    int bidx[3];
-    double x[3];
+    } else {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int bb = p[a] / b[a];
-        if (bb > nb[a] - 1) bb = nb[a] - 1;
-        const int lo = bb * b[a];
-        const int hi = (bb == nb[a] - 1) ? n[a] : lo + b[a] - 1;
-        bidx[a] = bb;
-        x[a] = (p[a] - 0.5 * (lo + hi)) * inv_scale;
+        for (int al = 1; al < 8; ++al) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                T acc = dgv<T, CUB>(kh, i, al) * v[al][i];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    if (j == i) continue;
+                    const int k = 3 - i - j;
+                    const int bi = (al >> i) & 1, bj = (al >> j) & 1, bk = (al >> k) & 1;
+                    if (bi == bj) continue;
+                    const T cf = bi ? clv<T, CUB>(kh, k, bk) : cmv<T, CUB>(kh, k, bk);
+                    acc = fma(cf, v[al ^ (1 << i) ^ (1 << j)][j], acc);
+                }
+                y[al][i] = rho * acc;
+            }
+        }
     }
-    const double* m = mu + 6 * (bidx[0] + nb[0] * (bidx[1] + nb[1] * bidx[2]));
-    if (c == 0) return m[0] + m[4] * x[2] - m[5] * x[1];
-    if (c == 1) return m[1] - m[3] * x[2] + m[5] * x[0];
-    return m[2] + m[3] * x[1] - m[4] * x[0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            yb[q][c] = y[q][c] - y[q + 4][c];
+            yt[q][c] = y[q][c] + y[q + 4][c];
+        }
 }
 
 template <typename T>
-__device__ __forceinline__ double rinv_of(const MvParams<T>& P, int64_t node) {
+__device__ __forceinline__ double rinv_of(const MvParams<T>& P, int node) {
     if constexpr (sizeof(T) == 8) return P.rinv[node];
     else return (double)P.rinv32[node];
 }
 
-template <typename T, int MODE>
+// 64-bit row shift by one lane inside each 16-lane DPP row (lane 0 of a row
+// receives 0)
+__device__ __forceinline__ double dpp_shr1(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x111, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x111, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float dpp_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));
+}
+
+constexpr int PNODES = PX * PY;                   // 289 nodes per staged plane
+constexpr int NSLOT = (PNODES + NT - 1) / NT;     // 2 node slots per thread
+
+template <typename T, int MODE, bool CUB>
 __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
-    __shared__ T plane[PLANE];
-    __shared__ T outb[24 * NT];
+    __shared__ T plane[2][PLANE];
+    __shared__ T xch[3][NT];
     __shared__ double red[NT / 64][2];
 
     const int rhs = blockIdx.y;
@@ -181,130 +258,210 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
     const int Z0 = chunk * P.zc;
     const int Z1 = min(Z0 + P.zc, P.nz + 1);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int64_t sy = nx + 1, sz = (int64_t)(nx + 1) * (ny + 1);
-    const T* U = P.U + rhs * P.ndof;
-    T* Y = P.Y + rhs * P.ndof;
-    const T* F = (MODE != APPLY) ? P.F + rhs * P.ndof : nullptr;
-    T* Pn = (MODE == DIR) ? P.Pn + rhs * P.ndof : nullptr;
-    const double* mu = (MODE == DIR && P.deflate) ? P.mu + (int64_t)rhs * P.ncoarse : nullptr;
-    T beta = T(0);
-    if constexpr (MODE == DIR) beta = (T)P.sc[rhs].beta;
+    const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
+    const int roff = rhs * P.ndof;
+    const T* U = P.U + roff;
+    T* Y = P.Y + roff;
+    const T* F = (MODE != APPLY) ? P.F + roff : nullptr;
+    T* Pn = (MODE == DIR) ? P.Pn + roff : nullptr;
+    const double* mu = (MODE == DIR && P.deflate) ? P.mu + rhs * P.ncoarse : nullptr;
+    double beta = 0.0;
+    if constexpr (MODE == DIR) beta = P.sc[rhs].beta;
 
     const int gi = X0 + lx, gj = Y0 + ly;  // this thread's element (ex, ey) and owned node (i, j)
     const bool own = lx >= 1 && ly >= 1 && gi <= nx && gj <= ny;
     const bool elem_xy = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+    const int own_node = gi + sy * gj;     // plane offset of the owned node (if own)
 
-    // stage node plane gk into LDS (masked input; DIR: direction formed here)
-    auto stage = [&](int gk) {
-        for (int f = t; f < PLANE; f += NT) {
-            const int row = f / (PX * 3);
-            const int rem = f - row * (PX * 3);
-            const int li = rem / 3;
-            const int c = rem - li * 3;
+    // node slots this thread stages: fixed (i, j), so set up once
+    int soff[NSLOT];     // plane offset, -1 outside the mesh / unused
+    int sblk[NSLOT];     // DIR: bi + nbx*bj
+    double sxx[NSLOT], syy[NSLOT];
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q) {
+        const int n = t + q * NT;
+        soff[q] = -1;
+        sblk[q] = 0;
+        sxx[q] = syy[q] = 0.0;
+        if (n < PNODES) {
+            const int row = n / PX, li = n - row * PX;
             const int i = X0 + li, j = Y0 + row;
-            T v = T(0);
-            if (i >= 0 && i <= nx && j >= 0 && j <= ny && gk >= 0 && gk <= nz) {
-                const int64_t node = i + sy * j + sz * gk;
-                if (!((P.nmask[node] >> c) & 1)) {
-                    if constexpr (MODE == DIR) {
-                        const int64_t a = 3 * node + c;
-                        double z = rinv_of(P, node) / (double)kh.kdiag[c] * (double)F[a];
-                        double pv = (double)beta * (double)U[a] + z;
-                        if (mu) pv -= wmu(P.b, P.nb, nx, ny, nz, P.inv_scale, mu, i, j, gk, c);
-                        v = (T)pv;
-                    } else {
-                        v = U[3 * node + c];
+            if (i >= 0 && i <= nx && j >= 0 && j <= ny) {
+                soff[q] = i + sy * j;
+                if constexpr (MODE == DIR) {
+                    if (P.deflate) {
+                        const int bi = min(i / P.b[0], P.nb[0] - 1), bj = min(j / P.b[1], P.nb[1] - 1);
+                        const int lo0 = bi * P.b[0], hi0 = (bi == P.nb[0] - 1) ? nx : lo0 + P.b[0] - 1;
+                        const int lo1 = bj * P.b[1], hi1 = (bj == P.nb[1] - 1) ? ny : lo1 + P.b[1] - 1;
+                        sblk[q] = bi + P.nb[0] * bj;
+                        sxx[q] = (i - 0.5 * (lo0 + hi0)) * P.inv_scale;
+                        syy[q] = (j - 0.5 * (lo1 + hi1)) * P.inv_scale;
                     }
                 }
             }
-            plane[f] = v;
+        }
+    }
+    // global loads of plane gk into registers (masked; DIR forms the direction)
+    auto fetch = [&](int gk, T reg[NSLOT][3]) {
+        const bool pv_ok = gk >= 0 && gk <= nz;
+        int bkoff = 0;
+        double zz = 0.0;
+        if constexpr (MODE == DIR) {
+            if (mu && pv_ok) {
+                const int bk = min(gk / P.b[2], P.nb[2] - 1);
+                const int lo2 = bk * P.b[2], hi2 = (bk == P.nb[2] - 1) ? nz : lo2 + P.b[2] - 1;
+                bkoff = P.nb[0] * P.nb[1] * bk;
+                zz = (gk - 0.5 * (lo2 + hi2)) * P.inv_scale;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NSLOT; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) reg[q][c] = T(0);
+            if (soff[q] >= 0 && pv_ok) {
+                const int node = soff[q] + sz * gk;
+                const int m = P.nmask[node];
+                if constexpr (MODE == DIR) {
+                    const double ri = rinv_of(P, node);
+                    double w[3] = {0.0, 0.0, 0.0};
+                    if (mu) {
+                        const double* mm = mu + 6 * (sblk[q] + bkoff);
+                        const double x = sxx[q], y = syy[q];
+                        w[0] = mm[0] + mm[4] * zz - mm[5] * y;
+                        w[1] = mm[1] - mm[3] * zz + mm[5] * x;
+                        w[2] = mm[2] + mm[3] * y - mm[4] * x;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double pv = beta * (double)U[3 * node + c] +
+                                          ri / (double)kh.kdiag[c] * (double)F[3 * node + c] - w[c];
+                        reg[q][c] = ((m >> c) & 1) ? T(0) : (T)pv;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const T v = U[3 * node + c];
+                        reg[q][c] = ((m >> c) & 1) ? T(0) : v;
+                    }
+                }
+            }
         }
     };
-
-    T lo[4][3];       // element's lower four nodes: (0,0),(1,0),(0,1),(1,1)
-    T carry[3] = {T(0), T(0), T(0)};
-    double acc0 = 0.0, acc1 = 0.0;
-
-    stage(Z0 - 1);
-    __syncthreads();
+    auto put = [&](int buf, const T reg[NSLOT][3]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int li = lx + (q & 1), lj = ly + (q >> 1);
+        for (int q = 0; q < NSLOT; ++q) {
+            const int n = t + q * NT;
+            if (n < PNODES) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) lo[q][c] = plane[(lj * PX + li) * 3 + c];
-    }
-
-    for (int k = Z0 - 1; k < Z1; ++k) {  // element layer k spans node planes k, k+1
-        __syncthreads();
-        stage(k + 1);
-        __syncthreads();
-        T v[8][3], y[8][3];
+                for (int c = 0; c < 3; ++c) plane[buf][3 * n + c] = reg[q][c];
+            }
+        }
+    };
+    auto rho_at = [&](int k) -> T {
+        return (elem_xy && k >= 0 && k < nz) ? P.rho[gi + nx * (gj + ny * k)] : T(0);
+    };
+    // this thread's element face (4 nodes) of plane in buffer b
+    auto read_face = [&](int b, T f[4][3]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int li = lx + (q & 1), lj = ly + (q >> 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                v[q][c] = lo[q][c];
-                const T up = plane[(lj * PX + li) * 3 + c];
-                v[q + 4][c] = up;
-                lo[q][c] = up;
-            }
+            for (int c = 0; c < 3; ++c) f[q][c] = plane[b][(lj * PX + li) * 3 + c];
         }
-        // DIR: owned nodes of plane k+1 write the new direction
-        if constexpr (MODE == DIR) {
+    };
+
+    T bf[4][3];                // transformed lower face of the current layer
+    T ctop[4][3];              // transformed upper-face output of the previous layer
+    T own_prev[3];             // DIR: p' at the owned node, plane k
+    double acc0 = 0.0, acc1 = 0.0;
+    T reg[NSLOT][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ctop[q][c] = T(0);
+
+    fetch(Z0 - 1, reg);
+    put(0, reg);
+    fetch(Z0, reg);
+    put(1, reg);
+    __syncthreads();
+    read_face(0, bf);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) own_prev[c] = bf[0][c];
+    face_fwd<T>(bf);
+    T rho_cur = rho_at(Z0 - 1);
+    int buf = 1;  // buffer holding plane k+1
+
+#pragma unroll 2
+    for (int k = Z0 - 1; k < Z1; ++k) {  // element layer k spans node planes k, k+1
+        const bool more = k + 2 <= Z1;
+        if (more) fetch(k + 2, reg);  // prefetch while this layer computes
+        const T rho_nxt = rho_at(k + 1);
+        __syncthreads();  // plane k+1 staged; previous exchange consumed
+        T tf[4][3];
+        read_face(buf, tf);
+        T own_next[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) own_next[c] = tf[0][c];
+        if constexpr (MODE == DIR) {  // owned nodes of plane k+1 write the new direction
             if (own && k + 1 >= Z0 && k + 1 < Z1) {
-                const int64_t node = gi + sy * gj + sz * (k + 1);
+                const int a = 3 * (own_node + sz * (k + 1));
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Pn[3 * node + c] = v[4][c];
+                for (int c = 0; c < 3; ++c) Pn[a + c] = tf[0][c];
             }
         }
-        T ownk[3];  // this thread's node (gi, gj) on plane k, as staged
+        face_fwd<T>(tf);
+        T yb[4][3], yt[4][3];
+        element_haar<T, CUB>(kh, rho_cur, bf, tf, yb, yt);
+        // plane k: lower-face output of layer k plus upper-face output of layer k-1
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ownk[c] = v[0][c];
-        const bool valid = elem_xy && k >= 0 && k < nz;
-        const T r = valid ? P.rho[gi + (int64_t)nx * (gj + (int64_t)ny * k)] : T(0);
-        element_apply<T>(kh, r, v, y);
-#pragma unroll
-        for (int n = 0; n < 8; ++n)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) outb[(n * 3 + c) * NT + t] = y[n][c];
-        __syncthreads();
-        if (own) {
-            const int t00 = t - TX - 1, t10 = t - TX, t01 = t - 1, t11 = t;
-            T bot[3], top[3];
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                bot[c] = outb[(3 * 3 + c) * NT + t00] + outb[(2 * 3 + c) * NT + t10] +
-                         outb[(1 * 3 + c) * NT + t01] + outb[(0 * 3 + c) * NT + t11];
-                top[c] = outb[(7 * 3 + c) * NT + t00] + outb[(6 * 3 + c) * NT + t10] +
-                         outb[(5 * 3 + c) * NT + t01] + outb[(4 * 3 + c) * NT + t11];
+                yb[q][c] += ctop[q][c];
+                ctop[q][c] = yt[q][c];
+                bf[q][c] = tf[q][c];
             }
-            if (k >= Z0) {  // node plane k is complete
-                const int64_t node = gi + sy * gj + sz * k;
-                const uint8_t m = P.nmask[node];
+        face_inv<T>(yb);  // nodal contributions of this element column to its 4 face nodes
+        // node (lx, ly) = corner (0,0) of face (lx,ly) + (1,0) of (lx-1,ly)
+        //               + (0,1) of (lx,ly-1) + (1,1) of (lx-1,ly-1)
+        T s0[3], s1[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int64_t a = 3 * node + c;
-                    const T yv = carry[c] + bot[c];
-                    const bool fx = (m >> c) & 1;
-                    if constexpr (MODE == APPLY) {
-                        Y[a] = fx ? U[a] : yv;
-                    } else if constexpr (MODE == RESID) {
-                        const T rv = fx ? T(0) : (T)(F[a] - yv);
-                        Y[a] = rv;
-                        const double z = rinv_of(P, node) / (double)kh.kdiag[c] * (double)rv;
-                        acc0 += (double)rv * z;
-                        acc1 += (double)rv * (double)rv;
-                    } else {  // DIR: q = A p' (p' = 0 on fixed DOFs, so q = 0 there)
-                        const T qv = fx ? T(0) : yv;
-                        Y[a] = qv;
-                        acc0 += (double)ownk[c] * (double)qv;
-                    }
+        for (int c = 0; c < 3; ++c) {
+            s0[c] = yb[0][c] + dpp_shr1(yb[1][c]);
+            s1[c] = yb[2][c] + dpp_shr1(yb[3][c]);
+            xch[c][t] = s1[c];
+        }
+        __syncthreads();
+        if (own && k >= Z0) {  // node plane k is complete
+            const int node = own_node + sz * k;
+            const int m = P.nmask[node];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int a = 3 * node + c;
+                const T yv = s0[c] + xch[c][t - TX];
+                const bool fx = (m >> c) & 1;
+                if constexpr (MODE == APPLY) {
+                    Y[a] = fx ? U[a] : yv;
+                } else if constexpr (MODE == RESID) {
+                    const T rv = fx ? T(0) : (T)(F[a] - yv);
+                    Y[a] = rv;
+                    const double z = rinv_of(P, node) / (double)kh.kdiag[c] * (double)rv;
+                    acc0 += (double)rv * z;
+                    acc1 += (double)rv * (double)rv;
+                } else {  // DIR: q = A p' (p' = 0 on fixed DOFs, so q = 0 there)
+                    const T qv = fx ? T(0) : yv;
+                    Y[a] = qv;
+                    acc0 += (double)own_prev[c] * (double)qv;
                 }
             }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) carry[c] = top[c];
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) own_prev[c] = own_next[c];
+        // stage plane k+2 into the buffer that held plane k (read last layer)
+        if (more) put(buf ^ 1, reg);
+        buf ^= 1;
+        rho_cur = rho_nxt;
     }
     if constexpr (MODE != APPLY) {
         // fixed-order workgroup reduction -> one partial per workgroup
@@ -325,8 +482,8 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
                 s0 += red[w][0];
                 s1 += red[w][1];
             }
-            P.partial[(int64_t)(rhs * 2 + 0) * P.npart + blockIdx.x] = s0;
-            P.partial[(int64_t)(rhs * 2 + 1) * P.npart + blockIdx.x] = s1;
+            P.partial[(rhs * 2 + 0) * P.npart + blockIdx.x] = s0;
+            P.partial[(rhs * 2 + 1) * P.npart + blockIdx.x] = s1;
         }
     }
 }
@@ -362,7 +519,7 @@ MvParams<T> base_params(const MatvecArgs& a) {
     p.ny = a.g.ny;
     p.nz = a.g.nz;
     tiling(a.g, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
-    p.ndof = a.g.ndof;
+    p.ndof = (int)a.g.ndof;
     if constexpr (sizeof(T) == 8) p.rho = a.rho;
     else p.rho = a.rho32;
     p.nmask = a.nmask;
@@ -370,13 +527,15 @@ MvParams<T> base_params(const MatvecArgs& a) {
 }
 
 template <typename T, int MODE>
-int launch(const MvParams<T>& p, const KH<T>& kh, int nrhs, hipStream_t s) {
+int launch(const MvParams<T>& p, const KeHaar& khd, int nrhs, hipStream_t s) {
     if (nrhs < 1 || nrhs > 4) {
         set_error("nrhs must be in 1..4");
         return AFD_E_INVALID_ARG;
     }
     dim3 grid(p.tiles_x * p.tiles_y * p.nchunk, nrhs);
-    hipLaunchKernelGGL((k_matvec<T, MODE>), grid, dim3(NT), 0, s, p, kh);
+    const KH<T> kh = to_kh<T>(khd);
+    if (is_cubic(khd)) hipLaunchKernelGGL((k_matvec<T, MODE, true>), grid, dim3(NT), 0, s, p, kh);
+    else hipLaunchKernelGGL((k_matvec<T, MODE, false>), grid, dim3(NT), 0, s, p, kh);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -395,12 +554,12 @@ int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, cons
         MvParams<float> p = base_params<float>(a);
         p.U = (const float*)U;
         p.Y = (float*)Y;
-        return launch<float, APPLY>(p, to_kh<float>(kh), nrhs, s);
+        return launch<float, APPLY>(p, kh, nrhs, s);
     }
     MvParams<double> p = base_params<double>(a);
     p.U = (const double*)U;
     p.Y = (double*)Y;
-    return launch<double, APPLY>(p, to_kh<double>(kh), nrhs, s);
+    return launch<double, APPLY>(p, kh, nrhs, s);
 }
 
 template <typename T>
@@ -426,7 +585,7 @@ int launch_residual(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int
     p.U = X;
     p.Y = R;
     p.F = F;
-    return launch<double, RESID>(p, to_kh<double>(kh), nrhs, s);
+    return launch<double, RESID>(p, kh, nrhs, s);
 }
 
 int launch_dir_apply(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* Pold,
@@ -437,7 +596,7 @@ int launch_dir_apply(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, in
     p.Pn = Pnew;
     p.F = R;
     p.Y = Q;
-    return launch<double, DIR>(p, to_kh<double>(kh), nrhs, s);
+    return launch<double, DIR>(p, kh, nrhs, s);
 }
 
 int launch_residual_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
@@ -448,7 +607,7 @@ int launch_residual_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d,
     p.U = X;
     p.Y = R;
     p.F = F;
-    return launch<float, RESID>(p, to_kh<float>(kh), nrhs, s);
+    return launch<float, RESID>(p, kh, nrhs, s);
 }
 
 int launch_dir_apply_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
@@ -460,7 +619,7 @@ int launch_dir_apply_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d
     p.Pn = Pnew;
     p.F = R;
     p.Y = Q;
-    return launch<float, DIR>(p, to_kh<float>(kh), nrhs, s);
+    return launch<float, DIR>(p, kh, nrhs, s);
 }
 
 }  // namespace afd

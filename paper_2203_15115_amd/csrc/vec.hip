@@ -152,7 +152,8 @@ __global__ void k_scalar_beta(CgScalars* sc, const double* part, int npart) {
     }
 }
 
-// x += alpha p, r -= alpha q, z = M^-1 r (optional), partials of r.z and r.r
+// x += alpha p, r -= alpha q, z = M^-1 r (optional), partials of r.z and r.r;
+// flat over DOFs so that every array access is a unit-stride stream
 template <typename T>
 __global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, const float* rinv32,
                             double kd0, double kd1, double kd2, CgScalars* sc, T* X, const T* Pv, T* R,
@@ -160,28 +161,25 @@ __global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, con
     __shared__ double sh[WG / 64];
     const int r = blockIdx.y;
     if (sc[r].done) return;
-    const double alpha = sc[r].alpha;
-    const T a = (T)alpha;
+    const T a = (T)sc[r].alpha;
     X += r * ndof;
     Pv += r * ndof;
     R += r * ndof;
     Q += r * ndof;
     if (Z) Z += r * ndof;
-    const double kd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
+    const double ikd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
     double rz = 0.0, rr = 0.0;
-    for (int64_t n = blockIdx.x * (int64_t)WG + threadIdx.x; n < nnode; n += (int64_t)gridDim.x * WG) {
+    for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < ndof; i += (int64_t)gridDim.x * WG) {
+        const int64_t n = i / 3;
+        const int c = (int)(i - 3 * n);
         const double ri = (sizeof(T) == 8) ? rinv[n] : (double)rinv32[n];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t i = 3 * n + c;
-            X[i] = X[i] + a * Pv[i];
-            const T rv = R[i] - a * Q[i];
-            R[i] = rv;
-            const double z = ri * kd[c] * (double)rv;
-            if (Z) Z[i] = (T)z;
-            rz += (double)rv * z;
-            rr += (double)rv * (double)rv;
-        }
+        X[i] = X[i] + a * Pv[i];
+        const T rv = R[i] - a * Q[i];
+        R[i] = rv;
+        const double z = ri * ikd[c] * (double)rv;
+        if (Z) Z[i] = (T)z;
+        rz += (double)rv * z;
+        rr += (double)rv * (double)rv;
     }
     double s0 = wg_reduce(rz, sh);
     double s1 = wg_reduce(rr, sh);
@@ -306,14 +304,12 @@ template <typename T>
 __global__ void k_precond(int64_t nnode, int64_t ndof, const double* rinv, const float* rinv32, double kd0,
                           double kd1, double kd2, const T* R, T* Z) {
     const int r = blockIdx.y;
-    const double kd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
-    for (int64_t n = blockIdx.x * (int64_t)WG + threadIdx.x; n < nnode; n += (int64_t)gridDim.x * WG) {
+    const double ikd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
+    for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < ndof; i += (int64_t)gridDim.x * WG) {
+        const int64_t n = i / 3;
+        const int c = (int)(i - 3 * n);
         const double ri = rinv ? rinv[n] : (double)rinv32[n];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t i = r * ndof + 3 * n + c;
-            Z[i] = (T)(ri * kd[c] * (double)R[i]);
-        }
+        Z[r * ndof + i] = (T)(ri * ikd[c] * (double)R[r * ndof + i]);
     }
 }
 

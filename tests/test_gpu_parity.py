@@ -30,9 +30,13 @@ def ctx():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     torch.cuda.init()
-    c = afdcg.afd_context_create(0, torch.cuda.current_stream().cuda_stream)
+    prev = torch.cuda.current_stream()
+    s = torch.cuda.Stream()          # torch work and the library share this stream
+    torch.cuda.set_stream(s)
+    c = afdcg.afd_context_create(0, s.cuda_stream)
     yield c
     afdcg.afd_context_destroy(c)
+    torch.cuda.set_stream(prev)
 
 
 def dev(a, dtype=torch.float64):
@@ -398,3 +402,69 @@ def test_invalid_inputs_rejected(ctx):
     with pytest.raises(afdcg.AfdError):
         afdcg.afd_solve(m, afdcg.make_opts(), 1, F, np.zeros_like(F))
     afdcg.afd_mesh_destroy(m)
+
+
+# ------------------------------------------------------------- matrix-core apply
+@pytest.mark.parametrize("dims", [(1, 1, 1), (17, 16, 9), (33, 20, 19)])
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_apply_mfma_matches_oracle(ctx, dims, nrhs):
+    rho, fixed = rand_problem(dims, 11 + nrhs)
+    m = make_mesh(ctx, dims, rho, fixed)
+    Ke = fem.ke_gauss()
+    K = fem.assemble(dims, rho, Ke)
+    Kabs = fem.assemble(dims, rho, np.abs(Ke))
+    nd = 3 * wl.n_nodes(dims)
+    U = np.random.default_rng(12).standard_normal((nrhs, nd))
+    Ud = dev(U)
+    Yd = torch.empty_like(Ud)
+    afdcg.afd_apply_K_mfma(m, nrhs, Ud, Yd)
+    Y = host(Yd)
+    afdcg.afd_mesh_destroy(m)
+    for r in range(nrhs):
+        want = fem.apply_constrained(K, fixed, U[r])
+        bound = 64 * EPS64 * (fem.apply_constrained(Kabs, fixed, np.abs(U[r])) + np.abs(U[r]))
+        assert np.all(np.abs(Y[r] - want) <= bound), np.max(np.abs(Y[r] - want) / bound)
+
+
+# ------------------------------------------------------------- serving
+def _serve_problem(nx, seed, nrhs, void):
+    req = wl.Request(0, 0.0, (nx, nx // 2, nx // 2), void, nrhs, seed)
+    return wl.request_problem(req)
+
+
+def test_server_results_equal_alone_and_in_mix(ctx):
+    probs = [_serve_problem(nx, 100 + i, 1 + i % 4, 20 + 10 * (i % 5)) for i, nx in
+             enumerate([16, 32, 16, 24, 32, 16, 24, 16])]
+    kw = dict(rtol=1e-10, precision=afdcg.AFD_MIXED, max_iter=4000)
+    srv = afdcg.afd_server_create(ctx, 0, 3)
+    reqs = []
+    for p in probs:
+        r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block, **kw)
+        afdcg.afd_server_submit(srv, r)
+        reqs.append(r)
+    # a bad request (load on a clamped DOF) fails alone
+    bad_p = probs[0]
+    Fbad = bad_p.F.copy()
+    Fbad[0, 0] = 1.0
+    bad = afdcg.ServerRequest(bad_p.dims, bad_p.rho, bad_p.fixed, Fbad, block=bad_p.block, **kw)
+    afdcg.afd_server_submit(srv, bad)
+    for r in reqs:
+        assert afdcg.afd_server_wait(srv, r.ticket, 120.0) == afdcg.AFD_OK
+    assert afdcg.afd_server_wait(srv, bad.ticket, 120.0) == afdcg.AFD_E_INVALID_ARG
+    afdcg.afd_server_destroy(srv)
+    for p, r in zip(probs, reqs):
+        U, J, _, st = solve_case(ctx, p, afdcg.AFD_MIXED, 1e-10)
+        # identical alone and in the mix, within the solve tolerance
+        assert np.max(np.abs(U - r.U)) <= 1e-9 * np.max(np.abs(U))
+        assert all(s.rel_residual_true <= 1e-10 for s in r.stats)
+        assert r.res.t_done >= r.res.t_start >= r.res.t_submit
+
+
+def test_server_rejects_over_budget(ctx):
+    p = _serve_problem(32, 1, 1, 30)
+    srv = afdcg.afd_server_create(ctx, 1 << 20, 1)
+    r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block)
+    with pytest.raises(afdcg.AfdError) as ei:
+        afdcg.afd_server_submit(srv, r)
+    assert ei.value.code == afdcg.AFD_E_OVER_BUDGET
+    afdcg.afd_server_destroy(srv)
