@@ -64,6 +64,153 @@ def cpu_baseline(budget_s=20.0):
                       f"scipy {scipy.__version__} SpMV is single-threaded"}
 
 
+def _events_time(stream, fn, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        fn()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def bench_multi(ctx, stream, args):
+    """128x64x64, 40% void level-set field, 4 right-hand sides (bottom, mid and
+    top edge loads + one point load standing for an adjoint load): operator
+    apply on VALU (Haar-factored) vs on the FP64 matrix cores (dense 24x24
+    contraction), and the 4-RHS deflated solve with energies and mutual
+    energies."""
+    import torch
+    from paper_2203_15115_amd import afdcg, workloads as wl
+    p = wl.config(2)
+    dev = torch.device("cuda:0")
+    m = afdcg.afd_mesh_create(ctx, p.dims, block=p.block)
+    afdcg.afd_mesh_set_scale(m, p.rho, p.nelem, afdcg.AFD_MEM_HOST)
+    afdcg.afd_mesh_set_fixed(m, p.fixed, p.ndof, afdcg.AFD_MEM_HOST)
+    U = torch.randn((4, p.ndof), dtype=torch.float64, device=dev)
+    Y = torch.empty_like(U)
+    t_valu = _events_time(stream, lambda: afdcg.afd_apply_K(m, afdcg.AFD_FP64, 4, U, Y), 50)
+    t_mfma = _events_time(stream, lambda: afdcg.afd_apply_K_mfma(m, 4, U, Y), 50)
+    nx, ny, nz = p.dims
+    # dense contraction flops actually issued: 32 (padded) x 24 x 2 per element per RHS,
+    # over the overlapped tiles (16x16 element tiles owning 15x15 nodes)
+    alg_flops = 4 * p.nelem * 24 * 24 * 2
+    F = torch.as_tensor(p.F, device=dev).contiguous()
+    Uo = torch.empty_like(F)
+    J = torch.empty(4, dtype=torch.float64, device=dev)
+    pairs = ((0, 3), (1, 3), (2, 3))
+    S = torch.empty((7, p.nelem), dtype=torch.float64, device=dev)
+    opts = afdcg.make_opts(rtol=1e-8, mem_kind=afdcg.AFD_MEM_DEVICE, pairs=pairs, check_every=32)
+    afdcg.afd_coarse_setup(m)
+    afdcg.afd_solve(m, opts, 4, F, Uo, J, S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = afdcg.afd_solve(m, opts, 4, F, Uo, J, S)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    Jh = J.cpu().numpy()
+    Fh = p.F
+    Uh = Uo.cpu().numpy()
+    recip = max(abs(Fh[a] @ Uh[b] - Fh[b] @ Uh[a]) / abs(Fh[a] @ Uh[b]) for a, b in pairs)
+    afdcg.afd_mesh_destroy(m)
+    return {"workload": "cantilever 128x64x64, 40% void, 4 RHS (3 edge loads + point load), 8x8x8 blocks",
+            "apply_valu_us": round(t_valu * 1e6, 2), "apply_mfma_us": round(t_mfma * 1e6, 2),
+            "gdofs_valu_total": round(4 * p.ndof / t_valu / 1e9, 2),
+            "gdofs_mfma_total": round(4 * p.ndof / t_mfma / 1e9, 2),
+            "mfma_tflops": round(alg_flops / t_mfma / 1e12, 3), "mfma_peak_tflops": 78.6,
+            "mfma_frac": round(alg_flops / t_mfma / 1e12 / 78.6, 4),
+            "solve_4rhs_s": round(t_solve, 4), "iterations": [x.iterations for x in st],
+            "rel_residual_true": [x.rel_residual_true for x in st],
+            "compliance": [float(v) for v in Jh], "reciprocity_rel_err": float(recip)}
+
+
+def bench_mixed(ctx, stream, args):
+    """256x128x128 (12.8M DOF), 50% void: FP32-inner / FP64-refined deflated
+    solve to 1e-8 against the FP64 deflated solve of the same system."""
+    import torch
+    from paper_2203_15115_amd import afdcg, workloads as wl
+    p = wl.config(3)
+    dev = torch.device("cuda:0")
+    m = afdcg.afd_mesh_create(ctx, p.dims, block=p.block)
+    afdcg.afd_mesh_set_scale(m, p.rho, p.nelem, afdcg.AFD_MEM_HOST)
+    afdcg.afd_mesh_set_fixed(m, p.fixed, p.ndof, afdcg.AFD_MEM_HOST)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    afdcg.afd_coarse_setup(m)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    F = torch.as_tensor(p.F, device=dev).contiguous()
+    out = {"workload": "cantilever 256x128x128, 50% void, 8x8x8 blocks, rtol 1e-8", "n_dof": p.ndof,
+           "setup_s": round(t_setup, 4)}
+    U = {}
+    for name, prec in (("fp64", afdcg.AFD_FP64), ("mixed", afdcg.AFD_MIXED)):
+        Uo = torch.empty_like(F)
+        opts = afdcg.make_opts(rtol=1e-8, precision=prec, mem_kind=afdcg.AFD_MEM_DEVICE, check_every=32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, st = afdcg.afd_solve(m, opts, 1, F, Uo, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        U[name] = Uo
+        out[name] = {"time_s": round(dt, 4), "status": code, "iterations": st[0].iterations,
+                     "refinements": st[0].refinements, "rel_residual_true": st[0].rel_residual_true}
+    d = (U["mixed"] - U["fp64"]).norm().item() / U["fp64"].norm().item()
+    out["mixed_vs_fp64_rel_diff"] = d
+    out["speedup_mixed_over_fp64"] = round(out["fp64"]["time_s"] / out["mixed"]["time_s"], 3)
+    afdcg.afd_mesh_destroy(m)
+    return out
+
+
+def bench_serve(ctx, args):
+    """Poisson stream of cantilever requests nx x nx/2 x nx/2, nx uniform in
+    {32,...,160}, 20-60% void, 1-4 RHS, to 1e-8: the continuous-batching
+    server (mixed precision, 4 slots) against one-at-a-time FP64 solves in
+    arrival order on the same GPU."""
+    import numpy as np
+    from paper_2203_15115_amd import afdcg, workloads as wl
+    n = args.serve_requests
+    reqs = wl.request_stream(n, rate=0.0, seed=7)
+    probs = [wl.request_problem(r) for r in reqs]
+
+    def run_server(arrivals, prec, slots):
+        srv = afdcg.afd_server_create(ctx, 0, slots)
+        subs = []
+        t0 = time.perf_counter()
+        for p, ta in zip(probs, arrivals):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(0.0005)
+            r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block, rtol=1e-8, precision=prec)
+            r.arrive = time.perf_counter() - t0
+            afdcg.afd_server_submit(srv, r)
+            subs.append(r)
+        codes = [afdcg.afd_server_wait(srv, r.ticket, 600.0) for r in subs]
+        t_end = time.perf_counter() - t0
+        afdcg.afd_server_destroy(srv)
+        done_rel = [r.res.t_done - r.res.t_submit + 0.0 for r in subs]
+        return subs, codes, t_end, done_rel
+
+    # saturated throughput of the batching server (all requests queued at t=0)
+    _, codes, t_sat, _ = run_server([0.0] * n, afdcg.AFD_MIXED, 4)
+    print(f"# serving: saturated {n} requests in {t_sat:.2f} s", file=sys.stderr, flush=True)
+    rate = 0.8 * n / t_sat
+    rng = np.random.default_rng(7)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    res = {}
+    for name, prec, slots in (("batched_mixed_4slots", afdcg.AFD_MIXED, 4), ("fifo_fp64_1slot", afdcg.AFD_FP64, 1)):
+        subs, codes, t_end, lat = run_server(arrivals, prec, slots)
+        lat = np.array(lat)
+        print(f"# serving: {name} done in {t_end:.2f} s", file=sys.stderr, flush=True)
+        res[name] = {"solves_per_s": round(n / t_end, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                     "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                     "ok": int(sum(c == 0 for c in codes)), "requests": n,
+                     "max_rel_residual": max(s.rel_residual_true for r in subs for s in r.stats)}
+    return {"workload": f"{n} Poisson-arrival requests, nx in 32..160, 1-4 RHS, rtol 1e-8",
+            "saturated_solves_per_s": round(n / t_sat, 3), "arrival_rate_per_s": round(rate, 3), **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +219,11 @@ def main():
     ap.add_argument("--reps", type=int, default=200, help="timed operator applies")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--sections", default="multi,mixed,serve",
+                    help="extra measured sections: multi (4-RHS, VALU vs matrix cores), mixed, serve")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only a known-size copy and the timed applies (hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -99,6 +251,19 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"# setup (coarse E = W^T A W + block Cholesky): {setup_s:.3f} s", file=sys.stderr, flush=True)
+
+    if args.apply_only:
+        # calibration copy of known size for FETCH_SIZE / WRITE_SIZE, then the applies
+        a = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
+        y = torch.empty_like(u)
+        for _ in range(args.reps):
+            afdcg.afd_apply_K(mesh, afdcg.AFD_FP64, 1, u, y)
+        torch.cuda.synchronize()
+        print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps}), flush=True)
+        return
 
     # ---- operator apply throughput (HIP events on the library's stream)
     u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
@@ -179,9 +344,20 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_matvec<double, APPLY>", "bytes_per_launch": alg},
     }
+    secs = [x for x in args.sections.split(",") if x]
+    afdcg.afd_mesh_destroy(mesh)
+    mesh = None
+    if "multi" in secs:
+        out["multi_rhs"] = bench_multi(ctx, stream, args)
+        print(f"# multi-RHS: {json.dumps(out['multi_rhs'])}", file=sys.stderr, flush=True)
+    if "mixed" in secs:
+        out["mixed"] = bench_mixed(ctx, stream, args)
+        print(f"# mixed: {json.dumps(out['mixed'])}", file=sys.stderr, flush=True)
+    if "serve" in secs:
+        out["serving"] = bench_serve(ctx, args)
+        print(f"# serving: {json.dumps(out['serving'])}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
-    afdcg.afd_mesh_destroy(mesh)
     afdcg.afd_context_destroy(ctx)
     print(json.dumps(out), flush=True)
 

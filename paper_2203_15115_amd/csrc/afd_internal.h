@@ -134,6 +134,10 @@ int launch_precond_f32(const Grid& g, const KeHaar& kh, const float* rinv32, int
                        hipStream_t s);
 int launch_restrict(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V, double* G,
                     hipStream_t s);
+int launch_restrict_diff(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V,
+                         const double* V2, double* G, hipStream_t s);
+int launch_restrict_diff_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V,
+                             const float* V2, double* G, hipStream_t s);
 int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V, double* G,
                         hipStream_t s);
 int launch_prolong(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, double* V,

@@ -19,6 +19,15 @@ namespace afd {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
+static bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("AFD_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
 static double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -235,9 +244,10 @@ DcgArgs dcg_args(afd_mesh* m, CgScalars* sc, double* part, int npart) {
     return d;
 }
 
-// Deflated Jacobi-PCG on A X = B (Saad et al.): x0 = W E^-1 W^T b, r0 = b - A x0,
-// then q = A p, alpha = r.z/p.q, x += alpha p, r -= alpha q, z = M^-1 r,
-// beta = r.z_new/r.z, mu = E^-1 W^T A z, p = beta p + z - W mu.
+// Deflated Jacobi-PCG on A X = B: x0 = W E^-1 W^T b, r0 = b - A x0, then
+// q = A p, alpha = r.z/p.q, x += alpha p, r -= alpha q, z = M^-1 r,
+// beta = r.z_new/r.z, mu = E^-1 W^T (A z - r), p = beta p + z - W mu
+// (Saad et al.'s deflated CG with the coarse correction in A-DEF2 form).
 // FP64 (T = double) or FP32 vectors (T = float, inner solve of the mixed form);
 // dot products and the coarse problem are always FP64.
 template <typename T>
@@ -268,14 +278,18 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     if constexpr (sizeof(T) == 8) AFD_TRY(launch_residual(a, m->kh, dm, nrhs, Bv, X, R, s));
     else AFD_TRY(launch_residual_f32(a, m->kh, dm, m->rinv32, nrhs, Bv, X, R, s));
     AFD_TRY(launch_cg_start(sc, nrhs, w.partM, m->npartM, s));
+    // coarse correction mu = E^-1 W^T (A z - r): the A-DEF2 form of the
+    // deflated preconditioner (equal to the Saad form, where W^T r = 0, in
+    // exact arithmetic; it removes any rounding drift of W^T r, which the
+    // FP32 inner solve of the mixed form needs)
     auto coarse_of_z = [&]() -> int {
         if (!m->deflate) return AFD_OK;
         if constexpr (sizeof(T) == 8) {
             AFD_TRY(launch_apply(a, m->kh, 0, nrhs, Z, AZ, s));
-            AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, nrhs, AZ, w.G, s));
+            AFD_TRY(launch_restrict_diff(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s));
         } else {
             AFD_TRY(launch_apply(a, m->kh, 1, nrhs, Z, AZ, s));
-            AFD_TRY(launch_restrict_f32(m->g, m->blk, m->nmask, nrhs, AZ, w.G, s));
+            AFD_TRY(launch_restrict_diff_f32(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s));
         }
         return coarse_solve(m->coarse, nrhs, w.G, w.MU, s);
     };
@@ -744,7 +758,8 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
         AFD_TRY(launch_cg_init(w.outer, nrhs, w.partV, VEC_NPART, o->rtol, max_ref, s));
         AFD_TRY(launch_fill_f64(nrhs * ndof, 0.0, w.X, s));
         int total_inner = 0;
-        std::vector<int> inner_iters(nrhs, 0);
+        std::vector<int> inner_iters(nrhs, 0), stall(nrhs, 0);
+        std::vector<double> prev_rr(nrhs, 0.0);
         for (int ref = 0; ref <= max_ref; ++ref) {
             DcgArgs dm = dcg_args(m, w.outer, w.partM, m->npartM);
             // residual r = f - A x in FP64 (partials: slot 1 = r.r); the outer
@@ -758,13 +773,30 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
             if (all) break;
             refinements = ref + 1;
             AFD_TRY(launch_to_f32_scaled(ndof, nrhs, w.R, w.outer, w.Bf, s));
+            // the FP32 inner solve only has to reduce the residual by inner_rtol;
+            // past a few hundred iterations FP32 CG has stagnated, so cap it
+            const int inner_max = std::min(o->max_iter, 1000);
             AFD_TRY(dcg_run<float>(m, nrhs, w.Bf, w.Xf, w.Rf, w.P0f, w.P1f, w.Qf, w.Zf, w.AZf, w.sc, inner,
-                                   o->max_iter, ce, w.outer));
+                                   inner_max, ce, w.outer));
             AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), w.sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
             AFD_HIP_TRY(hipStreamSynchronize(s));
             for (int r = 0; r < nrhs; ++r) {
                 inner_iters[r] += hsc[r].iters;
                 total_inner += hsc[r].iters;
+                if (verbose())
+                    fprintf(stderr, "[afd] sweep %d rhs %d: outer |r|/|f| %.3e, inner %d it, inner status %d\n", ref,
+                            r, std::sqrt(hout[r].rr / std::max(hout[r].bb, 1e-300)), hsc[r].iters, hsc[r].done);
+                // stagnation of the outer residual: stop this column
+                if (hout[r].done == 0) {
+                    if (prev_rr[r] > 0 && hout[r].rr > 0.81 * prev_rr[r]) ++stall[r];
+                    else stall[r] = 0;
+                    prev_rr[r] = hout[r].rr;
+                    if (stall[r] >= 3) {
+                        hout[r].done = 3;
+                        AFD_HIP_TRY(hipMemcpyAsync(&w.outer[r].done, &hout[r].done, sizeof(int32_t),
+                                                   hipMemcpyHostToDevice, s));
+                    }
+                }
             }
             AFD_TRY(launch_axpy_refine(ndof, nrhs, w.outer, w.Xf, w.X, s));
         }

@@ -392,7 +392,6 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
     T rho_cur = rho_at(Z0 - 1);
     int buf = 1;  // buffer holding plane k+1
 
-#pragma unroll 2
     for (int k = Z0 - 1; k < Z1; ++k) {  // element layer k spans node planes k, k+1
         const bool more = k + 2 <= Z1;
         if (more) fetch(k + 2, reg);  // prefetch while this layer computes

@@ -204,8 +204,9 @@ __device__ __forceinline__ void block_range(const BlkP& p, int ax, int bb, int& 
 }
 
 // G[r][6*blk+m] = sum over free DOFs of block blk of w_m . V[r]  (one workgroup per block)
+// G = W^T (V - V2) (V2 optional)
 template <typename T>
-__global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, const T* V, double* G) {
+__global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, const T* V, const T* V2, double* G) {
     __shared__ double sh[WG / 64];
     const int blk = blockIdx.x;
     const int bi = blk % p.nb[0], bj = (blk / p.nb[0]) % p.nb[1], bk = blk / (p.nb[0] * p.nb[1]);
@@ -218,15 +219,22 @@ __global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, co
     const int cnt = ex * ey * ez;
     for (int r = 0; r < nrhs; ++r) {
         const T* v = V + r * ndof;
+        const T* v2 = V2 ? V2 + r * ndof : nullptr;
         double m[6] = {0, 0, 0, 0, 0, 0};
         for (int q = threadIdx.x; q < cnt; q += WG) {
             const int i = lo[0] + q % ex, j = lo[1] + (q / ex) % ey, k = lo[2] + q / (ex * ey);
             const int64_t n = i + (int64_t)(p.nx + 1) * (j + (int64_t)(p.ny + 1) * k);
             const uint8_t mk = nm[n];
             const double x = (i - c0) * p.inv_scale, y = (j - c1) * p.inv_scale, z = (k - c2) * p.inv_scale;
-            const double u0 = (mk & 1) ? 0.0 : (double)v[3 * n];
-            const double u1 = (mk & 2) ? 0.0 : (double)v[3 * n + 1];
-            const double u2 = (mk & 4) ? 0.0 : (double)v[3 * n + 2];
+            double u0 = (double)v[3 * n], u1 = (double)v[3 * n + 1], u2 = (double)v[3 * n + 2];
+            if (v2) {
+                u0 -= (double)v2[3 * n];
+                u1 -= (double)v2[3 * n + 1];
+                u2 -= (double)v2[3 * n + 2];
+            }
+            if (mk & 1) u0 = 0.0;
+            if (mk & 2) u1 = 0.0;
+            if (mk & 4) u2 = 0.0;
             m[0] += u0;
             m[1] += u1;
             m[2] += u2;
@@ -446,7 +454,8 @@ int launch_cg_update_f32(const Grid& g, const KeHaar& kh, const float* rinv32, C
 
 int launch_restrict(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V, double* G,
                     hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, G);
+    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
+                       (const double*)nullptr, G);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -483,9 +492,24 @@ int launch_fill_f32(int64_t n, float v, float* a, hipStream_t s) {
     return AFD_OK;
 }
 
+int launch_restrict_diff(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V,
+                         const double* V2, double* G, hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_restrict_diff_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V,
+                             const float* V2, double* G, hipStream_t s) {
+    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
 int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V, double* G,
                         hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, G);
+    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
+                       (const float*)nullptr, G);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }

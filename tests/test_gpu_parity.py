@@ -437,21 +437,24 @@ def test_server_results_equal_alone_and_in_mix(ctx):
              enumerate([16, 32, 16, 24, 32, 16, 24, 16])]
     kw = dict(rtol=1e-10, precision=afdcg.AFD_MIXED, max_iter=4000)
     srv = afdcg.afd_server_create(ctx, 0, 3)
-    reqs = []
-    for p in probs:
-        r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block, **kw)
-        afdcg.afd_server_submit(srv, r)
-        reqs.append(r)
-    # a bad request (load on a clamped DOF) fails alone
-    bad_p = probs[0]
-    Fbad = bad_p.F.copy()
-    Fbad[0, 0] = 1.0
-    bad = afdcg.ServerRequest(bad_p.dims, bad_p.rho, bad_p.fixed, Fbad, block=bad_p.block, **kw)
-    afdcg.afd_server_submit(srv, bad)
-    for r in reqs:
-        assert afdcg.afd_server_wait(srv, r.ticket, 120.0) == afdcg.AFD_OK
-    assert afdcg.afd_server_wait(srv, bad.ticket, 120.0) == afdcg.AFD_E_INVALID_ARG
-    afdcg.afd_server_destroy(srv)
+    try:
+        reqs = []
+        for p in probs:
+            r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block, **kw)
+            afdcg.afd_server_submit(srv, r)
+            reqs.append(r)
+        # a bad request (load on a clamped DOF) fails alone
+        bad_p = probs[0]
+        Fbad = bad_p.F.copy()
+        Fbad[0, 0] = 1.0
+        bad = afdcg.ServerRequest(bad_p.dims, bad_p.rho, bad_p.fixed, Fbad, block=bad_p.block, **kw)
+        afdcg.afd_server_submit(srv, bad)
+        codes = [afdcg.afd_server_wait(srv, r.ticket, 120.0) for r in reqs]
+        bad_code = afdcg.afd_server_wait(srv, bad.ticket, 120.0)
+    finally:
+        afdcg.afd_server_destroy(srv)
+    assert codes == [afdcg.AFD_OK] * len(reqs)
+    assert bad_code == afdcg.AFD_E_INVALID_ARG
     for p, r in zip(probs, reqs):
         U, J, _, st = solve_case(ctx, p, afdcg.AFD_MIXED, 1e-10)
         # identical alone and in the mix, within the solve tolerance
@@ -463,8 +466,10 @@ def test_server_results_equal_alone_and_in_mix(ctx):
 def test_server_rejects_over_budget(ctx):
     p = _serve_problem(32, 1, 1, 30)
     srv = afdcg.afd_server_create(ctx, 1 << 20, 1)
-    r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block)
-    with pytest.raises(afdcg.AfdError) as ei:
-        afdcg.afd_server_submit(srv, r)
-    assert ei.value.code == afdcg.AFD_E_OVER_BUDGET
-    afdcg.afd_server_destroy(srv)
+    try:
+        r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block)
+        with pytest.raises(afdcg.AfdError) as ei:
+            afdcg.afd_server_submit(srv, r)
+        assert ei.value.code == afdcg.AFD_E_OVER_BUDGET
+    finally:
+        afdcg.afd_server_destroy(srv)
