@@ -27,6 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per FP64 apply launch at 192x96x96 from rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by the
+# same counter on a 512 MiB copy (kernel as of the committed counter summary); None when not measured
+TRAFFIC_BYTES = 192_480_000
 
 
 def matvec_algorithmic_bytes(dims, word=8):
@@ -341,7 +344,8 @@ def main():
         "apply_fp32_us": round(t_apply32 * 1e6, 3),
         "apply_fp32_gdofs": round(p.ndof / t_apply32 / 1e9, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": TRAFFIC_BYTES if args.config == 1 else None,
                      "kernel": "k_matvec<double, APPLY>", "bytes_per_launch": alg},
     }
     secs = [x for x in args.sections.split(",") if x]
