@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -65,6 +67,38 @@ struct Blocks {
     int K;                   // number of super-blocks
     int w;                   // half bandwidth in the permuted ordering
 };
+
+// Super-block size of the block-tridiagonal coarse factor: any multiple of 64
+// that is >= the half bandwidth w is valid.  A coarse solve is a chain of
+// 2(K-1) dependent P x P matrix-vector steps (K = ceil(n/P)) plus two batched
+// passes over the K triangular inverses; each step costs at least one launch
+// latency (~7 us) and otherwise streams P^2 doubles (~4 TB/s).  Pick the P of
+// least modelled time among w, 2w, ..., 6w (AFD_COARSE_P overrides).
+inline int choose_coarse_P(int ncoarse, int w) {
+    const int nc64 = ((ncoarse + 63) / 64) * 64;
+    int forced = 0;
+    if (const char* e = getenv("AFD_COARSE_P")) forced = atoi(e);
+    if (forced > 0) {
+        int P = ((std::max(forced, w) + 63) / 64) * 64;
+        return std::min(P, nc64);
+    }
+    const double lat = 7e-6, bw = 4e12;
+    int best = 0;
+    double best_t = 1e30;
+    for (int m = 1; m <= 6; ++m) {
+        int P = ((m * w + 63) / 64) * 64;
+        if (P > nc64) P = nc64;
+        const int K = (ncoarse + P - 1) / P;
+        const double step = std::max(lat, (double)P * P * 8.0 / bw);
+        const double t = 2.0 * (K - 1) * step + 2.0 * std::max(lat, (double)K * P * P * 4.0 / bw);
+        if (t < best_t - 1e-12) {
+            best_t = t;
+            best = P;
+        }
+        if (P == nc64) break;
+    }
+    return best;
+}
 
 // Per-right-hand-side CG scalars, device resident.
 struct CgScalars {

@@ -192,9 +192,7 @@ void setup_blocks(afd_mesh* m) {
     for (int a = 0; a < 3; ++a) b.perm[a] = ax[a];
     const int n0 = b.nb[ax[0]], n1 = b.nb[ax[1]];
     b.w = 6 * (n0 * n1 + n0 + 1) + 5;
-    int P = ((b.w + 63) / 64) * 64;
-    const int nc64 = ((b.ncoarse + 63) / 64) * 64;
-    if (P > nc64) P = nc64;
+    const int P = choose_coarse_P(b.ncoarse, b.w);
     b.P = P;
     b.K = (b.ncoarse + P - 1) / P;
 }

@@ -17,6 +17,7 @@
 // is dropped: its row and column of Linv are zeroed, so its mu is 0.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "afd_internal.h"
@@ -257,9 +258,11 @@ __global__ void k_extract_diag(int K, int P, const double* D, double* ed) {
 // y[r][i] = c[r][i] + alpha * sum_j M[i][j] x[r][j]: one workgroup per row so
 // that every lane's loads are independent (the row is streamed once, the
 // short x vectors come from cache); batched over blockIdx.y
+// tri = 1: M lower triangular (row i reads columns 0..i); tri = 2: upper
+// (columns i..P-1); the skipped entries are stored zeros
 __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t mstride, const double* x,
                                               int64_t xstride, const double* c, int64_t cstride, double alpha,
-                                              double* y, int64_t ystride, int nrhs, int64_t vstride) {
+                                              double* y, int64_t ystride, int nrhs, int64_t vstride, int tri) {
     __shared__ double sh[4][4];
     const int kb = blockIdx.y;
     const int row = blockIdx.x;
@@ -267,7 +270,8 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t ms
     x += kb * xstride;
     const int t = threadIdx.x;
     double acc[4] = {0, 0, 0, 0};
-    for (int j = t; j < P; j += 256) {
+    const int j0 = (tri == 2) ? row : 0, j1 = (tri == 1) ? row + 1 : P;
+    for (int j = j0 + t; j < j1; j += 256) {
         const double mv = m[j];
         for (int r = 0; r < nrhs; ++r) acc[r] = fma(mv, x[r * vstride + j], acc[r]);
     }
@@ -456,21 +460,22 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
     const int P = b.P, K = b.K;
     const int64_t PP = (int64_t)P * P;
     const int npad = K * P;
+
     dim3 gp((npad + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_perm_in, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, nrhs, G, c.gperm);
     // c_k = Linv_k g_k, all k
     hipLaunchKernelGGL(k_gemv, dim3(P, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad);
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 1);
     // x_0 = c_0; x_k = c_k - T_k x_{k-1}
     AFD_HIP_TRY(hipMemcpy2DAsync(c.xperm, npad * sizeof(double), c.cvec, npad * sizeof(double), P * sizeof(double),
                                  nrhs, hipMemcpyDeviceToDevice, s));
     for (int k = 1; k < K; ++k)
         hipLaunchKernelGGL(k_gemv, dim3(P, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
                            c.xperm + (int64_t)(k - 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad);
+                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0);
     // c'_k = Linv_k^T x_k, all k
     hipLaunchKernelGGL(k_gemv, dim3(P, K), dim3(256), 0, s, P, c.LinvT, PP, c.xperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad);
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 2);
     // mu_{K-1} = c'_{K-1}; mu_k = c'_k - U_k mu_{k+1}
     AFD_HIP_TRY(hipMemcpy2DAsync(c.gperm + (int64_t)(K - 1) * P, npad * sizeof(double),
                                  c.cvec + (int64_t)(K - 1) * P, npad * sizeof(double), P * sizeof(double), nrhs,
@@ -478,7 +483,7 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
     for (int k = K - 2; k >= 0; --k)
         hipLaunchKernelGGL(k_gemv, dim3(P, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
                            c.gperm + (int64_t)(k + 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad);
+                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0);
     hipLaunchKernelGGL(k_perm_out, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, c.gperm, MU);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;

@@ -18,6 +18,7 @@
 // Modes: APPLY (Y = A U), RESID (R = F - A X, with partial sums of r.M^-1 r and
 // r.r) and DIR (the deflated CG direction P' = beta P + M^-1 R - W mu formed
 // while staging, Q = A P', partial sums of p'.q).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 
@@ -404,11 +405,24 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
     T rho_cur = rho_at(Z0 - 1);
     int buf = 1;  // buffer holding plane k+1
 
+    // outputs of plane k are stored after the first barrier of layer k+1, so
+    // that the barrier's wait for outstanding memory operations does not
+    // wait for stores issued just before it
+    T pend[3];
+    int pend_a = -1;
+    int own_m_next = (own && Z0 - 1 >= 0) ? (int)P.nmask[own_node + sz * (Z0 - 1)] : 0;
     for (int k = Z0 - 1; k < Z1; ++k) {  // element layer k spans node planes k, k+1
         const bool more = k + 2 <= Z1;
         if (more) fetch(k + 2, reg);  // prefetch while this layer computes
+        const int own_m = own_m_next;  // fixity of the owned node on plane k
+        if (own && k + 1 <= nz) own_m_next = P.nmask[own_node + sz * (k + 1)];
         const T rho_nxt = rho_at(k + 1);
         __syncthreads();  // plane k+1 staged; previous exchange consumed
+        if (pend_a >= 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Y[pend_a + c] = pend[c];
+            pend_a = -1;
+        }
         T tf[4][3];
         read_face(buf, tf);
         T own_next[3];
@@ -446,26 +460,27 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
         __syncthreads();
         if (own && k >= Z0) {  // node plane k is complete
             const int node = own_node + sz * k;
-            const int m = P.nmask[node];
+            const int m = own_m;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int a = 3 * node + c;
                 const T yv = s0[c] + xch[c][t - TX];
                 const bool fx = (m >> c) & 1;
                 if constexpr (MODE == APPLY) {
-                    Y[a] = fx ? U[a] : yv;
+                    pend[c] = fx ? U[a] : yv;
                 } else if constexpr (MODE == RESID) {
                     const T rv = fx ? T(0) : (T)(F[a] - yv);
-                    Y[a] = rv;
+                    pend[c] = rv;
                     const double z = rinv_of(P, node) / (double)kh.kdiag[c] * (double)rv;
                     acc0 += (double)rv * z;
                     acc1 += (double)rv * (double)rv;
                 } else {  // DIR: q = A p' (p' = 0 on fixed DOFs, so q = 0 there)
                     const T qv = fx ? T(0) : yv;
-                    Y[a] = qv;
+                    pend[c] = qv;
                     acc0 += (double)own_prev[c] * (double)qv;
                 }
             }
+            pend_a = 3 * node;
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) own_prev[c] = own_next[c];
@@ -473,6 +488,10 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
         if (more) put(buf ^ 1, reg);
         buf ^= 1;
         rho_cur = rho_nxt;
+    }
+    if (pend_a >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Y[pend_a + c] = pend[c];
     }
     if constexpr (MODE != APPLY) {
         // fixed-order workgroup reduction -> one partial per workgroup
@@ -496,6 +515,12 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
             P.partial[(rhs * 2 + 0) * P.npart + blockIdx.x] = s0;
             P.partial[(rhs * 2 + 1) * P.npart + blockIdx.x] = s1;
         }
+        // slots beyond this grid (sized for the larger of the FP64/FP32 grids) read as zero
+        if (blockIdx.x == 0)
+            for (int i = gridDim.x + t; i < P.npart; i += NT) {
+                P.partial[(rhs * 2 + 0) * P.npart + i] = 0.0;
+                P.partial[(rhs * 2 + 1) * P.npart + i] = 0.0;
+            }
     }
 }
 
@@ -640,9 +665,19 @@ __global__ __launch_bounds__(NT) void k_apply_dma(MvParams<T> P, KH<T> kh) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) ctop[q][c] = T(0);
 
+    // outputs of plane k are stored at the top of layer k+1 (after its
+    // barrier), so that a whole layer of compute covers their completion
+    // before the next vmcnt(0) wait (gfx9 counts stores in vmcnt)
+    T pend[3];
+    int pend_a = -1;
     for (int k = Z0 - 1; k < Z1; ++k) {  // element layer k (node planes k, k+1)
         // plane k+2 (issued one layer ago) has landed; masks of plane k+2 are in mk
         wait_all_and_barrier();
+        if (pend_a >= 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Y[pend_a + c] = pend[c];
+            pend_a = -1;
+        }
         const int own_m = own_m_next;
         // all ring accesses of this layer first ...
         if (k + 2 <= Z1) fix_masks(slot(k + 2), mk);
@@ -680,9 +715,14 @@ __global__ __launch_bounds__(NT) void k_apply_dma(MvParams<T> P, KH<T> kh) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const T yv = s0[c] + xch[c][t - TX];
-                Y[a0 + c] = ((own_m >> c) & 1) ? U[a0 + c] : yv;
+                pend[c] = ((own_m >> c) & 1) ? U[a0 + c] : yv;
             }
+            pend_a = a0;
         }
+    }
+    if (pend_a >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Y[pend_a + c] = pend[c];
     }
 }
 
@@ -698,25 +738,39 @@ bool use_dma() {
     return g_dma == 1;
 }
 
-void tiling(const Grid& g, int& tx, int& ty, int& zc, int& nchunk) {
+int g_slots[2] = {-1, -1};  // resident 256-thread workgroups of the apply (FP64, FP32) on this device
+
+// z-chunking: as many chunks as fit in one round of resident workgroups, so
+// that no partly filled second round trails the launch; at least 4 node
+// planes per chunk.  The FP32 kernels fit more workgroups per CU.
+void tiling(const Grid& g, int fp32, int& tx, int& ty, int& zc, int& nchunk) {
     tx = (g.nx + 1 + (TX - 2)) / (TX - 1);  // ceil((nx+1)/15)
     ty = (g.ny + 1 + (TY - 2)) / (TY - 1);
     if (g_zc_override < 0) {
         const char* e = getenv("AFD_MATVEC_ZC");
         g_zc_override = e ? atoi(e) : 0;
     }
+    if (g_slots[fp32] < 0) {
+        int dev = 0, cus = 256, per = fp32 ? 5 : 3, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_dma<float, true>, NT, 0)
+                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_dma<double, true>, NT, 0);
+        if (e == hipSuccess && n > 0) per = n;
+        g_slots[fp32] = cus * per;
+    }
     const int planes = g.nz + 1;
     if (g_zc_override > 0) {
         zc = g_zc_override;
     } else {
-        // aim at ~1024 workgroups (4 per CU) while keeping the one-layer
-        // z-overlap small
-        int want = (1024 + tx * ty - 1) / (tx * ty);
+        int want = g_slots[fp32] / (tx * ty);
         if (want < 1) want = 1;
+        const int maxc = (planes + 3) / 4;
+        if (want > maxc) want = maxc;
         zc = (planes + want - 1) / want;
-        if (zc < 8) zc = 8;
     }
     if (zc > planes) zc = planes;
+    if (zc < 1) zc = 1;
     nchunk = (planes + zc - 1) / zc;
 }
 
@@ -726,7 +780,7 @@ MvParams<T> base_params(const MatvecArgs& a) {
     p.nx = a.g.nx;
     p.ny = a.g.ny;
     p.nz = a.g.nz;
-    tiling(a.g, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
+    tiling(a.g, sizeof(T) == 4 ? 1 : 0, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
     p.ndof = (int)a.g.ndof;
     if constexpr (sizeof(T) == 8) p.rho = a.rho;
     else p.rho = a.rho32;
@@ -758,9 +812,13 @@ int launch(const MvParams<T>& p, const KeHaar& khd, int nrhs, hipStream_t s) {
 }  // namespace
 
 int matvec_num_tiles(const Grid& g) {
-    int tx, ty, zc, nc;
-    tiling(g, tx, ty, zc, nc);
-    return tx * ty * nc;
+    // partial-sum slots: the larger of the FP64 and FP32 grids
+    int tx, ty, zc, nc, best = 0;
+    for (int f = 0; f < 2; ++f) {
+        tiling(g, f, tx, ty, zc, nc);
+        best = std::max(best, tx * ty * nc);
+    }
+    return best;
 }
 
 int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,

@@ -85,9 +85,7 @@ uint64_t footprint_of(const afd_mesh_desc& d, int nrhs, int precision) {
         std::sort(nb, nb + 3);
         const int w = 6 * (nb[0] * nb[1] + nb[0] + 1) + 5;
         const int nc = 6 * nb[0] * nb[1] * nb[2];
-        int P = ((w + 63) / 64) * 64;
-        const int nc64 = ((nc + 63) / 64) * 64;
-        if (P > nc64) P = nc64;
+        const int P = afd::choose_coarse_P(nc, w);
         const int K = (nc + P - 1) / P;
         b += (uint64_t)P * P * K * 8 * 6 + (uint64_t)P * P * 8 + (uint64_t)K * P * 8 * 14;
     }
