@@ -70,9 +70,10 @@ struct Blocks {
 
 // Super-block size of the block-tridiagonal coarse factor: any multiple of 64
 // that is >= the half bandwidth w is valid.  A coarse solve is a chain of
-// 2(K-1) dependent P x P matrix-vector steps (K = ceil(n/P)) plus two batched
-// passes over the K triangular inverses; each step costs at least one launch
-// latency (~7 us) and otherwise streams P^2 doubles (~4 TB/s).  Pick the P of
+// 2(K-1) dependent P x w matrix-vector steps (K = ceil(n/P); the coupling
+// blocks are zero outside a w-column window) plus two batched passes over the
+// K triangular inverses (K P^2 / 2 doubles each); each launch costs at least
+// a launch latency (~6 us) and otherwise streams at ~4 TB/s.  Pick the P of
 // least modelled time among w, 2w, ..., 6w (AFD_COARSE_P overrides).
 inline int choose_coarse_P(int ncoarse, int w) {
     const int nc64 = ((ncoarse + 63) / 64) * 64;
@@ -82,14 +83,14 @@ inline int choose_coarse_P(int ncoarse, int w) {
         int P = ((std::max(forced, w) + 63) / 64) * 64;
         return std::min(P, nc64);
     }
-    const double lat = 7e-6, bw = 4e12;
+    const double lat = 6e-6, bw = 4e12;
     int best = 0;
     double best_t = 1e30;
     for (int m = 1; m <= 6; ++m) {
         int P = ((m * w + 63) / 64) * 64;
         if (P > nc64) P = nc64;
         const int K = (ncoarse + P - 1) / P;
-        const double step = std::max(lat, (double)P * P * 8.0 / bw);
+        const double step = std::max(lat, (double)P * std::min(P, w) * 8.0 / bw);
         const double t = 2.0 * (K - 1) * step + 2.0 * std::max(lat, (double)K * P * P * 4.0 / bw);
         if (t < best_t - 1e-12) {
             best_t = t;
@@ -117,6 +118,9 @@ struct MatvecArgs {
     const double* rho;       // nelem
     const float* rho32;      // nelem (FP32 path)
     const uint8_t* nmask;    // nnode, bit c = DOF c fixed
+    const double* rho_t;     // tile-major densities (plain apply), see launch_tile_rho
+    const float* rho32_t;
+    const uint16_t* fm_t;    // tile-major face fixity words, see launch_tile_fmask
 };
 struct DcgArgs {
     const double* rinv;      // nnode: 1 / sum of rho over the node's elements
@@ -128,6 +132,11 @@ struct DcgArgs {
     int npart;
 };
 int matvec_num_tiles(const Grid& g);
+// element counts of the tile-major side arrays of the plain apply: returns the
+// fixity-word count, *nrho the density count
+int64_t tile_layout_sizes(const Grid& g, int64_t* nrho);
+int launch_tile_rho(const Grid& g, const double* rho, double* rho_t, float* rho32_t, hipStream_t s);
+int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipStream_t s);
 int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,
                  hipStream_t s);
 int launch_residual(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* F,

@@ -71,6 +71,9 @@ struct afd_mesh {
     float* rho32 = nullptr;
     uint8_t* nmask = nullptr;
     uint8_t* dofmask = nullptr;  // staging for set_fixed
+    double* rho_t = nullptr;     // tile-major copies for the plain apply
+    float* rho32_t = nullptr;
+    uint16_t* fm_t = nullptr;
     double* rinv = nullptr;
     float* rinv32 = nullptr;
     double* ke_dev = nullptr;    // dense Ke (576) for the matrix-core path
@@ -161,6 +164,9 @@ MatvecArgs mv_args(afd_mesh* m) {
     a.rho = m->rho;
     a.rho32 = m->rho32;
     a.nmask = m->nmask;
+    a.rho_t = m->rho_t;
+    a.rho32_t = m->rho32_t;
+    a.fm_t = m->fm_t;
     return a;
 }
 
@@ -426,17 +432,21 @@ int afd_mesh_create(afd_context* ctx, const afd_mesh_desc* d, afd_mesh** out) {
     m->npartM = matvec_num_tiles(m->g);
     std::vector<double> ke(576);
     make_ke_dense(h, d->E, d->nu, ke.data());
+    int64_t ntr = 0;
+    const int64_t ntm = tile_layout_sizes(m->g, &ntr);
     int rc = AFD_OK;
     if ((rc = dalloc(&m->rho, m->g.nelem)) || (rc = dalloc(&m->rho32, m->g.nelem)) ||
         (rc = dalloc(&m->nmask, m->g.nnode)) || (rc = dalloc(&m->dofmask, m->g.ndof)) ||
         (rc = dalloc(&m->rinv, m->g.nnode)) || (rc = dalloc(&m->rinv32, m->g.nnode)) ||
-        (rc = dalloc(&m->ke_dev, 576))) {
+        (rc = dalloc(&m->ke_dev, 576)) || (rc = dalloc(&m->rho_t, ntr)) || (rc = dalloc(&m->rho32_t, ntr)) ||
+        (rc = dalloc(&m->fm_t, ntm))) {
         afd_mesh_destroy(m);
         return rc;
     }
     hipStream_t s = ctx->stream;
     if (launch_fill_f64(m->g.nelem, 1.0, m->rho, s) || launch_fill_f32(m->g.nelem, 1.0f, m->rho32, s) ||
         hipMemsetAsync(m->nmask, 0, m->g.nnode, s) != hipSuccess ||
+        launch_tile_rho(m->g, m->rho, m->rho_t, m->rho32_t, s) || launch_tile_fmask(m->g, m->nmask, m->fm_t, s) ||
         hipMemcpyAsync(m->ke_dev, ke.data(), 576 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
         afd_mesh_destroy(m);
@@ -454,7 +464,7 @@ void afd_mesh_destroy(afd_mesh* m) {
     free_work(m->w);
     coarse_free(m->coarse);
     dfree(&m->rho), dfree(&m->rho32), dfree(&m->nmask), dfree(&m->dofmask), dfree(&m->rinv), dfree(&m->rinv32),
-        dfree(&m->ke_dev);
+        dfree(&m->ke_dev), dfree(&m->rho_t), dfree(&m->rho32_t), dfree(&m->fm_t);
     delete m;
 }
 
@@ -494,6 +504,7 @@ int afd_mesh_set_scale(afd_mesh* m, const double* rho, int64_t n, int mem_kind) 
     AFD_TRY(host_or_dev_to_dev(m, rho, n * sizeof(double), mem_kind, m->rho));
     hipLaunchKernelGGL(k_rho32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, m->ctx->stream, n, m->rho, m->rho32);
     AFD_HIP_TRY(hipGetLastError());
+    AFD_TRY(launch_tile_rho(m->g, m->rho, m->rho_t, m->rho32_t, m->ctx->stream));
     m->jacobi_valid = false;
     m->coarse.valid = false;
     return AFD_OK;
@@ -518,6 +529,7 @@ int afd_mesh_set_fixed(afd_mesh* m, const uint8_t* mask, int64_t n, int mem_kind
     }
     AFD_TRY(host_or_dev_to_dev(m, mask, n, mem_kind, m->dofmask));
     AFD_TRY(launch_pack_mask(m->g, m->dofmask, m->nmask, m->ctx->stream));
+    AFD_TRY(launch_tile_fmask(m->g, m->nmask, m->fm_t, m->ctx->stream));
     m->coarse.valid = false;
     return AFD_OK;
 }
@@ -529,6 +541,9 @@ int afd_mesh_footprint(const afd_mesh* m, int32_t nrhs, int32_t precision, uint6
     }
     const uint64_t nd = m->g.ndof, nn = m->g.nnode, ne = m->g.nelem;
     uint64_t b = ne * 12 + nn * (1 + 12) + nd + 576 * 8;                 // rho, rho32, masks, rinv
+    int64_t ntr = 0;
+    const int64_t ntm = tile_layout_sizes(m->g, &ntr);
+    b += (uint64_t)ntr * 12 + (uint64_t)ntm * 2;                         // tile-major apply inputs
     b += (uint64_t)nrhs * nd * 8 * 8;                                    // FP64 work vectors
     if (precision == AFD_MIXED) b += (uint64_t)nrhs * nd * 4 * 8;        // FP32 inner vectors
     if (m->deflate) {

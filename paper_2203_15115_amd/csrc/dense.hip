@@ -255,37 +255,56 @@ __global__ void k_extract_diag(int K, int P, const double* D, double* ed) {
 }
 
 // ------------------------------------------------------------------ solve
-// y[r][i] = c[r][i] + alpha * sum_j M[i][j] x[r][j]: one workgroup per row so
-// that every lane's loads are independent (the row is streamed once, the
-// short x vectors come from cache); batched over blockIdx.y
-// tri = 1: M lower triangular (row i reads columns 0..i); tri = 2: upper
-// (columns i..P-1); the skipped entries are stored zeros
+// y[r][i] = c[r][i] + alpha * sum_j M[i][j] x[r][j] over j in [lo(i), hi(i)):
+// one wavefront per row (coalesced row stream, x from cache), four rows per
+// workgroup, batched over blockIdx.y.  tri = 1: M lower triangular
+// (j <= i); tri = 2: upper (j >= i); tri = 0: the column window
+// [c0, c1).  Entries outside the range are stored zeros and are not read.
 __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t mstride, const double* x,
                                               int64_t xstride, const double* c, int64_t cstride, double alpha,
-                                              double* y, int64_t ystride, int nrhs, int64_t vstride, int tri) {
-    __shared__ double sh[4][4];
+                                              double* y, int64_t ystride, int nrhs, int64_t vstride, int tri, int c0,
+                                              int c1) {
     const int kb = blockIdx.y;
-    const int row = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= P) return;
     const double* m = M + kb * mstride + (int64_t)row * P;
     x += kb * xstride;
-    const int t = threadIdx.x;
     double acc[4] = {0, 0, 0, 0};
-    const int j0 = (tri == 2) ? row : 0, j1 = (tri == 1) ? row + 1 : P;
-    for (int j = j0 + t; j < j1; j += 256) {
-        const double mv = m[j];
-        for (int r = 0; r < nrhs; ++r) acc[r] = fma(mv, x[r * vstride + j], acc[r]);
+    const int j0 = tri == 2 ? row : (tri == 1 ? 0 : c0);
+    const int j1 = tri == 1 ? row + 1 : (tri == 2 ? P : c1);
+    // aligned pairs (P, the block offsets and the vector strides are even), four
+    // 16-byte loads per lane in flight; pair members outside [j0, j1) count zero
+    for (int jj = (j0 & ~1) + 2 * lane; jj < j1; jj += 512) {
+        double2 mv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = jj + 128 * u;
+            mv[u] = j < j1 ? *reinterpret_cast<const double2*>(m + j) : make_double2(0.0, 0.0);
+            if (j < j0) mv[u].x = 0.0;
+            if (j + 1 >= j1) mv[u].y = 0.0;
+        }
+        for (int r = 0; r < nrhs; ++r) {
+            const double* xr = x + r * vstride;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = jj + 128 * u;
+                if (j < j1) {
+                    const double2 xv = *reinterpret_cast<const double2*>(xr + j);
+                    acc[r] = fma(mv[u].x, xv.x, acc[r]);
+                    acc[r] = fma(mv[u].y, xv.y, acc[r]);
+                }
+            }
+        }
     }
     for (int r = 0; r < nrhs; ++r) {
         double v = acc[r];
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
-        if ((t & 63) == 0) sh[r][t >> 6] = v;
-    }
-    __syncthreads();
-    if (t < nrhs) {
-        const double v = (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
-        const int64_t o = t * vstride + row;
-        y[kb * ystride + o] = (c ? c[kb * cstride + o] : 0.0) + alpha * v;
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) {
+            const int64_t o = r * vstride + row;
+            y[kb * ystride + o] = (c ? c[kb * cstride + o] : 0.0) + alpha * v;
+        }
     }
 }
 
@@ -460,30 +479,35 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
     const int P = b.P, K = b.K;
     const int64_t PP = (int64_t)P * P;
     const int npad = K * P;
+    // coupling blocks E(k, k-1) are zero outside their last w columns, E(k, k+1)
+    // outside their first w columns (half bandwidth w <= P), so the chain
+    // products only stream that window
+    const int w = std::min(b.w, P);
+    const unsigned rb = (unsigned)((P + 3) / 4);
 
     dim3 gp((npad + 255) / 256, nrhs);
     hipLaunchKernelGGL(k_perm_in, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, nrhs, G, c.gperm);
     // c_k = Linv_k g_k, all k
-    hipLaunchKernelGGL(k_gemv, dim3(P, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 1);
+    hipLaunchKernelGGL(k_gemv, dim3(rb, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 1, 0, P);
     // x_0 = c_0; x_k = c_k - T_k x_{k-1}
     AFD_HIP_TRY(hipMemcpy2DAsync(c.xperm, npad * sizeof(double), c.cvec, npad * sizeof(double), P * sizeof(double),
                                  nrhs, hipMemcpyDeviceToDevice, s));
     for (int k = 1; k < K; ++k)
-        hipLaunchKernelGGL(k_gemv, dim3(P, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
+        hipLaunchKernelGGL(k_gemv, dim3(rb, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
                            c.xperm + (int64_t)(k - 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0);
+                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, P - w, P);
     // c'_k = Linv_k^T x_k, all k
-    hipLaunchKernelGGL(k_gemv, dim3(P, K), dim3(256), 0, s, P, c.LinvT, PP, c.xperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 2);
+    hipLaunchKernelGGL(k_gemv, dim3(rb, K), dim3(256), 0, s, P, c.LinvT, PP, c.xperm, (int64_t)P,
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 2, 0, P);
     // mu_{K-1} = c'_{K-1}; mu_k = c'_k - U_k mu_{k+1}
     AFD_HIP_TRY(hipMemcpy2DAsync(c.gperm + (int64_t)(K - 1) * P, npad * sizeof(double),
                                  c.cvec + (int64_t)(K - 1) * P, npad * sizeof(double), P * sizeof(double), nrhs,
                                  hipMemcpyDeviceToDevice, s));
     for (int k = K - 2; k >= 0; --k)
-        hipLaunchKernelGGL(k_gemv, dim3(P, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
+        hipLaunchKernelGGL(k_gemv, dim3(rb, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
                            c.gperm + (int64_t)(k + 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0);
+                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, 0, w);
     hipLaunchKernelGGL(k_perm_out, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, c.gperm, MU);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;

@@ -93,6 +93,8 @@ struct MvParams {
     T* Y;           // APPLY: output; RESID: R; DIR: Q
     const T* F;     // RESID: F; DIR: R (residual)
     T* Pn;          // DIR: new direction (owned nodes written)
+    const T* rho_t;          // tile-major densities (plain apply)
+    const uint16_t* fm_t;    // tile-major face fixity words (plain apply)
     const double* rinv;  // per node 1/sum rho (double)
     const float* rinv32;
     // deflation
@@ -726,19 +728,372 @@ __global__ __launch_bounds__(NT) void k_apply_dma(MvParams<T> P, KH<T> kh) {
     }
 }
 
-int g_zc_override = -1;
-int g_dma = -1;
-
-// LDS-DMA staging for the plain apply (AFD_MATVEC_DMA=0 selects register staging)
-bool use_dma() {
-    if (g_dma < 0) {
-        const char* e = getenv("AFD_MATVEC_DMA");
-        g_dma = (e && *e == '0') ? 0 : 1;
+// Tile-major side arrays of the plain apply, rebuilt whenever the densities
+// or the fixity change: per (tile, element layer) the 16x16 densities of the
+// tile's elements, and per (tile, node plane) a 12-bit fixity word for each
+// of the 16x16 node positions, bit 3q + c set when component c of face
+// corner q (node (lx + (q & 1), ly + (q >> 1))) is fixed.  Entries outside
+// the mesh are zero.  Both are contiguous per tile and layer, so the apply
+// stages them with aligned LDS DMA instead of many narrow loads.
+template <typename T>
+__global__ void k_tile_rho(int nx, int ny, int nz, int tiles_x, int ntile, const double* rho, T* out) {
+    const int64_t n = (int64_t)ntile * nz * NT;
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n; f += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(f % NT);
+        const int64_t r = f / NT;
+        const int k = (int)(r % nz), tile = (int)(r / nz);
+        const int gi = (tile % tiles_x) * (TX - 1) - 1 + t % TX, gj = (tile / tiles_x) * (TY - 1) - 1 + t / TX;
+        T v = T(0);
+        if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) v = (T)rho[gi + (int64_t)nx * (gj + (int64_t)ny * k)];
+        out[f] = v;
     }
-    return g_dma == 1;
+}
+__global__ void k_tile_fmask(int nx, int ny, int nz, int tiles_x, int ntile, const uint8_t* nmask, uint16_t* out) {
+    const int64_t n = (int64_t)ntile * (nz + 1) * NT;
+    const int64_t sy = nx + 1, sz = (int64_t)(nx + 1) * (ny + 1);
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n; f += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(f % NT);
+        const int64_t r = f / NT;
+        const int k = (int)(r % (nz + 1)), tile = (int)(r / (nz + 1));
+        const int gi = (tile % tiles_x) * (TX - 1) - 1 + t % TX, gj = (tile / tiles_x) * (TY - 1) - 1 + t / TX;
+        int word = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = gi + (q & 1), j = gj + (q >> 1);
+            if (i >= 0 && i <= nx && j >= 0 && j <= ny) word |= (nmask[i + sy * j + sz * k] & 7) << (3 * q);
+        }
+        out[f] = (uint16_t)word;
+    }
 }
 
-int g_slots[2] = {-1, -1};  // resident 256-thread workgroups of the apply (FP64, FP32) on this device
+// Plain apply with every input staged by LDS DMA.  Same tiles and element
+// arithmetic as above; the z march proceeds in steps of D layers: at the top
+// of a step the node planes, fixity words and densities needed one step
+// later are put in flight (rings of 2D + 1 planes and 2D density layers),
+// and one wait + barrier per step lands them.  Staged planes stay raw: each
+// thread zeroes the fixed components of its own face after reading it, which
+// also hands it the unmasked value of its own node for the identity rows.
+// The y exchange of layer k is completed after the barrier at the top of
+// layer k + 1, so each layer has a single barrier.  LDS reads are inline
+// assembly with their own lgkmcnt wait: the compiler would otherwise put a
+// vmcnt(0) before each of them (it cannot tell that the DMAs in flight
+// target other ring slots), which would cap the prefetch distance at one
+// layer.
+
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ uint32_t lds_off(const T* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) T*)p;
+}
+
+// Face of a staged plane at LDS byte address a (node (lx, ly); corners
+// q = ax + 2 ay, three components; node rows PX * 3 values apart), the
+// density at ar and the fixity word at am, with one wait.
+__device__ __forceinline__ void lds_face(uint32_t a, uint32_t ar, uint32_t am, double f[4][3], double& rho,
+                                         int& fm) {
+    dv2 r0, r1, r2, r3, r4, r5;
+    double rr;
+    uint32_t mm;
+    asm volatile(
+        "ds_read2_b64 %0, %8 offset1:1\n\t"
+        "ds_read2_b64 %1, %8 offset0:2 offset1:3\n\t"
+        "ds_read2_b64 %2, %8 offset0:4 offset1:5\n\t"
+        "ds_read2_b64 %3, %8 offset0:51 offset1:52\n\t"
+        "ds_read2_b64 %4, %8 offset0:53 offset1:54\n\t"
+        "ds_read2_b64 %5, %8 offset0:55 offset1:56\n\t"
+        "ds_read_b64 %6, %9\n\t"
+        "ds_read_u16 %7, %10\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(rr), "=&v"(mm)
+        : "v"(a), "v"(ar), "v"(am));
+    f[0][0] = r0.x; f[0][1] = r0.y; f[0][2] = r1.x;
+    f[1][0] = r1.y; f[1][1] = r2.x; f[1][2] = r2.y;
+    f[2][0] = r3.x; f[2][1] = r3.y; f[2][2] = r4.x;
+    f[3][0] = r4.y; f[3][1] = r5.x; f[3][2] = r5.y;
+    rho = rr;
+    fm = (int)mm;
+}
+__device__ __forceinline__ void lds_face(uint32_t a, uint32_t ar, uint32_t am, float f[4][3], float& rho, int& fm) {
+    fv2 r0, r1, r2, r3, r4, r5;
+    float rr;
+    uint32_t mm;
+    asm volatile(
+        "ds_read2_b32 %0, %8 offset1:1\n\t"
+        "ds_read2_b32 %1, %8 offset0:2 offset1:3\n\t"
+        "ds_read2_b32 %2, %8 offset0:4 offset1:5\n\t"
+        "ds_read2_b32 %3, %8 offset0:51 offset1:52\n\t"
+        "ds_read2_b32 %4, %8 offset0:53 offset1:54\n\t"
+        "ds_read2_b32 %5, %8 offset0:55 offset1:56\n\t"
+        "ds_read_b32 %6, %9\n\t"
+        "ds_read_u16 %7, %10\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(rr), "=&v"(mm)
+        : "v"(a), "v"(ar), "v"(am));
+    f[0][0] = r0.x; f[0][1] = r0.y; f[0][2] = r1.x;
+    f[1][0] = r1.y; f[1][1] = r2.x; f[1][2] = r2.y;
+    f[2][0] = r3.x; f[2][1] = r3.y; f[2][2] = r4.x;
+    f[3][0] = r4.y; f[3][1] = r5.x; f[3][2] = r5.y;
+    rho = rr;
+    fm = (int)mm;
+}
+// bottom face and its fixity only (start of a chunk)
+template <typename T>
+__device__ __forceinline__ void lds_face0(uint32_t a, uint32_t am, T f[4][3], int& fm) {
+    T rho_unused;
+    lds_face(a, a, am, f, rho_unused, fm);
+}
+// three components of one exchange slot: [c][NT] layout, a = slot of c = 0
+__device__ __forceinline__ void lds_xch(uint32_t a, double x[3]) {
+    dv2 r01;
+    double r2;
+    asm volatile(
+        "ds_read2st64_b64 %0, %2 offset1:4\n\t"
+        "ds_read_b64 %1, %2 offset:4096\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r01), "=&v"(r2)
+        : "v"(a));
+    x[0] = r01.x;
+    x[1] = r01.y;
+    x[2] = r2;
+}
+__device__ __forceinline__ void lds_xch(uint32_t a, float x[3]) {
+    fv2 r01;
+    float r2;
+    asm volatile(
+        "ds_read2st64_b32 %0, %2 offset1:4\n\t"
+        "ds_read_b32 %1, %2 offset:2048\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r01), "=&v"(r2)
+        : "v"(a));
+    x[0] = r01.x;
+    x[1] = r01.y;
+    x[2] = r2;
+}
+static_assert(PX * 3 == 51 && NT == 256, "assembly offsets assume 17-node rows and 256-slot exchange planes");
+
+template <typename T, bool CUB, int D>
+__global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
+    using S = DmaShape<T>;
+    constexpr int R = 2 * D + 1;   // node-plane slots: D + 1 in use, D in flight
+    constexpr int RR = 2 * D;      // density-layer slots
+    __shared__ __attribute__((aligned(16))) T ring[R][PLANE];
+    __shared__ __attribute__((aligned(16))) T rring[RR][NT];
+    __shared__ __attribute__((aligned(16))) uint16_t mring[R][NT];
+    __shared__ __attribute__((aligned(16))) T xch[2][3][NT];
+
+    const int rhs = blockIdx.y;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int lx = t % TX, ly = t / TX;
+    const int L = xcd_tile(blockIdx.x, gridDim.x);
+    const int ntile = P.tiles_x * P.tiles_y;
+    const int tile = L % ntile;
+    const int chunk = L / ntile;
+    const int X0 = (tile % P.tiles_x) * (TX - 1) - 1;
+    const int Y0 = (tile / P.tiles_x) * (TY - 1) - 1;
+    const int Z0 = chunk * P.zc;
+    const int Z1 = min(Z0 + P.zc, P.nz + 1);
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
+    const int roff = rhs * P.ndof;
+    const T* U = P.U + roff;
+    T* Y = P.Y + roff;
+    const uint32_t* Udw = reinterpret_cast<const uint32_t*>(U);
+    const uint32_t* Rdw = reinterpret_cast<const uint32_t*>(P.rho_t) + (size_t)tile * nz * NT * S::DW;
+    const uint32_t* Mdw = reinterpret_cast<const uint32_t*>(P.fm_t) + (size_t)tile * (nz + 1) * (NT / 2);
+
+    const int gi = X0 + lx, gj = Y0 + ly;
+    const bool own = lx >= 1 && ly >= 1 && gi <= nx && gj <= ny;
+    const int own_node = gi + sy * gj;
+
+    int goff[S::J];  // node-plane DMA plan: instruction j of wave w moves dwords (4j + w) * 64 + lane
+#pragma unroll
+    for (int j = 0; j < S::J; ++j) {
+        const int f = (4 * j + w) * 64 + lane;
+        goff[j] = -1;
+        if (f < S::NDW) {
+            const int row = f / S::ROWDW, c = f - row * S::ROWDW;
+            const int i = X0 + c / (3 * S::DW), jj = Y0 + row;
+            if (i >= 0 && i <= nx && jj >= 0 && jj <= ny) goff[j] = (X0 + sy * jj) * 3 * S::DW + c;
+        }
+    }
+    const int kfirst = Z0 - 1;
+    auto pslot = [&](int g) { return (g - kfirst) % R; };
+    auto rslot = [&](int k) { return (k - kfirst) % RR; };
+    auto issue_plane = [&](int g) {  // node plane g and its fixity words
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&ring[pslot(g)][0]);
+        uint32_t* mdst = reinterpret_cast<uint32_t*>(&mring[pslot(g)][0]);
+        if (g >= 0 && g <= nz) {
+            const int base = g * sz * 3 * S::DW;
+#pragma unroll
+            for (int j = 0; j < S::J; ++j) {
+                if (goff[j] >= 0)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)(Udw + base + goff[j]),
+                        (__attribute__((address_space(3))) void*)(dst + (4 * j + w) * 64), 4, 0, 0);
+            }
+            if (w < 2)
+                __builtin_amdgcn_global_load_lds((const void*)(Mdw + g * (NT / 2) + t),
+                                                 (__attribute__((address_space(3))) void*)(mdst + w * 64), 4, 0, 0);
+        } else {
+            for (int f = t; f < S::NDW; f += NT) dst[f] = 0u;
+            if (t < NT / 2) mdst[t] = 0u;
+        }
+    };
+    auto issue_rho = [&](int k) {  // density layer k
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&rring[rslot(k)][0]);
+        if (k >= 0 && k < nz) {
+#pragma unroll
+            for (int j = 0; j < S::DW; ++j)
+                __builtin_amdgcn_global_load_lds((const void*)(Rdw + (size_t)k * NT * S::DW + (4 * j + w) * 64 + lane),
+                                                 (__attribute__((address_space(3))) void*)(dst + (4 * j + w) * 64), 4,
+                                                 0, 0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < S::DW; ++j) dst[j * NT + t] = 0u;
+        }
+    };
+    // zero the fixed components of a face (bit 3q + c of fm)
+    auto mask_face = [&](int fm, T f[4][3]) {
+        if (fm) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if ((fm >> (3 * q + c)) & 1) f[q][c] = T(0);
+        }
+    };
+    const uint32_t face_off = (uint32_t)((ly * PX + lx) * 3 * sizeof(T));
+    const uint32_t ring_base = lds_off(&ring[0][0]) + face_off;
+    const uint32_t rring_base = lds_off(&rring[0][0]) + (uint32_t)(t * sizeof(T));
+    const uint32_t mring_base = lds_off(&mring[0][0]) + (uint32_t)(t * 2);
+    const uint32_t xch_base = lds_off(&xch[0][0][0]) + (uint32_t)(max(t - TX, 0) * sizeof(T));
+    constexpr uint32_t PLANE_B = PLANE * sizeof(T), RL_B = NT * sizeof(T), ML_B = NT * 2, XB_B = 3 * NT * sizeof(T);
+
+    for (int f = t; f < R * PLANE; f += NT) (&ring[0][0])[f] = T(0);
+    lds_barrier();
+
+    // prologue: planes kfirst .. kfirst + D, densities of layers kfirst .. kfirst + D - 1
+#pragma unroll
+    for (int j = 0; j <= D; ++j)
+        if (kfirst + j <= Z1) issue_plane(kfirst + j);
+#pragma unroll
+    for (int d = 0; d < D; ++d) issue_rho(kfirst + d);
+    wait_all_and_barrier();
+
+    T bf[4][3], ctop[4][3];
+    int fm0;
+    lds_face0<T>(ring_base + pslot(kfirst) * PLANE_B, mring_base + pslot(kfirst) * ML_B, bf, fm0);
+    mask_face(fm0, bf);
+    face_fwd<T>(bf);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ctop[q][c] = T(0);
+    T rawb[3] = {T(0), T(0), T(0)};  // unmasked own-node values of the bottom plane
+    int mownb = 0;                    // and their fixity bits
+    T pend[3] = {T(0), T(0), T(0)};   // plane k - 1 output before the y exchange
+    int pend_m = 0, pend_a = -1, pend_x = 0;
+
+    for (int k0 = kfirst; k0 < Z1; k0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int k = k0 + d;
+            if (k < Z1) {
+                if (d == 0) wait_all_and_barrier();  // planes k0 + 1 .. k0 + D and their densities landed
+                else lds_barrier();
+                if (pend_a >= 0) {  // finish plane k - 1 with the row below's exchange
+                    T xr[3];
+                    lds_xch(xch_base + pend_x * XB_B, xr);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Y[pend_a + c] = ((pend_m >> c) & 1) ? pend[c] : pend[c] + xr[c];
+                    pend_a = -1;
+                }
+                if (d == 0) {  // next step's planes and densities
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        if (k0 + D + 1 + j <= Z1) issue_plane(k0 + D + 1 + j);
+                        if (k0 + D + j < Z1) issue_rho(k0 + D + j);
+                    }
+                }
+                T tf[4][3], rho_k;
+                int fmt;
+                lds_face(ring_base + pslot(k + 1) * PLANE_B, rring_base + rslot(k) * RL_B,
+                         mring_base + pslot(k + 1) * ML_B, tf, rho_k, fmt);
+                T rawt[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rawt[c] = tf[0][c];
+                mask_face(fmt, tf);
+                face_fwd<T>(tf);
+                T yb[4][3], yt[4][3];
+                element_haar<T, CUB>(kh, rho_k, bf, tf, yb, yt);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        yb[q][c] += ctop[q][c];
+                        ctop[q][c] = yt[q][c];
+                        bf[q][c] = tf[q][c];
+                    }
+                face_inv<T>(yb);
+                const int xb = k & 1;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T s0 = yb[0][c] + dpp_shr1(yb[1][c]);
+                    xch[xb][c][t] = yb[2][c] + dpp_shr1(yb[3][c]);
+                    pend[c] = ((mownb >> c) & 1) ? rawb[c] : s0;
+                }
+                if (own && k >= Z0) {
+                    pend_a = 3 * (own_node + sz * k);
+                    pend_m = mownb;
+                    pend_x = xb;
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rawb[c] = rawt[c];
+                mownb = fmt & 7;
+            }
+        }
+    }
+    lds_barrier();
+    if (pend_a >= 0) {
+        T xr[3];
+        lds_xch(xch_base + pend_x * XB_B, xr);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Y[pend_a + c] = ((pend_m >> c) & 1) ? pend[c] : pend[c] + xr[c];
+    }
+}
+
+int g_zc_override = -1;
+int g_variant = -1;
+
+// plain-apply kernel: 0 register staging, 1 single-step LDS DMA, 2..4 the
+// tile-major DMA kernel with 1..3 layers per step (AFD_APPLY_KERNEL)
+int apply_variant() {
+    if (g_variant < 0) {
+        const char* e = getenv("AFD_APPLY_KERNEL");
+        int v = e ? atoi(e) : 2;
+        if (v < 0 || v > 4) v = 2;
+        g_variant = v;
+    }
+    return g_variant;
+}
+
+template <typename T>
+int apply_occupancy(int variant) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (variant) {
+        case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_matvec<T, APPLY, true>, NT, 0); break;
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_dma<T, true>, NT, 0); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 1>, NT, 0); break;
+        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 2>, NT, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 3>, NT, 0); break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 0;
+}
+
+int g_slots[2] = {-1, -1};  // resident 256-thread workgroups of the plain apply (FP64, FP32) on this device
 
 // z-chunking: as many chunks as fit in one round of resident workgroups, so
 // that no partly filled second round trails the launch; at least 4 node
@@ -751,12 +1106,11 @@ void tiling(const Grid& g, int fp32, int& tx, int& ty, int& zc, int& nchunk) {
         g_zc_override = e ? atoi(e) : 0;
     }
     if (g_slots[fp32] < 0) {
-        int dev = 0, cus = 256, per = fp32 ? 5 : 3, n = 0;
+        int dev = 0, cus = 256, per = fp32 ? 4 : 2;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_dma<float, true>, NT, 0)
-                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_dma<double, true>, NT, 0);
-        if (e == hipSuccess && n > 0) per = n;
+        const int n = fp32 ? apply_occupancy<float>(apply_variant()) : apply_occupancy<double>(apply_variant());
+        if (n > 0) per = n;
         g_slots[fp32] = cus * per;
     }
     const int planes = g.nz + 1;
@@ -782,9 +1136,15 @@ MvParams<T> base_params(const MatvecArgs& a) {
     p.nz = a.g.nz;
     tiling(a.g, sizeof(T) == 4 ? 1 : 0, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
     p.ndof = (int)a.g.ndof;
-    if constexpr (sizeof(T) == 8) p.rho = a.rho;
-    else p.rho = a.rho32;
+    if constexpr (sizeof(T) == 8) {
+        p.rho = a.rho;
+        p.rho_t = a.rho_t;
+    } else {
+        p.rho = a.rho32;
+        p.rho_t = a.rho32_t;
+    }
     p.nmask = a.nmask;
+    p.fm_t = a.fm_t;
     return p;
 }
 
@@ -797,9 +1157,26 @@ int launch(const MvParams<T>& p, const KeHaar& khd, int nrhs, hipStream_t s) {
     dim3 grid(p.tiles_x * p.tiles_y * p.nchunk, nrhs);
     const KH<T> kh = to_kh<T>(khd);
     const bool cub = is_cubic(khd);
-    if (MODE == APPLY && use_dma()) {
-        if (cub) hipLaunchKernelGGL((k_apply_dma<T, true>), grid, dim3(NT), 0, s, p, kh);
-        else hipLaunchKernelGGL((k_apply_dma<T, false>), grid, dim3(NT), 0, s, p, kh);
+    const int v = MODE == APPLY ? apply_variant() : 0;
+    if (v >= 1) {
+        switch (v) {
+            case 1:
+                if (cub) hipLaunchKernelGGL((k_apply_dma<T, true>), grid, dim3(NT), 0, s, p, kh);
+                else hipLaunchKernelGGL((k_apply_dma<T, false>), grid, dim3(NT), 0, s, p, kh);
+                break;
+            case 2:
+                if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 1>), grid, dim3(NT), 0, s, p, kh);
+                else hipLaunchKernelGGL((k_apply_tm<T, false, 1>), grid, dim3(NT), 0, s, p, kh);
+                break;
+            case 3:
+                if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 2>), grid, dim3(NT), 0, s, p, kh);
+                else hipLaunchKernelGGL((k_apply_tm<T, false, 2>), grid, dim3(NT), 0, s, p, kh);
+                break;
+            default:
+                if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 3>), grid, dim3(NT), 0, s, p, kh);
+                else hipLaunchKernelGGL((k_apply_tm<T, false, 3>), grid, dim3(NT), 0, s, p, kh);
+                break;
+        }
     } else if (cub) {
         hipLaunchKernelGGL((k_matvec<T, MODE, true>), grid, dim3(NT), 0, s, p, kh);
     } else {
@@ -819,6 +1196,27 @@ int matvec_num_tiles(const Grid& g) {
         best = std::max(best, tx * ty * nc);
     }
     return best;
+}
+
+int64_t tile_layout_sizes(const Grid& g, int64_t* nrho) {
+    const int tx = (g.nx + 1 + (TX - 2)) / (TX - 1), ty = (g.ny + 1 + (TY - 2)) / (TY - 1);
+    if (nrho) *nrho = (int64_t)tx * ty * g.nz * NT;
+    return (int64_t)tx * ty * (g.nz + 1) * NT;
+}
+
+int launch_tile_rho(const Grid& g, const double* rho, double* rho_t, float* rho32_t, hipStream_t s) {
+    const int tx = (g.nx + 1 + (TX - 2)) / (TX - 1), ty = (g.ny + 1 + (TY - 2)) / (TY - 1);
+    hipLaunchKernelGGL(k_tile_rho<double>, dim3(2048), dim3(256), 0, s, g.nx, g.ny, g.nz, tx, tx * ty, rho, rho_t);
+    hipLaunchKernelGGL(k_tile_rho<float>, dim3(2048), dim3(256), 0, s, g.nx, g.ny, g.nz, tx, tx * ty, rho, rho32_t);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipStream_t s) {
+    const int tx = (g.nx + 1 + (TX - 2)) / (TX - 1), ty = (g.ny + 1 + (TY - 2)) / (TY - 1);
+    hipLaunchKernelGGL(k_tile_fmask, dim3(2048), dim3(256), 0, s, g.nx, g.ny, g.nz, tx, tx * ty, nmask, fm_t);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
 }
 
 int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,

@@ -79,6 +79,11 @@ uint64_t footprint_of(const afd_mesh_desc& d, int nrhs, int precision) {
     const uint64_t nn = (uint64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1), ne = (uint64_t)d.nx * d.ny * d.nz,
                    nd = 3 * nn;
     uint64_t b = ne * 12 + nn * 13 + nd + 576 * 8 + (uint64_t)4 * nd * 8 * 8;
+    afd::Grid g{};
+    g.nx = d.nx, g.ny = d.ny, g.nz = d.nz;
+    int64_t ntr = 0;
+    const int64_t ntm = afd::tile_layout_sizes(g, &ntr);
+    b += (uint64_t)ntr * 12 + (uint64_t)ntm * 2;
     if (precision == AFD_MIXED) b += (uint64_t)4 * nd * 4 * 8;
     if (d.bx > 0 && d.by > 0 && d.bz > 0) {
         int nb[3] = {(d.nx + d.bx - 1) / d.bx, (d.ny + d.by - 1) / d.by, (d.nz + d.bz - 1) / d.bz};
