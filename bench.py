@@ -6,9 +6,10 @@ median, clamped on x=0, unit -z load on the x=L bottom edge, 8x8x8 deflation
 blocks, FP64, relative residual 1e-8.  Inputs are synthetic (seeded) and
 resident in HBM before timing starts.
 
-A step is one pass of the whole hot path: deflated PCG to 1e-8 (coarse
-factor already built for this density field), compliance, strain-energy
-sensitivity field and topology extraction at a volume fraction.  The headline
+A step is one pass of the whole hot path from device-resident inputs:
+density and fixity made current, Jacobi diagonal, coarse matrix W^T K W and
+its factor, deflated PCG to 1e-8, compliance, strain-energy sensitivity field
+and topology extraction at a volume fraction.  The headline
 value is the throughput of the element-by-element operator apply (GDOF/s =
 DOFs / time per apply), timed with HIP events on the stream the library
 launches on; the roofline object prices that kernel against HBM.
@@ -28,8 +29,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per FP64 apply launch at 192x96x96 from rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by the
-# same counter on a 512 MiB copy (kernel as of the committed counter summary); None when not measured
-TRAFFIC_BYTES = 192_480_000
+# same counter on a 512 MiB copy (kernel as of the committed counter summary
+# profiles/apply_fp64_192x96x96_counters.md); None when not measured
+TRAFFIC_BYTES = 74_585_907 + 43_811_021
 
 
 def matvec_algorithmic_bytes(dims, word=8):
@@ -261,11 +263,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps}), flush=True)
         return
-    t0 = time.perf_counter()
-    afdcg.afd_coarse_setup(mesh)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    print(f"# setup (coarse E = W^T A W + block Cholesky): {setup_s:.3f} s", file=sys.stderr, flush=True)
 
     # ---- operator apply throughput (HIP events on the library's stream)
     u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
@@ -304,6 +301,12 @@ def main():
     vf = float((p.rho == 1.0).mean()) - 0.025
 
     def step():
+        # the whole hot path from device-resident inputs: density and fixity
+        # made current (this invalidates the Jacobi diagonal and the coarse
+        # factor), Jacobi + coarse E = W^T K W + block Cholesky, deflated PCG
+        # to 1e-8, compliance, sensitivity, topology
+        afdcg.afd_mesh_set_scale(mesh, rho_d, p.nelem, afdcg.AFD_MEM_DEVICE)
+        afdcg.afd_mesh_set_fixed(mesh, fix_d, p.ndof, afdcg.AFD_MEM_DEVICE)
         code, st = afdcg.afd_solve(mesh, opts, 1, F_d, U, J, S)
         afdcg.afd_threshold(ctx, S, p.nelem, vf, solid)
         return st[0]
@@ -316,7 +319,8 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(1, args.steps)
     st = stats[-1]
-    print(f"# solve: {dt * 1e3:.1f} ms/step, {st.iterations} iterations, true rel residual "
+    print(f"# step: {dt * 1e3:.1f} ms (setup {st.t_setup * 1e3:.1f}, iterations {st.t_iter * 1e3:.1f}, "
+          f"post {st.t_post * 1e3:.1f}), {st.iterations} iterations, true rel residual "
           f"{st.rel_residual_true:.2e}", file=sys.stderr, flush=True)
 
     out = {
@@ -335,17 +339,19 @@ def main():
         "config": {"workload": f"cantilever {p.dims[0]}x{p.dims[1]}x{p.dims[2]} hex8, 50% void, "
                                f"8x8x8 deflation blocks, FP64 deflated PCG to 1e-8",
                    "n_dof": p.ndof, "n_elem": p.nelem},
-        "time_to_1e-8_s": round(dt, 5),
+        "time_to_1e-8_s": round(st.t_setup + st.t_iter, 5),
         "iterations": st.iterations,
         "rel_residual_true": st.rel_residual_true,
-        "setup_s": round(setup_s, 4),
+        "setup_s": round(st.t_setup, 4),
+        "iterations_s": round(st.t_iter, 4),
+        "post_s": round(st.t_post, 4),
         "apply_us": round(t_apply * 1e6, 3),
         "apply_fp32_us": round(t_apply32 * 1e6, 3),
         "apply_fp32_gdofs": round(p.ndof / t_apply32 / 1e9, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": TRAFFIC_BYTES if args.config == 1 else None,
-                     "kernel": "k_matvec<double, APPLY>", "bytes_per_launch": alg},
+                     "kernel": "k_apply_tm<double, cubic, 1>", "bytes_per_launch": alg},
     }
     secs = [x for x in args.sections.split(",") if x]
     afdcg.afd_mesh_destroy(mesh)

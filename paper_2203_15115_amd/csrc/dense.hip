@@ -97,11 +97,100 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
         }
 }
 
+// The same product on the FP64 matrix cores: a 64 x 64 tile of C per
+// workgroup, 2 x 2 wavefronts of 32 x 32, each a 2 x 2 set of
+// v_mfma_f64_16x16x4f64 tiles; K in steps of 16 staged through LDS, the next
+// step's operands prefetched into registers while the current one is
+// multiplied.  Operand layouts of the instruction (64 lanes): A lane l holds
+// (row l % 16, k l / 16), B lane l holds (k l / 16, col l % 16), and
+// accumulator register v of lane l is (row l / 16 + 4 v, col l % 16).
+typedef double dacc4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double alpha, const double* A, int lda,
+                                                   int ta, const double* B, int ldb, int tb, double beta, double* C,
+                                                   int ldc) {
+    __shared__ double As[GK][GT + 2];
+    __shared__ double Bs[GK][GT + 2];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int wr = wv >> 1, wc = wv & 1;
+    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+    // loader: element e = t + 256 q (q < 4) of the 64 x 16 A tile and the 16 x 64 B tile
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;
+            int ii, kk;
+            if (ta) { ii = e % GT; kk = e / GT; } else { kk = e % GK; ii = e / GK; }
+            const int gi = i0 + ii, gk = k0 + kk;
+            ra[q] = (gi < M && gk < K) ? (ta ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : 0.0;
+            int jj, kb;
+            if (tb) { kb = e % GK; jj = e / GK; } else { jj = e % GT; kb = e / GT; }
+            const int gj = j0 + jj, gkb = k0 + kb;
+            rb[q] = (gj < N && gkb < K) ? (tb ? B[(int64_t)gj * ldb + gkb] : B[(int64_t)gkb * ldb + gj]) : 0.0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;
+            int ii, kk;
+            if (ta) { ii = e % GT; kk = e / GT; } else { kk = e % GK; ii = e / GK; }
+            As[kk][ii] = ra[q];
+            int jj, kb;
+            if (tb) { kb = e % GK; jj = e / GK; } else { jj = e % GT; kb = e / GT; }
+            Bs[kb][jj] = rb[q];
+        }
+    };
+    dacc4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = dacc4{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        __syncthreads();  // previous step's operands consumed
+        store();
+        __syncthreads();
+        if (k0 + GK < K) load(k0 + GK);
+#pragma unroll
+        for (int sk = 0; sk < GK / 4; ++sk) {
+            const int kk = 4 * sk + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[kk][32 * wr + 16 * a + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][32 * wc + 16 * b + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = i0 + 32 * wr + 16 * a + (lane >> 4) + 4 * v;
+                const int gj = j0 + 32 * wc + 16 * b + (lane & 15);
+                if (gi < M && gj < N) {
+                    double* c = C + (int64_t)gi * ldc + gj;
+                    *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[a][b][v];
+                }
+            }
+}
+
 int gemm(int M, int N, int K, double alpha, const double* A, int lda, int ta, const double* B, int ldb, int tb,
          double beta, double* C, int ldc, hipStream_t s) {
     if (M <= 0 || N <= 0) return AFD_OK;
     dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
+    if (K <= 0) {
+        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
+    } else {
+        hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
+    }
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -112,51 +201,68 @@ int gemm(int M, int N, int K, double alpha, const double* A, int lda, int ta, co
 // dropped pivots zeroed) to the same position of Linv.
 __global__ __launch_bounds__(256) void k_potrf_tile(double* A, double* Linv, int P, int j0, int nb,
                                                     const double* ediag, int32_t* dropped) {
-    __shared__ double L[NB][NB + 1];
-    __shared__ double X[NB][NB + 1];
+    static_assert(NB == 64, "the register layout assumes 64 x 64 tiles and 256 threads");
+    __shared__ double colc[NB];  // column c of L below the pivot
+    __shared__ double rowc[NB];  // row c of X
+    __shared__ double pinv_s;
     __shared__ int drop[NB];
     const int t = threadIdx.x;
-    for (int e = t; e < NB * NB; e += 256) {
-        const int r = e / NB, c = e % NB;
-        L[r][c] = (r < nb && c < nb && c <= r) ? A[(int64_t)(j0 + r) * P + j0 + c] : 0.0;
-        X[r][c] = 0.0;
+    const int r = t >> 2, q0 = t & 3;  // thread owns L[r][q0 + 4i] and X[r][q0 + 4i], i < 16
+    double Lr[16], Xr[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int q = q0 + 4 * i;
+        // rows beyond nb are padded with the identity (pivot 1, never dropped)
+        Lr[i] = (r < nb && q <= r) ? A[(int64_t)(j0 + r) * P + j0 + q] : (r == q ? 1.0 : 0.0);
+        Xr[i] = (r == q) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (int c = 0; c < nb; ++c) {
-        if (t == 0) {
-            const double d = L[c][c];
-            const double e0 = ediag[j0 + c];
-            const bool dr = !(e0 > 0.0) || !(d > DROP_TOL * e0);
+    const double edr = r < nb ? ediag[j0 + r] : 1.0;
+    // right-looking Cholesky, and alongside it the forward substitution
+    // L X = I: once column c of L is final, row c of X is scaled by the pivot
+    // and eliminated from the rows below
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int ic = c >> 2, qc = c & 3;
+        if (r == c && q0 == qc) {
+            const double d = Lr[ic];
+            const bool dr = !(edr > 0.0) || !(d > DROP_TOL * edr);
+            const double pv = dr ? 1.0 : sqrt(d);
+            Lr[ic] = pv;
+            pinv_s = 1.0 / pv;
             drop[c] = dr ? 1 : 0;
-            L[c][c] = dr ? 1.0 : sqrt(d);
         }
         __syncthreads();
-        const double piv = L[c][c];
+        const double pi = pinv_s;
         const int dr = drop[c];
-        for (int r = c + 1 + t; r < nb; r += 256) L[r][c] = dr ? 0.0 : L[r][c] / piv;
-        __syncthreads();
-        // trailing update of the tile
-        for (int e = t; e < nb * nb; e += 256) {
-            const int r = e / nb, q = e % nb;
-            if (r > c && q > c && q <= r) L[r][q] -= L[r][c] * L[q][c];
+        if (q0 == qc && r > c) {
+            Lr[ic] = dr ? 0.0 : Lr[ic] * pi;
+            colc[r] = Lr[ic];
+        }
+        if (r == c) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (q0 + 4 * i <= c) {
+                    Xr[i] *= pi;
+                    rowc[q0 + 4 * i] = Xr[i];
+                }
         }
         __syncthreads();
-    }
-    // tile inverse by forward substitution, one column per thread
-    for (int col = t; col < nb; col += 256) {
-        for (int r = col; r < nb; ++r) {
-            double s = (r == col) ? 1.0 : 0.0;
-            for (int q = col; q < r; ++q) s -= L[r][q] * X[q][col];
-            X[r][col] = s / L[r][r];
+        if (r > c) {
+            const double lrc = colc[r];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int q = q0 + 4 * i;
+                if (q > c && q <= r) Lr[i] -= lrc * colc[q];
+                else if (q <= c) Xr[i] -= lrc * rowc[q];
+            }
         }
     }
-    __syncthreads();
-    for (int e = t; e < nb * nb; e += 256) {
-        const int r = e / nb, c = e % nb;
-        if (c <= r) {
-            A[(int64_t)(j0 + r) * P + j0 + c] = L[r][c];
-            const double x = (drop[r] || drop[c]) ? 0.0 : X[r][c];
-            Linv[(int64_t)(j0 + r) * P + j0 + c] = x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int q = q0 + 4 * i;
+        if (r < nb && q <= r) {
+            A[(int64_t)(j0 + r) * P + j0 + q] = Lr[i];
+            Linv[(int64_t)(j0 + r) * P + j0 + q] = (drop[r] || drop[q]) ? 0.0 : Xr[i];
         }
     }
     if (t < nb) dropped[j0 + t] = drop[t];
@@ -167,21 +273,29 @@ __global__ __launch_bounds__(256) void k_panel(double* A, const double* Linv, in
     __shared__ double Ti[NB][NB + 1];
     __shared__ double Ar[64][NB + 1];
     const int t = threadIdx.x;
+    const int r = t >> 2, q0 = t & 3;  // thread owns panel row r, columns q0 + 4 i
     const int r0 = j0 + nb + blockIdx.x * 64;
-    for (int e = t; e < NB * NB; e += 256) {
-        const int r = e / NB, c = e % NB;
-        Ti[r][c] = (r < nb && c < nb) ? Linv[(int64_t)(j0 + r) * P + j0 + c] : 0.0;
-        const int gr = r0 + r;
-        Ar[r][c] = (gr < P && c < nb) ? A[(int64_t)gr * P + j0 + c] : 0.0;
+    const int gr = r0 + r;
+#pragma unroll 4
+    for (int i = 0; i < NB / 4; ++i) {
+        const int q = q0 + 4 * i;
+        Ti[r][q] = (r < nb && q < nb) ? Linv[(int64_t)(j0 + r) * P + j0 + q] : 0.0;
+        Ar[r][q] = (gr < P && q < nb) ? A[(int64_t)gr * P + j0 + q] : 0.0;
     }
     __syncthreads();
-    for (int e = t; e < 64 * nb; e += 256) {
-        const int r = e / nb, c = e % nb;
-        const int gr = r0 + r;
-        if (gr >= P) continue;
-        double s = 0.0;
-        for (int q = 0; q <= c; ++q) s += Ar[r][q] * Ti[c][q];
-        A[(int64_t)gr * P + j0 + c] = s;
+    if (gr >= P) return;
+    double acc[NB / 4];
+#pragma unroll
+    for (int i = 0; i < NB / 4; ++i) acc[i] = 0.0;
+    for (int q = 0; q < nb; ++q) {
+        const double a = Ar[r][q];
+#pragma unroll
+        for (int i = 0; i < NB / 4; ++i) acc[i] = fma(a, Ti[q0 + 4 * i][q], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NB / 4; ++i) {
+        const int c = q0 + 4 * i;
+        if (c < nb) A[(int64_t)gr * P + j0 + c] = acc[i];
     }
 }
 
@@ -420,11 +534,18 @@ int coarse_factor(Coarse& c, hipStream_t s) {
     AFD_HIP_TRY(hipMemsetAsync(c.Linv, 0, PP * K * sizeof(double), s));
     AFD_HIP_TRY(hipMemsetAsync(c.T, 0, PP * K * sizeof(double), s));
     AFD_HIP_TRY(hipMemsetAsync(c.U, 0, PP * K * sizeof(double), s));
+    // The coupling block B_k = E(k+1, k) is zero outside its first w rows and
+    // last w columns (half bandwidth w <= P), and so is C_k = B_k Linv_k^T
+    // (Linv_k lower triangular); the Schur update then touches only the
+    // leading w x w corner of D_{k+1}, T_k = Linv_k C_{k-1} only its last w
+    // columns and U_k = Linv_k^T C_k^T only its first w columns.
+    const int w = std::min(b.w, P), o = P - w;
     for (int k = 0; k < K; ++k) {
         double* Dk = blkptr(c.D, k, P);
         double* Li = blkptr(c.Linv, k, P);
-        if (k > 0) {  // D_k -= C_{k-1} C_{k-1}^T  (C stored in B[k-1])
-            AFD_TRY(gemm(P, P, P, -1.0, blkptr(c.B, k - 1, P), P, 0, blkptr(c.B, k - 1, P), P, 1, 1.0, Dk, P, s));
+        if (k > 0) {  // D_k[0:w, 0:w] -= C_{k-1} C_{k-1}^T  (C stored in B[k-1])
+            const double* Ck = blkptr(c.B, k - 1, P) + o;
+            AFD_TRY(gemm(w, w, w, -1.0, Ck, P, 0, Ck, P, 1, 1.0, Dk, P, s));
         }
         // dense blocked Cholesky of D_k, tile inverses into Linv's diagonal tiles
         for (int j0 = 0; j0 < P; j0 += NB) {
@@ -451,13 +572,17 @@ int coarse_factor(Coarse& c, hipStream_t s) {
                            c.dropped_dev + (int64_t)k * P);
         hipLaunchKernelGGL(k_transpose, dim3((P + 31) / 32, (P + 31) / 32), dim3(32, 8), 0, s, P, Li,
                            blkptr(c.LinvT, k, P));
-        if (k > 0) {  // T_k = Linv_k C_{k-1}
-            AFD_TRY(gemm(P, P, P, 1.0, Li, P, 0, blkptr(c.B, k - 1, P), P, 0, 0.0, blkptr(c.T, k, P), P, s));
+        if (k > 0) {  // T_k[:, o:P] = Linv_k[:, 0:w] C_{k-1}[0:w, o:P]
+            AFD_TRY(gemm(P, w, w, 1.0, Li, P, 0, blkptr(c.B, k - 1, P) + o, P, 0, 0.0, blkptr(c.T, k, P) + o, P, s));
         }
-        if (k < K - 1) {  // C_k = B_k Linv_k^T (in work, then back into B[k]); U_k = Linv_k^T C_k^T
-            AFD_TRY(gemm(P, P, P, 1.0, blkptr(c.B, k, P), P, 0, Li, P, 1, 0.0, c.work, P, s));
-            AFD_HIP_TRY(hipMemcpyAsync(blkptr(c.B, k, P), c.work, PP * sizeof(double), hipMemcpyDeviceToDevice, s));
-            AFD_TRY(gemm(P, P, P, 1.0, Li, P, 1, blkptr(c.B, k, P), P, 1, 0.0, blkptr(c.U, k, P), P, s));
+        if (k < K - 1) {
+            // C_k[0:w, o:P] = B_k[0:w, o:P] Linv_k[o:P, o:P]^T (in work, then back into B[k])
+            double* Bk = blkptr(c.B, k, P);
+            AFD_TRY(gemm(w, w, w, 1.0, Bk + o, P, 0, Li + (int64_t)o * P + o, P, 1, 0.0, c.work, P, s));
+            AFD_HIP_TRY(hipMemcpy2DAsync(Bk + o, P * sizeof(double), c.work, P * sizeof(double), w * sizeof(double), w,
+                                         hipMemcpyDeviceToDevice, s));
+            // U_k[:, 0:w] = Linv_k[o:P, :]^T C_k[0:w, o:P]^T
+            AFD_TRY(gemm(P, w, w, 1.0, Li + (int64_t)o * P, P, 1, Bk + o, P, 1, 0.0, blkptr(c.U, k, P), P, s));
         }
     }
     hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, c.dropped_dev, b.ncoarse, c.dropped_dev + npad);
