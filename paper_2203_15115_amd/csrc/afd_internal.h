@@ -72,9 +72,10 @@ struct Blocks {
 // that is >= the half bandwidth w is valid.  A coarse solve is a chain of
 // 2(K-1) dependent P x w matrix-vector steps (K = ceil(n/P); the coupling
 // blocks are zero outside a w-column window) plus two batched passes over the
-// K triangular inverses (K P^2 / 2 doubles each); each launch costs at least
-// a launch latency (~6 us) and otherwise streams at ~4 TB/s.  Pick the P of
-// least modelled time among w, 2w, ..., 6w (AFD_COARSE_P overrides).
+// K triangular inverses (K P^2 / 2 doubles each).  Cost model fitted to
+// measured solves on MI355X: ~6 us per dependent launch plus the streamed
+// bytes at ~4.5 TB/s.  Pick the P of least modelled time among w, 2w, ...,
+// 6w (AFD_COARSE_P overrides).
 inline int choose_coarse_P(int ncoarse, int w) {
     const int nc64 = ((ncoarse + 63) / 64) * 64;
     int forced = 0;
@@ -83,15 +84,15 @@ inline int choose_coarse_P(int ncoarse, int w) {
         int P = ((std::max(forced, w) + 63) / 64) * 64;
         return std::min(P, nc64);
     }
-    const double lat = 6e-6, bw = 4e12;
+    const double lat = 6e-6, bw = 4.5e12;
     int best = 0;
     double best_t = 1e30;
     for (int m = 1; m <= 6; ++m) {
         int P = ((m * w + 63) / 64) * 64;
         if (P > nc64) P = nc64;
         const int K = (ncoarse + P - 1) / P;
-        const double step = std::max(lat, (double)P * std::min(P, w) * 8.0 / bw);
-        const double t = 2.0 * (K - 1) * step + 2.0 * std::max(lat, (double)K * P * P * 4.0 / bw);
+        const double bytes = 2.0 * (K - 1) * P * std::min(P, w) * 8.0 + 2.0 * K * (double)P * P * 4.0;
+        const double t = (2.0 * K) * lat + bytes / bw;
         if (t < best_t - 1e-12) {
             best_t = t;
             best = P;
@@ -210,6 +211,8 @@ struct Coarse {
     double* work = nullptr;  // P x P
     int32_t* dropped_dev = nullptr;
     int32_t* perm = nullptr; // natural coarse index -> ordered index
+    int32_t* iperm = nullptr; // ordered index -> natural coarse index (-1: padding), K*P
+    std::vector<int32_t> iperm_host;  // staging of iperm (lives until the copy has run)
     double* gperm = nullptr; // [4][K*P]
     double* xperm = nullptr; // [4][K*P]
     double* cvec = nullptr;  // [4][K*P]

@@ -374,10 +374,22 @@ __global__ void k_extract_diag(int K, int P, const double* D, double* ed) {
 // workgroup, batched over blockIdx.y.  tri = 1: M lower triangular
 // (j <= i); tri = 2: upper (j >= i); tri = 0: the column window
 // [c0, c1).  Entries outside the range are stored zeros and are not read.
+// The copies at the ends of the coarse solve ride along: batch io.dual_k is
+// also written to io.y2, and with io.mu the results (of batch io.mu_k, or of
+// every batch) are also scattered to natural order.
+struct GemvIO {
+    const int32_t* iperm;  // ordered position -> natural coarse index (-1: padding)
+    int ncoarse;
+    double* y2;            // second output for batch dual_k (null: none)
+    int dual_k;
+    double* mu;            // scatter target [nrhs][ncoarse] (null: none)
+    int mu_k;              // batch to scatter (-1: every batch)
+    int qbase;             // ordered position of row 0 of batch 0
+};
 __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t mstride, const double* x,
                                               int64_t xstride, const double* c, int64_t cstride, double alpha,
                                               double* y, int64_t ystride, int nrhs, int64_t vstride, int tri, int c0,
-                                              int c1) {
+                                              int c1, GemvIO io) {
     const int kb = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -387,26 +399,29 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t ms
     double acc[4] = {0, 0, 0, 0};
     const int j0 = tri == 2 ? row : (tri == 1 ? 0 : c0);
     const int j1 = tri == 1 ? row + 1 : (tri == 2 ? P : c1);
-    // aligned pairs (P, the block offsets and the vector strides are even), four
-    // 16-byte loads per lane in flight; pair members outside [j0, j1) count zero
-    for (int jj = (j0 & ~1) + 2 * lane; jj < j1; jj += 512) {
-        double2 mv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = jj + 128 * u;
-            mv[u] = j < j1 ? *reinterpret_cast<const double2*>(m + j) : make_double2(0.0, 0.0);
-            if (j < j0) mv[u].x = 0.0;
-            if (j + 1 >= j1) mv[u].y = 0.0;
-        }
-        for (int r = 0; r < nrhs; ++r) {
-            const double* xr = x + r * vstride;
+    {
+        // aligned pairs (P, the block offsets and the vector strides are even),
+        // four 16-byte loads per lane in flight; pair members outside [j0, j1)
+        // count zero
+        for (int jj = (j0 & ~1) + 2 * lane; jj < j1; jj += 512) {
+            double2 mv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = jj + 128 * u;
-                if (j < j1) {
-                    const double2 xv = *reinterpret_cast<const double2*>(xr + j);
-                    acc[r] = fma(mv[u].x, xv.x, acc[r]);
-                    acc[r] = fma(mv[u].y, xv.y, acc[r]);
+                mv[u] = j < j1 ? *reinterpret_cast<const double2*>(m + j) : make_double2(0.0, 0.0);
+                if (j < j0) mv[u].x = 0.0;
+                if (j + 1 >= j1) mv[u].y = 0.0;
+            }
+            for (int r = 0; r < nrhs; ++r) {
+                const double* xr = x + r * vstride;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = jj + 128 * u;
+                    if (j < j1) {
+                        const double2 xv = *reinterpret_cast<const double2*>(xr + j);
+                        acc[r] = fma(mv[u].x, xv.x, acc[r]);
+                        acc[r] = fma(mv[u].y, xv.y, acc[r]);
+                    }
                 }
             }
         }
@@ -417,7 +432,13 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t ms
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) {
             const int64_t o = r * vstride + row;
-            y[kb * ystride + o] = (c ? c[kb * cstride + o] : 0.0) + alpha * v;
+            const double out = (c ? c[kb * cstride + o] : 0.0) + alpha * v;
+            y[kb * ystride + o] = out;
+            if (io.y2 && kb == io.dual_k) io.y2[kb * ystride + o] = out;
+            if (io.mu && (io.mu_k < 0 || kb == io.mu_k)) {
+                const int nat = io.iperm[io.qbase + (int64_t)kb * P + row];
+                if (nat >= 0) io.mu[(int64_t)r * io.ncoarse + nat] = out;
+            }
         }
     }
 }
@@ -428,12 +449,6 @@ __global__ void k_perm_in(int ncoarse, int npad, const int32_t* perm, int nrhs, 
     if (i < npad && i >= ncoarse) gp[(int64_t)r * npad + i] = 0.0;
     if (i >= ncoarse) return;
     gp[(int64_t)r * npad + perm[i]] = G[(int64_t)r * ncoarse + i];
-}
-__global__ void k_perm_out(int ncoarse, int npad, const int32_t* perm, const double* xp, double* MU) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    if (i >= ncoarse) return;
-    MU[(int64_t)r * ncoarse + i] = xp[(int64_t)r * npad + perm[i]];
 }
 
 __global__ void k_count(const int32_t* a, int n, int32_t* out) {
@@ -473,6 +488,7 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
     AFD_HIP_TRY(hipMalloc((void**)&c.xperm, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.cvec, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.perm, b.ncoarse * sizeof(int32_t)));
+    AFD_HIP_TRY(hipMalloc((void**)&c.iperm, npad * sizeof(int32_t)));
     // ordering: axes of fewest blocks fastest
     std::vector<int32_t> perm(b.ncoarse);
     const int a0 = b.perm[0], a1 = b.perm[1], a2 = b.perm[2];
@@ -485,6 +501,9 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
                 for (int m = 0; m < 6; ++m) perm[6 * nat + m] = 6 * ord + m;
             }
     AFD_HIP_TRY(hipMemcpyAsync(c.perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    c.iperm_host.assign(npad, -1);
+    for (int i = 0; i < b.ncoarse; ++i) c.iperm_host[perm[i]] = i;
+    AFD_HIP_TRY(hipMemcpyAsync(c.iperm, c.iperm_host.data(), npad * sizeof(int32_t), hipMemcpyHostToDevice, s));
     AFD_HIP_TRY(hipStreamSynchronize(s));
     return AFD_OK;
 }
@@ -498,6 +517,8 @@ void coarse_free(Coarse& c) {
         }
     if (c.dropped_dev) (void)hipFree(c.dropped_dev);
     if (c.perm) (void)hipFree(c.perm);
+    if (c.iperm) (void)hipFree(c.iperm);
+    c.iperm = nullptr;
     c.dropped_dev = nullptr;
     c.perm = nullptr;
     c.valid = false;
@@ -609,31 +630,39 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
     // products only stream that window
     const int w = std::min(b.w, P);
     const unsigned rb = (unsigned)((P + 3) / 4);
+    GemvIO none{c.iperm, b.ncoarse, nullptr, -1, nullptr, -1, 0};
 
-    dim3 gp((npad + 255) / 256, nrhs);
-    hipLaunchKernelGGL(k_perm_in, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, nrhs, G, c.gperm);
-    // c_k = Linv_k g_k, all k
+    // c_k = Linv_k g_k, all k (g in the banded ordering); x_0 = c_0
+    hipLaunchKernelGGL(k_perm_in, dim3((npad + 255) / 256, nrhs), dim3(256), 0, s, b.ncoarse, npad, c.perm, nrhs, G,
+                       c.gperm);
+    GemvIO in = none;
+    in.y2 = c.xperm;
+    in.dual_k = 0;
     hipLaunchKernelGGL(k_gemv, dim3(rb, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 1, 0, P);
-    // x_0 = c_0; x_k = c_k - T_k x_{k-1}
-    AFD_HIP_TRY(hipMemcpy2DAsync(c.xperm, npad * sizeof(double), c.cvec, npad * sizeof(double), P * sizeof(double),
-                                 nrhs, hipMemcpyDeviceToDevice, s));
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 1, 0, P, in);
+    // x_k = c_k - T_k x_{k-1}
     for (int k = 1; k < K; ++k)
         hipLaunchKernelGGL(k_gemv, dim3(rb, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
                            c.xperm + (int64_t)(k - 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, P - w, P);
-    // c'_k = Linv_k^T x_k, all k
+                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, P - w, P, none);
+    // c'_k = Linv_k^T x_k, all k; mu_{K-1} = c'_{K-1} (kept and scattered)
+    GemvIO last = none;
+    last.y2 = c.gperm;
+    last.dual_k = K - 1;
+    last.mu = MU;
+    last.mu_k = K - 1;
     hipLaunchKernelGGL(k_gemv, dim3(rb, K), dim3(256), 0, s, P, c.LinvT, PP, c.xperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 2, 0, P);
-    // mu_{K-1} = c'_{K-1}; mu_k = c'_k - U_k mu_{k+1}
-    AFD_HIP_TRY(hipMemcpy2DAsync(c.gperm + (int64_t)(K - 1) * P, npad * sizeof(double),
-                                 c.cvec + (int64_t)(K - 1) * P, npad * sizeof(double), P * sizeof(double), nrhs,
-                                 hipMemcpyDeviceToDevice, s));
-    for (int k = K - 2; k >= 0; --k)
+                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 2, 0, P,
+                       last);
+    // mu_k = c'_k - U_k mu_{k+1}, scattered to natural order as produced
+    for (int k = K - 2; k >= 0; --k) {
+        GemvIO sc = none;
+        sc.mu = MU;
+        sc.qbase = k * P;
         hipLaunchKernelGGL(k_gemv, dim3(rb, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
                            c.gperm + (int64_t)(k + 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, 0, w);
-    hipLaunchKernelGGL(k_perm_out, gp, dim3(256), 0, s, b.ncoarse, npad, c.perm, c.gperm, MU);
+                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, 0, w, sc);
+    }
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
