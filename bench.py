@@ -264,6 +264,14 @@ def main():
         print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps}), flush=True)
         return
 
+    # ---- apply execution picked by the autotuner on this mesh (outside the timed region)
+    tune = {}
+    for name, prec in (("fp64", afdcg.AFD_FP64), ("fp32", afdcg.AFD_FP32)):
+        r = afdcg.afd_mesh_autotune(mesh, prec, 1)
+        tune[name] = {"variant": r.variant, "zc": r.zc, "us": round(r.us, 2), "default_us": round(r.default_us, 2),
+                      "candidates": r.ncandidates}
+    print(f"# autotune: {json.dumps(tune)}", file=sys.stderr, flush=True)
+
     # ---- operator apply throughput (HIP events on the library's stream)
     u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
     y = torch.empty_like(u)
@@ -348,6 +356,7 @@ def main():
         "apply_us": round(t_apply * 1e6, 3),
         "apply_fp32_us": round(t_apply32 * 1e6, 3),
         "apply_fp32_gdofs": round(p.ndof / t_apply32 / 1e9, 3),
+        "apply_tuning": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": TRAFFIC_BYTES if args.config == 1 else None,

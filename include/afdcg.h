@@ -141,6 +141,28 @@ int afd_apply_K(afd_mesh* mesh, int32_t precision, int32_t nrhs, const void* U, 
  * FP64 matrix cores (same result as afd_apply_K, FP64 only, nrhs 1..4). */
 int afd_apply_K_mfma(afd_mesh* mesh, int32_t nrhs, const double* U, double* Y);
 
+/* Autotuner of afd_apply_K for this mesh (the operator of Sec. 3.5 is fixed;
+ * only its execution is tuned): times every candidate kernel variant x z
+ * chunking of the element-by-element apply for `precision` (AFD_FP64 or
+ * AFD_FP32) and `nrhs` on the context stream with HIP events, and keeps the
+ * fastest for later afd_apply_K calls on this mesh with that precision
+ * (every candidate evaluates the same element operator; results agree to
+ * rounding).  Synchronous; allocates and frees two scratch vectors of
+ * nrhs x n_dof.  report may be NULL. */
+typedef struct afd_tune_report {
+    int32_t variant;        /* chosen kernel: 0 register-staged, 2 / 3 LDS-DMA with 1 / 2 layers per step */
+    int32_t zc;             /* chosen node planes per z chunk                                           */
+    double us;              /* its time per launch (microseconds)                                       */
+    double default_us;      /* time of the untuned default                                              */
+    int32_t ncandidates;    /* candidates timed                                                         */
+} afd_tune_report;
+int afd_mesh_autotune(afd_mesh* mesh, int32_t precision, int32_t nrhs, afd_tune_report* report);
+/* Sets the afd_apply_K execution for `precision` by hand (what the autotuner
+ * picks): variant 0 register-staged, 2 / 3 LDS-DMA with 1 / 2 layers per
+ * step, -1 the default; zc node planes per z chunk, 0 the default.  Returns
+ * AFD_E_INVALID_ARG for other values. */
+int afd_mesh_apply_config(afd_mesh* mesh, int32_t precision, int32_t variant, int32_t zc);
+
 /* Jacobi diagonal of A (Sec. 3.5: preconditioner formed assembly-free):
  * d[3n+c] = Ke_cc * sum of rho over the elements touching node n for a free
  * DOF, 1 for a fixed DOF.  d: ndof doubles. */

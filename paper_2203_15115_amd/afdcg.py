@@ -37,7 +37,9 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVALID_ARG", -2: "E_NO_DEVICE", -
 EXPORTED = [
     "afd_context_create", "afd_context_destroy", "afd_last_error", "afd_context_sync",
     "afd_mesh_create", "afd_mesh_destroy", "afd_mesh_sizes", "afd_mesh_set_scale", "afd_mesh_set_fixed",
-    "afd_mesh_footprint", "afd_mesh_ke", "afd_apply_K", "afd_apply_K_mfma", "afd_jacobi", "afd_dot",
+    "afd_mesh_footprint", "afd_mesh_ke", "afd_apply_K", "afd_apply_K_mfma", "afd_mesh_autotune", "afd_mesh_apply_config",
+    "afd_jacobi",
+    "afd_dot",
     "afd_restrict", "afd_prolong", "afd_coarse_setup", "afd_coarse_matrix", "afd_coarse_solve",
     "afd_sensitivity", "afd_threshold", "afd_solve", "afd_server_create", "afd_server_submit",
     "afd_server_poll", "afd_server_wait", "afd_server_clock", "afd_server_destroy",
@@ -61,6 +63,11 @@ class afd_solve_stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("refinements", C.c_int32), ("status", C.c_int32),
                 ("coarse_dropped", C.c_int32), ("rel_residual_true", C.c_double),
                 ("t_setup", C.c_double), ("t_iter", C.c_double), ("t_post", C.c_double)]
+
+
+class afd_tune_report(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("zc", C.c_int32), ("us", C.c_double), ("default_us", C.c_double),
+                ("ncandidates", C.c_int32)]
 
 
 class afd_request(C.Structure):
@@ -98,6 +105,8 @@ def lib():
             "afd_mesh_ke": (C.c_int, [vp, vp]),
             "afd_apply_K": (C.c_int, [vp, i32, i32, vp, vp]),
             "afd_apply_K_mfma": (C.c_int, [vp, i32, vp, vp]),
+            "afd_mesh_autotune": (C.c_int, [vp, i32, i32, C.POINTER(afd_tune_report)]),
+            "afd_mesh_apply_config": (C.c_int, [vp, i32, i32, i32]),
             "afd_jacobi": (C.c_int, [vp, vp]),
             "afd_dot": (C.c_int, [vp, i64, vp, vp, vp]),
             "afd_restrict": (C.c_int, [vp, i32, vp, vp]),
@@ -207,6 +216,17 @@ def afd_apply_K(mesh, precision, nrhs, U, Y):
 
 def afd_apply_K_mfma(mesh, nrhs, U, Y):
     check(lib().afd_apply_K_mfma(mesh, nrhs, _ptr(U), _ptr(Y)), "afd_apply_K_mfma")
+
+
+def afd_mesh_autotune(mesh, precision, nrhs):
+    """Times the apply candidates on this mesh and keeps the fastest; returns the report."""
+    rep = afd_tune_report()
+    check(lib().afd_mesh_autotune(mesh, precision, nrhs, C.byref(rep)), "afd_mesh_autotune")
+    return rep
+
+
+def afd_mesh_apply_config(mesh, precision, variant, zc=0):
+    check(lib().afd_mesh_apply_config(mesh, precision, variant, zc), "afd_mesh_apply_config")
 
 
 def afd_jacobi(mesh, d):

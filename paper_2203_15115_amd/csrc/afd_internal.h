@@ -122,6 +122,8 @@ struct MatvecArgs {
     const double* rho_t;     // tile-major densities (plain apply), see launch_tile_rho
     const float* rho32_t;
     const uint16_t* fm_t;    // tile-major face fixity words, see launch_tile_fmask
+    int apply_variant[2] = {-1, -1};  // plain-apply kernel per precision (FP64, FP32), -1 default
+    int apply_zc[2] = {0, 0};         // plain-apply z chunk per precision, 0 default
 };
 struct DcgArgs {
     const double* rinv;      // nnode: 1 / sum of rho over the node's elements
@@ -136,6 +138,8 @@ int matvec_num_tiles(const Grid& g);
 // element counts of the tile-major side arrays of the plain apply: returns the
 // fixity-word count, *nrho the density count
 int64_t tile_layout_sizes(const Grid& g, int64_t* nrho);
+// default z chunk of a plain-apply kernel variant (zc_req > 0 forces it)
+void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int* zc, int* nchunk);
 int launch_tile_rho(const Grid& g, const double* rho, double* rho_t, float* rho32_t, hipStream_t s);
 int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipStream_t s);
 int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,

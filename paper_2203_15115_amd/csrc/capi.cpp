@@ -79,6 +79,8 @@ struct afd_mesh {
     double* ke_dev = nullptr;    // dense Ke (576) for the matrix-core path
     bool jacobi_valid = false;
     bool any_fixed = false;
+    int tune_variant[2] = {-1, -1};  // autotuned plain-apply kernel per precision (FP64, FP32)
+    int tune_zc[2] = {0, 0};
     Coarse coarse;
     Work w;
     int npartM = 0;
@@ -167,6 +169,10 @@ MatvecArgs mv_args(afd_mesh* m) {
     a.rho_t = m->rho_t;
     a.rho32_t = m->rho32_t;
     a.fm_t = m->fm_t;
+    for (int f = 0; f < 2; ++f) {
+        a.apply_variant[f] = m->tune_variant[f];
+        a.apply_zc[f] = m->tune_zc[f];
+    }
     return a;
 }
 
@@ -562,6 +568,103 @@ int afd_mesh_ke(const afd_mesh* m, double* ke) {
     }
     const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
     make_ke_dense(h, m->desc.E, m->desc.nu, ke);
+    return AFD_OK;
+}
+
+int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_report* rep) {
+    if (!m || nrhs < 1 || nrhs > 4 || (precision != AFD_FP64 && precision != AFD_FP32)) {
+        set_error("autotune: bad argument (nrhs 1..4, precision FP64 or FP32)");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    hipStream_t s = m->ctx->stream;
+    const int f = precision == AFD_FP32 ? 1 : 0;
+    const size_t word = f ? 4 : 8, n = (size_t)nrhs * m->g.ndof;
+    void *U = nullptr, *Y = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(&U, n * word) != hipSuccess || hipMalloc(&Y, n * word) != hipSuccess) {
+        if (U) (void)hipFree(U);
+        set_error("autotune: scratch allocation failed");
+        return AFD_E_OOM;
+    }
+    int rc = AFD_OK;
+    if (f) rc = launch_fill_f32((int64_t)n, 1.0f, (float*)U, s);
+    else rc = launch_fill_f64((int64_t)n, 1.0, (double*)U, s);
+    if (rc == AFD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+        set_error("autotune: event creation failed");
+        rc = AFD_E_HIP;
+    }
+    // candidates: each kernel variant at its one-round chunking, and at half
+    // and twice as many chunks
+    struct Cand {
+        int v, zc;
+    };
+    std::vector<Cand> cands;
+    for (int v : {2, 3, 0}) {
+        int zc = 0, nch = 0;
+        apply_tiling(m->g, f, v, 0, &zc, &nch);
+        for (int mult : {2, 1, 4}) {  // chunks x mult / 2
+            const int want = std::max(1, nch * mult / 2);
+            const int planes = m->g.nz + 1;
+            const int z = std::max(1, (planes + want - 1) / want);
+            bool dup = false;
+            for (const Cand& c : cands) dup = dup || (c.v == v && c.zc == z);
+            if (!dup) cands.push_back({v, z});
+        }
+    }
+    auto time_of = [&](int v, int zc, double* us) -> int {
+        MatvecArgs a = mv_args(m);
+        a.apply_variant[f] = v;
+        a.apply_zc[f] = zc;
+        for (int i = 0; i < 3; ++i) AFD_TRY(launch_apply(a, m->kh, f, nrhs, U, Y, s));
+        const int reps = 10;
+        AFD_HIP_TRY(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i) AFD_TRY(launch_apply(a, m->kh, f, nrhs, U, Y, s));
+        AFD_HIP_TRY(hipEventRecord(e1, s));
+        AFD_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        AFD_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *us = 1e3 * ms / reps;
+        return AFD_OK;
+    };
+    double best_us = 1e30, def_us = 0.0;
+    int best_v = -1, best_zc = 0;
+    if (rc == AFD_OK) rc = time_of(-1, 0, &def_us);
+    for (size_t i = 0; rc == AFD_OK && i < cands.size(); ++i) {
+        double us = 0.0;
+        rc = time_of(cands[i].v, cands[i].zc, &us);
+        if (rc == AFD_OK && us < best_us) {
+            best_us = us;
+            best_v = cands[i].v;
+            best_zc = cands[i].zc;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(U);
+    (void)hipFree(Y);
+    if (rc != AFD_OK) return rc;
+    m->tune_variant[f] = best_v;
+    m->tune_zc[f] = best_zc;
+    if (rep) {
+        rep->variant = best_v;
+        rep->zc = best_zc;
+        rep->us = best_us;
+        rep->default_us = def_us;
+        rep->ncandidates = (int32_t)cands.size();
+    }
+    return AFD_OK;
+}
+
+int afd_mesh_apply_config(afd_mesh* m, int32_t precision, int32_t variant, int32_t zc) {
+    if (!m || (precision != AFD_FP64 && precision != AFD_FP32) ||
+        !(variant == -1 || variant == 0 || variant == 2 || variant == 3) || zc < 0) {
+        set_error("apply_config: bad argument (variant -1, 0, 2 or 3; zc >= 0)");
+        return AFD_E_INVALID_ARG;
+    }
+    const int f = precision == AFD_FP32 ? 1 : 0;
+    m->tune_variant[f] = variant;
+    m->tune_zc[f] = zc;
     return AFD_OK;
 }
 

@@ -93,6 +93,7 @@ struct MvParams {
     T* Y;           // APPLY: output; RESID: R; DIR: Q
     const T* F;     // RESID: F; DIR: R (residual)
     T* Pn;          // DIR: new direction (owned nodes written)
+    int variant;             // plain-apply kernel variant
     const T* rho_t;          // tile-major densities (plain apply)
     const uint16_t* fm_t;    // tile-major face fixity words (plain apply)
     const double* rinv;  // per node 1/sum rho (double)
@@ -1093,31 +1094,34 @@ int apply_occupancy(int variant) {
     return (e == hipSuccess && n > 0) ? n : 0;
 }
 
-int g_slots[2] = {-1, -1};  // resident 256-thread workgroups of the plain apply (FP64, FP32) on this device
+int g_slots[5][2];  // resident 256-thread workgroups per (apply variant, FP32) on this device, 0 = unknown
 
-// z-chunking: as many chunks as fit in one round of resident workgroups, so
-// that no partly filled second round trails the launch; at least 4 node
-// planes per chunk.  The FP32 kernels fit more workgroups per CU.
-void tiling(const Grid& g, int fp32, int& tx, int& ty, int& zc, int& nchunk) {
+// z-chunking: as many chunks as fit in one round of resident workgroups of
+// the given kernel variant, so that no partly filled second round trails the
+// launch; at least 4 node planes per chunk.  zc_req > 0 forces the chunk.
+void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, int& zc, int& nchunk) {
     tx = (g.nx + 1 + (TX - 2)) / (TX - 1);  // ceil((nx+1)/15)
     ty = (g.ny + 1 + (TY - 2)) / (TY - 1);
     if (g_zc_override < 0) {
         const char* e = getenv("AFD_MATVEC_ZC");
         g_zc_override = e ? atoi(e) : 0;
     }
-    if (g_slots[fp32] < 0) {
+    if (variant < 0 || variant > 4) variant = apply_variant();
+    if (g_slots[variant][fp32] <= 0) {
         int dev = 0, cus = 256, per = fp32 ? 4 : 2;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const int n = fp32 ? apply_occupancy<float>(apply_variant()) : apply_occupancy<double>(apply_variant());
+        const int n = fp32 ? apply_occupancy<float>(variant) : apply_occupancy<double>(variant);
         if (n > 0) per = n;
-        g_slots[fp32] = cus * per;
+        g_slots[variant][fp32] = cus * per;
     }
     const int planes = g.nz + 1;
-    if (g_zc_override > 0) {
+    if (zc_req > 0) {
+        zc = zc_req;
+    } else if (g_zc_override > 0) {
         zc = g_zc_override;
     } else {
-        int want = g_slots[fp32] / (tx * ty);
+        int want = g_slots[variant][fp32] / (tx * ty);
         if (want < 1) want = 1;
         const int maxc = (planes + 3) / 4;
         if (want > maxc) want = maxc;
@@ -1128,13 +1132,18 @@ void tiling(const Grid& g, int fp32, int& tx, int& ty, int& zc, int& nchunk) {
     nchunk = (planes + zc - 1) / zc;
 }
 
+// plain = the plain apply (its kernel variant and chunking may be tuned per
+// mesh); the fused solver modes keep the default tiling, which also sizes the
+// partial-sum buffers
 template <typename T>
-MvParams<T> base_params(const MatvecArgs& a) {
+MvParams<T> base_params(const MatvecArgs& a, bool plain = false) {
     MvParams<T> p{};
     p.nx = a.g.nx;
     p.ny = a.g.ny;
     p.nz = a.g.nz;
-    tiling(a.g, sizeof(T) == 4 ? 1 : 0, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
+    const int f = sizeof(T) == 4 ? 1 : 0;
+    p.variant = plain ? (a.apply_variant[f] >= 0 ? a.apply_variant[f] : apply_variant()) : 0;
+    tiling(a.g, f, plain ? p.variant : -1, plain ? a.apply_zc[f] : 0, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
     p.ndof = (int)a.g.ndof;
     if constexpr (sizeof(T) == 8) {
         p.rho = a.rho;
@@ -1157,7 +1166,7 @@ int launch(const MvParams<T>& p, const KeHaar& khd, int nrhs, hipStream_t s) {
     dim3 grid(p.tiles_x * p.tiles_y * p.nchunk, nrhs);
     const KH<T> kh = to_kh<T>(khd);
     const bool cub = is_cubic(khd);
-    const int v = MODE == APPLY ? apply_variant() : 0;
+    const int v = MODE == APPLY ? p.variant : 0;
     if (v >= 1) {
         switch (v) {
             case 1:
@@ -1192,10 +1201,15 @@ int matvec_num_tiles(const Grid& g) {
     // partial-sum slots: the larger of the FP64 and FP32 grids
     int tx, ty, zc, nc, best = 0;
     for (int f = 0; f < 2; ++f) {
-        tiling(g, f, tx, ty, zc, nc);
+        tiling(g, f, -1, 0, tx, ty, zc, nc);
         best = std::max(best, tx * ty * nc);
     }
     return best;
+}
+
+void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int* zc, int* nchunk) {
+    int tx, ty;
+    tiling(g, fp32, variant, zc_req, tx, ty, *zc, *nchunk);
 }
 
 int64_t tile_layout_sizes(const Grid& g, int64_t* nrho) {
@@ -1222,12 +1236,12 @@ int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipSt
 int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,
                  hipStream_t s) {
     if (fp32) {
-        MvParams<float> p = base_params<float>(a);
+        MvParams<float> p = base_params<float>(a, true);
         p.U = (const float*)U;
         p.Y = (float*)Y;
         return launch<float, APPLY>(p, kh, nrhs, s);
     }
-    MvParams<double> p = base_params<double>(a);
+    MvParams<double> p = base_params<double>(a, true);
     p.U = (const double*)U;
     p.Y = (double*)Y;
     return launch<double, APPLY>(p, kh, nrhs, s);

@@ -121,6 +121,55 @@ def test_apply_fp32_matches_oracle(ctx, dims):
         assert np.all(np.abs(Y[r] - want) <= bound)
 
 
+@pytest.mark.parametrize("variant,zc", [(0, 0), (0, 3), (2, 0), (2, 1), (2, 5), (3, 0), (3, 2), (3, 7)])
+@pytest.mark.parametrize("prec", [afdcg.AFD_FP64, afdcg.AFD_FP32])
+def test_apply_every_tuning_candidate_matches_oracle(ctx, variant, zc, prec):
+    # every kernel variant / z chunk the autotuner may pick, on a ragged mesh
+    # with several tiles, chunks and a partial last step
+    dims = (33, 20, 19)
+    rho, fixed = rand_problem(dims, 11)
+    m = make_mesh(ctx, dims, rho, fixed)
+    afdcg.afd_mesh_apply_config(m, prec, variant, zc)
+    Ke = fem.ke_gauss()
+    K = fem.assemble(dims, rho, Ke)
+    Kabs = fem.assemble(dims, rho, np.abs(Ke))
+    nd = 3 * wl.n_nodes(dims)
+    f32 = prec == afdcg.AFD_FP32
+    U = np.random.default_rng(9).standard_normal((2, nd))
+    if f32:
+        U = U.astype(np.float32).astype(np.float64)
+    Ud = dev(U, torch.float32 if f32 else torch.float64)
+    Yd = torch.empty_like(Ud)
+    afdcg.afd_apply_K(m, prec, 2, Ud, Yd)
+    Y = host(Yd).astype(np.float64)
+    afdcg.afd_mesh_destroy(m)
+    eps = EPS32 if f32 else EPS64
+    for r in range(2):
+        want = fem.apply_constrained(K, fixed, U[r])
+        bound = 64 * eps * (fem.apply_constrained(Kabs, fixed, np.abs(U[r])) + np.abs(U[r]))
+        assert np.all(np.abs(Y[r] - want) <= bound), np.max(np.abs(Y[r] - want) / bound)
+
+
+def test_autotune_keeps_results(ctx):
+    dims = (47, 31, 12)
+    rho, fixed = rand_problem(dims, 12)
+    m = make_mesh(ctx, dims, rho, fixed)
+    nd = 3 * wl.n_nodes(dims)
+    U = np.random.default_rng(10).standard_normal((1, nd))
+    Ud = dev(U)
+    Y0, Y1 = torch.empty_like(Ud), torch.empty_like(Ud)
+    afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, Ud, Y0)
+    rep = afdcg.afd_mesh_autotune(m, afdcg.AFD_FP64, 1)
+    assert rep.ncandidates >= 3 and rep.variant in (0, 2, 3) and rep.zc >= 1
+    assert 0 < rep.us <= rep.default_us * 1.5
+    afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, Ud, Y1)
+    a, b = host(Y0), host(Y1)
+    with pytest.raises(afdcg.AfdError):
+        afdcg.afd_mesh_apply_config(m, afdcg.AFD_FP64, 1, 0)  # variant 1 is not selectable
+    afdcg.afd_mesh_destroy(m)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
 def test_apply_full_size_sampled(ctx):
     # the 192x96x96 workload in the launch configuration the benchmark times,
     # checked on sampled nodes (incl. tile seams and the far faces)
