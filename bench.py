@@ -34,6 +34,11 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_BYTES = 74_585_907 + 43_811_021
 
 
+# plain-apply kernel of each autotuner variant
+KERNEL_NAMES = {0: "k_matvec<double, APPLY, cubic>", 2: "k_apply_tm<double, cubic, 1>",
+                3: "k_apply_tm<double, cubic, 2>"}
+
+
 def matvec_algorithmic_bytes(dims, word=8):
     """Bytes the apply must move: read u and write y (3 words per node each),
     one fixity byte per node, one density word per element."""
@@ -359,8 +364,9 @@ def main():
         "apply_tuning": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC_BYTES if args.config == 1 else None,
-                     "kernel": "k_apply_tm<double, cubic, 1>", "bytes_per_launch": alg},
+                     # counters were taken on the one-layer-per-step tile-major kernel
+                     "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] == 2 else None,
+                     "kernel": KERNEL_NAMES[tune["fp64"]["variant"]], "bytes_per_launch": alg},
     }
     secs = [x for x in args.sections.split(",") if x]
     afdcg.afd_mesh_destroy(mesh)
