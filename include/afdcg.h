@@ -104,6 +104,10 @@ void afd_context_destroy(afd_context* ctx);
 const char* afd_last_error(void);
 /* Blocks until the context's stream is idle. */
 int afd_context_sync(afd_context* ctx);
+/* Solver iterations between host convergence checks (check_every, when even)
+ * are recorded once per mesh as a HIP graph and replayed (default on); 0
+ * launches them one by one instead.  Results are identical either way. */
+int afd_context_use_graphs(afd_context* ctx, int32_t enable);
 
 /* ---- mesh -------------------------------------------------------------- */
 /* Creates the device-resident state of a voxel mesh (no stiffness matrix is

@@ -40,6 +40,7 @@ struct afd_context {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool graphs = true;         // replay recorded solver iteration chunks
     double* scratch = nullptr;  // dot partials
 };
 
@@ -58,6 +59,17 @@ struct Work {
     CgScalars* outer = nullptr;          // [4] refinement
     double *partM = nullptr, *partV = nullptr;
     double* Jdev = nullptr;
+};
+
+// one recorded chunk of solver iterations and what was baked into it
+struct IterGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> key;
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key.clear();
+    }
 };
 
 struct afd_mesh {
@@ -79,6 +91,7 @@ struct afd_mesh {
     double* ke_dev = nullptr;    // dense Ke (576) for the matrix-core path
     bool jacobi_valid = false;
     bool any_fixed = false;
+    IterGraph graphs[2];             // recorded iteration chunks (FP64 solve, FP32 inner solve)
     int tune_variant[2] = {-1, -1};  // autotuned plain-apply kernel per precision (FP64, FP32)
     int tune_zc[2] = {0, 0};
     Coarse coarse;
@@ -315,26 +328,69 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     std::swap(P0, P1);
     std::vector<CgScalars> hsc(nrhs);
     const int ce = std::max(1, check_every);
-    for (int it = 0; it < max_iter; ++it) {
-        AFD_TRY(launch_scalar_alpha(sc, nrhs, w.partM, m->npartM, s));
-        if constexpr (sizeof(T) == 8)
-            AFD_TRY(launch_cg_update(m->g, m->kh, m->rinv, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr, w.partV,
-                                     VEC_NPART, s));
-        else
-            AFD_TRY(launch_cg_update_f32(m->g, m->kh, m->rinv32, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr,
+    auto iterate = [&](int n) -> int {
+        for (int j = 0; j < n; ++j) {
+            AFD_TRY(launch_scalar_alpha(sc, nrhs, w.partM, m->npartM, s));
+            if constexpr (sizeof(T) == 8)
+                AFD_TRY(launch_cg_update(m->g, m->kh, m->rinv, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr,
                                          w.partV, VEC_NPART, s));
-        AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
-        AFD_TRY(coarse_of_z());
-        if constexpr (sizeof(T) == 8) AFD_TRY(launch_dir_apply(a, m->kh, dm, nrhs, P0, P1, R, Q, s));
-        else AFD_TRY(launch_dir_apply_f32(a, m->kh, dm, m->rinv32, nrhs, P0, P1, R, Q, s));
-        std::swap(P0, P1);
-        if ((it + 1) % ce == 0 || it + 1 == max_iter) {
-            AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-            AFD_HIP_TRY(hipStreamSynchronize(s));
-            bool all = true;
-            for (int r = 0; r < nrhs; ++r) all = all && hsc[r].done != 0;
-            if (all) break;
+            else
+                AFD_TRY(launch_cg_update_f32(m->g, m->kh, m->rinv32, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr,
+                                             w.partV, VEC_NPART, s));
+            AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
+            AFD_TRY(coarse_of_z());
+            if constexpr (sizeof(T) == 8) AFD_TRY(launch_dir_apply(a, m->kh, dm, nrhs, P0, P1, R, Q, s));
+            else AFD_TRY(launch_dir_apply_f32(a, m->kh, dm, m->rinv32, nrhs, P0, P1, R, Q, s));
+            std::swap(P0, P1);
         }
+        return AFD_OK;
+    };
+    // The ce iterations between host convergence checks only launch kernels
+    // (iterations past convergence are no-ops on X and R, each kernel checks
+    // the per-RHS done flag), so they are recorded once as a HIP graph and
+    // replayed; an even ce leaves the direction buffers where they started.
+    // The graph is kept on the mesh and re-recorded when any buffer, size or
+    // launch configuration baked into it changes.
+    const bool graphs = m->ctx->graphs && ce >= 2 && ce % 2 == 0;
+    IterGraph& gr = m->graphs[sizeof(T) == 4 ? 1 : 0];
+    if (graphs) {
+        const Coarse& c = m->coarse;
+        const std::vector<uintptr_t> key = {
+            (uintptr_t)nrhs, (uintptr_t)ce, (uintptr_t)m->deflate, (uintptr_t)X, (uintptr_t)R, (uintptr_t)P0,
+            (uintptr_t)P1, (uintptr_t)Q, (uintptr_t)Z, (uintptr_t)AZ, (uintptr_t)sc, (uintptr_t)w.G,
+            (uintptr_t)w.MU, (uintptr_t)w.partM, (uintptr_t)w.partV, (uintptr_t)m->npartM, (uintptr_t)c.Linv,
+            (uintptr_t)c.LinvT, (uintptr_t)c.T, (uintptr_t)c.U, (uintptr_t)c.perm, (uintptr_t)c.iperm,
+            (uintptr_t)c.gperm, (uintptr_t)c.xperm, (uintptr_t)c.cvec, (uintptr_t)c.blk.P, (uintptr_t)c.blk.K,
+            (uintptr_t)(m->tune_variant[0] + 8), (uintptr_t)(m->tune_variant[1] + 8), (uintptr_t)m->tune_zc[0],
+            (uintptr_t)m->tune_zc[1]};
+        if (!gr.exec || gr.key != key) {
+            gr.release();
+            AFD_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            T *p0 = P0, *p1 = P1;
+            const int rc = iterate(ce);
+            P0 = p0, P1 = p1;
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(s, &graph);
+            if (rc != AFD_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            AFD_HIP_TRY(ec);
+            const hipError_t ei = hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            AFD_HIP_TRY(ei);
+            gr.key = key;
+        }
+    }
+    for (int it = 0; it < max_iter; it += ce) {
+        const int n = std::min(ce, max_iter - it);
+        if (graphs && n == ce) AFD_HIP_TRY(hipGraphLaunch(gr.exec, s));
+        else AFD_TRY(iterate(n));
+        AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        AFD_HIP_TRY(hipStreamSynchronize(s));
+        bool all = true;
+        for (int r = 0; r < nrhs; ++r) all = all && hsc[r].done != 0;
+        if (all) break;
     }
     (void)f32;
     return AFD_OK;
@@ -397,6 +453,15 @@ void afd_context_destroy(afd_context* c) {
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
+}
+
+int afd_context_use_graphs(afd_context* c, int32_t enable) {
+    if (!c) {
+        set_error("null context");
+        return AFD_E_INVALID_ARG;
+    }
+    c->graphs = enable != 0;
+    return AFD_OK;
 }
 
 int afd_context_sync(afd_context* c) {
@@ -467,6 +532,8 @@ void afd_mesh_destroy(afd_mesh* m) {
     if (!m) return;
     (void)hipSetDevice(m->ctx->device);
     (void)hipStreamSynchronize(m->ctx->stream);
+    m->graphs[0].release();
+    m->graphs[1].release();
     free_work(m->w);
     coarse_free(m->coarse);
     dfree(&m->rho), dfree(&m->rho32), dfree(&m->nmask), dfree(&m->dofmask), dfree(&m->rinv), dfree(&m->rinv32),

@@ -349,6 +349,33 @@ def test_solve_mixed_config0(ctx, c0_direct):
     assert st[0].refinements >= 1
 
 
+@pytest.mark.parametrize("precision", [afdcg.AFD_FP64, afdcg.AFD_MIXED])
+def test_graph_replays_match_eager_solve(ctx, precision):
+    # the recorded iteration chunks, replayed across several solves on one
+    # mesh with eager library and torch work in between, give the eager result
+    p = wl.config(2, small=True)
+    m = make_mesh(ctx, p.dims, p.rho, p.fixed, block=p.block)
+    opts = afdcg.make_opts(rtol=1e-10, max_iter=20000, precision=precision, check_every=8)
+    F = np.ascontiguousarray(p.F)
+    nr = F.shape[0]
+    outs = []
+    for graphs in (False, True, True, True):
+        afdcg.afd_context_use_graphs(ctx, graphs)
+        U = np.zeros((nr, p.ndof))
+        _, st = afdcg.afd_solve(m, opts, nr, F, U)
+        outs.append((U, [s.iterations for s in st], [s.refinements for s in st]))
+        u = torch.ones(p.ndof, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(u)
+        afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, u, y)
+        assert float((y * 0.0 + 1.0).sum()) == p.ndof
+    afdcg.afd_context_use_graphs(ctx, True)
+    afdcg.afd_mesh_destroy(m)
+    U0, it0, rf0 = outs[0]
+    for U, it, rf in outs[1:]:
+        assert it == it0 and rf == rf0
+        assert np.array_equal(U, U0)
+
+
 def test_solve_undeflated_equals_deflated(ctx, c0_direct):
     p, K, ud = c0_direct
     p2 = wl.Problem(p.dims, p.rho, p.fixed, p.F, (0, 0, 0))
