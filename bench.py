@@ -36,7 +36,7 @@ TRAFFIC_BYTES = 74_585_907 + 43_811_021
 
 # plain-apply kernel of each autotuner variant
 KERNEL_NAMES = {0: "k_matvec<double, APPLY, cubic>", 2: "k_apply_tm<double, cubic, 1>",
-                3: "k_apply_tm<double, cubic, 2>"}
+                3: "k_apply_tm<double, cubic, 2>", -1: "k_apply_tm<double, cubic, 1>"}
 
 
 def matvec_algorithmic_bytes(dims, word=8):
@@ -365,7 +365,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      # counters were taken on the one-layer-per-step tile-major kernel
-                     "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] == 2 else None,
+                     "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] in (-1, 2) else None,
                      "kernel": KERNEL_NAMES[tune["fp64"]["variant"]], "bytes_per_launch": alg},
     }
     secs = [x for x in args.sections.split(",") if x]

@@ -149,12 +149,14 @@ int afd_apply_K_mfma(afd_mesh* mesh, int32_t nrhs, const double* U, double* Y);
  * only its execution is tuned): times every candidate kernel variant x z
  * chunking of the element-by-element apply for `precision` (AFD_FP64 or
  * AFD_FP32) and `nrhs` on the context stream with HIP events, and keeps the
- * fastest for later afd_apply_K calls on this mesh with that precision
+ * fastest (if it beats the default by 3% or more) for later afd_apply_K calls
+ * on this mesh with that precision
  * (every candidate evaluates the same element operator; results agree to
  * rounding).  Synchronous; allocates and frees two scratch vectors of
  * nrhs x n_dof.  report may be NULL. */
 typedef struct afd_tune_report {
-    int32_t variant;        /* chosen kernel: 0 register-staged, 2 / 3 LDS-DMA with 1 / 2 layers per step */
+    int32_t variant;        /* chosen kernel: 0 register-staged, 2 / 3 LDS-DMA with 1 / 2 layers per step,
+                               -1 the default (kept unless a candidate is >= 3% faster)           */
     int32_t zc;             /* chosen node planes per z chunk                                           */
     double us;              /* its time per launch (microseconds)                                       */
     double default_us;      /* time of the untuned default                                              */

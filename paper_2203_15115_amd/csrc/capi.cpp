@@ -711,6 +711,13 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
     (void)hipFree(U);
     (void)hipFree(Y);
     if (rc != AFD_OK) return rc;
+    // keep the default unless a candidate is clearly faster (timing noise is
+    // a few percent between runs)
+    if (!(best_us < 0.97 * def_us)) {
+        best_v = -1;
+        best_zc = 0;
+        best_us = def_us;
+    }
     m->tune_variant[f] = best_v;
     m->tune_zc[f] = best_zc;
     if (rep) {

@@ -160,7 +160,7 @@ def test_autotune_keeps_results(ctx):
     Y0, Y1 = torch.empty_like(Ud), torch.empty_like(Ud)
     afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, Ud, Y0)
     rep = afdcg.afd_mesh_autotune(m, afdcg.AFD_FP64, 1)
-    assert rep.ncandidates >= 3 and rep.variant in (0, 2, 3) and rep.zc >= 1
+    assert rep.ncandidates >= 3 and rep.variant in (-1, 0, 2, 3) and rep.zc >= 0
     assert 0 < rep.us <= rep.default_us * 1.5
     afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, Ud, Y1)
     a, b = host(Y0), host(Y1)
