@@ -106,7 +106,11 @@ const char* afd_last_error(void);
 int afd_context_sync(afd_context* ctx);
 /* Solver iterations between host convergence checks (check_every, when even)
  * are recorded once per mesh as a HIP graph and replayed (default on); 0
- * launches them one by one instead.  Results are identical either way. */
+ * launches them one by one instead.  Results are identical either way.
+ * Recording is a stream capture: no other thread may make device-synchronising
+ * HIP calls (hipMalloc, hipFree, synchronous copies) on the device meanwhile,
+ * so turn it off for contexts that solve while other threads allocate (the
+ * server's slot contexts have it off). */
 int afd_context_use_graphs(afd_context* ctx, int32_t enable);
 
 /* ---- mesh -------------------------------------------------------------- */

@@ -282,6 +282,100 @@ def test_coarse_matrix_and_solve(ctx, dims, block):
         assert np.linalg.norm(mu[r] - want) <= 1e-9 * np.linalg.norm(want)
 
 
+@pytest.fixture
+def coarse_P(monkeypatch):
+    # the super-block size is read at mesh creation; forcing a small one gives
+    # several super-blocks (the chain and the windowed products) on small meshes
+    def set_p(p):
+        monkeypatch.setenv("AFD_COARSE_P", str(p))
+    return set_p
+
+
+@pytest.mark.parametrize("P", [64, 320])  # 64 -> max(64, w) = 192: K = 4; 320: K = 3 with a ragged last block
+def test_coarse_several_superblocks_match_oracle(ctx, coarse_P, P):
+    dims, block = (16, 8, 8), (2, 2, 2)
+    coarse_P(P)
+    rho, _ = rand_problem(dims, 13)
+    fixed = wl.clamp_x0(dims)
+    m = make_mesh(ctx, dims, rho, fixed, block=block)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    Eo, _ = solvers.coarse_matrix(K, fixed, dims, block)
+    nc = Eo.shape[0]
+    assert nc == 768
+    E = np.zeros((nc, nc))
+    afdcg.afd_coarse_matrix(m, E)
+    assert np.max(np.abs(E - Eo)) <= 1e-12 * np.max(np.abs(Eo))
+    assert afdcg.afd_coarse_setup(m) == 0
+    g = np.random.default_rng(4).standard_normal((3, nc))
+    MU = torch.empty((3, nc), dtype=torch.float64, device="cuda")
+    afdcg.afd_coarse_solve(m, 3, dev(g), MU)
+    mu = host(MU)
+    afdcg.afd_mesh_destroy(m)
+    for r in range(3):
+        want = np.linalg.solve(Eo, g[r])
+        assert np.linalg.norm(mu[r] - want) <= 1e-9 * np.linalg.norm(want)
+
+
+def test_solve_several_superblocks_matches_direct(ctx, c0_direct, coarse_P):
+    # 24x12x12 with 2x2x2 blocks: 2592 coarse unknowns in 9 super-blocks
+    p, K, ud = c0_direct
+    coarse_P(320)
+    p2 = wl.Problem(p.dims, p.rho, p.fixed, p.F, (2, 2, 2))
+    U, J, S, st = solve_case(ctx, p2, afdcg.AFD_FP64, 1e-12)
+    assert np.linalg.norm(U[0] - ud) / np.linalg.norm(ud) <= 1e-8
+    U, J, S, st = solve_case(ctx, p2, afdcg.AFD_MIXED, 1e-11)
+    assert np.linalg.norm(U[0] - ud) / np.linalg.norm(ud) <= 1e-6
+
+
+def test_box_voxels_apply_and_solve(ctx):
+    # non-cubic voxels take the general Haar coefficients (51 values)
+    dims, h, E, nu = (19, 9, 8), (1.0, 2.0, 0.5), 2.5, 0.27
+    rho = np.where(np.random.default_rng(14).random(wl.n_elems(dims)) < 0.3, 1e-3, 1.0)
+    fixed = wl.clamp_x0(dims)
+    Ke = fem.ke_gauss(h, E, nu)
+    K = fem.assemble(dims, rho, Ke)
+    Kabs = fem.assemble(dims, rho, np.abs(Ke))
+    nd = 3 * wl.n_nodes(dims)
+    U = np.random.default_rng(15).standard_normal((1, nd))
+    for prec, eps, variant in [(afdcg.AFD_FP64, EPS64, -1), (afdcg.AFD_FP64, EPS64, 0), (afdcg.AFD_FP64, EPS64, 3),
+                               (afdcg.AFD_FP32, EPS32, -1), (afdcg.AFD_FP32, EPS32, 0)]:
+        m = make_mesh(ctx, dims, rho, fixed, h=h, E=E, nu=nu)
+        afdcg.afd_mesh_apply_config(m, prec, variant, 0)
+        u = U.astype(np.float32).astype(np.float64) if prec == afdcg.AFD_FP32 else U
+        Ud = dev(u, torch.float32 if prec == afdcg.AFD_FP32 else torch.float64)
+        Yd = torch.empty_like(Ud)
+        afdcg.afd_apply_K(m, prec, 1, Ud, Yd)
+        Y = host(Yd).astype(np.float64)
+        afdcg.afd_mesh_destroy(m)
+        want = fem.apply_constrained(K, fixed, u[0])
+        bound = 64 * eps * (fem.apply_constrained(Kabs, fixed, np.abs(u[0])) + np.abs(u[0]))
+        assert np.all(np.abs(Y[0] - want) <= bound), (prec, variant)
+    F = wl.edge_load(dims, "bottom")[None]
+    ud = solvers.solve_direct(K, fixed, F[0])
+    m = make_mesh(ctx, dims, rho, fixed, block=(4, 4, 4), h=h, E=E, nu=nu)
+    Us = np.zeros_like(F)
+    Jv = np.zeros(1)
+    S = np.zeros((1, wl.n_elems(dims)))
+    _, st = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-12), 1, F, Us, Jv, S)
+    afdcg.afd_mesh_destroy(m)
+    assert np.linalg.norm(Us[0] - ud) / np.linalg.norm(ud) <= 1e-8
+    s_or = post.element_energy(dims, rho, Ke, Us[0])
+    assert np.max(np.abs(S[0] - s_or)) <= 1e-10 * np.max(np.abs(s_or))
+
+
+def test_zero_load_gives_zero_solution(ctx):
+    dims = (12, 6, 6)
+    rho, _ = rand_problem(dims, 16)
+    m = make_mesh(ctx, dims, rho, wl.clamp_x0(dims), block=(4, 4, 4))
+    F = np.zeros((2, 3 * wl.n_nodes(dims)))
+    U = np.full_like(F, 7.0)
+    J = np.full(2, 7.0)
+    code, st = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-8), 2, F, U, J)
+    afdcg.afd_mesh_destroy(m)
+    assert code == afdcg.AFD_OK and all(s.status == 0 for s in st)
+    assert not U.any() and not J.any()
+
+
 def test_coarse_drops_fully_fixed_blocks(ctx):
     # with one-element blocks along x the x=0 node plane forms blocks whose
     # every DOF is fixed: their six coarse columns are zero and must be dropped
