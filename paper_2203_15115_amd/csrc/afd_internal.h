@@ -142,6 +142,17 @@ int64_t tile_layout_sizes(const Grid& g, int64_t* nrho);
 void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int* zc, int* nchunk);
 int launch_tile_rho(const Grid& g, const double* rho, double* rho_t, float* rho32_t, hipStream_t s);
 int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipStream_t s);
+// p' = beta p + M^-1 r - W mu (MU null: no deflation), zero on fixed DOFs
+int launch_form_dir(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh, const CgScalars* sc,
+                    int nrhs, const double* MU, const double* rinv, const double* Pold, const double* R,
+                    double* Pnew, hipStream_t s);
+int launch_form_dir_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh,
+                        const CgScalars* sc, int nrhs, const double* MU, const float* rinv32, const float* Pold,
+                        const float* R, float* Pnew, hipStream_t s);
+// Q = A P with the per-workgroup partial sums of P.Q (d.partial, slot 0 of
+// each right-hand side), skipping converged right-hand sides (d.sc)
+int launch_apply_dot(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int fp32, int nrhs, const void* P,
+                     void* Q, hipStream_t s);
 int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,
                  hipStream_t s);
 int launch_residual(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* F,

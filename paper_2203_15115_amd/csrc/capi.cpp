@@ -101,6 +101,15 @@ struct afd_mesh {
 
 namespace {
 
+int g_dir_fused = -1;
+bool dir_fused() {
+    if (g_dir_fused < 0) {
+        const char* e = getenv("AFD_DIR_FUSED");
+        g_dir_fused = (e && *e == '1') ? 1 : 0;
+    }
+    return g_dir_fused == 1;
+}
+
 int check_ctx(afd_context* c) {
     if (!c) {
         set_error("null context");
@@ -316,6 +325,20 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
         }
         return coarse_solve(m->coarse, nrhs, w.G, w.MU, s);
     };
+    // p' = beta p + M^-1 r - W mu (Pnew), then q = A p' with the p'.q partials;
+    // AFD_DIR_FUSED=1 selects the single fused register-staged kernel instead
+    auto direction = [&](T* Pold, T* Pnew) -> int {
+        if (dir_fused()) {
+            if constexpr (sizeof(T) == 8) return launch_dir_apply(a, m->kh, dm, nrhs, Pold, Pnew, R, Q, s);
+            else return launch_dir_apply_f32(a, m->kh, dm, m->rinv32, nrhs, Pold, Pnew, R, Q, s);
+        }
+        const double* mu = m->deflate ? w.MU : nullptr;
+        if constexpr (sizeof(T) == 8)
+            AFD_TRY(launch_form_dir(m->g, m->blk, m->nmask, m->kh, sc, nrhs, mu, m->rinv, Pold, R, Pnew, s));
+        else
+            AFD_TRY(launch_form_dir_f32(m->g, m->blk, m->nmask, m->kh, sc, nrhs, mu, m->rinv32, Pold, R, Pnew, s));
+        return launch_apply_dot(a, m->kh, dm, sizeof(T) == 4 ? 1 : 0, nrhs, Pnew, Q, s);
+    };
     if (m->deflate) {
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_precond(m->g, m->kh, m->rinv, nrhs, R, Z, s));
         else AFD_TRY(launch_precond_f32(m->g, m->kh, m->rinv32, nrhs, R, Z, s));
@@ -323,8 +346,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     }
     if constexpr (sizeof(T) == 8) AFD_TRY(launch_fill_f64(nrhs * ndof, 0.0, (double*)P0, s));
     else AFD_TRY(launch_fill_f32(nrhs * ndof, 0.0f, (float*)P0, s));
-    if constexpr (sizeof(T) == 8) AFD_TRY(launch_dir_apply(a, m->kh, dm, nrhs, P0, P1, R, Q, s));
-    else AFD_TRY(launch_dir_apply_f32(a, m->kh, dm, m->rinv32, nrhs, P0, P1, R, Q, s));
+    AFD_TRY(direction(P0, P1));
     std::swap(P0, P1);
     std::vector<CgScalars> hsc(nrhs);
     const int ce = std::max(1, check_every);
@@ -339,8 +361,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
                                              w.partV, VEC_NPART, s));
             AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
             AFD_TRY(coarse_of_z());
-            if constexpr (sizeof(T) == 8) AFD_TRY(launch_dir_apply(a, m->kh, dm, nrhs, P0, P1, R, Q, s));
-            else AFD_TRY(launch_dir_apply_f32(a, m->kh, dm, m->rinv32, nrhs, P0, P1, R, Q, s));
+            AFD_TRY(direction(P0, P1));
             std::swap(P0, P1);
         }
         return AFD_OK;

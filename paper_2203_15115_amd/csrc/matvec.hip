@@ -874,7 +874,10 @@ __device__ __forceinline__ void lds_xch(uint32_t a, float x[3]) {
 }
 static_assert(PX * 3 == 51 && NT == 256, "assembly offsets assume 17-node rows and 256-slot exchange planes");
 
-template <typename T, bool CUB, int D>
+// DOT: also the per-workgroup partial of P.Q over owned nodes (slot 0 of
+// this right-hand side; unused slots zeroed by workgroup 0), and converged
+// right-hand sides skipped (the solver's direction apply)
+template <typename T, bool CUB, int D, bool DOT = false>
 __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
     using S = DmaShape<T>;
     constexpr int R = 2 * D + 1;   // node-plane slots: D + 1 in use, D in flight
@@ -883,8 +886,12 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
     __shared__ __attribute__((aligned(16))) T rring[RR][NT];
     __shared__ __attribute__((aligned(16))) uint16_t mring[R][NT];
     __shared__ __attribute__((aligned(16))) T xch[2][3][NT];
+    __shared__ double dred[NT / 64];
 
     const int rhs = blockIdx.y;
+    if constexpr (DOT) {
+        if (P.sc[rhs].done) return;
+    }
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int lx = t % TX, ly = t / TX;
     const int L = xcd_tile(blockIdx.x, gridDim.x);
@@ -995,7 +1002,9 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
     T rawb[3] = {T(0), T(0), T(0)};  // unmasked own-node values of the bottom plane
     int mownb = 0;                    // and their fixity bits
     T pend[3] = {T(0), T(0), T(0)};   // plane k - 1 output before the y exchange
+    T pin[3] = {T(0), T(0), T(0)};    // DOT: the input at that node
     int pend_m = 0, pend_a = -1, pend_x = 0;
+    double dot = 0.0;
 
     for (int k0 = kfirst; k0 < Z1; k0 += D) {
 #pragma unroll
@@ -1008,7 +1017,11 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
                     T xr[3];
                     lds_xch(xch_base + pend_x * XB_B, xr);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) Y[pend_a + c] = ((pend_m >> c) & 1) ? pend[c] : pend[c] + xr[c];
+                    for (int c = 0; c < 3; ++c) {
+                        const T yv = ((pend_m >> c) & 1) ? pend[c] : pend[c] + xr[c];
+                        Y[pend_a + c] = yv;
+                        if constexpr (DOT) dot += (double)pin[c] * (double)yv;
+                    }
                     pend_a = -1;
                 }
                 if (d == 0) {  // next step's planes and densities
@@ -1049,6 +1062,10 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
                     pend_a = 3 * (own_node + sz * k);
                     pend_m = mownb;
                     pend_x = xb;
+                    if constexpr (DOT) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) pin[c] = ((mownb >> c) & 1) ? T(0) : rawb[c];
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) rawb[c] = rawt[c];
@@ -1061,7 +1078,29 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
         T xr[3];
         lds_xch(xch_base + pend_x * XB_B, xr);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Y[pend_a + c] = ((pend_m >> c) & 1) ? pend[c] : pend[c] + xr[c];
+        for (int c = 0; c < 3; ++c) {
+            const T yv = ((pend_m >> c) & 1) ? pend[c] : pend[c] + xr[c];
+            Y[pend_a + c] = yv;
+            if constexpr (DOT) dot += (double)pin[c] * (double)yv;
+        }
+    }
+    if constexpr (DOT) {
+        // fixed-order workgroup reduction -> one partial per workgroup
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) dot += __shfl_down(dot, off, 64);
+        if (lane == 0) dred[w] = dot;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+            for (int q = 0; q < NT / 64; ++q) sum += dred[q];
+            P.partial[(rhs * 2 + 0) * P.npart + blockIdx.x] = sum;
+            P.partial[(rhs * 2 + 1) * P.npart + blockIdx.x] = 0.0;
+        }
+        if (blockIdx.x == 0)
+            for (int i = gridDim.x + t; i < P.npart; i += NT) {
+                P.partial[(rhs * 2 + 0) * P.npart + i] = 0.0;
+                P.partial[(rhs * 2 + 1) * P.npart + i] = 0.0;
+            }
     }
 }
 
@@ -1282,6 +1321,35 @@ int launch_dir_apply(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, in
     p.F = R;
     p.Y = Q;
     return launch<double, DIR>(p, kh, nrhs, s);
+}
+
+template <typename T>
+int launch_dot_t(const MatvecArgs& a, const KeHaar& khd, const DcgArgs& d, int nrhs, const T* U, T* Y,
+                 hipStream_t s) {
+    if (nrhs < 1 || nrhs > 4) {
+        set_error("nrhs must be in 1..4");
+        return AFD_E_INVALID_ARG;
+    }
+    MvParams<T> p = base_params<T>(a);  // default tiling: the partial-sum buffer is sized for it
+    set_dcg(p, d);
+    p.U = U;
+    p.Y = Y;
+    if (p.tiles_x * p.tiles_y * p.nchunk > p.npart) {
+        set_error("apply_dot: grid larger than the partial-sum buffer");
+        return AFD_E_INVALID_ARG;
+    }
+    dim3 grid(p.tiles_x * p.tiles_y * p.nchunk, nrhs);
+    const KH<T> kh = to_kh<T>(khd);
+    if (is_cubic(khd)) hipLaunchKernelGGL((k_apply_tm<T, true, 1, true>), grid, dim3(NT), 0, s, p, kh);
+    else hipLaunchKernelGGL((k_apply_tm<T, false, 1, true>), grid, dim3(NT), 0, s, p, kh);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_apply_dot(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int fp32, int nrhs, const void* P,
+                     void* Q, hipStream_t s) {
+    if (fp32) return launch_dot_t<float>(a, kh, d, nrhs, (const float*)P, (float*)Q, s);
+    return launch_dot_t<double>(a, kh, d, nrhs, (const double*)P, (double*)Q, s);
 }
 
 int launch_residual_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,

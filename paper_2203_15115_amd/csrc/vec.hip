@@ -286,6 +286,49 @@ __global__ void k_prolong(BlkP p, const uint8_t* nm, int nrhs, int64_t nnode, co
     v[2] = (mk & 4) ? T(0) : (T)(m[2] + m[3] * x[1] - m[4] * x[0]);
 }
 
+// p' = beta p + M^-1 r - W mu (zero on fixed DOFs), the direction update of
+// the deflated PCG; one thread per node, skipped for converged right-hand sides
+template <typename T>
+__global__ void k_form_dir(BlkP p, const uint8_t* nm, int64_t nnode, const CgScalars* sc, const double* MU,
+                           const T* Pold, const T* R, const double* rinv, const float* rinv32, double kd0, double kd1,
+                           double kd2, T* Pnew) {
+    const int r = blockIdx.y;
+    if (sc[r].done) return;
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nnode) return;
+    const double beta = sc[r].beta;
+    double w[3] = {0.0, 0.0, 0.0};
+    if (MU) {
+        const int i = (int)(n % (p.nx + 1));
+        const int j = (int)((n / (p.nx + 1)) % (p.ny + 1));
+        const int k = (int)(n / ((int64_t)(p.nx + 1) * (p.ny + 1)));
+        const int pp[3] = {i, j, k};
+        int bb[3];
+        double x[3];
+        for (int a = 0; a < 3; ++a) {
+            int q = pp[a] / p.b[a];
+            if (q > p.nb[a] - 1) q = p.nb[a] - 1;
+            int lo, hi;
+            block_range(p, a, q, lo, hi);
+            bb[a] = q;
+            x[a] = (pp[a] - 0.5 * (lo + hi)) * p.inv_scale;
+        }
+        const double* m = MU + (int64_t)r * p.ncoarse + 6 * (bb[0] + p.nb[0] * (bb[1] + p.nb[1] * bb[2]));
+        w[0] = m[0] + m[4] * x[2] - m[5] * x[1];
+        w[1] = m[1] - m[3] * x[2] + m[5] * x[0];
+        w[2] = m[2] + m[3] * x[1] - m[4] * x[0];
+    }
+    const double ri = rinv ? rinv[n] : (double)rinv32[n];
+    const double kd[3] = {kd0, kd1, kd2};
+    const uint8_t mk = nm[n];
+    const int64_t o = (int64_t)r * 3 * nnode + 3 * n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double v = beta * (double)Pold[o + c] + ri / kd[c] * (double)R[o + c] - w[c];
+        Pnew[o + c] = ((mk >> c) & 1) ? T(0) : (T)v;
+    }
+}
+
 __global__ void k_copy(int64_t n, const double* a, double* b) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         b[i] = a[i];
@@ -464,6 +507,24 @@ int launch_prolong(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrh
                    hipStream_t s) {
     hipLaunchKernelGGL((k_prolong<double>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, nrhs,
                        g.nnode, MU, V, -1, 0);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_form_dir(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh, const CgScalars* sc,
+                    int nrhs, const double* MU, const double* rinv, const double* Pold, const double* R,
+                    double* Pnew, hipStream_t s) {
+    hipLaunchKernelGGL((k_form_dir<double>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, g.nnode,
+                       sc, MU, Pold, R, rinv, (const float*)nullptr, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], Pnew);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_form_dir_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh,
+                        const CgScalars* sc, int nrhs, const double* MU, const float* rinv32, const float* Pold,
+                        const float* R, float* Pnew, hipStream_t s) {
+    hipLaunchKernelGGL((k_form_dir<float>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, g.nnode,
+                       sc, MU, Pold, R, (const double*)nullptr, rinv32, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], Pnew);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
