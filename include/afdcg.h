@@ -77,7 +77,9 @@ typedef struct {
     double rtol;          /* stop when ||f - A u||_2 <= rtol * ||f||_2            */
     int32_t max_iter;     /* CG iterations (FP64) or inner iterations per sweep   */
     int32_t precision;    /* AFD_FP64 or AFD_MIXED                               */
-    double inner_rtol;    /* MIXED: relative residual reduction per inner solve  */
+    double inner_rtol;    /* MIXED: residual reduction of the first inner solve;
+                             later sweeps reduce by what is still missing to rtol
+                             (x1/2 margin), within [max(inner_rtol/100, 1e-6), 1/2] */
     int32_t check_every;  /* iterations between host convergence checks (>=1)    */
     int32_t mem_kind;     /* AFD_MEM_HOST or AFD_MEM_DEVICE for F, U, J, S       */
     const int32_t* pairs; /* host array of 2*npairs RHS indices (a,b)            */

@@ -984,10 +984,24 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
             if (all) break;
             refinements = ref + 1;
             AFD_TRY(launch_to_f32_scaled(ndof, nrhs, w.R, w.outer, w.Bf, s));
-            // the FP32 inner solve only has to reduce the residual by inner_rtol;
-            // past a few hundred iterations FP32 CG has stagnated, so cap it
+            // the FP32 inner solve reduces the residual by inner_rtol in the first
+            // sweep; later sweeps by what is still missing to the outer target
+            // (with a factor 2 of margin), within [max(inner_rtol / 100, 1e-6),
+            // 1/2] (FP32 inner solves here reach 3e-6 reliably), so that the
+            // refinement usually needs two sweeps and the last one does not solve
+            // far past rtol.  Past a few hundred iterations FP32 CG has
+            // stagnated, so cap it.
+            double inner_k = inner;
+            if (ref > 0) {
+                double rel_max = 0.0;
+                for (int r = 0; r < nrhs; ++r)
+                    if (hout[r].done == 0 && hout[r].bb > 0)
+                        rel_max = std::max(rel_max, std::sqrt(hout[r].rr / hout[r].bb));
+                const double floor_k = std::max(0.01 * inner, 1e-6);
+                if (rel_max > 0) inner_k = std::min(0.5, std::max(floor_k, 0.5 * o->rtol / rel_max));
+            }
             const int inner_max = std::min(o->max_iter, 1000);
-            AFD_TRY(dcg_run<float>(m, nrhs, w.Bf, w.Xf, w.Rf, w.P0f, w.P1f, w.Qf, w.Zf, w.AZf, w.sc, inner,
+            AFD_TRY(dcg_run<float>(m, nrhs, w.Bf, w.Xf, w.Rf, w.P0f, w.P1f, w.Qf, w.Zf, w.AZf, w.sc, inner_k,
                                    inner_max, ce, w.outer));
             AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), w.sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
             AFD_HIP_TRY(hipStreamSynchronize(s));
