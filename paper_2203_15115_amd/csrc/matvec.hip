@@ -528,12 +528,9 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
 }
 
 // ---------------------------------------------------------------------------
-// APPLY with direct global->LDS plane staging (global_load_lds_dword): the
-// node planes land in a 3-deep LDS ring without passing through registers,
-// so the load of plane k+3 is issued at the top of layer k and has a whole
-// layer of compute to arrive.  Barriers are plain s_barrier with explicit
-// waits: a fenced __syncthreads would wait for the in-flight plane loads.
-// Fixed DOFs are zeroed in LDS after their plane has landed.
+// Helpers of the LDS-DMA staged apply below.  Barriers are plain s_barrier
+// with explicit waits: a fenced __syncthreads would also wait for the plane
+// loads in flight.
 template <typename T>
 struct DmaShape {
     static constexpr int DW = sizeof(T) / 4;          // dwords per value
@@ -546,188 +543,6 @@ __device__ __forceinline__ void wait_all_and_barrier() {
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-template <typename T, bool CUB>
-__global__ __launch_bounds__(NT) void k_apply_dma(MvParams<T> P, KH<T> kh) {
-    using S = DmaShape<T>;
-    __shared__ __attribute__((aligned(16))) T ring[3][PLANE];
-    __shared__ T xch[3][NT];
-
-    const int rhs = blockIdx.y;
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    const int lx = t % TX, ly = t / TX;
-    const int L = xcd_tile(blockIdx.x, gridDim.x);
-    const int tile = L % (P.tiles_x * P.tiles_y);
-    const int chunk = L / (P.tiles_x * P.tiles_y);
-    const int X0 = (tile % P.tiles_x) * (TX - 1) - 1;
-    const int Y0 = (tile / P.tiles_x) * (TY - 1) - 1;
-    const int Z0 = chunk * P.zc;
-    const int Z1 = min(Z0 + P.zc, P.nz + 1);
-    const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
-    const int roff = rhs * P.ndof;
-    const T* U = P.U + roff;
-    T* Y = P.Y + roff;
-    const uint32_t* Udw = reinterpret_cast<const uint32_t*>(U);
-
-    const int gi = X0 + lx, gj = Y0 + ly;
-    const bool own = lx >= 1 && ly >= 1 && gi <= nx && gj <= ny;
-    const bool elem_xy = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
-    const int own_node = gi + sy * gj;
-
-    // DMA plan: instruction j of wave w moves plane dwords f = (4j + w)*64 + lane
-    int goff[S::J];  // dword offset within a node plane, -1 if outside the mesh
-#pragma unroll
-    for (int j = 0; j < S::J; ++j) {
-        const int f = (4 * j + w) * 64 + lane;
-        goff[j] = -1;
-        if (f < S::NDW) {
-            const int row = f / S::ROWDW, c = f - row * S::ROWDW;
-            const int i = X0 + c / (3 * S::DW), jj = Y0 + row;
-            if (i >= 0 && i <= nx && jj >= 0 && jj <= ny) goff[j] = (X0 + sy * jj) * 3 * S::DW + c;
-        }
-    }
-    // mask-fix plan: node slots n = t, t + 256 of the staged plane
-    int moff[NSLOT];
-#pragma unroll
-    for (int q = 0; q < NSLOT; ++q) {
-        const int n = t + q * NT;
-        moff[q] = -1;
-        if (n < PNODES) {
-            const int row = n / PX, li = n - row * PX;
-            const int i = X0 + li, j = Y0 + row;
-            if (i >= 0 && i <= nx && j >= 0 && j <= ny) moff[q] = i + sy * j;
-        }
-    }
-    auto issue_plane = [&](int gk, int b) {  // DMA (or zero) plane gk into ring[b]
-        uint32_t* dst = reinterpret_cast<uint32_t*>(&ring[b][0]);
-        if (gk >= 0 && gk <= nz) {
-            const int base = gk * sz * 3 * S::DW;
-#pragma unroll
-            for (int j = 0; j < S::J; ++j) {
-                if (goff[j] >= 0)
-                    __builtin_amdgcn_global_load_lds(
-                        (const void*)(Udw + base + goff[j]),
-                        (__attribute__((address_space(3))) void*)(dst + (4 * j + w) * 64), 4, 0, 0);
-            }
-        } else {
-            for (int f = t; f < S::NDW; f += NT) dst[f] = 0u;
-        }
-    };
-    auto load_masks = [&](int gk, int m[NSLOT]) {
-#pragma unroll
-        for (int q = 0; q < NSLOT; ++q)
-            m[q] = (moff[q] >= 0 && gk >= 0 && gk <= nz) ? (int)P.nmask[moff[q] + sz * gk] : 0;
-    };
-    auto fix_masks = [&](int b, const int m[NSLOT]) {
-#pragma unroll
-        for (int q = 0; q < NSLOT; ++q)
-            if (m[q]) {
-                const int n = t + q * NT;
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    if ((m[q] >> c) & 1) ring[b][3 * n + c] = T(0);
-            }
-    };
-    auto rho_at = [&](int k) -> T {
-        return (elem_xy && k >= 0 && k < nz) ? P.rho[gi + nx * (gj + ny * k)] : T(0);
-    };
-    auto read_face = [&](int b, T f[4][3]) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int li = lx + (q & 1), lj = ly + (q >> 1);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) f[q][c] = ring[b][(lj * PX + li) * 3 + c];
-        }
-    };
-
-    // ring slot of plane g: (g - Z0 + 1) mod 3 (plane Z0-1 in slot 0)
-    auto slot = [&](int g) { return (g - Z0 + 1) % 3; };
-    for (int f = t; f < 3 * PLANE; f += NT) (&ring[0][0])[f] = T(0);
-    lds_barrier();
-    int mk[NSLOT], own_m_next = 0;
-    issue_plane(Z0 - 1, slot(Z0 - 1));
-    issue_plane(Z0, slot(Z0));
-    int m0[NSLOT];
-    load_masks(Z0 - 1, m0);
-    load_masks(Z0, mk);
-    wait_all_and_barrier();
-    fix_masks(slot(Z0 - 1), m0);
-    fix_masks(slot(Z0), mk);
-    issue_plane(Z0 + 1, slot(Z0 + 1));
-    load_masks(Z0 + 1, mk);
-    T rho_cur = rho_at(Z0 - 1);
-    T rho_nxt = rho_at(Z0);
-    if (own && Z0 <= nz) own_m_next = P.nmask[own_node + sz * Z0];
-    lds_barrier();
-    T bf[4][3], ctop[4][3];
-    read_face(slot(Z0 - 1), bf);
-    face_fwd<T>(bf);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ctop[q][c] = T(0);
-
-    // outputs of plane k are stored at the top of layer k+1 (after its
-    // barrier), so that a whole layer of compute covers their completion
-    // before the next vmcnt(0) wait (gfx9 counts stores in vmcnt)
-    T pend[3];
-    int pend_a = -1;
-    for (int k = Z0 - 1; k < Z1; ++k) {  // element layer k (node planes k, k+1)
-        // plane k+2 (issued one layer ago) has landed; masks of plane k+2 are in mk
-        wait_all_and_barrier();
-        if (pend_a >= 0) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Y[pend_a + c] = pend[c];
-            pend_a = -1;
-        }
-        const int own_m = own_m_next;
-        // all ring accesses of this layer first ...
-        if (k + 2 <= Z1) fix_masks(slot(k + 2), mk);
-        T tf[4][3];
-        read_face(slot(k + 1), tf);
-        // ... then the plane three layers ahead, so that no wait the compiler
-        // places before later LDS accesses falls before the element compute
-        if (k + 3 <= Z1) issue_plane(k + 3, slot(k + 3));
-        if (k + 3 <= Z1) load_masks(k + 3, mk);
-        const T rho_k = rho_cur;
-        rho_cur = rho_nxt;
-        rho_nxt = rho_at(k + 2);
-        if (own && k + 1 >= Z0 && k + 1 <= nz) own_m_next = P.nmask[own_node + sz * (k + 1)];
-        face_fwd<T>(tf);
-        T yb[4][3], yt[4][3];
-        element_haar<T, CUB>(kh, rho_k, bf, tf, yb, yt);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                yb[q][c] += ctop[q][c];
-                ctop[q][c] = yt[q][c];
-                bf[q][c] = tf[q][c];
-            }
-        face_inv<T>(yb);
-        T s0[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            s0[c] = yb[0][c] + dpp_shr1(yb[1][c]);
-            xch[c][t] = yb[2][c] + dpp_shr1(yb[3][c]);
-        }
-        lds_barrier();
-        if (own && k >= Z0) {
-            const int a0 = 3 * (own_node + sz * k);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T yv = s0[c] + xch[c][t - TX];
-                pend[c] = ((own_m >> c) & 1) ? U[a0 + c] : yv;
-            }
-            pend_a = a0;
-        }
-    }
-    if (pend_a >= 0) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Y[pend_a + c] = pend[c];
-    }
-}
 
 // Tile-major side arrays of the plain apply, rebuilt whenever the densities
 // or the fixity change: per (tile, element layer) the 16x16 densities of the
@@ -962,9 +777,10 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
             for (int j = 0; j < S::DW; ++j) dst[j * NT + t] = 0u;
         }
     };
-    // zero the fixed components of a face (bit 3q + c of fm)
+    // zero the fixed components of a face (bit 3q + c of fm); a wave-uniform
+    // branch, so that the many waves without any fixed face node skip it
     auto mask_face = [&](int fm, T f[4][3]) {
-        if (fm) {
+        if (__builtin_amdgcn_ballot_w64(fm != 0)) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -1107,13 +923,13 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
 int g_zc_override = -1;
 int g_variant = -1;
 
-// plain-apply kernel: 0 register staging, 1 single-step LDS DMA, 2..4 the
-// tile-major DMA kernel with 1..3 layers per step (AFD_APPLY_KERNEL)
+// plain-apply kernel: 0 register staging, 2 / 3 the tile-major DMA kernel with
+// 1 / 2 layers per step (AFD_APPLY_KERNEL; the autotuner picks per mesh)
 int apply_variant() {
     if (g_variant < 0) {
         const char* e = getenv("AFD_APPLY_KERNEL");
         int v = e ? atoi(e) : 2;
-        if (v < 0 || v > 4) v = 2;
+        if (v != 0 && v != 3) v = 2;
         g_variant = v;
     }
     return g_variant;
@@ -1125,15 +941,13 @@ int apply_occupancy(int variant) {
     hipError_t e = hipErrorInvalidValue;
     switch (variant) {
         case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_matvec<T, APPLY, true>, NT, 0); break;
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_dma<T, true>, NT, 0); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 1>, NT, 0); break;
         case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 2>, NT, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 3>, NT, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 1>, NT, 0); break;
     }
     return (e == hipSuccess && n > 0) ? n : 0;
 }
 
-int g_slots[5][2];  // resident 256-thread workgroups per (apply variant, FP32) on this device, 0 = unknown
+int g_slots[4][2];  // resident 256-thread workgroups per (apply variant, FP32) on this device, 0 = unknown
 
 // z-chunking: as many chunks as fit in one round of resident workgroups of
 // the given kernel variant, so that no partly filled second round trails the
@@ -1145,7 +959,7 @@ void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, 
         const char* e = getenv("AFD_MATVEC_ZC");
         g_zc_override = e ? atoi(e) : 0;
     }
-    if (variant < 0 || variant > 4) variant = apply_variant();
+    if (variant != 0 && variant != 2 && variant != 3) variant = apply_variant();
     if (g_slots[variant][fp32] <= 0) {
         int dev = 0, cus = 256, per = fp32 ? 4 : 2;
         if (hipGetDevice(&dev) == hipSuccess)
@@ -1208,21 +1022,13 @@ int launch(const MvParams<T>& p, const KeHaar& khd, int nrhs, hipStream_t s) {
     const int v = MODE == APPLY ? p.variant : 0;
     if (v >= 1) {
         switch (v) {
-            case 1:
-                if (cub) hipLaunchKernelGGL((k_apply_dma<T, true>), grid, dim3(NT), 0, s, p, kh);
-                else hipLaunchKernelGGL((k_apply_dma<T, false>), grid, dim3(NT), 0, s, p, kh);
-                break;
-            case 2:
-                if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 1>), grid, dim3(NT), 0, s, p, kh);
-                else hipLaunchKernelGGL((k_apply_tm<T, false, 1>), grid, dim3(NT), 0, s, p, kh);
-                break;
             case 3:
                 if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 2>), grid, dim3(NT), 0, s, p, kh);
                 else hipLaunchKernelGGL((k_apply_tm<T, false, 2>), grid, dim3(NT), 0, s, p, kh);
                 break;
             default:
-                if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 3>), grid, dim3(NT), 0, s, p, kh);
-                else hipLaunchKernelGGL((k_apply_tm<T, false, 3>), grid, dim3(NT), 0, s, p, kh);
+                if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 1>), grid, dim3(NT), 0, s, p, kh);
+                else hipLaunchKernelGGL((k_apply_tm<T, false, 1>), grid, dim3(NT), 0, s, p, kh);
                 break;
         }
     } else if (cub) {
