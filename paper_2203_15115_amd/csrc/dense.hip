@@ -105,14 +105,18 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
 // (row l % 16, k l / 16), B lane l holds (k l / 16, col l % 16), and
 // accumulator register v of lane l is (row l / 16 + 4 v, col l % 16).
 typedef double dacc4 __attribute__((ext_vector_type(4)));
+// Split K: workgroup z of gridDim.z covers k in [z kchunk, (z + 1) kchunk) and
+// writes its partial product to C + z czs (beta must then be 0).
 __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double alpha, const double* A, int lda,
                                                    int ta, const double* B, int ldb, int tb, double beta, double* C,
-                                                   int ldc) {
+                                                   int ldc, int kchunk, int64_t czs) {
     __shared__ double As[GK][GT + 2];
     __shared__ double Bs[GK][GT + 2];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1;
     const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
+    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    C += blockIdx.z * czs;
     // loader: element e = t + 256 q (q < 4) of the 64 x 16 A tile and the 16 x 64 B tile
     double ra[4], rb[4];
     auto load = [&](int k0) {
@@ -122,11 +126,11 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double a
             int ii, kk;
             if (ta) { ii = e % GT; kk = e / GT; } else { kk = e % GK; ii = e / GK; }
             const int gi = i0 + ii, gk = k0 + kk;
-            ra[q] = (gi < M && gk < K) ? (ta ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : 0.0;
+            ra[q] = (gi < M && gk < kend) ? (ta ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : 0.0;
             int jj, kb;
             if (tb) { kb = e % GK; jj = e / GK; } else { jj = e % GT; kb = e / GT; }
             const int gj = j0 + jj, gkb = k0 + kb;
-            rb[q] = (gj < N && gkb < K) ? (tb ? B[(int64_t)gj * ldb + gkb] : B[(int64_t)gkb * ldb + gj]) : 0.0;
+            rb[q] = (gj < N && gkb < kend) ? (tb ? B[(int64_t)gj * ldb + gkb] : B[(int64_t)gkb * ldb + gj]) : 0.0;
         }
     };
     auto store = [&]() {
@@ -146,12 +150,12 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double a
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = dacc4{0.0, 0.0, 0.0, 0.0};
-    load(0);
-    for (int k0 = 0; k0 < K; k0 += GK) {
+    load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
         __syncthreads();  // previous step's operands consumed
         store();
         __syncthreads();
-        if (k0 + GK < K) load(k0 + GK);
+        if (k0 + GK < kend) load(k0 + GK);
 #pragma unroll
         for (int sk = 0; sk < GK / 4; ++sk) {
             const int kk = 4 * sk + (lane >> 4);
@@ -189,8 +193,37 @@ int gemm(int M, int N, int K, double alpha, const double* A, int lda, int ta, co
     if (K <= 0) {
         hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
     } else {
-        hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
+        hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc,
+                           K, (int64_t)0);
     }
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+// dst[i][j] = sum_z src[z][i][j] (M x N, row strides ld / ldd, batch stride zs)
+__global__ void k_sum_split(int M, int N, int S, const double* src, int ld, int64_t zs, double* dst, int ldd) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= N) return;
+    double v = 0.0;
+    for (int z = 0; z < S; ++z) v += src[z * zs + (int64_t)i * ld + j];
+    dst[(int64_t)i * ldd + j] = v;
+}
+
+// C = alpha op(A) op(B) with K split over S workgroup slices whose partial
+// products go to part (S x M x ldp) and are then summed into C: for the
+// short-and-wide products whose output tiles alone cannot fill the GPU
+int gemm_split(int M, int N, int K, double alpha, const double* A, int lda, int ta, const double* B, int ldb, int tb,
+               double* C, int ldc, double* part, int ldp, int S, hipStream_t s) {
+    if (M <= 0 || N <= 0) return AFD_OK;
+    const int kchunk = ((K + S - 1) / S + GK - 1) / GK * GK;
+    S = (K + kchunk - 1) / kchunk;
+    if (S <= 1) return gemm(M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, C, ldc, s);
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, S);
+    const int64_t zs = (int64_t)M * ldp;
+    hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, ta, B, ldb, tb, 0.0, part, ldp,
+                       kchunk, zs);
+    hipLaunchKernelGGL(k_sum_split, dim3((N + 255) / 256, M), dim3(256), 0, s, M, N, S, (const double*)part, ldp, zs,
+                       C, ldc);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -582,10 +615,15 @@ int coarse_factor(Coarse& c, hipStream_t s) {
             }
         }
         AFD_HIP_TRY(hipGetLastError());
-        // Linv: row tile i: X[i, 0:i] = -X_ii (L[i, 0:i] X[0:i, 0:i])
+        // Linv: row tile i: X[i, 0:i] = -X_ii (L[i, 0:i] X[0:i, 0:i]); the first
+        // product is nb x i0 x i0, too few output tiles for the GPU, so K is
+        // split (partials in work rows nb.., the sum in work rows 0..nb-1)
         for (int i0 = NB; i0 < P; i0 += NB) {
             const int nb = std::min(NB, P - i0);
-            AFD_TRY(gemm(nb, i0, i0, 1.0, Dk + (int64_t)i0 * P, P, 0, Li, P, 0, 0.0, c.work, P, s));
+            const int tiles = (i0 + GT - 1) / GT;
+            const int S = std::max(1, std::min({(P - nb) / nb, 256 / tiles, i0 / 128}));
+            AFD_TRY(gemm_split(nb, i0, i0, 1.0, Dk + (int64_t)i0 * P, P, 0, Li, P, 0, c.work, P, c.work + (int64_t)nb * P,
+                               P, S, s));
             AFD_TRY(gemm(nb, i0, nb, -1.0, Li + (int64_t)i0 * P + i0, P, 0, c.work, P, 0, 0.0, Li + (int64_t)i0 * P,
                          P, s));
         }
