@@ -256,6 +256,14 @@ def main():
     afdcg.afd_mesh_set_scale(mesh, rho_d, p.nelem, afdcg.AFD_MEM_DEVICE)
     afdcg.afd_mesh_set_fixed(mesh, fix_d, p.ndof, afdcg.AFD_MEM_DEVICE)
     torch.cuda.synchronize()
+    # ---- apply execution picked by the autotuner on this mesh (outside the timed region)
+    tune = {}
+    for name, prec in (("fp64", afdcg.AFD_FP64), ("fp32", afdcg.AFD_FP32)):
+        r = afdcg.afd_mesh_autotune(mesh, prec, 1)
+        tune[name] = {"variant": r.variant, "zc": r.zc, "us": round(r.us, 2), "default_us": round(r.default_us, 2),
+                      "candidates": r.ncandidates}
+    print(f"# autotune: {json.dumps(tune)}", file=sys.stderr, flush=True)
+
     if args.apply_only:
         # calibration copy of known size for FETCH_SIZE / WRITE_SIZE, then the applies
         a = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
@@ -266,16 +274,9 @@ def main():
         for _ in range(args.reps):
             afdcg.afd_apply_K(mesh, afdcg.AFD_FP64, 1, u, y)
         torch.cuda.synchronize()
-        print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps}), flush=True)
+        print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps,
+                          "apply_tuning": tune}), flush=True)
         return
-
-    # ---- apply execution picked by the autotuner on this mesh (outside the timed region)
-    tune = {}
-    for name, prec in (("fp64", afdcg.AFD_FP64), ("fp32", afdcg.AFD_FP32)):
-        r = afdcg.afd_mesh_autotune(mesh, prec, 1)
-        tune[name] = {"variant": r.variant, "zc": r.zc, "us": round(r.us, 2), "default_us": round(r.default_us, 2),
-                      "candidates": r.ncandidates}
-    print(f"# autotune: {json.dumps(tune)}", file=sys.stderr, flush=True)
 
     # ---- operator apply throughput (HIP events on the library's stream)
     u = torch.randn(p.ndof, dtype=torch.float64, device=dev)

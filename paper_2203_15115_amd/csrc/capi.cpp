@@ -682,8 +682,9 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
         set_error("autotune: event creation failed");
         rc = AFD_E_HIP;
     }
-    // candidates: each kernel variant at its one-round chunking, and at half
-    // and twice as many chunks
+    // candidates: each kernel variant at its one-round chunking, and at 1/2,
+    // 2, 3 and 4 times as many chunks (more, shorter z chunks trade z overlap
+    // for parallelism)
     struct Cand {
         int v, zc;
     };
@@ -691,7 +692,7 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
     for (int v : {2, 3, 0}) {
         int zc = 0, nch = 0;
         apply_tiling(m->g, f, v, 0, &zc, &nch);
-        for (int mult : {2, 1, 4}) {  // chunks x mult / 2
+        for (int mult : {2, 1, 4, 6, 8}) {  // chunks x mult / 2
             const int want = std::max(1, nch * mult / 2);
             const int planes = m->g.nz + 1;
             const int z = std::max(1, (planes + want - 1) / want);
