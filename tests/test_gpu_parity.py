@@ -195,6 +195,48 @@ def test_apply_full_size_sampled(ctx):
     assert np.all(np.abs(got - want) <= bound)
 
 
+def _oracle_residual(p, U):
+    # ||f - K u||_2 / ||f||_2 over free DOFs with the oracle's element-by-element
+    # apply (independent of the library); u is zero on fixed DOFs
+    free = np.asarray(p.fixed) == 0
+    Ke = fem.ke_gauss()
+    out = []
+    for r in range(U.shape[0]):
+        u = np.where(free, U[r], 0.0)
+        res = (p.F[r] - fem.apply_ebe(p.dims, p.rho, Ke, u))[free]
+        out.append(np.linalg.norm(res) / np.linalg.norm(p.F[r][free]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("idx,precision", [(1, afdcg.AFD_FP64), (3, afdcg.AFD_MIXED), (2, afdcg.AFD_FP64)])
+def test_full_size_solve_residual_by_oracle(ctx, idx, precision):
+    # the full-size workloads (192x96x96 FP64, 256x128x128 mixed, 128x64x64 with
+    # 4 right-hand sides) solved to 1e-8: the residual of the returned
+    # displacements recomputed by the oracle, compliance = f.u, and for the
+    # 4 load cases the Maxwell-Betti reciprocity of the mutual energies
+    p = wl.config(idx)
+    nr = p.F.shape[0]
+    pairs = ((0, 3), (1, 3), (2, 3)) if nr == 4 else ()
+    m = make_mesh(ctx, p.dims, p.rho, p.fixed, block=p.block)
+    U = np.zeros((nr, p.ndof))
+    J = np.zeros(nr)
+    S = np.zeros((nr + len(pairs), p.nelem))
+    opts = afdcg.make_opts(rtol=1e-8, max_iter=20000, precision=precision, pairs=pairs, check_every=32)
+    _, st = afdcg.afd_solve(m, opts, nr, np.ascontiguousarray(p.F), U, J, S)
+    afdcg.afd_mesh_destroy(m)
+    rel = _oracle_residual(p, U)
+    assert np.all(rel <= 1.05e-8), rel
+    for r in range(nr):
+        assert abs(st[r].rel_residual_true - rel[r]) <= 1e-3 * rel[r] + 1e-12
+        assert abs(J[r] - p.F[r] @ U[r]) <= 1e-12 * abs(J[r])
+        assert abs(S[r].sum() - J[r]) <= 1e-8 * abs(J[r])
+    for q, (a, b) in enumerate(pairs):
+        # mutual energy of load case a and the adjoint field b: f_a . u_b = f_b . u_a
+        mutual = S[nr + q].sum()
+        assert abs(mutual - p.F[a] @ U[b]) <= 1e-7 * abs(mutual)
+        assert abs(p.F[a] @ U[b] - p.F[b] @ U[a]) <= 1e-6 * abs(mutual)
+
+
 def test_apply_is_bitwise_reproducible(ctx):
     dims = (33, 20, 19)
     rho, fixed = rand_problem(dims, 4)
