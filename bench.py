@@ -31,12 +31,13 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per FP64 apply launch at 192x96x96 from rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by the
 # same counter on a 512 MiB copy (kernel as of the committed counter summary
 # profiles/apply_fp64_192x96x96_counters.md); None when not measured
-TRAFFIC_BYTES = 74_585_907 + 43_811_021
+TRAFFIC_BYTES = None
 
 
 # plain-apply kernel of each autotuner variant
 KERNEL_NAMES = {0: "k_matvec<double, APPLY, cubic>", 2: "k_apply_tm<double, cubic, 1>",
-                3: "k_apply_tm<double, cubic, 2>", -1: "k_apply_tm<double, cubic, 1>"}
+                3: "k_apply_tm<double, cubic, 2>", 4: "k_apply_bl<double, cubic, 2>",
+                6: "k_apply_bl<double, cubic, 1>", -1: "k_apply_bl<double, cubic, 1>"}
 
 
 def matvec_algorithmic_bytes(dims, word=8):
@@ -365,8 +366,8 @@ def main():
         "apply_tuning": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     # counters were taken on the one-layer-per-step tile-major kernel
-                     "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] in (-1, 2) else None,
+                     # counters were taken on the default kernel (buffer loads, prefetch distance 1)
+                     "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] in (-1, 6) else None,
                      "kernel": KERNEL_NAMES[tune["fp64"]["variant"]], "bytes_per_launch": alg},
     }
     secs = [x for x in args.sections.split(",") if x]

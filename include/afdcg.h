@@ -162,7 +162,8 @@ int afd_apply_K_mfma(afd_mesh* mesh, int32_t nrhs, const double* U, double* Y);
  * nrhs x n_dof.  report may be NULL. */
 typedef struct afd_tune_report {
     int32_t variant;        /* chosen kernel: 0 register-staged, 2 / 3 LDS-DMA with 1 / 2 layers per step,
-                               -1 the default (kept unless a candidate is >= 3% faster)           */
+                               4 / 6 buffer-load LDS-DMA with a prefetch distance of 2 / 1 layers,
+                               -1 the default (variant 6; kept unless a candidate is >= 3% faster) */
     int32_t zc;             /* chosen node planes per z chunk                                           */
     double us;              /* its time per launch (microseconds)                                       */
     double default_us;      /* time of the untuned default                                              */
@@ -171,7 +172,8 @@ typedef struct afd_tune_report {
 int afd_mesh_autotune(afd_mesh* mesh, int32_t precision, int32_t nrhs, afd_tune_report* report);
 /* Sets the afd_apply_K execution for `precision` by hand (what the autotuner
  * picks): variant 0 register-staged, 2 / 3 LDS-DMA with 1 / 2 layers per
- * step, -1 the default; zc node planes per z chunk, 0 the default.  Returns
+ * step, 4 / 6 buffer-load LDS-DMA with a prefetch distance of 2 / 1 layers,
+ * -1 the default; zc node planes per z chunk, 0 the default.  Returns
  * AFD_E_INVALID_ARG for other values. */
 int afd_mesh_apply_config(afd_mesh* mesh, int32_t precision, int32_t variant, int32_t zc);
 

@@ -689,7 +689,7 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
         int v, zc;
     };
     std::vector<Cand> cands;
-    for (int v : {2, 3, 0}) {
+    for (int v : {6, 4, 2, 3, 0}) {
         int zc = 0, nch = 0;
         apply_tiling(m->g, f, v, 0, &zc, &nch);
         for (int mult : {2, 1, 4, 6, 8}) {  // chunks x mult / 2
@@ -754,8 +754,8 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
 
 int afd_mesh_apply_config(afd_mesh* m, int32_t precision, int32_t variant, int32_t zc) {
     if (!m || (precision != AFD_FP64 && precision != AFD_FP32) ||
-        !(variant == -1 || variant == 0 || variant == 2 || variant == 3) || zc < 0) {
-        set_error("apply_config: bad argument (variant -1, 0, 2 or 3; zc >= 0)");
+        !(variant == -1 || variant == 0 || variant == 2 || variant == 3 || variant == 4 || variant == 6) || zc < 0) {
+        set_error("apply_config: bad argument (variant -1, 0, 2, 3, 4 or 6; zc >= 0)");
         return AFD_E_INVALID_ARG;
     }
     const int f = precision == AFD_FP32 ? 1 : 0;

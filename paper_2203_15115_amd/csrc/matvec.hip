@@ -230,14 +230,15 @@ __device__ __forceinline__ double rinv_of(const MvParams<T>& P, int node) {
 }
 
 // 64-bit row shift by one lane inside each 16-lane DPP row (lane 0 of a row
-// receives 0)
+// receives 0: bound_ctrl zeroes reads from outside the row, so the old value
+// of the destination needs no initialisation)
 __device__ __forceinline__ double dpp_shr1(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x111, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x111, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x111, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x111, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float dpp_shr1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -660,6 +661,68 @@ __device__ __forceinline__ void lds_face0(uint32_t a, uint32_t am, T f[4][3], in
     T rho_unused;
     lds_face(a, a, am, f, rho_unused, fm);
 }
+// lds_face plus, from another staged plane (byte address ab of the same
+// node), the three unmasked components of the own node and its fixity word
+__device__ __forceinline__ void lds_face_own(uint32_t a, uint32_t ar, uint32_t am, uint32_t ab, uint32_t amb,
+                                             double f[4][3], double& rho, int& fm, double own[3], int& fmb) {
+    dv2 r0, r1, r2, r3, r4, r5, o01;
+    double rr, o2;
+    uint32_t mm, mb;
+    asm volatile(
+        "ds_read2_b64 %0, %11 offset1:1\n\t"
+        "ds_read2_b64 %1, %11 offset0:2 offset1:3\n\t"
+        "ds_read2_b64 %2, %11 offset0:4 offset1:5\n\t"
+        "ds_read2_b64 %3, %11 offset0:51 offset1:52\n\t"
+        "ds_read2_b64 %4, %11 offset0:53 offset1:54\n\t"
+        "ds_read2_b64 %5, %11 offset0:55 offset1:56\n\t"
+        "ds_read_b64 %6, %12\n\t"
+        "ds_read_u16 %7, %13\n\t"
+        "ds_read2_b64 %8, %14 offset1:1\n\t"
+        "ds_read_b64 %9, %14 offset:16\n\t"
+        "ds_read_u16 %10, %15\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(rr), "=&v"(mm), "=&v"(o01),
+          "=&v"(o2), "=&v"(mb)
+        : "v"(a), "v"(ar), "v"(am), "v"(ab), "v"(amb));
+    f[0][0] = r0.x; f[0][1] = r0.y; f[0][2] = r1.x;
+    f[1][0] = r1.y; f[1][1] = r2.x; f[1][2] = r2.y;
+    f[2][0] = r3.x; f[2][1] = r3.y; f[2][2] = r4.x;
+    f[3][0] = r4.y; f[3][1] = r5.x; f[3][2] = r5.y;
+    rho = rr;
+    fm = (int)mm;
+    own[0] = o01.x; own[1] = o01.y; own[2] = o2;
+    fmb = (int)mb;
+}
+__device__ __forceinline__ void lds_face_own(uint32_t a, uint32_t ar, uint32_t am, uint32_t ab, uint32_t amb,
+                                             float f[4][3], float& rho, int& fm, float own[3], int& fmb) {
+    fv2 r0, r1, r2, r3, r4, r5, o01;
+    float rr, o2;
+    uint32_t mm, mb;
+    asm volatile(
+        "ds_read2_b32 %0, %11 offset1:1\n\t"
+        "ds_read2_b32 %1, %11 offset0:2 offset1:3\n\t"
+        "ds_read2_b32 %2, %11 offset0:4 offset1:5\n\t"
+        "ds_read2_b32 %3, %11 offset0:51 offset1:52\n\t"
+        "ds_read2_b32 %4, %11 offset0:53 offset1:54\n\t"
+        "ds_read2_b32 %5, %11 offset0:55 offset1:56\n\t"
+        "ds_read_b32 %6, %12\n\t"
+        "ds_read_u16 %7, %13\n\t"
+        "ds_read2_b32 %8, %14 offset1:1\n\t"
+        "ds_read_b32 %9, %14 offset:8\n\t"
+        "ds_read_u16 %10, %15\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(rr), "=&v"(mm), "=&v"(o01),
+          "=&v"(o2), "=&v"(mb)
+        : "v"(a), "v"(ar), "v"(am), "v"(ab), "v"(amb));
+    f[0][0] = r0.x; f[0][1] = r0.y; f[0][2] = r1.x;
+    f[1][0] = r1.y; f[1][1] = r2.x; f[1][2] = r2.y;
+    f[2][0] = r3.x; f[2][1] = r3.y; f[2][2] = r4.x;
+    f[3][0] = r4.y; f[3][1] = r5.x; f[3][2] = r5.y;
+    rho = rr;
+    fm = (int)mm;
+    own[0] = o01.x; own[1] = o01.y; own[2] = o2;
+    fmb = (int)mb;
+}
 // three components of one exchange slot: [c][NT] layout, a = slot of c = 0
 __device__ __forceinline__ void lds_xch(uint32_t a, double x[3]) {
     dv2 r01;
@@ -688,6 +751,27 @@ __device__ __forceinline__ void lds_xch(uint32_t a, float x[3]) {
     x[2] = r2;
 }
 static_assert(PX * 3 == 51 && NT == 256, "assembly offsets assume 17-node rows and 256-slot exchange planes");
+// write the three components of this thread's exchange slot ([c][NT]
+// layout, a = slot of c = 0).  Assembly, so that the compiler, which cannot
+// tell the exchange planes from the targets of buffer-load DMAs in flight,
+// does not put a vmcnt wait in front of it.
+__device__ __forceinline__ void lds_xch_put(uint32_t a, double x0, double x1, double x2) {
+    asm volatile(
+        "ds_write2st64_b64 %0, %1, %2 offset1:4\n\t"
+        "ds_write_b64 %0, %3 offset:4096"
+        :
+        : "v"(a), "v"(x0), "v"(x1), "v"(x2)
+        : "memory");
+}
+__device__ __forceinline__ void lds_xch_put(uint32_t a, float x0, float x1, float x2) {
+    asm volatile(
+        "ds_write2st64_b32 %0, %1, %2 offset1:4\n\t"
+        "ds_write_b32 %0, %3 offset:2048"
+        :
+        : "v"(a), "v"(x0), "v"(x1), "v"(x2)
+        : "memory");
+}
+
 
 // DOT: also the per-workgroup partial of P.Q over owned nodes (slot 0 of
 // this right-hand side; unused slots zeroed by workgroup 0), and converged
@@ -920,19 +1004,261 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
     }
 }
 
+// The same apply with the staging issued as untyped buffer loads into LDS.
+// A load whose byte offset lies beyond the range of its buffer resource
+// returns zero, so every wave issues the same loads for every layer (node
+// positions outside the mesh, planes outside the chunk and the pad of a ring
+// slot are simply out of range), and each wave knows how many of its loads
+// are younger than the plane it needs.  That allows a partial vmcnt wait and
+// hence a prefetch distance of DIST layers with one layer per step: at the
+// top of layer k the wave waits for the loads of plane k + 1, issued DIST
+// layers earlier, while the DIST - 1 younger batches stay in flight.  Vector
+// loads return in order; stores in between do not matter, because the wait
+// counts only the loads of the younger batches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void dma_dword(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t* lds_wave) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_wave, 4, voff, 0, 0,
+                                             0);
+}
+template <int N>
+__device__ __forceinline__ void wait_vm_and_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+constexpr uint32_t OOB = 0x80000000u;  // beyond every buffer range used below
+
+template <typename T, bool CUB, int DIST, bool DOT = false>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_apply_bl(MvParams<T> P, KH<T> kh) {
+    using S = DmaShape<T>;
+    constexpr int R = DIST + 2;        // plane ring slots: planes k and k + 1 being read, DIST in flight
+    constexpr int RR = DIST + 1;       // density ring slots: layer k being read, DIST in flight
+    constexpr int SLOT = S::J * NT;    // dwords per plane slot (whole-wave DMA, pad included)
+    constexpr int NB = S::J + S::DW;   // loads per wave and layer (waves 0 and 1 issue one more)
+    __shared__ __attribute__((aligned(16))) uint32_t ring[R][SLOT];
+    __shared__ __attribute__((aligned(16))) T rring[RR][NT];
+    __shared__ __attribute__((aligned(16))) uint16_t mring[R][NT];
+    __shared__ __attribute__((aligned(16))) T xch[2][3][NT];
+    __shared__ double dred[NT / 64];
+
+    const int rhs = blockIdx.y;
+    if constexpr (DOT) {
+        if (P.sc[rhs].done) return;
+    }
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lx = t % TX, ly = t / TX;
+    const int L = xcd_tile(blockIdx.x, gridDim.x);
+    const int ntile = P.tiles_x * P.tiles_y;
+    const int tile = L % ntile;
+    const int chunk = L / ntile;
+    const int X0 = (tile % P.tiles_x) * (TX - 1) - 1;
+    const int Y0 = (tile / P.tiles_x) * (TY - 1) - 1;
+    const int Z0 = chunk * P.zc;
+    const int Z1 = min(Z0 + P.zc, P.nz + 1);
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
+    const int roff = rhs * P.ndof;
+    const T* U = P.U + roff;
+    T* Y = P.Y + roff;
+    const T* Rt = P.rho_t + (size_t)tile * nz * NT;
+    const uint16_t* Mt = P.fm_t + (size_t)tile * (nz + 1) * NT;
+    const uint32_t plane_bytes = (uint32_t)(3u * (uint32_t)sz * sizeof(T));
+
+    const int gi = X0 + lx, gj = Y0 + ly;
+    const bool own = lx >= 1 && ly >= 1 && gi <= nx && gj <= ny;
+    const int own_node = gi + sy * gj;
+
+    uint32_t voff[S::J];  // plane DMA: instruction j of wave w moves dword (4j + w) * 64 + lane of the slot
+#pragma unroll
+    for (int j = 0; j < S::J; ++j) {
+        const int f = (4 * j + w) * 64 + lane;
+        voff[j] = OOB;
+        if (f < S::NDW) {
+            const int row = f / S::ROWDW, c = f - row * S::ROWDW;
+            const int i = X0 + c / (3 * S::DW), jj = Y0 + row;
+            if (i >= 0 && i <= nx && jj >= 0 && jj <= ny) voff[j] = (uint32_t)(((X0 + sy * jj) * 3 * S::DW + c) * 4);
+        }
+    }
+    const int kfirst = Z0 - 1;
+    auto slot = [&](int g) { return (g - kfirst) % R; };
+    auto rslot = [&](int k) { return (k - kfirst) % RR; };
+    // node plane g with its fixity words (zeros outside 0..min(nz, Z1))
+    auto issue_plane = [&](int g) {
+        const bool in = g >= 0 && g <= Z1 && g <= nz;
+        const int gc = in ? g : 0;
+        const __amdgpu_buffer_rsrc_t ru = raw_rsrc(U + (size_t)gc * sz * 3, in ? plane_bytes : 0u);
+        uint32_t* dst = &ring[slot(g)][0] + w * 64;
+#pragma unroll
+        for (int j = 0; j < S::J; ++j) dma_dword(ru, voff[j], dst + 4 * j * 64);
+        if (w < 2) {
+            const __amdgpu_buffer_rsrc_t rm = raw_rsrc(Mt + (size_t)gc * NT, in ? NT * 2u : 0u);
+            dma_dword(rm, (uint32_t)(t * 4), reinterpret_cast<uint32_t*>(&mring[slot(g)][0]) + w * 64);
+        }
+    };
+    // densities of element layer k (zeros outside 0..min(nz, Z1) - 1)
+    auto issue_rho = [&](int k) {
+        const bool in = k >= 0 && k < Z1 && k < nz;
+        const __amdgpu_buffer_rsrc_t rr = raw_rsrc(Rt + (size_t)(in ? k : 0) * NT, in ? (uint32_t)(NT * sizeof(T)) : 0u);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&rring[rslot(k)][0]) + w * 64;
+#pragma unroll
+        for (int j = 0; j < S::DW; ++j) dma_dword(rr, (uint32_t)((j * NT + t) * 4), dst + 4 * j * 64);
+    };
+    auto mask_face = [&](int fm, T f[4][3]) {
+        if (__builtin_amdgcn_ballot_w64(fm != 0)) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if ((fm >> (3 * q + c)) & 1) f[q][c] = T(0);
+        }
+    };
+    const uint32_t face_off = (uint32_t)((ly * PX + lx) * 3 * sizeof(T));
+    const uint32_t ring_base = lds_off(&ring[0][0]) + face_off;
+    const uint32_t rring_base = lds_off(&rring[0][0]) + (uint32_t)(t * sizeof(T));
+    const uint32_t mring_base = lds_off(&mring[0][0]) + (uint32_t)(t * 2);
+    const uint32_t xch_base = lds_off(&xch[0][0][0]) + (uint32_t)(max(t - TX, 0) * sizeof(T));
+    const uint32_t xch_put = lds_off(&xch[0][0][0]) + (uint32_t)(t * sizeof(T));
+    constexpr uint32_t PLANE_B = SLOT * 4, RL_B = NT * sizeof(T), ML_B = NT * 2, XB_B = 3 * NT * sizeof(T);
+
+    // prologue: plane kfirst, then DIST batches (plane kfirst + 1 + d, densities kfirst + d)
+    issue_plane(kfirst);
+#pragma unroll
+    for (int d = 0; d < DIST; ++d) {
+        issue_plane(kfirst + 1 + d);
+        issue_rho(kfirst + d);
+    }
+    wait_vm_and_barrier<(DIST - 1) * NB>();  // plane kfirst and the first batch landed (read at layer kfirst)
+
+    // state carried from layer k - 1 to layer k, in two alternating sets (the
+    // loop below is unrolled by hand so that no registers are copied): the
+    // transformed bottom face and the top-face output of layer k - 1.  The
+    // unmasked own-node values of the bottom plane and their fixity bits are
+    // re-read from its ring slot, which is refilled only at the top of
+    // layer k + 1.
+    T bfA[4][3], ctA[4][3], bfB[4][3], ctB[4][3];
+    int fm0;
+    lds_face0<T>(ring_base + slot(kfirst) * PLANE_B, mring_base + slot(kfirst) * ML_B, bfA, fm0);
+    mask_face(fm0, bfA);
+    face_fwd<T>(bfA);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ctA[q][c] = T(0);
+    T pend[3] = {T(0), T(0), T(0)};   // plane k - 1 output of the own node before the y exchange
+    T pin[3] = {T(0), T(0), T(0)};    // DOT: the input at that node (zero where fixed)
+    int pend_m = 0;                   // and its fixity bits
+    double dot = 0.0;
+    // completes the own node of plane g (computed in layer g) with the
+    // contribution of the row below (fixed DOFs keep their input value)
+    auto finish = [&](int g) {
+        T xr[3], yv[3];
+        lds_xch(xch_base + (g & 1) * XB_B, xr);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) yv[c] = pend[c] + xr[c];
+        if (__builtin_amdgcn_ballot_w64(pend_m != 0)) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if ((pend_m >> c) & 1) yv[c] = pend[c];
+        }
+        T* y = Y + 3 * ((size_t)own_node + (size_t)sz * g);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            y[c] = yv[c];
+            if constexpr (DOT) dot += (double)pin[c] * (double)yv[c];
+        }
+    };
+
+    // element layer k: state in (bfc, ctc), state for layer k + 1 out to (bfn, ctn)
+    auto layer = [&](int k, const T (&bfc)[4][3], const T (&ctc)[4][3], T (&bfn)[4][3], T (&ctn)[4][3]) {
+        // plane k + 1 and densities k landed; every wave is done with layer k - 1
+        // (at k = kfirst: with the bottom face, whose slot is refilled next)
+        wait_vm_and_barrier<(DIST - 1) * NB>();
+        if (own && k - 1 >= Z0) finish(k - 1);  // plane k - 1, with the row below's exchange
+        issue_plane(k + 1 + DIST);  // into the slot of plane k - 1, done with before the barrier
+        issue_rho(k + DIST);        // into the slot of densities k - 1
+        T rho_k, rbc[3];
+        int fmt, mbc;
+        lds_face_own(ring_base + slot(k + 1) * PLANE_B, rring_base + rslot(k) * RL_B, mring_base + slot(k + 1) * ML_B,
+                     ring_base + slot(k) * PLANE_B, mring_base + slot(k) * ML_B, bfn, rho_k, fmt, rbc, mbc);
+        mbc &= 7;
+        mask_face(fmt, bfn);
+        face_fwd<T>(bfn);
+        T yb[4][3];
+        element_haar<T, CUB>(kh, rho_k, bfc, bfn, yb, ctn);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yb[q][c] += ctc[q][c];
+        face_inv<T>(yb);
+        const int xb = k & 1;
+        T up[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pend[c] = yb[0][c] + dpp_shr1(yb[1][c]);
+            up[c] = yb[2][c] + dpp_shr1(yb[3][c]);
+        }
+        lds_xch_put(xch_put + xb * XB_B, up[0], up[1], up[2]);
+        if (__builtin_amdgcn_ballot_w64(mbc != 0)) {  // identity rows of fixed DOFs: the input value
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if ((mbc >> c) & 1) pend[c] = rbc[c];
+        }
+        pend_m = mbc;
+        if constexpr (DOT) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pin[c] = ((mbc >> c) & 1) ? T(0) : rbc[c];
+        }
+    };
+    for (int k = kfirst;; k += 2) {
+        layer(k, bfA, ctA, bfB, ctB);
+        if (k + 1 >= Z1) break;
+        layer(k + 1, bfB, ctB, bfA, ctA);
+        if (k + 2 >= Z1) break;
+    }
+    wait_vm_and_barrier<0>();  // the trailing out-of-range batches too, before the LDS is released
+    if (own && Z1 - 1 >= Z0) finish(Z1 - 1);
+    if constexpr (DOT) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) dot += __shfl_down(dot, off, 64);
+        if (lane == 0) dred[w] = dot;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+            for (int q = 0; q < NT / 64; ++q) sum += dred[q];
+            P.partial[(rhs * 2 + 0) * P.npart + blockIdx.x] = sum;
+            P.partial[(rhs * 2 + 1) * P.npart + blockIdx.x] = 0.0;
+        }
+        if (blockIdx.x == 0)
+            for (int i = gridDim.x + t; i < P.npart; i += NT) {
+                P.partial[(rhs * 2 + 0) * P.npart + i] = 0.0;
+                P.partial[(rhs * 2 + 1) * P.npart + i] = 0.0;
+            }
+    }
+}
+
 int g_zc_override = -1;
 int g_variant = -1;
 
-// plain-apply kernel: 0 register staging, 2 / 3 the tile-major DMA kernel with
-// 1 / 2 layers per step (AFD_APPLY_KERNEL; the autotuner picks per mesh)
+// plain-apply kernel: 0 register staging; 2 / 3 the tile-major DMA kernel with
+// 1 / 2 layers per step; 4 / 6 the buffer-load kernel with a prefetch distance
+// of 2 / 1 layers (AFD_APPLY_KERNEL; the autotuner picks per mesh)
+bool valid_variant(int v) { return v == 0 || v == 2 || v == 3 || v == 4 || v == 6; }
 int apply_variant() {
     if (g_variant < 0) {
         const char* e = getenv("AFD_APPLY_KERNEL");
-        int v = e ? atoi(e) : 2;
-        if (v != 0 && v != 3) v = 2;
+        int v = e ? atoi(e) : 6;
+        if (!valid_variant(v)) v = 6;
         g_variant = v;
     }
     return g_variant;
+}
+// buffer-load kernels address a node plane with 32-bit byte offsets
+template <typename T>
+int usable_variant(int v, const Grid& g) {
+    if (v >= 4 && (int64_t)3 * (g.nx + 1) * (g.ny + 1) * (int64_t)sizeof(T) >= (int64_t)OOB) return 2;
+    return v;
 }
 
 template <typename T>
@@ -942,12 +1268,14 @@ int apply_occupancy(int variant) {
     switch (variant) {
         case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_matvec<T, APPLY, true>, NT, 0); break;
         case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 2>, NT, 0); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_bl<T, true, 2>, NT, 0); break;
+        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_bl<T, true, 1>, NT, 0); break;
         default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_apply_tm<T, true, 1>, NT, 0); break;
     }
     return (e == hipSuccess && n > 0) ? n : 0;
 }
 
-int g_slots[4][2];  // resident 256-thread workgroups per (apply variant, FP32) on this device, 0 = unknown
+int g_slots[8][2];  // resident 256-thread workgroups per (apply variant, FP32) on this device, 0 = unknown
 
 // z-chunking: as many chunks as fit in one round of resident workgroups of
 // the given kernel variant, so that no partly filled second round trails the
@@ -959,7 +1287,7 @@ void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, 
         const char* e = getenv("AFD_MATVEC_ZC");
         g_zc_override = e ? atoi(e) : 0;
     }
-    if (variant != 0 && variant != 2 && variant != 3) variant = apply_variant();
+    if (!valid_variant(variant)) variant = apply_variant();
     if (g_slots[variant][fp32] <= 0) {
         int dev = 0, cus = 256, per = fp32 ? 4 : 2;
         if (hipGetDevice(&dev) == hipSuccess)
@@ -995,7 +1323,7 @@ MvParams<T> base_params(const MatvecArgs& a, bool plain = false) {
     p.ny = a.g.ny;
     p.nz = a.g.nz;
     const int f = sizeof(T) == 4 ? 1 : 0;
-    p.variant = plain ? (a.apply_variant[f] >= 0 ? a.apply_variant[f] : apply_variant()) : 0;
+    p.variant = usable_variant<T>(plain ? (a.apply_variant[f] >= 0 ? a.apply_variant[f] : apply_variant()) : 0, a.g);
     tiling(a.g, f, plain ? p.variant : -1, plain ? a.apply_zc[f] : 0, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
     p.ndof = (int)a.g.ndof;
     if constexpr (sizeof(T) == 8) {
@@ -1025,6 +1353,14 @@ int launch(const MvParams<T>& p, const KeHaar& khd, int nrhs, hipStream_t s) {
             case 3:
                 if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 2>), grid, dim3(NT), 0, s, p, kh);
                 else hipLaunchKernelGGL((k_apply_tm<T, false, 2>), grid, dim3(NT), 0, s, p, kh);
+                break;
+            case 4:
+                if (cub) hipLaunchKernelGGL((k_apply_bl<T, true, 2>), grid, dim3(NT), 0, s, p, kh);
+                else hipLaunchKernelGGL((k_apply_bl<T, false, 2>), grid, dim3(NT), 0, s, p, kh);
+                break;
+            case 6:
+                if (cub) hipLaunchKernelGGL((k_apply_bl<T, true, 1>), grid, dim3(NT), 0, s, p, kh);
+                else hipLaunchKernelGGL((k_apply_bl<T, false, 1>), grid, dim3(NT), 0, s, p, kh);
                 break;
             default:
                 if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 1>), grid, dim3(NT), 0, s, p, kh);
@@ -1146,8 +1482,21 @@ int launch_dot_t(const MatvecArgs& a, const KeHaar& khd, const DcgArgs& d, int n
     }
     dim3 grid(p.tiles_x * p.tiles_y * p.nchunk, nrhs);
     const KH<T> kh = to_kh<T>(khd);
-    if (is_cubic(khd)) hipLaunchKernelGGL((k_apply_tm<T, true, 1, true>), grid, dim3(NT), 0, s, p, kh);
-    else hipLaunchKernelGGL((k_apply_tm<T, false, 1, true>), grid, dim3(NT), 0, s, p, kh);
+    const bool cub = is_cubic(khd);
+    switch (usable_variant<T>(apply_variant(), a.g)) {  // the staging of the default plain apply
+        case 4:
+            if (cub) hipLaunchKernelGGL((k_apply_bl<T, true, 2, true>), grid, dim3(NT), 0, s, p, kh);
+            else hipLaunchKernelGGL((k_apply_bl<T, false, 2, true>), grid, dim3(NT), 0, s, p, kh);
+            break;
+        case 6:
+            if (cub) hipLaunchKernelGGL((k_apply_bl<T, true, 1, true>), grid, dim3(NT), 0, s, p, kh);
+            else hipLaunchKernelGGL((k_apply_bl<T, false, 1, true>), grid, dim3(NT), 0, s, p, kh);
+            break;
+        default:
+            if (cub) hipLaunchKernelGGL((k_apply_tm<T, true, 1, true>), grid, dim3(NT), 0, s, p, kh);
+            else hipLaunchKernelGGL((k_apply_tm<T, false, 1, true>), grid, dim3(NT), 0, s, p, kh);
+            break;
+    }
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }

@@ -121,7 +121,8 @@ def test_apply_fp32_matches_oracle(ctx, dims):
         assert np.all(np.abs(Y[r] - want) <= bound)
 
 
-@pytest.mark.parametrize("variant,zc", [(0, 0), (0, 3), (2, 0), (2, 1), (2, 5), (3, 0), (3, 2), (3, 7)])
+@pytest.mark.parametrize("variant,zc", [(0, 0), (0, 3), (2, 0), (2, 1), (2, 5), (3, 0), (3, 2), (3, 7), (4, 0), (4, 1),
+                                        (4, 5), (6, 0), (6, 2), (6, 3), (6, 20)])
 @pytest.mark.parametrize("prec", [afdcg.AFD_FP64, afdcg.AFD_FP32])
 def test_apply_every_tuning_candidate_matches_oracle(ctx, variant, zc, prec):
     # every kernel variant / z chunk the autotuner may pick, on a ragged mesh
@@ -160,7 +161,7 @@ def test_autotune_keeps_results(ctx):
     Y0, Y1 = torch.empty_like(Ud), torch.empty_like(Ud)
     afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, Ud, Y0)
     rep = afdcg.afd_mesh_autotune(m, afdcg.AFD_FP64, 1)
-    assert rep.ncandidates >= 3 and rep.variant in (-1, 0, 2, 3) and rep.zc >= 0
+    assert rep.ncandidates >= 3 and rep.variant in (-1, 0, 2, 3, 4, 6) and rep.zc >= 0
     assert 0 < rep.us <= rep.default_us * 1.5
     afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, Ud, Y1)
     a, b = host(Y0), host(Y1)
@@ -380,7 +381,8 @@ def test_box_voxels_apply_and_solve(ctx):
     nd = 3 * wl.n_nodes(dims)
     U = np.random.default_rng(15).standard_normal((1, nd))
     for prec, eps, variant in [(afdcg.AFD_FP64, EPS64, -1), (afdcg.AFD_FP64, EPS64, 0), (afdcg.AFD_FP64, EPS64, 3),
-                               (afdcg.AFD_FP32, EPS32, -1), (afdcg.AFD_FP32, EPS32, 0)]:
+                               (afdcg.AFD_FP64, EPS64, 2), (afdcg.AFD_FP32, EPS32, -1), (afdcg.AFD_FP32, EPS32, 0),
+                               (afdcg.AFD_FP32, EPS32, 2)]:
         m = make_mesh(ctx, dims, rho, fixed, h=h, E=E, nu=nu)
         afdcg.afd_mesh_apply_config(m, prec, variant, 0)
         u = U.astype(np.float32).astype(np.float64) if prec == afdcg.AFD_FP32 else U
