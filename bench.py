@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per FP64 apply launch at 192x96x96 from rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by the
 # same counter on a 512 MiB copy (kernel as of the committed counter summary
 # profiles/apply_fp64_192x96x96_counters.md); None when not measured
-TRAFFIC_BYTES = None
+TRAFFIC_BYTES = 74_624_819 + 43_943_424
 
 
 # plain-apply kernel of each autotuner variant
@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--apply-only", action="store_true",
                     help="only a known-size copy and the timed applies (hardware-counter runs)")
+    ap.add_argument("--apply-config", default="-1:0",
+                    help="with --apply-only: variant:zc of the applies (-1:0 the default; no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -257,17 +259,12 @@ def main():
     afdcg.afd_mesh_set_scale(mesh, rho_d, p.nelem, afdcg.AFD_MEM_DEVICE)
     afdcg.afd_mesh_set_fixed(mesh, fix_d, p.ndof, afdcg.AFD_MEM_DEVICE)
     torch.cuda.synchronize()
-    # ---- apply execution picked by the autotuner on this mesh (outside the timed region)
-    tune = {}
-    for name, prec in (("fp64", afdcg.AFD_FP64), ("fp32", afdcg.AFD_FP32)):
-        r = afdcg.afd_mesh_autotune(mesh, prec, 1)
-        tune[name] = {"variant": r.variant, "zc": r.zc, "us": round(r.us, 2), "default_us": round(r.default_us, 2),
-                      "candidates": r.ncandidates}
-    print(f"# autotune: {json.dumps(tune)}", file=sys.stderr, flush=True)
-
     if args.apply_only:
-        # calibration copy of known size for FETCH_SIZE / WRITE_SIZE, then the applies
-        a = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
+        # counter runs time one fixed configuration (the autotuner's pick would
+        # vary from run to run under counter collection)
+        v, zc = (int(x) for x in args.apply_config.split(":"))
+        afdcg.afd_mesh_apply_config(mesh, afdcg.AFD_FP64, v, zc)
+        a = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB calibration copy
         b = torch.empty_like(a)
         b.copy_(a)
         u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
@@ -276,8 +273,16 @@ def main():
             afdcg.afd_apply_K(mesh, afdcg.AFD_FP64, 1, u, y)
         torch.cuda.synchronize()
         print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps,
-                          "apply_tuning": tune}), flush=True)
+                          "apply_config": {"variant": v, "zc": zc}}), flush=True)
         return
+
+    # ---- apply execution picked by the autotuner on this mesh (outside the timed region)
+    tune = {}
+    for name, prec in (("fp64", afdcg.AFD_FP64), ("fp32", afdcg.AFD_FP32)):
+        r = afdcg.afd_mesh_autotune(mesh, prec, 1)
+        tune[name] = {"variant": r.variant, "zc": r.zc, "us": round(r.us, 2), "default_us": round(r.default_us, 2),
+                      "candidates": r.ncandidates}
+    print(f"# autotune: {json.dumps(tune)}", file=sys.stderr, flush=True)
 
     # ---- operator apply throughput (HIP events on the library's stream)
     u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
@@ -366,8 +371,9 @@ def main():
         "apply_tuning": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     # counters were taken on the default kernel (buffer loads, prefetch distance 1)
-                     "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] in (-1, 6) else None,
+                     # counters were taken on the default configuration (buffer-load kernel,
+                     # prefetch distance 1, one-round z chunking)
+                     "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] == -1 else None,
                      "kernel": KERNEL_NAMES[tune["fp64"]["variant"]], "bytes_per_launch": alg},
     }
     secs = [x for x in args.sections.split(",") if x]
