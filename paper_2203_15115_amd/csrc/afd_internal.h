@@ -231,15 +231,24 @@ struct Coarse {
     double* gperm = nullptr; // [4][K*P]
     double* xperm = nullptr; // [4][K*P]
     double* cvec = nullptr;  // [4][K*P]
+    // FP32 copies of Linv, LinvT, T and U for the FP32 inner solves of the
+    // mixed form (made on demand after a factorisation; FP64 accumulation)
+    float* Linv32 = nullptr;
+    float* LinvT32 = nullptr;
+    float* T32 = nullptr;
+    float* U32 = nullptr;
     int dropped = 0;
     bool valid = false;
+    bool valid32 = false;
 };
 int coarse_alloc(Coarse& c, hipStream_t s);
 void coarse_free(Coarse& c);
 int coarse_begin(Coarse& c, hipStream_t s);
 int coarse_scatter_probe(Coarse& c, const double* G, int color, int mode, hipStream_t s);
 int coarse_factor(Coarse& c, hipStream_t s);
-int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s);
+int coarse_make_f32(Coarse& c, hipStream_t s);  // FP32 copies of the solve matrices (after coarse_factor)
+// mu = E^-1 g; f32: stream the FP32 copies (requires valid32), vectors and accumulation stay FP64
+int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, bool f32 = false);
 int coarse_to_dense_host(Coarse& c, double* E_host, hipStream_t s);  // before factor only
 
 // post.hip

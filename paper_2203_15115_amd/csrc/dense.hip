@@ -419,41 +419,66 @@ struct GemvIO {
     int mu_k;              // batch to scatter (-1: every batch)
     int qbase;             // ordered position of row 0 of batch 0
 };
-__global__ __launch_bounds__(256) void k_gemv(int P, const double* M, int64_t mstride, const double* x,
+// per-lane 16-byte loads of the streamed matrix: 2 FP64 or 4 FP32 elements
+template <typename TM>
+struct Lanes {
+    static constexpr int N = 16 / sizeof(TM);
+};
+__device__ __forceinline__ void load_lane(const double* p, double v[2]) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+}
+__device__ __forceinline__ void load_lane(const float* p, double v[4]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+}
+// TM: element type of the streamed matrix (FP64, or the FP32 copies); x, c,
+// y and the accumulation are FP64
+template <typename TM>
+__global__ __launch_bounds__(256) void k_gemv(int P, const TM* M, int64_t mstride, const double* x,
                                               int64_t xstride, const double* c, int64_t cstride, double alpha,
                                               double* y, int64_t ystride, int nrhs, int64_t vstride, int tri, int c0,
                                               int c1, GemvIO io) {
+    constexpr int N = Lanes<TM>::N;
     const int kb = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= P) return;
-    const double* m = M + kb * mstride + (int64_t)row * P;
+    const TM* m = M + kb * mstride + (int64_t)row * P;
     x += kb * xstride;
     double acc[4] = {0, 0, 0, 0};
     const int j0 = tri == 2 ? row : (tri == 1 ? 0 : c0);
     const int j1 = tri == 1 ? row + 1 : (tri == 2 ? P : c1);
     {
-        // aligned pairs (P, the block offsets and the vector strides are even),
-        // four 16-byte loads per lane in flight; pair members outside [j0, j1)
-        // count zero
-        for (int jj = (j0 & ~1) + 2 * lane; jj < j1; jj += 512) {
-            double2 mv[4];
+        // aligned groups of N (P, the block offsets and the vector strides are
+        // multiples of 4), four 16-byte loads per lane in flight; group members
+        // outside [j0, j1) count zero
+        for (int jj = (j0 & ~(N - 1)) + N * lane; jj < j1; jj += 256 * N) {
+            double mv[4][N];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int j = jj + 128 * u;
-                mv[u] = j < j1 ? *reinterpret_cast<const double2*>(m + j) : make_double2(0.0, 0.0);
-                if (j < j0) mv[u].x = 0.0;
-                if (j + 1 >= j1) mv[u].y = 0.0;
+                const int j = jj + 64 * N * u;
+                if (j < j1) load_lane(m + j, mv[u]);
+#pragma unroll
+                for (int e = 0; e < N; ++e)
+                    if (j >= j1 || j + e < j0 || j + e >= j1) mv[u][e] = 0.0;
             }
             for (int r = 0; r < nrhs; ++r) {
                 const double* xr = x + r * vstride;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int j = jj + 128 * u;
+                    const int j = jj + 64 * N * u;
                     if (j < j1) {
-                        const double2 xv = *reinterpret_cast<const double2*>(xr + j);
-                        acc[r] = fma(mv[u].x, xv.x, acc[r]);
-                        acc[r] = fma(mv[u].y, xv.y, acc[r]);
+#pragma unroll
+                        for (int e = 0; e < N; e += 2) {
+                            const double2 xv = *reinterpret_cast<const double2*>(xr + j + e);
+                            acc[r] = fma(mv[u][e], xv.x, acc[r]);
+                            acc[r] = fma(mv[u][e + 1], xv.y, acc[r]);
+                        }
                     }
                 }
             }
@@ -497,7 +522,8 @@ __global__ void k_count(const int32_t* a, int n, int32_t* out) {
     }
 }
 
-inline double* blkptr(double* base, int k, int P) { return base + (int64_t)k * P * P; }
+template <typename TM>
+inline TM* blkptr(TM* base, int k, int P) { return base + (int64_t)k * P * P; }
 
 }  // namespace
 
@@ -548,6 +574,13 @@ void coarse_free(Coarse& c) {
             (void)hipFree(*a);
             *a = nullptr;
         }
+    float** arrs32[] = {&c.Linv32, &c.LinvT32, &c.T32, &c.U32};
+    for (float** a : arrs32)
+        if (*a) {
+            (void)hipFree(*a);
+            *a = nullptr;
+        }
+    c.valid32 = false;
     if (c.dropped_dev) (void)hipFree(c.dropped_dev);
     if (c.perm) (void)hipFree(c.perm);
     if (c.iperm) (void)hipFree(c.iperm);
@@ -563,6 +596,34 @@ int coarse_begin(Coarse& c, hipStream_t s) {
     AFD_HIP_TRY(hipMemsetAsync(c.D, 0, PP * b.K * sizeof(double), s));
     AFD_HIP_TRY(hipMemsetAsync(c.B, 0, PP * b.K * sizeof(double), s));
     c.valid = false;
+    c.valid32 = false;
+    return AFD_OK;
+}
+
+__global__ void k_narrow(int64_t n, const double* a, float* b) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+int coarse_make_f32(Coarse& c, hipStream_t s) {
+    if (!c.valid) {
+        set_error("coarse: FP32 copy requested before the factorisation");
+        return AFD_E_INVALID_ARG;
+    }
+    if (c.valid32) return AFD_OK;
+    const Blocks& b = c.blk;
+    const int64_t n = (int64_t)b.P * b.P * b.K;
+    float** dst[] = {&c.Linv32, &c.LinvT32, &c.T32, &c.U32};
+    const double* src[] = {c.Linv, c.LinvT, c.T, c.U};
+    for (int i = 0; i < 4; ++i) {
+        if (!*dst[i] && hipMalloc((void**)dst[i], n * sizeof(float)) != hipSuccess) {
+            set_error("coarse: out of device memory for the FP32 copies");
+            return AFD_E_OOM;
+        }
+        hipLaunchKernelGGL(k_narrow, dim3(2048), dim3(256), 0, s, n, src[i], *dst[i]);
+    }
+    AFD_HIP_TRY(hipGetLastError());
+    c.valid32 = true;
     return AFD_OK;
 }
 
@@ -651,6 +712,7 @@ int coarse_factor(Coarse& c, hipStream_t s) {
     AFD_HIP_TRY(hipStreamSynchronize(s));
     c.dropped = nd;
     c.valid = true;
+    c.valid32 = false;
     if (nd >= b.ncoarse) {
         set_error("coarse: every pivot dropped");
         return AFD_E_COARSE_SINGULAR;
@@ -658,7 +720,9 @@ int coarse_factor(Coarse& c, hipStream_t s) {
     return AFD_OK;
 }
 
-int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s) {
+template <typename TM>
+int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, const TM* Linv, const TM* LinvT,
+                   const TM* T, const TM* U) {
     const Blocks& b = c.blk;
     const int P = b.P, K = b.K;
     const int64_t PP = (int64_t)P * P;
@@ -676,11 +740,11 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
     GemvIO in = none;
     in.y2 = c.xperm;
     in.dual_k = 0;
-    hipLaunchKernelGGL(k_gemv, dim3(rb, K), dim3(256), 0, s, P, c.Linv, PP, c.gperm, (int64_t)P,
+    hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, K), dim3(256), 0, s, P, Linv, PP, c.gperm, (int64_t)P,
                        (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 1, 0, P, in);
     // x_k = c_k - T_k x_{k-1}
     for (int k = 1; k < K; ++k)
-        hipLaunchKernelGGL(k_gemv, dim3(rb, 1), dim3(256), 0, s, P, blkptr(c.T, k, P), (int64_t)0,
+        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(T, k, P), (int64_t)0,
                            c.xperm + (int64_t)(k - 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
                            c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, P - w, P, none);
     // c'_k = Linv_k^T x_k, all k; mu_{K-1} = c'_{K-1} (kept and scattered)
@@ -689,7 +753,7 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
     last.dual_k = K - 1;
     last.mu = MU;
     last.mu_k = K - 1;
-    hipLaunchKernelGGL(k_gemv, dim3(rb, K), dim3(256), 0, s, P, c.LinvT, PP, c.xperm, (int64_t)P,
+    hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, K), dim3(256), 0, s, P, LinvT, PP, c.xperm, (int64_t)P,
                        (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 2, 0, P,
                        last);
     // mu_k = c'_k - U_k mu_{k+1}, scattered to natural order as produced
@@ -697,12 +761,23 @@ int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s
         GemvIO sc = none;
         sc.mu = MU;
         sc.qbase = k * P;
-        hipLaunchKernelGGL(k_gemv, dim3(rb, 1), dim3(256), 0, s, P, blkptr(c.U, k, P), (int64_t)0,
+        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(U, k, P), (int64_t)0,
                            c.gperm + (int64_t)(k + 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
                            c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, 0, w, sc);
     }
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
+}
+
+int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, bool f32) {
+    if (f32) {
+        if (!c.valid32) {
+            set_error("coarse: FP32 solve without the FP32 copies");
+            return AFD_E_INVALID_ARG;
+        }
+        return coarse_solve_t<float>(c, nrhs, G, MU, s, c.Linv32, c.LinvT32, c.T32, c.U32);
+    }
+    return coarse_solve_t<double>(c, nrhs, G, MU, s, c.Linv, c.LinvT, c.T, c.U);
 }
 
 int coarse_to_dense_host(Coarse& c, double* E, hipStream_t s) {
