@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per FP64 apply launch at 192x96x96 from rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by the
 # same counter on a 512 MiB copy (kernel as of the committed counter summary
 # profiles/apply_fp64_192x96x96_counters.md); None when not measured
-TRAFFIC_BYTES = 74_624_819 + 43_943_424
+TRAFFIC_BYTES = 74_631_168 + 43_918_438
 
 
 # plain-apply kernel of each autotuner variant
@@ -269,10 +269,10 @@ def main():
         b.copy_(a)
         u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
         y = torch.empty_like(u)
-        for _ in range(args.reps):
+        for _ in range(2000 + args.reps):  # 2000 warm-up launches (steady clocks), then the counted ones
             afdcg.afd_apply_K(mesh, afdcg.AFD_FP64, 1, u, y)
         torch.cuda.synchronize()
-        print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps,
+        print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps, "warmup": 2000,
                           "apply_config": {"variant": v, "zc": zc}}), flush=True)
         return
 
@@ -284,18 +284,57 @@ def main():
                       "candidates": r.ncandidates}
     print(f"# autotune: {json.dumps(tune)}", file=sys.stderr, flush=True)
 
-    # ---- operator apply throughput (HIP events on the library's stream)
+    # ---- operator apply throughput (HIP events on the library's stream).  The
+    # launches are recorded as a HIP graph of 20 applies and replayed, so the
+    # host's per-call cost (Python, ctypes) does not leave the GPU idle between
+    # kernels of ~30 us; one replay is checked against the eager result; after
+    # a warm-up of 10,000 applies the median of three timed batches of --reps
+    # applies is reported.
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_applies(prec, uu, yy):
+        for _ in range(10):
+            afdcg.afd_apply_K(mesh, prec, 1, uu, yy)
+        stream.synchronize()
+        ref = yy.clone()
+        per = 20
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                for _ in range(per):
+                    afdcg.afd_apply_K(mesh, prec, 1, uu, yy)
+            yy.zero_()
+            g.replay()
+            stream.synchronize()
+            assert torch.equal(yy, ref), "graph replay differs from the eager apply"
+            # the apply speeds up over the first few hundred launches of a
+            # process (35 -> 30 us measured): warm up for ~0.3 s of applies
+            for _ in range(500):
+                g.replay()
+            stream.synchronize()
+            nrep = max(1, args.reps // per)
+            batches = []
+            for _ in range(3):  # three timed batches; the median is reported
+                ev0.record(stream)
+                for _ in range(nrep):
+                    g.replay()
+                ev1.record(stream)
+                ev1.synchronize()
+                batches.append(ev0.elapsed_time(ev1) / 1e3 / (nrep * per))
+            print(f"# apply batches (us): {[round(b * 1e6, 2) for b in batches]}", file=sys.stderr, flush=True)
+            return sorted(batches)[1], "graph"
+        except RuntimeError as e:  # capture unavailable: eager launches
+            print(f"# apply timing without a graph: {e}", file=sys.stderr, flush=True)
+            ev0.record(stream)
+            for _ in range(args.reps):
+                afdcg.afd_apply_K(mesh, prec, 1, uu, yy)
+            ev1.record(stream)
+            ev1.synchronize()
+            return ev0.elapsed_time(ev1) / 1e3 / args.reps, "eager"
+
     u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
     y = torch.empty_like(u)
-    for _ in range(10):
-        afdcg.afd_apply_K(mesh, afdcg.AFD_FP64, 1, u, y)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.reps):
-        afdcg.afd_apply_K(mesh, afdcg.AFD_FP64, 1, u, y)
-    ev1.record(stream)
-    ev1.synchronize()
-    t_apply = ev0.elapsed_time(ev1) / 1e3 / args.reps
+    t_apply, apply_launch = time_applies(afdcg.AFD_FP64, u, y)
     gdofs = p.ndof / t_apply / 1e9
     alg = matvec_algorithmic_bytes(p.dims)
     achieved = alg / t_apply / 1e9
@@ -303,14 +342,7 @@ def main():
           file=sys.stderr, flush=True)
     # FP32 apply (inner operator of the mixed form)
     uf, yf = u.float(), torch.empty(p.ndof, dtype=torch.float32, device=dev)
-    for _ in range(10):
-        afdcg.afd_apply_K(mesh, afdcg.AFD_FP32, 1, uf, yf)
-    ev0.record(stream)
-    for _ in range(args.reps):
-        afdcg.afd_apply_K(mesh, afdcg.AFD_FP32, 1, uf, yf)
-    ev1.record(stream)
-    ev1.synchronize()
-    t_apply32 = ev0.elapsed_time(ev1) / 1e3 / args.reps
+    t_apply32, _ = time_applies(afdcg.AFD_FP32, uf, yf)
 
     # ---- full hot-path steps
     U = torch.empty_like(F_d)
@@ -366,6 +398,7 @@ def main():
         "iterations_s": round(st.t_iter, 4),
         "post_s": round(st.t_post, 4),
         "apply_us": round(t_apply * 1e6, 3),
+        "apply_launch": apply_launch,
         "apply_fp32_us": round(t_apply32 * 1e6, 3),
         "apply_fp32_gdofs": round(p.ndof / t_apply32 / 1e9, 3),
         "apply_tuning": tune,

@@ -732,6 +732,14 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
     };
     double best_us = 1e30, def_us = 0.0;
     int best_v = -1, best_zc = 0;
+    // the apply speeds up over the first few hundred launches of a process
+    // (clocks ramping under load): warm up with the default before timing
+    if (rc == AFD_OK) {
+        MatvecArgs a = mv_args(m);
+        a.apply_variant[f] = -1;
+        a.apply_zc[f] = 0;
+        for (int i = 0; rc == AFD_OK && i < 300; ++i) rc = launch_apply(a, m->kh, f, nrhs, U, Y, s);
+    }
     if (rc == AFD_OK) rc = time_of(-1, 0, &def_us);
     for (size_t i = 0; rc == AFD_OK && i < cands.size(); ++i) {
         double us = 0.0;
