@@ -980,8 +980,11 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
     std::vector<CgScalars> hsc(nrhs), hout(nrhs);
     int refinements = 0;
     if (!mixed) {
-        AFD_TRY(dcg_run<double>(m, nrhs, w.F, w.X, w.R, w.P0, w.P1, w.Q, w.Z, w.AZ, w.sc, o->rtol, o->max_iter, ce,
-                                nullptr));
+        // stop on the recursive residual at 0.99 rtol: it drifts from the true
+        // residual (checked at exit) by ~1e-5 relative on these meshes, and a
+        // true residual just above rtol was seen; the margin costs < 1 iteration
+        AFD_TRY(dcg_run<double>(m, nrhs, w.F, w.X, w.R, w.P0, w.P1, w.Q, w.Z, w.AZ, w.sc, 0.99 * o->rtol, o->max_iter,
+                                ce, nullptr));
         AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), w.sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     } else {
         // FP64 iterative refinement around an FP32 deflated PCG, whose coarse
