@@ -41,26 +41,35 @@ __device__ __forceinline__ void haar_fwd(double v[8][3]) {
 
 // S[f][e] = rho_e * u_e^T Ke v_e = rho_e * (T u_e)^T Khat (T v_e)
 __global__ void k_sensitivity(SensP p, const double* rho, double* S) {
-    const int64_t nE = (int64_t)p.nx * p.ny * p.nz;
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // 32-bit element and node indices (the host checks n_elem and n_node < 2^31)
+    const int nE = p.nx * p.ny * p.nz;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nE) return;
-    const int ex = (int)(e % p.nx), ey = (int)((e / p.nx) % p.ny), ez = (int)(e / ((int64_t)p.nx * p.ny));
-    const int64_t sy = p.nx + 1, sz = (int64_t)(p.nx + 1) * (p.ny + 1);
-    int64_t nd[8];
+    const int ex = e % p.nx, exy = e / p.nx, ey = exy % p.ny, ez = exy / p.ny;
+    const int sy = p.nx + 1, sz = (p.nx + 1) * (p.ny + 1);
+    int nd[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) nd[a] = (ex + (a & 1)) + sy * (ey + ((a >> 1) & 1)) + sz * (ez + (a >> 2));
     const double r = rho[e];
-    for (int f = 0; f < p.nfields; ++f) {
-        double u[8][3], v[8][3];
+    auto gather = [&](const double* x, double w[8][3]) {
 #pragma unroll
         for (int a = 0; a < 8; ++a)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                u[a][c] = p.ua[f][3 * nd[a] + c];
-                v[a][c] = p.ub[f][3 * nd[a] + c];
-            }
+            for (int c = 0; c < 3; ++c) w[a][c] = x[3 * (int64_t)nd[a] + c];
+    };
+    for (int f = 0; f < p.nfields; ++f) {
+        double u[8][3], v[8][3];
+        gather(p.ua[f], u);
         haar_fwd(u);
-        haar_fwd(v);
+        if (p.ub[f] == p.ua[f]) {  // self energy: one gather and one transform
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[a][c] = u[a][c];
+        } else {
+            gather(p.ub[f], v);
+            haar_fwd(v);
+        }
         double s = 0.0;
 #pragma unroll
         for (int al = 1; al < 8; ++al)
@@ -199,6 +208,10 @@ int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int n
                        const double* const* Ub, double* S, hipStream_t s) {
     if (nfields < 1 || nfields > MAXF) {
         set_error("sensitivity: 1..16 fields");
+        return AFD_E_INVALID_ARG;
+    }
+    if (g.nelem >= ((int64_t)1 << 31) || g.nnode >= ((int64_t)1 << 31)) {
+        set_error("sensitivity: more than 2^31 elements or nodes");
         return AFD_E_INVALID_ARG;
     }
     SensP p;
