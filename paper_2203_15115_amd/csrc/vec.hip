@@ -203,6 +203,23 @@ __device__ __forceinline__ void block_range(const BlkP& p, int ax, int bb, int& 
     hi = (bb == p.nb[ax] - 1) ? n : lo + p.b[ax] - 1;
 }
 
+// block of node n (32-bit node index) and the node's position relative to the
+// block centre, scaled by inv_scale
+__device__ __forceinline__ void node_block(const BlkP& p, int n, int bb[3], double x[3]) {
+    const int sx = p.nx + 1, sxy = (p.nx + 1) * (p.ny + 1);
+    const int k = n / sxy, rem = n - k * sxy, j = rem / sx, i = rem - j * sx;
+    const int pp[3] = {i, j, k};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int q = pp[a] / p.b[a];
+        if (q > p.nb[a] - 1) q = p.nb[a] - 1;
+        int lo, hi;
+        block_range(p, a, q, lo, hi);
+        bb[a] = q;
+        x[a] = (pp[a] - 0.5 * (lo + hi)) * p.inv_scale;
+    }
+}
+
 // G[r][6*blk+m] = sum over free DOFs of block blk of w_m . V[r]  (one workgroup per block)
 // G = W^T (V - V2) (V2 optional)
 template <typename T>
@@ -254,23 +271,12 @@ __global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, co
 template <typename T>
 __global__ void k_prolong(BlkP p, const uint8_t* nm, int nrhs, int64_t nnode, const double* MU, T* V,
                           int color, int mode) {
-    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;  // 3 nnode < 2^31 (checked at mesh creation)
     if (n >= nnode) return;
     const int r = blockIdx.y;
-    const int i = (int)(n % (p.nx + 1));
-    const int j = (int)((n / (p.nx + 1)) % (p.ny + 1));
-    const int k = (int)(n / ((int64_t)(p.nx + 1) * (p.ny + 1)));
-    const int pp[3] = {i, j, k};
     int bb[3];
     double x[3];
-    for (int a = 0; a < 3; ++a) {
-        int q = pp[a] / p.b[a];
-        if (q > p.nb[a] - 1) q = p.nb[a] - 1;
-        int lo, hi;
-        block_range(p, a, q, lo, hi);
-        bb[a] = q;
-        x[a] = (pp[a] - 0.5 * (lo + hi)) * p.inv_scale;
-    }
+    node_block(p, n, bb, x);
     const uint8_t mk = nm[n];
     double m[6];
     if (color >= 0) {
@@ -280,7 +286,7 @@ __global__ void k_prolong(BlkP p, const uint8_t* nm, int nrhs, int64_t nnode, co
         const double* mu = MU + (int64_t)r * p.ncoarse + 6 * (bb[0] + p.nb[0] * (bb[1] + p.nb[1] * bb[2]));
         for (int a = 0; a < 6; ++a) m[a] = mu[a];
     }
-    T* v = V + (int64_t)r * 3 * nnode + 3 * n;
+    T* v = V + (int64_t)r * 3 * nnode + 3 * (int64_t)n;
     v[0] = (mk & 1) ? T(0) : (T)(m[0] + m[4] * x[2] - m[5] * x[1]);
     v[1] = (mk & 2) ? T(0) : (T)(m[1] - m[3] * x[2] + m[5] * x[0]);
     v[2] = (mk & 4) ? T(0) : (T)(m[2] + m[3] * x[1] - m[4] * x[0]);
@@ -294,37 +300,27 @@ __global__ void k_form_dir(BlkP p, const uint8_t* nm, int64_t nnode, const CgSca
                            double kd2, T* Pnew) {
     const int r = blockIdx.y;
     if (sc[r].done) return;
-    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;  // 3 nnode < 2^31 (checked at mesh creation)
     if (n >= nnode) return;
     const double beta = sc[r].beta;
     double w[3] = {0.0, 0.0, 0.0};
     if (MU) {
-        const int i = (int)(n % (p.nx + 1));
-        const int j = (int)((n / (p.nx + 1)) % (p.ny + 1));
-        const int k = (int)(n / ((int64_t)(p.nx + 1) * (p.ny + 1)));
-        const int pp[3] = {i, j, k};
         int bb[3];
         double x[3];
-        for (int a = 0; a < 3; ++a) {
-            int q = pp[a] / p.b[a];
-            if (q > p.nb[a] - 1) q = p.nb[a] - 1;
-            int lo, hi;
-            block_range(p, a, q, lo, hi);
-            bb[a] = q;
-            x[a] = (pp[a] - 0.5 * (lo + hi)) * p.inv_scale;
-        }
+        node_block(p, n, bb, x);
         const double* m = MU + (int64_t)r * p.ncoarse + 6 * (bb[0] + p.nb[0] * (bb[1] + p.nb[1] * bb[2]));
         w[0] = m[0] + m[4] * x[2] - m[5] * x[1];
         w[1] = m[1] - m[3] * x[2] + m[5] * x[0];
         w[2] = m[2] + m[3] * x[1] - m[4] * x[0];
     }
     const double ri = rinv ? rinv[n] : (double)rinv32[n];
-    const double kd[3] = {kd0, kd1, kd2};
+    // M^-1 r formed exactly as in k_cg_update and k_precond
+    const double ikd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
     const uint8_t mk = nm[n];
-    const int64_t o = (int64_t)r * 3 * nnode + 3 * n;
+    const int64_t o = (int64_t)r * 3 * nnode + 3 * (int64_t)n;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double v = beta * (double)Pold[o + c] + ri / kd[c] * (double)R[o + c] - w[c];
+        const double v = beta * (double)Pold[o + c] + ri * ikd[c] * (double)R[o + c] - w[c];
         Pnew[o + c] = ((mk >> c) & 1) ? T(0) : (T)v;
     }
 }
