@@ -235,12 +235,33 @@ int gemm_split(int M, int N, int K, double alpha, const double* A, int lda, int 
 __global__ __launch_bounds__(256) void k_potrf_tile(double* A, double* Linv, int P, int j0, int nb,
                                                     const double* ediag, int32_t* dropped) {
     static_assert(NB == 64, "the register layout assumes 64 x 64 tiles and 256 threads");
-    __shared__ double colc[NB];  // column c of L below the pivot
-    __shared__ double rowc[NB];  // row c of X
-    __shared__ double pinv_s;
+    // Right-looking Cholesky of the tile and, alongside, the forward
+    // substitution L X = I, written to be nearly free of divergent branches
+    // (the tile factorisation is a chain of 64 dependent steps; branches and
+    // barriers set its pace).  Thread (r, q0) owns row r of L and of X at
+    // columns q0 + 4 i.  The pivot loop is rolled over 16 groups of 4
+    // (unrolled) pivots; within group g the L registers are shifted so that
+    // column q0 + 4 (g + i) sits in Lr[i].  Each step reads the not yet
+    // scaled column c of L and row c of X from LDS (double buffered,
+    // published at the end of the previous step: one barrier per pivot):
+    //  * rows above the pivot get a zero row factor, so their updates are
+    //    no-ops; only Lr[0] needs a mask (its column may be <= c);
+    //  * the column buffer is padded with zeros to 2 NB entries and the X row
+    //    is zero beyond column c, so the updates read fixed offsets;
+    //  * entries above the diagonal of L take garbage updates but are never
+    //    published or stored;
+    //  * threads that do not own the published column store to a slot of
+    //    their own.
+    __shared__ double ucol[2][2 * NB];  // column c of the partly factored tile, rows >= c, not scaled
+    __shared__ double urow[2][NB];      // row c of X, not scaled (zero beyond column c)
+    __shared__ double dummy[256];
+    __shared__ double ed[NB];           // diagonal of E (drop test)
     __shared__ int drop[NB];
     const int t = threadIdx.x;
-    const int r = t >> 2, q0 = t & 3;  // thread owns L[r][q0 + 4i] and X[r][q0 + 4i], i < 16
+    const int r = t >> 2, q0 = t & 3;
+    for (int i = t; i < 2 * 2 * NB; i += 256) (&ucol[0][0])[i] = 0.0;
+    for (int i = t; i < 2 * NB; i += 256) (&urow[0][0])[i] = 0.0;
+    __syncthreads();
     double Lr[16], Xr[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -249,54 +270,57 @@ __global__ __launch_bounds__(256) void k_potrf_tile(double* A, double* Linv, int
         Lr[i] = (r < nb && q <= r) ? A[(int64_t)(j0 + r) * P + j0 + q] : (r == q ? 1.0 : 0.0);
         Xr[i] = (r == q) ? 1.0 : 0.0;
     }
-    const double edr = r < nb ? ediag[j0 + r] : 1.0;
-    // right-looking Cholesky, and alongside it the forward substitution
-    // L X = I: once column c of L is final, row c of X is scaled by the pivot
-    // and eliminated from the rows below
+    if (t < NB) ed[t] = t < nb ? ediag[j0 + t] : 1.0;
+    if (q0 == 0) ucol[0][r] = Lr[0];
+    if (t == 0) urow[0][0] = 1.0;
+    for (int g = 0; g < NB / 4; ++g) {
+        const int cb = q0 + 4 * g;  // column of Lr[0]
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        const int ic = c >> 2, qc = c & 3;
-        if (r == c && q0 == qc) {
-            const double d = Lr[ic];
-            const bool dr = !(edr > 0.0) || !(d > DROP_TOL * edr);
-            const double pv = dr ? 1.0 : sqrt(d);
-            Lr[ic] = pv;
-            pinv_s = 1.0 / pv;
-            drop[c] = dr ? 1 : 0;
-        }
-        __syncthreads();
-        const double pi = pinv_s;
-        const int dr = drop[c];
-        if (q0 == qc && r > c) {
-            Lr[ic] = dr ? 0.0 : Lr[ic] * pi;
-            colc[r] = Lr[ic];
-        }
-        if (r == c) {
+        for (int qc = 0; qc < 4; ++qc) {
+            const int c = 4 * g + qc, b = qc & 1;
+            __syncthreads();
+            const double d = ucol[b][c];
+            const double edc = ed[c];
+            const bool dr = !(edc > 0.0) || !(d > DROP_TOL * edc);
+            const double id = dr ? 0.0 : 1.0 / d;
+            const double f = r > c ? ucol[b][r] * id : 0.0;
+            const double* uc = &ucol[b][cb];
+            const double* ur = &urow[b][q0];
+            Lr[0] = fma(q0 > qc ? -f : 0.0, uc[0], Lr[0]);
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (q0 + 4 * i <= c) {
-                    Xr[i] *= pi;
-                    rowc[q0 + 4 * i] = Xr[i];
+            for (int i = 1; i < 16; ++i) Lr[i] = fma(-f, uc[4 * i], Lr[i]);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Xr[i] = fma(-f, ur[4 * i], Xr[i]);
+            // publish column c + 1 and row c + 1 of X for the next step
+            if (c + 1 < NB) {
+                const bool own = q0 == ((qc + 1) & 3) && r > c;
+                *(own ? &ucol[b ^ 1][r] : &dummy[t]) = qc == 3 ? Lr[1] : Lr[0];
+                if (r == c + 1) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) urow[b ^ 1][q0 + 4 * i] = Xr[i];
                 }
-        }
-        __syncthreads();
-        if (r > c) {
-            const double lrc = colc[r];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int q = q0 + 4 * i;
-                if (q > c && q <= r) Lr[i] -= lrc * colc[q];
-                else if (q <= c) Xr[i] -= lrc * rowc[q];
             }
+            // column c of L and row c of X are final once scaled
+            const double pv = dr ? 1.0 : sqrt(d);
+            const double pi = 1.0 / pv;
+            if (q0 == qc) Lr[0] = r > c ? (dr ? 0.0 : Lr[0] * pi) : (r == c ? pv : Lr[0]);
+            if (r == c) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) Xr[i] *= pi;
+            }
+            drop[c] = dr ? 1 : 0;  // every thread stores the same value
         }
+        // column cb of L is final: store it and shift the rest down
+        if (r < nb && cb <= r) A[(int64_t)(j0 + r) * P + j0 + cb] = Lr[0];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) Lr[i] = Lr[i + 1];
+        Lr[15] = 0.0;
     }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int q = q0 + 4 * i;
-        if (r < nb && q <= r) {
-            A[(int64_t)(j0 + r) * P + j0 + q] = Lr[i];
-            Linv[(int64_t)(j0 + r) * P + j0 + q] = (drop[r] || drop[q]) ? 0.0 : Xr[i];
-        }
+        if (r < nb && q <= r) Linv[(int64_t)(j0 + r) * P + j0 + q] = (drop[r] || drop[q]) ? 0.0 : Xr[i];
     }
     if (t < nb) dropped[j0 + t] = drop[t];
 }
