@@ -18,6 +18,15 @@
 // Modes: APPLY (Y = A U), RESID (R = F - A X, with partial sums of r.M^-1 r and
 // r.r) and DIR (the deflated CG direction P' = beta P + M^-1 R - W mu formed
 // while staging, Q = A P', partial sums of p'.q).
+//
+// Kernels (same tiles, element arithmetic and summation order):
+//  * k_matvec: register-staged planes, every mode (the residual and fused
+//    direction forms, and apply variant 0);
+//  * k_apply_tm: plain apply with tile-major densities and fixity words and
+//    every input staged by global_load_lds DMA (variants 2 and 3);
+//  * k_apply_bl: the same staging by untyped buffer loads, out-of-range lanes
+//    reading zero, with partial vmcnt waits (variants 4 and 6; 6 is the
+//    default plain apply, and its DOT form is the solver's direction apply).
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
