@@ -220,11 +220,13 @@ __device__ __forceinline__ void node_block(const BlkP& p, int n, int bb[3], doub
     }
 }
 
-// G[r][6*blk+m] = sum over free DOFs of block blk of w_m . V[r]  (one workgroup per block)
-// G = W^T (V - V2) (V2 optional)
+// G[r][6*blk+m] = sum over free DOFs of block blk of w_m . V[r]; G = W^T (V - V2)
+// (V2 optional).  One wavefront per block (a block has 512-729 nodes), so the
+// six sums reduce with shuffles in a fixed order and no barriers.
+constexpr int RWG = 64;
 template <typename T>
-__global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, const T* V, const T* V2, double* G) {
-    __shared__ double sh[WG / 64];
+__global__ __launch_bounds__(RWG) void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, const T* V,
+                                                  const T* V2, double* G) {
     const int blk = blockIdx.x;
     const int bi = blk % p.nb[0], bj = (blk / p.nb[0]) % p.nb[1], bk = blk / (p.nb[0] * p.nb[1]);
     int lo[3], hi[3];
@@ -238,7 +240,7 @@ __global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, co
         const T* v = V + r * ndof;
         const T* v2 = V2 ? V2 + r * ndof : nullptr;
         double m[6] = {0, 0, 0, 0, 0, 0};
-        for (int q = threadIdx.x; q < cnt; q += WG) {
+        for (int q = threadIdx.x; q < cnt; q += RWG) {
             const int i = lo[0] + q % ex, j = lo[1] + (q / ex) % ey, k = lo[2] + q / (ex * ey);
             const int64_t n = i + (int64_t)(p.nx + 1) * (j + (int64_t)(p.ny + 1) * k);
             const uint8_t mk = nm[n];
@@ -259,8 +261,11 @@ __global__ void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, co
             m[4] += z * u0 - x * u2;
             m[5] += -y * u0 + x * u1;
         }
+#pragma unroll
         for (int a = 0; a < 6; ++a) {
-            double s = wg_reduce(m[a], sh);
+            double s = m[a];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) s += __shfl_down(s, off, 64);
             if (threadIdx.x == 0) G[(int64_t)r * p.ncoarse + 6 * blk + a] = s;
         }
     }
@@ -493,7 +498,7 @@ int launch_cg_update_f32(const Grid& g, const KeHaar& kh, const float* rinv32, C
 
 int launch_restrict(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V, double* G,
                     hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
+    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
                        (const double*)nullptr, G);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
@@ -551,21 +556,21 @@ int launch_fill_f32(int64_t n, float v, float* a, hipStream_t s) {
 
 int launch_restrict_diff(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V,
                          const double* V2, double* G, hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
+    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
 
 int launch_restrict_diff_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V,
                              const float* V2, double* G, hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
+    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
 
 int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V, double* G,
                         hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(WG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
+    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
                        (const float*)nullptr, G);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
