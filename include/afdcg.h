@@ -222,7 +222,10 @@ int afd_threshold(afd_context* ctx, const double* s, int64_t n, double vol_frac,
 
 /* ---- the whole solve ---------------------------------------------------- */
 /* Solves A U[r] = F[r] for r < nrhs (1..4) by deflated Jacobi-PCG (Sec. 3.5),
- * FP64 or FP32-inner/FP64-refined per opts->precision, then writes the
+ * FP64 or FP32-inner/FP64-refined per opts->precision (the coarse factor is
+ * computed in FP64; the iterations apply it from FP32 copies with FP64
+ * vectors and accumulation, environment AFD_COARSE_F32=0 keeps FP64; the
+ * stopping test and the reported true residual are FP64), then writes the
  * compliances J[r] = F[r].U[r] (Eq. 1.3) and, if S != NULL, the energy fields
  * of afd_sensitivity (opts->pairs).  F, U, J, S are host or device per
  * opts->mem_kind.  F must be zero on fixed DOFs (AFD_E_INVALID_ARG

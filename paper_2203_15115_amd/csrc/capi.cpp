@@ -110,7 +110,9 @@ bool dir_fused() {
     return g_dir_fused == 1;
 }
 
-// FP32 coarse factor in the inner solves of the mixed form (AFD_COARSE_F32=0 disables)
+// The deflated iterations (FP64 and the FP32 inner solves of the mixed form)
+// stream FP32 copies of the coarse solve matrices, with FP64 vectors and
+// accumulation (AFD_COARSE_F32=0: the FP64 factor)
 int g_coarse_f32 = -1;
 bool coarse_f32_enabled() {
     if (g_coarse_f32 < 0) {
@@ -310,7 +312,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     if (m->deflate) {
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
         else AFD_TRY(launch_restrict_f32(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
-        AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, f32 && m->coarse.valid32));
+        AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, m->coarse.valid32));
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_prolong(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
         else AFD_TRY(launch_prolong_f32(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
     } else {
@@ -334,7 +336,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             AFD_TRY(launch_apply(a, m->kh, 1, nrhs, Z, AZ, s));
             AFD_TRY(launch_restrict_diff_f32(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s));
         }
-        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, f32 && m->coarse.valid32);
+        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, m->coarse.valid32);
     };
     // p' = beta p + M^-1 r - W mu (Pnew), then q = A p' with the p'.q partials;
     // AFD_DIR_FUSED=1 selects the single fused register-staged kernel instead
@@ -394,7 +396,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             (uintptr_t)c.LinvT, (uintptr_t)c.T, (uintptr_t)c.U, (uintptr_t)c.perm, (uintptr_t)c.iperm,
             (uintptr_t)c.gperm, (uintptr_t)c.xperm, (uintptr_t)c.cvec, (uintptr_t)c.blk.P, (uintptr_t)c.blk.K,
             (uintptr_t)c.Linv32, (uintptr_t)c.LinvT32, (uintptr_t)c.T32, (uintptr_t)c.U32,
-            (uintptr_t)(f32 && c.valid32),
+            (uintptr_t)c.valid32,
             (uintptr_t)(m->tune_variant[0] + 8), (uintptr_t)(m->tune_variant[1] + 8), (uintptr_t)m->tune_zc[0],
             (uintptr_t)m->tune_zc[1]};
         if (!gr.exec || gr.key != key) {
@@ -656,7 +658,7 @@ int afd_mesh_footprint(const afd_mesh* m, int32_t nrhs, int32_t precision, uint6
     if (m->deflate) {
         const uint64_t PP = (uint64_t)m->blk.P * m->blk.P;
         b += PP * m->blk.K * 8 * 6 + PP * 8 + (uint64_t)m->blk.K * m->blk.P * 8 * 14;
-        if (precision == AFD_MIXED) b += PP * m->blk.K * 4 * 4;         // FP32 copies of the solve matrices
+        b += PP * m->blk.K * 4 * 4;                                     // FP32 copies of the solve matrices
     }
     b += (uint64_t)m->npartM * 64 + VEC_NPART * 64;
     *bytes = b;
@@ -979,6 +981,9 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
     const int ce = o->check_every > 0 ? o->check_every : 16;
     std::vector<CgScalars> hsc(nrhs), hout(nrhs);
     int refinements = 0;
+    // FP32 copies of the coarse solve matrices for the iterations (made once per
+    // factorisation; without memory for them the FP64 factor is used)
+    if (m->deflate && coarse_f32_enabled() && coarse_make_f32(m->coarse, s) != AFD_OK) clear_error();
     if (!mixed) {
         // stop on the recursive residual at 0.99 rtol: it drifts from the true
         // residual (checked at exit) by ~1e-5 relative on these meshes, and a
@@ -987,10 +992,7 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
                                 ce, nullptr));
         AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), w.sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     } else {
-        // FP64 iterative refinement around an FP32 deflated PCG, whose coarse
-        // solves stream FP32 copies of the factor (AFD_COARSE_F32=0: the FP64
-        // factor); without memory for the copies the FP64 factor is used
-        if (m->deflate && coarse_f32_enabled() && coarse_make_f32(m->coarse, s) != AFD_OK) clear_error();
+        // FP64 iterative refinement around an FP32 deflated PCG
         MatvecArgs a = mv_args(m);
         const int max_ref = o->max_refine > 0 ? o->max_refine : 30;
         const double inner = (o->inner_rtol > 0 && o->inner_rtol < 1) ? o->inner_rtol : 1e-4;

@@ -93,7 +93,7 @@ uint64_t footprint_of(const afd_mesh_desc& d, int nrhs, int precision) {
         const int P = afd::choose_coarse_P(nc, w);
         const int K = (nc + P - 1) / P;
         b += (uint64_t)P * P * K * 8 * 6 + (uint64_t)P * P * 8 + (uint64_t)K * P * 8 * 14;
-        if (precision == AFD_MIXED) b += (uint64_t)P * P * K * 4 * 4;  // FP32 copies of the solve matrices
+        b += (uint64_t)P * P * K * 4 * 4;                             // FP32 copies of the solve matrices
     }
     (void)nrhs;
     return b + (64ull << 20);  // partials, radix scratch, allocator slack
