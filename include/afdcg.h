@@ -56,7 +56,8 @@ extern "C" {
 
 #define AFD_FP64  0   /* FP64 throughout                                         */
 #define AFD_MIXED 1   /* FP32 inner deflated PCG under FP64 iterative refinement */
-#define AFD_FP32  2   /* afd_apply_K only: FP32 vectors and FP32 arithmetic      */
+#define AFD_FP32  2   /* afd_apply_K, autotuner: FP32 vectors and arithmetic;     *
+                       * afd_mesh_coarse_precision: FP32 coarse solve matrices   */
 
 typedef struct afd_context afd_context;
 typedef struct afd_mesh afd_mesh;
@@ -176,6 +177,14 @@ int afd_mesh_autotune(afd_mesh* mesh, int32_t precision, int32_t nrhs, afd_tune_
  * -1 the default; zc node planes per z chunk, 0 the default.  Returns
  * AFD_E_INVALID_ARG for other values. */
 int afd_mesh_apply_config(afd_mesh* mesh, int32_t precision, int32_t variant, int32_t zc);
+/* Element type of the coarse solve matrices the deflated iterations of
+ * afd_solve stream (Sec. 3.5's coarse problem W^T K W, always factored in
+ * FP64): AFD_FP32 (the default unless the environment sets AFD_COARSE_F32=0)
+ * uses FP32 copies made once per factorisation, with FP64 vectors and
+ * accumulation (half the bytes per coarse solve; the coarse correction is
+ * then exact to ~1e-7 relative, the stopping test and the true residual stay
+ * FP64); AFD_FP64 streams the FP64 factor.  AFD_E_INVALID_ARG otherwise. */
+int afd_mesh_coarse_precision(afd_mesh* mesh, int32_t precision);
 
 /* Jacobi diagonal of A (Sec. 3.5: preconditioner formed assembly-free):
  * d[3n+c] = Ke_cc * sum of rho over the elements touching node n for a free

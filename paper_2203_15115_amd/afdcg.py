@@ -36,6 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVALID_ARG", -2: "E_NO_DEVICE", -
 
 EXPORTED = [
     "afd_context_create", "afd_context_destroy", "afd_last_error", "afd_context_sync", "afd_context_use_graphs",
+    "afd_mesh_coarse_precision",
     "afd_mesh_create", "afd_mesh_destroy", "afd_mesh_sizes", "afd_mesh_set_scale", "afd_mesh_set_fixed",
     "afd_mesh_footprint", "afd_mesh_ke", "afd_apply_K", "afd_apply_K_mfma", "afd_mesh_autotune", "afd_mesh_apply_config",
     "afd_jacobi",
@@ -97,6 +98,7 @@ def lib():
             "afd_last_error": (C.c_char_p, []),
             "afd_context_sync": (C.c_int, [vp]),
             "afd_context_use_graphs": (C.c_int, [vp, i32]),
+            "afd_mesh_coarse_precision": (C.c_int, [vp, i32]),
             "afd_mesh_create": (C.c_int, [vp, C.POINTER(afd_mesh_desc), C.POINTER(vp)]),
             "afd_mesh_destroy": (None, [vp]),
             "afd_mesh_sizes": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
@@ -177,6 +179,10 @@ def afd_context_sync(ctx):
 
 def afd_context_use_graphs(ctx, enable):
     check(lib().afd_context_use_graphs(ctx, 1 if enable else 0), "afd_context_use_graphs")
+
+
+def afd_mesh_coarse_precision(mesh, precision):
+    check(lib().afd_mesh_coarse_precision(mesh, int(precision)), "afd_mesh_coarse_precision")
 
 
 def afd_mesh_create(ctx, dims, h=(1.0, 1.0, 1.0), E=1.0, nu=0.3, block=(0, 0, 0)):

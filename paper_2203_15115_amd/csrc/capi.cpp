@@ -92,6 +92,7 @@ struct afd_mesh {
     bool jacobi_valid = false;
     bool any_fixed = false;
     IterGraph graphs[2];             // recorded iteration chunks (FP64 solve, FP32 inner solve)
+    int coarse_f32 = -1;             // coarse solve matrices streamed in FP32 (1) or FP64 (0); -1: default
     int tune_variant[2] = {-1, -1};  // autotuned plain-apply kernel per precision (FP64, FP32)
     int tune_zc[2] = {0, 0};
     Coarse coarse;
@@ -122,6 +123,7 @@ bool coarse_f32_enabled() {
     return g_coarse_f32 == 1;
 }
 void clear_error() { g_err.clear(); }
+bool use_coarse_f32(const afd_mesh* m) { return m->coarse_f32 < 0 ? coarse_f32_enabled() : m->coarse_f32 == 1; }
 
 int check_ctx(afd_context* c) {
     if (!c) {
@@ -312,7 +314,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     if (m->deflate) {
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
         else AFD_TRY(launch_restrict_f32(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
-        AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, m->coarse.valid32));
+        AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32));
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_prolong(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
         else AFD_TRY(launch_prolong_f32(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
     } else {
@@ -336,7 +338,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             AFD_TRY(launch_apply(a, m->kh, 1, nrhs, Z, AZ, s));
             AFD_TRY(launch_restrict_diff_f32(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s));
         }
-        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, m->coarse.valid32);
+        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32);
     };
     // p' = beta p + M^-1 r - W mu (Pnew), then q = A p' with the p'.q partials;
     // AFD_DIR_FUSED=1 selects the single fused register-staged kernel instead
@@ -396,7 +398,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             (uintptr_t)c.LinvT, (uintptr_t)c.T, (uintptr_t)c.U, (uintptr_t)c.perm, (uintptr_t)c.iperm,
             (uintptr_t)c.gperm, (uintptr_t)c.xperm, (uintptr_t)c.cvec, (uintptr_t)c.blk.P, (uintptr_t)c.blk.K,
             (uintptr_t)c.Linv32, (uintptr_t)c.LinvT32, (uintptr_t)c.T32, (uintptr_t)c.U32,
-            (uintptr_t)c.valid32,
+            (uintptr_t)(use_coarse_f32(m) && c.valid32),
             (uintptr_t)(m->tune_variant[0] + 8), (uintptr_t)(m->tune_variant[1] + 8), (uintptr_t)m->tune_zc[0],
             (uintptr_t)m->tune_zc[1]};
         if (!gr.exec || gr.key != key) {
@@ -788,6 +790,15 @@ int afd_mesh_apply_config(afd_mesh* m, int32_t precision, int32_t variant, int32
     return AFD_OK;
 }
 
+int afd_mesh_coarse_precision(afd_mesh* m, int32_t precision) {
+    if (!m || (precision != AFD_FP64 && precision != AFD_FP32)) {
+        set_error("coarse_precision: AFD_FP64 or AFD_FP32");
+        return AFD_E_INVALID_ARG;
+    }
+    m->coarse_f32 = precision == AFD_FP32 ? 1 : 0;
+    return AFD_OK;
+}
+
 int afd_apply_K(afd_mesh* m, int32_t precision, int32_t nrhs, const void* U, void* Y) {
     if (!m || !U || !Y || nrhs < 1 || nrhs > 4 || (precision != AFD_FP64 && precision != AFD_FP32)) {
         set_error("apply_K: bad argument (nrhs 1..4, precision FP64 or FP32)");
@@ -983,7 +994,7 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
     int refinements = 0;
     // FP32 copies of the coarse solve matrices for the iterations (made once per
     // factorisation; without memory for them the FP64 factor is used)
-    if (m->deflate && coarse_f32_enabled() && coarse_make_f32(m->coarse, s) != AFD_OK) clear_error();
+    if (m->deflate && use_coarse_f32(m) && coarse_make_f32(m->coarse, s) != AFD_OK) clear_error();
     if (!mixed) {
         // stop on the recursive residual at 0.99 rtol: it drifts from the true
         // residual (checked at exit) by ~1e-5 relative on these meshes, and a

@@ -370,6 +370,31 @@ def test_solve_several_superblocks_matches_direct(ctx, c0_direct, coarse_P):
     assert np.linalg.norm(U[0] - ud) / np.linalg.norm(ud) <= 1e-6
 
 
+def test_coarse_precision_fp32_and_fp64_agree(ctx, c0_direct):
+    # the deflated iterations stream FP32 copies of the coarse solve matrices by
+    # default; with the FP64 factor the same solve needs about as many
+    # iterations and both reach the direct solution
+    p, K, ud = c0_direct
+    p2 = wl.Problem(p.dims, p.rho, p.fixed, p.F, (2, 2, 2))
+    res = {}
+    for cp in (afdcg.AFD_FP64, afdcg.AFD_FP32):
+        m = make_mesh(ctx, p2.dims, p2.rho, p2.fixed, block=p2.block)
+        afdcg.afd_mesh_coarse_precision(m, cp)
+        U = np.zeros((1, p2.ndof))
+        J = np.zeros(1)
+        opts = afdcg.make_opts(rtol=1e-12, max_iter=20000, precision=afdcg.AFD_FP64)
+        code, st = afdcg.afd_solve(m, opts, 1, np.ascontiguousarray(p2.F[:1]), U, J, None)
+        assert code == afdcg.AFD_OK and st[0].rel_residual_true <= 1e-12, (cp, st[0].rel_residual_true)
+        res[cp] = (U[0].copy(), st[0].iterations)
+        with pytest.raises(afdcg.AfdError):
+            afdcg.afd_mesh_coarse_precision(m, afdcg.AFD_MIXED)
+        afdcg.afd_mesh_destroy(m)
+    for cp, (u, it) in res.items():
+        assert np.linalg.norm(u - ud) / np.linalg.norm(ud) <= 1e-8, cp
+    it64, it32 = res[afdcg.AFD_FP64][1], res[afdcg.AFD_FP32][1]
+    assert it32 <= 1.1 * it64 + 2, (it64, it32)
+
+
 def test_box_voxels_apply_and_solve(ctx):
     # non-cubic voxels take the general Haar coefficients (51 values)
     dims, h, E, nu = (19, 9, 8), (1.0, 2.0, 0.5), 2.5, 0.27
