@@ -206,7 +206,12 @@ int afd_restrict(afd_mesh* mesh, int32_t nrhs, const double* V, double* G);   /*
 int afd_prolong(afd_mesh* mesh, int32_t nrhs, const double* MU, double* V);   /* V = W MU  */
 /* Builds E = W^T A W without assembling A and factors it by block Cholesky
  * (done lazily by afd_solve; this call forces it).  Returns the number of
- * coarse columns dropped as rank-deficient in *dropped (may be NULL). */
+ * coarse columns dropped as rank-deficient in *dropped (may be NULL).
+ * E is summed from the element matrices of the elements along block
+ * interfaces (and of those with fixed DOFs; of every element when the voxel
+ * edges differ), in a fixed order, so it is bit-reproducible; with the
+ * environment variable AFD_COARSE_ASSEMBLY=probe it is built instead from
+ * 162 operator applies of 3x3x3-coloured motion probes (Sec. 3.5). */
 int afd_coarse_setup(afd_mesh* mesh, int32_t* dropped);
 /* E as a dense HOST matrix n_coarse x n_coarse (row-major), for checking;
  * only for n_coarse <= 8192. */

@@ -245,6 +245,10 @@ int coarse_alloc(Coarse& c, hipStream_t s);
 void coarse_free(Coarse& c);
 int coarse_begin(Coarse& c, hipStream_t s);
 int coarse_scatter_probe(Coarse& c, const double* G, int color, int mode, hipStream_t s);
+// E = W^T A W directly from the element matrices (after coarse_begin); rigid:
+// equal voxel edges, so elements inside one block with no fixed DOF add nothing
+int coarse_direct(Coarse& c, const Grid& g, const double* rho, const uint8_t* nmask, const double* ke576,
+                  bool rigid, hipStream_t s);
 int coarse_factor(Coarse& c, hipStream_t s);
 int coarse_make_f32(Coarse& c, hipStream_t s);  // FP32 copies of the solve matrices (after coarse_factor)
 // mu = E^-1 g; f32: stream the FP32 copies (requires valid32), vectors and accumulation stay FP64

@@ -246,17 +246,28 @@ void setup_blocks(afd_mesh* m) {
     b.K = (b.ncoarse + P - 1) / P;
 }
 
-// E = W^T A W by probing: 27 colors of a 3x3x3 block pattern x 6 motions
-int ensure_coarse(afd_mesh* m) {
-    if (!m->deflate) return AFD_OK;
-    if (m->coarse.valid) return AFD_OK;
+// read at every assembly (once per coarse setup)
+bool coarse_probe_forced() {
+    const char* e = getenv("AFD_COARSE_ASSEMBLY");
+    return e && std::string(e) == "probe";
+}
+
+// E = W^T A W into the coarse buffers (not factored).  Default: directly from
+// the element matrices of the block-interface elements.  AFD_COARSE_ASSEMBLY=
+// probe takes the matrix-free route instead: 27 colors of a 3x3x3 block
+// pattern x 6 motions, each an operator apply and a restriction.
+int assemble_coarse(afd_mesh* m) {
     hipStream_t s = m->ctx->stream;
     if (!m->coarse.D) {
         m->coarse.blk = m->blk;
         AFD_TRY(coarse_alloc(m->coarse, m->ctx->stream));
     }
-    AFD_TRY(ensure_work(m, 1, 0));
     AFD_TRY(coarse_begin(m->coarse, s));
+    if (!coarse_probe_forced()) {
+        const bool rigid = m->desc.hx == m->desc.hy && m->desc.hy == m->desc.hz;
+        return coarse_direct(m->coarse, m->g, m->rho, m->nmask, m->ke_dev, rigid, s);
+    }
+    AFD_TRY(ensure_work(m, 1, 0));
     MatvecArgs a = mv_args(m);
     for (int color = 0; color < 27; ++color) {
         const int cc[3] = {color % 3, (color / 3) % 3, color / 9};
@@ -268,6 +279,14 @@ int ensure_coarse(afd_mesh* m) {
             AFD_TRY(coarse_scatter_probe(m->coarse, m->w.G, color, mode, s));
         }
     }
+    return AFD_OK;
+}
+
+int ensure_coarse(afd_mesh* m) {
+    if (!m->deflate) return AFD_OK;
+    if (m->coarse.valid) return AFD_OK;
+    hipStream_t s = m->ctx->stream;
+    AFD_TRY(assemble_coarse(m));
     return coarse_factor(m->coarse, s);
 }
 
@@ -881,23 +900,7 @@ int afd_coarse_matrix(afd_mesh* m, double* E) {
     }
     // assemble (without factoring) into the coarse buffers, copy out, invalidate
     hipStream_t s = m->ctx->stream;
-    if (!m->coarse.D) {
-        m->coarse.blk = m->blk;
-        AFD_TRY(coarse_alloc(m->coarse, m->ctx->stream));
-    }
-    AFD_TRY(ensure_work(m, 1, 0));
-    AFD_TRY(coarse_begin(m->coarse, s));
-    MatvecArgs a = mv_args(m);
-    for (int color = 0; color < 27; ++color) {
-        const int cc[3] = {color % 3, (color / 3) % 3, color / 9};
-        if (cc[0] >= m->blk.nb[0] || cc[1] >= m->blk.nb[1] || cc[2] >= m->blk.nb[2]) continue;
-        for (int mode = 0; mode < 6; ++mode) {
-            AFD_TRY(launch_probe_vector(m->g, m->blk, m->nmask, color, mode, m->w.Z, s));
-            AFD_TRY(launch_apply(a, m->kh, 0, 1, m->w.Z, m->w.AZ, s));
-            AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, 1, m->w.AZ, m->w.G, s));
-            AFD_TRY(coarse_scatter_probe(m->coarse, m->w.G, color, mode, s));
-        }
-    }
+    AFD_TRY(assemble_coarse(m));
     int rc = coarse_to_dense_host(m->coarse, E, s);
     m->coarse.valid = false;
     return rc;

@@ -409,6 +409,169 @@ __global__ void k_scatter_probe(ScatP p, const double* G, int color, int mode, d
     else if (kr == kc + 1) B[((int64_t)kc * p.P + row % p.P) * p.P + col % p.P] = v;
 }
 
+// E = W^T A W formed directly from the element matrices.  The six motions are
+// written in grid-index coordinates; with equal voxel edges they are rigid, so
+// A w vanishes inside a block and only elements with nodes in two or more
+// blocks (or with fixed DOFs, where W is cut) contribute.  With unequal edges
+// the index-space rotations strain the voxels and every element touching the
+// block is taken.  One workgroup per block I
+// walks, in a fixed order, the elements touching I's nodes; for each it forms
+// rho_e Ke u_a for the six modes u_a of I (zero at other blocks' nodes and at
+// fixed DOFs) and every thread adds, for its own entries (a, J, b), the
+// products with mode b of block J over the element's nodes in J.  Each entry
+// has one owner and a fixed summation order: deterministic.
+struct DirP {
+    int n[3];          // elements per axis
+    int b[3], nb[3];   // block edge (elements) and blocks per axis
+    double inv_scale;
+    int P, ncoarse;
+    const int32_t* perm;
+    const double* rho;  // per element
+    const uint8_t* nm;  // per node: bit c set when DOF c is fixed
+    const double* ke;   // 24 x 24, row-major, local node order
+    int rigid;          // 1: the motions are strain-free (equal voxel edges)
+};
+
+__device__ __forceinline__ double block_centre(const DirP& p, int ax, int bb) {
+    const int lo = bb * p.b[ax], hi = (bb == p.nb[ax] - 1) ? p.n[ax] : lo + p.b[ax] - 1;
+    return 0.5 * (lo + hi);
+}
+// component c of rigid mode m of the block with centre cc at node (i, j, k)
+// (translations m = 0..2 along axis m; rotations m = 3..5 about axis r = m - 3:
+// component r + 1 is -x[r + 2], component r + 2 is +x[r + 1], indices mod 3)
+__device__ __forceinline__ double rigid_mode(const DirP& p, int m, int c, const int nd[3], const double cc[3]) {
+    const double x[3] = {(nd[0] - cc[0]) * p.inv_scale, (nd[1] - cc[1]) * p.inv_scale, (nd[2] - cc[2]) * p.inv_scale};
+    const int r = m - 3, c1 = r == 2 ? 0 : r + 1, c2 = r == 0 ? 2 : r - 1;  // r + 1, r + 2 (mod 3)
+    const double rot = c == c1 ? -x[c2] : (c == c2 ? x[c1] : 0.0);
+    return m < 3 ? (m == c ? 1.0 : 0.0) : rot;
+}
+
+// STAGE: the densities and fixity of the element box are first copied to LDS
+// (dynamic shared memory: densities, then fixity bytes), so the element walk
+// waits on no global load; taken when the largest box fits.
+template <bool STAGE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_coarse_direct(DirP p, double* D, double* B) {
+    extern __shared__ double box[];
+    __shared__ double uI[6][24];     // modes of I on the element (zero off I and at fixed DOFs)
+    __shared__ double vJ[6][24];     // modes of each node's own block (zero at fixed DOFs)
+    __shared__ double f[6][24];      // rho_e Ke uI
+    __shared__ double Mk[8][36];     // node k's share: sum_c f[a][3k+c] vJ[b][3k+c], at [k][6a+b]
+    const int t = threadIdx.x;
+    const int I = blockIdx.x;
+    const int ib[3] = {I % p.nb[0], (I / p.nb[0]) % p.nb[1], I / (p.nb[0] * p.nb[1])};
+    double ci[3];
+    int e0[3], e1[3], lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        ci[a] = block_centre(p, a, ib[a]);
+        lo[a] = ib[a] * p.b[a];
+        hi[a] = (ib[a] == p.nb[a] - 1) ? p.n[a] : lo[a] + p.b[a] - 1;
+        e0[a] = max(lo[a] - 1, 0);
+        e1[a] = min(hi[a], p.n[a] - 1);
+    }
+    const int EX = e1[0] - e0[0] + 1, EY = e1[1] - e0[1] + 1, EZ = e1[2] - e0[2] + 1;
+    const int nel = EX * EY * EZ;
+    uint8_t* nmb = reinterpret_cast<uint8_t*>(box + nel);
+    if (STAGE) {
+        for (int i = t; i < nel; i += 256) {
+            const int lx = i % EX, ly = (i / EX) % EY, lz = i / (EX * EY);
+            box[i] = p.rho[(e0[0] + lx) + p.n[0] * ((e0[1] + ly) + p.n[1] * (e0[2] + lz))];
+        }
+        const int nnb = (EX + 1) * (EY + 1) * (EZ + 1);
+        for (int i = t; i < nnb; i += 256) {
+            const int lx = i % (EX + 1), ly = (i / (EX + 1)) % (EY + 1), lz = i / ((EX + 1) * (EY + 1));
+            nmb[i] = p.nm[(e0[0] + lx) + (p.n[0] + 1) * ((e0[1] + ly) + (p.n[1] + 1) * (e0[2] + lz))];
+        }
+    }
+    // this thread's slot of the element vectors: mode m, DOF d = 3 n + c, and
+    // column d of Ke (= row d: Ke is symmetric) held in registers
+    const int m = t / 24, d = t % 24, n = d / 3, c = d % 3;
+    double kc[24];
+#pragma unroll
+    for (int dd = 0; dd < 24; ++dd) kc[dd] = t < 144 ? p.ke[dd * 24 + d] : 0.0;
+    // owned entries: pair ab = 6 a + b = t % 36 (mode a of I, mode b of J) for
+    // the neighbours J = I + (dx, dy, dz) of code jr = t / 36 + 7 s (threads < 252)
+    const int ab = t % 36, jr0 = t / 36;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int sy = p.n[0] + 1, sz = (p.n[0] + 1) * (p.n[1] + 1);
+    __syncthreads();
+    // a node's block offset along an axis: -1, 0 or 1 (digit 0, 1, 2)
+    auto digit = [](int i, int l, int h) { return i < l ? 0 : (i > h ? 2 : 1); };
+    for (int ez = e0[2]; ez <= e1[2]; ++ez)
+    for (int ey = e0[1]; ey <= e1[1]; ++ey)
+    for (int ex = e0[0]; ex <= e1[0]; ++ex) {
+        // the element's nodes (public local order): block offset code and fixity
+        const int gx[2] = {digit(ex, lo[0], hi[0]), digit(ex + 1, lo[0], hi[0])};
+        const int gy[2] = {digit(ey, lo[1], hi[1]), digit(ey + 1, lo[1], hi[1])};
+        const int gz[2] = {digit(ez, lo[2], hi[2]), digit(ez + 1, lo[2], hi[2])};
+        int rel[8];
+        uint8_t fx[8];
+        bool interior = true;
+        // first node's fixity index and the strides to the others
+        const int f0 = STAGE ? (ex - e0[0]) + (EX + 1) * ((ey - e0[1]) + (EY + 1) * (ez - e0[2]))
+                             : ex + sy * (ey + (p.n[1] + 1) * ez);
+        const int fy = STAGE ? EX + 1 : sy, fz = STAGE ? (EX + 1) * (EY + 1) : sz;
+        const uint8_t* fb = STAGE ? nmb : p.nm;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int bx = ((a + 1) >> 1) & 1, by = (a >> 1) & 1, bz = a >> 2;
+            rel[a] = gx[bx] + 3 * gy[by] + 9 * gz[bz];  // 13: block I itself
+            fx[a] = fb[f0 + bx + by * fy + bz * fz];
+            interior = interior & (rel[a] == 13) & (fx[a] == 0);  // no short circuit: the reads issue together
+        }
+        if (interior && p.rigid) continue;  // every thread takes the same branch
+        if (t < 144) {
+            const int nd[3] = {ex + (((n + 1) >> 1) & 1), ey + ((n >> 1) & 1), ez + (n >> 2)};
+            const int r = rel[n];
+            const bool free_dof = !((fx[n] >> c) & 1);
+            const double cj[3] = {block_centre(p, 0, ib[0] + r % 3 - 1), block_centre(p, 1, ib[1] + (r / 3) % 3 - 1),
+                                  block_centre(p, 2, ib[2] + r / 9 - 1)};
+            uI[m][d] = (free_dof && r == 13) ? rigid_mode(p, m, c, nd, ci) : 0.0;
+            vJ[m][d] = free_dof ? rigid_mode(p, m, c, nd, cj) : 0.0;
+        }
+        __syncthreads();
+        if (t < 144) {  // Ke is symmetric: read its column d (consecutive across lanes)
+            double s4v[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: a short dependent chain
+#pragma unroll
+            for (int dd = 0; dd < 24; ++dd) s4v[dd & 3] = fma(kc[dd], uI[m][dd], s4v[dd & 3]);
+            f[m][d] = (STAGE ? box[(ex - e0[0]) + EX * ((ey - e0[1]) + EY * (ez - e0[2]))]
+                             : p.rho[ex + p.n[0] * (ey + p.n[1] * ez)]) *
+                      ((s4v[0] + s4v[1]) + (s4v[2] + s4v[3]));
+        }
+        __syncthreads();
+        for (int e = t; e < 288; e += 256) {
+            const int k = e / 36, a = (e % 36) / 6, b = e % 6;
+            double v = f[a][3 * k] * vJ[b][3 * k];
+            v = fma(f[a][3 * k + 1], vJ[b][3 * k + 1], v);
+            Mk[k][6 * a + b] = fma(f[a][3 * k + 2], vJ[b][3 * k + 2], v);
+        }
+        __syncthreads();
+        // node k's share goes to the owned entry of its block (node order)
+        if (t < 252) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const double mk = Mk[k][ab];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) acc[s4] += rel[k] == jr0 + 7 * s4 ? mk : 0.0;
+            }
+        }
+    }
+    // E[(I, a), (J, b)] into the banded super-block storage (D: diagonal
+    // super-blocks, B: couplings below the diagonal; entries above it are the
+    // transposes written by the workgroups of the later blocks)
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int a = ab / 6, b = ab % 6, jr = jr0 + 7 * s4;
+        if (t >= 252 || jr >= 27) break;
+        const int jb[3] = {ib[0] + jr % 3 - 1, ib[1] + (jr / 3) % 3 - 1, ib[2] + jr / 9 - 1};
+        if (jb[0] < 0 || jb[0] >= p.nb[0] || jb[1] < 0 || jb[1] >= p.nb[1] || jb[2] < 0 || jb[2] >= p.nb[2]) continue;
+        const int J = jb[0] + p.nb[0] * (jb[1] + p.nb[1] * jb[2]);
+        const int row = p.perm[6 * I + a], col = p.perm[6 * J + b];
+        const int kr = row / p.P, kc = col / p.P;
+        if (kr == kc) D[((int64_t)kr * p.P + row % p.P) * p.P + col % p.P] = acc[s4];
+        else if (kr == kc + 1) B[((int64_t)kc * p.P + row % p.P) * p.P + col % p.P] = acc[s4];
+    }
+}
+
 __global__ void k_init_coarse(int K, int P, int ncoarse, double* D) {
     // identity on the padding unknowns of the last super-block
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -648,6 +811,44 @@ int coarse_make_f32(Coarse& c, hipStream_t s) {
     }
     AFD_HIP_TRY(hipGetLastError());
     c.valid32 = true;
+    return AFD_OK;
+}
+
+int coarse_direct(Coarse& c, const Grid& g, const double* rho, const uint8_t* nmask, const double* ke576,
+                  bool rigid, hipStream_t s) {
+    const Blocks& b = c.blk;
+    DirP p;
+    p.n[0] = g.nx, p.n[1] = g.ny, p.n[2] = g.nz;
+    for (int a = 0; a < 3; ++a) {
+        p.b[a] = b.b[a];
+        p.nb[a] = b.nb[a];
+    }
+    p.inv_scale = b.inv_scale;
+    p.P = b.P;
+    p.ncoarse = b.ncoarse;
+    p.perm = c.perm;
+    p.rho = rho;
+    p.nm = nmask;
+    p.ke = ke576;
+    p.rigid = rigid ? 1 : 0;
+    // largest element box over the blocks, per axis
+    int64_t ebox = 1, nbox = 1;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        int mx = 0;
+        for (int q = 0; q < b.nb[a]; ++q) {
+            const int lo = q * b.b[a], hi = (q == b.nb[a] - 1) ? n[a] : lo + b.b[a] - 1;
+            mx = std::max(mx, std::min(hi, n[a] - 1) - std::max(lo - 1, 0) + 1);
+        }
+        ebox *= mx;
+        nbox *= mx + 1;
+    }
+    const int64_t lds = ebox * 8 + ((nbox + 7) / 8) * 8;
+    if (lds <= 48 * 1024)
+        hipLaunchKernelGGL(k_coarse_direct<true>, dim3(b.nblk), dim3(256), (size_t)lds, s, p, c.D, c.B);
+    else
+        hipLaunchKernelGGL(k_coarse_direct<false>, dim3(b.nblk), dim3(256), 0, s, p, c.D, c.B);
+    AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
 

@@ -325,6 +325,41 @@ def test_coarse_matrix_and_solve(ctx, dims, block):
         assert np.linalg.norm(mu[r] - want) <= 1e-9 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("dims,block,h", [((10, 7, 6), (4, 3, 4), (1.0, 1.0, 1.0)),
+                                          ((12, 8, 8), (4, 4, 4), (0.5, 0.5, 0.5)),
+                                          ((9, 6, 5), (4, 3, 2), (1.0, 2.0, 0.5)),
+                                          ((24, 22, 21), (20, 20, 20), (1.0, 1.0, 1.0))])
+def test_coarse_direct_assembly_scattered_fixity(ctx, monkeypatch, dims, block, h):
+    # E is formed from the element matrices of the interface elements; with
+    # single fixed DOFs inside blocks (W is cut there) the interior elements
+    # contribute too, and with unequal voxel edges (the grid-index rotations
+    # then strain the voxels) every element does.  Oracle E and the matrix-free
+    # probing route agree with it.  The 20^3 blocks are too large for the LDS
+    # copy of the element box: the kernel then reads densities and fixity from
+    # global memory.
+    rho, fixed = rand_problem(dims, 21, fixed_frac=0.08)
+    K = fem.assemble(dims, rho, fem.ke_gauss(h, 1.0, 0.3))
+    Eo, _ = solvers.coarse_matrix(K, fixed, dims, block)
+    nc = Eo.shape[0]
+    got = {}
+    for route in ("direct", "probe"):
+        monkeypatch.setenv("AFD_COARSE_ASSEMBLY", route)
+        m = make_mesh(ctx, dims, rho, fixed, block=block, h=h)
+        E = np.zeros((nc, nc))
+        afdcg.afd_coarse_matrix(m, E)
+        afdcg.afd_mesh_destroy(m)
+        got[route] = E
+        assert np.max(np.abs(E - Eo)) <= 1e-12 * np.max(np.abs(Eo)), route
+    assert np.max(np.abs(got["direct"] - got["probe"])) <= 1e-12 * np.max(np.abs(Eo))
+    # deterministic: a second assembly is bit-identical
+    monkeypatch.setenv("AFD_COARSE_ASSEMBLY", "direct")
+    m = make_mesh(ctx, dims, rho, fixed, block=block, h=h)
+    E2 = np.zeros((nc, nc))
+    afdcg.afd_coarse_matrix(m, E2)
+    afdcg.afd_mesh_destroy(m)
+    assert np.array_equal(E2, got["direct"])
+
+
 @pytest.fixture
 def coarse_P(monkeypatch):
     # the super-block size is read at mesh creation; forcing a small one gives
@@ -384,7 +419,9 @@ def test_coarse_precision_fp32_and_fp64_agree(ctx, c0_direct):
         J = np.zeros(1)
         opts = afdcg.make_opts(rtol=1e-12, max_iter=20000, precision=afdcg.AFD_FP64)
         code, st = afdcg.afd_solve(m, opts, 1, np.ascontiguousarray(p2.F[:1]), U, J, None)
-        assert code == afdcg.AFD_OK and st[0].rel_residual_true <= 1e-12, (cp, st[0].rel_residual_true)
+        # the iteration stops on its recursive residual; at 1e-12 the true FP64
+        # residual sits near the attainable accuracy and may end a few percent above
+        assert code == afdcg.AFD_OK and st[0].rel_residual_true <= 1.1e-12, (cp, st[0].rel_residual_true)
         res[cp] = (U[0].copy(), st[0].iterations)
         with pytest.raises(afdcg.AfdError):
             afdcg.afd_mesh_coarse_precision(m, afdcg.AFD_MIXED)
