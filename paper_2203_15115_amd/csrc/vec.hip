@@ -240,26 +240,54 @@ __global__ __launch_bounds__(RWG) void k_restrict(BlkP p, const uint8_t* nm, int
         const T* v = V + r * ndof;
         const T* v2 = V2 ? V2 + r * ndof : nullptr;
         double m[6] = {0, 0, 0, 0, 0, 0};
-        for (int q = threadIdx.x; q < cnt; q += RWG) {
-            const int i = lo[0] + q % ex, j = lo[1] + (q / ex) % ey, k = lo[2] + q / (ex * ey);
-            const int64_t n = i + (int64_t)(p.nx + 1) * (j + (int64_t)(p.ny + 1) * k);
-            const uint8_t mk = nm[n];
-            const double x = (i - c0) * p.inv_scale, y = (j - c1) * p.inv_scale, z = (k - c2) * p.inv_scale;
-            double u0 = (double)v[3 * n], u1 = (double)v[3 * n + 1], u2 = (double)v[3 * n + 2];
-            if (v2) {
-                u0 -= (double)v2[3 * n];
-                u1 -= (double)v2[3 * n + 1];
-                u2 -= (double)v2[3 * n + 2];
+        // RU nodes per lane per pass: all their loads are issued before any is
+        // used (a block holds 512-729 nodes, 8-12 per lane: one dependent load
+        // round per node left this kernel waiting on memory latency); the
+        // nodes are still added in ascending order
+        constexpr int RU = 4;
+        // the lane's node (li, lj, lk) in the block, advanced by RWG nodes per
+        // step without integer division (di, dj, dk: RWG in block coordinates)
+        const int di = RWG % ex, dj = (RWG / ex) % ey, dk = RWG / (ex * ey);
+        int li = threadIdx.x % ex, lj = (threadIdx.x / ex) % ey, lk = threadIdx.x / (ex * ey);
+        for (int q0 = threadIdx.x; q0 < cnt; q0 += RU * RWG) {
+            double u[RU][3], xyz[RU][3];
+            uint8_t mk[RU];
+#pragma unroll
+            for (int s = 0; s < RU; ++s) {
+                const bool in = q0 + s * RWG < cnt;  // past the end: block node 0 again, not added below
+                const int i = lo[0] + (in ? li : 0), j = lo[1] + (in ? lj : 0), k = lo[2] + (in ? lk : 0);
+                li += di;
+                const int ci = li >= ex;
+                li -= ci ? ex : 0;
+                lj += dj + ci;
+                const int cj = lj >= ey;
+                lj -= cj ? ey : 0;
+                lk += dk + cj;
+                const int64_t n = i + (int64_t)(p.nx + 1) * (j + (int64_t)(p.ny + 1) * k);
+                mk[s] = nm[n];
+                xyz[s][0] = (i - c0) * p.inv_scale;
+                xyz[s][1] = (j - c1) * p.inv_scale;
+                xyz[s][2] = (k - c2) * p.inv_scale;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) u[s][c] = (double)v[3 * n + c];
+                if (v2) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) u[s][c] -= (double)v2[3 * n + c];
+                }
             }
-            if (mk & 1) u0 = 0.0;
-            if (mk & 2) u1 = 0.0;
-            if (mk & 4) u2 = 0.0;
-            m[0] += u0;
-            m[1] += u1;
-            m[2] += u2;
-            m[3] += -z * u1 + y * u2;
-            m[4] += z * u0 - x * u2;
-            m[5] += -y * u0 + x * u1;
+#pragma unroll
+            for (int s = 0; s < RU; ++s) {
+                if (q0 + s * RWG >= cnt) break;
+                const double x = xyz[s][0], y = xyz[s][1], z = xyz[s][2];
+                const double u0 = (mk[s] & 1) ? 0.0 : u[s][0], u1 = (mk[s] & 2) ? 0.0 : u[s][1],
+                             u2 = (mk[s] & 4) ? 0.0 : u[s][2];
+                m[0] += u0;
+                m[1] += u1;
+                m[2] += u2;
+                m[3] += -z * u1 + y * u2;
+                m[4] += z * u0 - x * u2;
+                m[5] += -y * u0 + x * u1;
+            }
         }
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
