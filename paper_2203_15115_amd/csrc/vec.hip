@@ -6,6 +6,7 @@
 // Every reduction is two-stage with a fixed order (per-workgroup partials,
 // then one workgroup summing the partials in index order), so results are
 // bitwise reproducible; no floating-point atomics are used.
+#include <algorithm>
 #include <cmath>
 
 #include "afd_internal.h"
@@ -195,7 +196,17 @@ struct BlkP {
     int b[3], nb[3];
     double inv_scale;
     int ncoarse;
+    double rsx, rsxy, rb[3];  // 1/(nx+1), 1/((nx+1)(ny+1)), 1/b: quotients without integer division
 };
+
+// floor(a / d) for 0 <= a < 2^31, d >= 1, from rd = 1/d: the double product
+// is within one of the quotient, and the two integer tests correct it
+__device__ __forceinline__ int quot(int a, int d, double rd) {
+    int q = (int)((double)a * rd);
+    q -= (int64_t)q * d > a;
+    q += (int64_t)(q + 1) * d <= a;
+    return q;
+}
 
 __device__ __forceinline__ void block_range(const BlkP& p, int ax, int bb, int& lo, int& hi) {
     const int n = ax == 0 ? p.nx : (ax == 1 ? p.ny : p.nz);
@@ -207,11 +218,11 @@ __device__ __forceinline__ void block_range(const BlkP& p, int ax, int bb, int& 
 // block centre, scaled by inv_scale
 __device__ __forceinline__ void node_block(const BlkP& p, int n, int bb[3], double x[3]) {
     const int sx = p.nx + 1, sxy = (p.nx + 1) * (p.ny + 1);
-    const int k = n / sxy, rem = n - k * sxy, j = rem / sx, i = rem - j * sx;
+    const int k = quot(n, sxy, p.rsxy), rem = n - k * sxy, j = quot(rem, sx, p.rsx), i = rem - j * sx;
     const int pp[3] = {i, j, k};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int q = pp[a] / p.b[a];
+        int q = quot(pp[a], p.b[a], p.rb[a]);
         if (q > p.nb[a] - 1) q = p.nb[a] - 1;
         int lo, hi;
         block_range(p, a, q, lo, hi);
@@ -438,6 +449,9 @@ BlkP blkp(const Grid& g, const Blocks& b) {
     }
     p.inv_scale = b.inv_scale;
     p.ncoarse = b.ncoarse;
+    p.rsx = 1.0 / (g.nx + 1);
+    p.rsxy = 1.0 / ((double)(g.nx + 1) * (g.ny + 1));
+    for (int a = 0; a < 3; ++a) p.rb[a] = 1.0 / std::max(b.b[a], 1);
     return p;
 }
 
