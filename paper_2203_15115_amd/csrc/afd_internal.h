@@ -66,16 +66,34 @@ struct Blocks {
     int P;                   // super-block size of the block-tridiagonal coarse matrix
     int K;                   // number of super-blocks
     int w;                   // half bandwidth in the permuted ordering
+    int m;                   // middle super-block of the two-ended order, (K - 1) / 2
 };
 
+// Two-ended order of the super-blocks of the banded coarse matrix: the first
+// m keep their place and orientation (chain A, positions 0..m-1), the last
+// K-1-m follow in reverse order with their unknowns reversed (chain B,
+// positions m..K-2; reversing a banded matrix keeps it banded, so B is block
+// tridiagonal with the same coupling windows as A), and super-block m,
+// reversed, goes last (position K-1), coupled to both chain ends.  The
+// factorisation and both triangular solves then run the two chains side by
+// side toward or away from the middle: about K/2 dependent steps instead of
+// K - 1.  Position of banded index q:
+inline int twist_position(int q, int P, int K, int m) {
+    const int j = q / P, r = q - j * P;
+    if (j < m) return q;
+    if (j == m) return (K - 1) * P + (P - 1 - r);
+    return (m + K - 1 - j) * P + (P - 1 - r);
+}
+
 // Super-block size of the block-tridiagonal coarse factor: any multiple of 64
-// that is >= the half bandwidth w is valid.  A coarse solve is a chain of
-// 2(K-1) dependent P x w matrix-vector steps (K = ceil(n/P); the coupling
-// blocks are zero outside a w-column window) plus two batched passes over the
-// K triangular inverses (K P^2 / 2 doubles each).  Cost model fitted to
-// measured solves on MI355X: ~6 us per dependent launch plus the streamed
-// bytes at ~4.5 TB/s.  Pick the P of least modelled time among w, 2w, ...,
-// 6w (AFD_COARSE_P overrides).
+// that is >= the half bandwidth w is valid.  A coarse solve (two-ended order,
+// see twist_position) is 2 floor((K-2)/2) + 7 dependent launches: the paired
+// chain steps (P x w matrix-vector products; the coupling blocks are zero
+// outside a w-column window), the middle block's two couplings each way, the
+// permutation and two batched passes over the K triangular inverses (K P^2 / 2
+// entries each).  Cost model fitted to measured solves on MI355X: ~6 us per
+// dependent launch plus the streamed bytes at ~4.5 TB/s.  Pick the P of least
+// modelled time among w, 2w, ..., 6w (AFD_COARSE_P overrides).
 inline int choose_coarse_P(int ncoarse, int w) {
     const int nc64 = ((ncoarse + 63) / 64) * 64;
     int forced = 0;
@@ -92,7 +110,7 @@ inline int choose_coarse_P(int ncoarse, int w) {
         if (P > nc64) P = nc64;
         const int K = (ncoarse + P - 1) / P;
         const double bytes = 2.0 * (K - 1) * P * std::min(P, w) * 8.0 + 2.0 * K * (double)P * P * 4.0;
-        const double t = (2.0 * K) * lat + bytes / bw;
+        const double t = (K >= 2 ? 2.0 * ((K - 2) / 2) + 7.0 : 3.0) * lat + bytes / bw;
         if (t < best_t - 1e-12) {
             best_t = t;
             best = P;
@@ -224,6 +242,9 @@ struct Coarse {
     double* U = nullptr;     // K x P x P : U_k = Linv_k^T C_k^T
     double* Ediag = nullptr; // K*P original diagonal
     double* work = nullptr;  // P x P
+    double* work2 = nullptr; // P x P, for the second chain of the factorisation
+    hipStream_t s2 = nullptr;                        // second chain's stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int32_t* dropped_dev = nullptr;
     int32_t* perm = nullptr; // natural coarse index -> ordered index
     int32_t* iperm = nullptr; // ordered index -> natural coarse index (-1: padding), K*P

@@ -244,6 +244,7 @@ void setup_blocks(afd_mesh* m) {
     const int P = choose_coarse_P(b.ncoarse, b.w);
     b.P = P;
     b.K = (b.ncoarse + P - 1) / P;
+    b.m = (b.K - 1) / 2;
 }
 
 // read at every assembly (once per coarse setup)
@@ -678,7 +679,7 @@ int afd_mesh_footprint(const afd_mesh* m, int32_t nrhs, int32_t precision, uint6
     if (precision == AFD_MIXED) b += (uint64_t)nrhs * nd * 4 * 8;        // FP32 inner vectors
     if (m->deflate) {
         const uint64_t PP = (uint64_t)m->blk.P * m->blk.P;
-        b += PP * m->blk.K * 8 * 6 + PP * 8 + (uint64_t)m->blk.K * m->blk.P * 8 * 14;
+        b += PP * m->blk.K * 8 * 6 + PP * 8 * 2 + (uint64_t)m->blk.K * m->blk.P * 8 * 14;  // 2 work blocks
         b += PP * m->blk.K * 4 * 4;                                     // FP32 copies of the solve matrices
     }
     b += (uint64_t)m->npartM * 64 + VEC_NPART * 64;

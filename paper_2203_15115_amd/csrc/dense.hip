@@ -377,10 +377,25 @@ __global__ void k_transpose(int P, const double* A, double* B) {
 }
 
 // -------------------------------------------------------------- assembly
+// Where entry (row, col) of E lives in the two-ended order (positions kr, kc of
+// row and column): the diagonal super-block D[kr], the coupling B[kc] to the
+// next position, or, for the middle (position K-1) against the end of chain A
+// (position m-1), B[m-1] (that slot couples nothing else: chain A's end and
+// chain B's start are not neighbours).  Entries above the diagonal are not
+// stored.  Returns null for them.
+__host__ __device__ inline double* coarse_slot(double* D, double* B, int P, int K, int m, int row, int col) {
+    const int kr = row / P, kc = col / P;
+    const int64_t at = (int64_t)(row % P) * P + col % P;
+    if (kr == kc) return D + (int64_t)kr * P * P + at;
+    // (positions m and m-1 are not neighbours: B[m-1] holds the middle's coupling)
+    if ((kr == kc + 1 && kc != m - 1) || (kr == K - 1 && kc == m - 1)) return B + (int64_t)kc * P * P + at;
+    return nullptr;
+}
+
 struct ScatP {
     int nb[3];
-    int P, ncoarse;
-    const int32_t* perm;  // natural coarse index -> ordered index
+    int P, ncoarse, K, m;
+    const int32_t* perm;  // natural coarse index -> position
 };
 
 // one thread per (block J, row mode m'): E[(J,m'),(I,m)] = G[6J+m'] with I the
@@ -402,11 +417,8 @@ __global__ void k_scatter_probe(ScatP p, const double* G, int color, int mode, d
         if (ib[a] < 0) return;
     }
     const int I = ib[0] + p.nb[0] * (ib[1] + p.nb[1] * ib[2]);
-    const int row = p.perm[6 * J + mr], col = p.perm[6 * I + mode];
-    const int kr = row / p.P, kc = col / p.P;
-    const double v = G[6 * J + mr];
-    if (kr == kc) D[((int64_t)kr * p.P + row % p.P) * p.P + col % p.P] = v;
-    else if (kr == kc + 1) B[((int64_t)kc * p.P + row % p.P) * p.P + col % p.P] = v;
+    double* at = coarse_slot(D, B, p.P, p.K, p.m, p.perm[6 * J + mr], p.perm[6 * I + mode]);
+    if (at) *at = G[6 * J + mr];
 }
 
 // E = W^T A W formed directly from the element matrices.  The six motions are
@@ -424,7 +436,7 @@ struct DirP {
     int n[3];          // elements per axis
     int b[3], nb[3];   // block edge (elements) and blocks per axis
     double inv_scale;
-    int P, ncoarse;
+    int P, ncoarse, K, m;
     const int32_t* perm;
     const double* rho;  // per element
     const uint8_t* nm;  // per node: bit c set when DOF c is fixed
@@ -565,18 +577,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int jb[3] = {ib[0] + jr % 3 - 1, ib[1] + (jr / 3) % 3 - 1, ib[2] + jr / 9 - 1};
         if (jb[0] < 0 || jb[0] >= p.nb[0] || jb[1] < 0 || jb[1] >= p.nb[1] || jb[2] < 0 || jb[2] >= p.nb[2]) continue;
         const int J = jb[0] + p.nb[0] * (jb[1] + p.nb[1] * jb[2]);
-        const int row = p.perm[6 * I + a], col = p.perm[6 * J + b];
-        const int kr = row / p.P, kc = col / p.P;
-        if (kr == kc) D[((int64_t)kr * p.P + row % p.P) * p.P + col % p.P] = acc[s4];
-        else if (kr == kc + 1) B[((int64_t)kc * p.P + row % p.P) * p.P + col % p.P] = acc[s4];
+        double* at = coarse_slot(D, B, p.P, p.K, p.m, p.perm[6 * I + a], p.perm[6 * J + b]);
+        if (at) *at = acc[s4];
     }
 }
 
-__global__ void k_init_coarse(int K, int P, int ncoarse, double* D) {
-    // identity on the padding unknowns of the last super-block
+__global__ void k_init_coarse(int K, int P, const int32_t* iperm, double* D) {
+    // identity on the padding unknowns (positions holding no coarse unknown)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = K * P;
-    if (i >= n || i < ncoarse) return;
+    if (i >= n || iperm[i] >= 0) return;
     const int k = i / P, r = i % P;
     D[((int64_t)k * P + r) * P + r] = 1.0;
 }
@@ -604,7 +614,8 @@ struct GemvIO {
     int dual_k;
     double* mu;            // scatter target [nrhs][ncoarse] (null: none)
     int mu_k;              // batch to scatter (-1: every batch)
-    int qbase;             // ordered position of row 0 of batch 0
+    int qbase;             // position of row 0 of batch 0
+    int qstride;           // positions from one batch to the next
 };
 // per-lane 16-byte loads of the streamed matrix: 2 FP64 or 4 FP32 elements
 template <typename TM>
@@ -681,17 +692,18 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const TM* M, int64_t mstrid
             y[kb * ystride + o] = out;
             if (io.y2 && kb == io.dual_k) io.y2[kb * ystride + o] = out;
             if (io.mu && (io.mu_k < 0 || kb == io.mu_k)) {
-                const int nat = io.iperm[io.qbase + (int64_t)kb * P + row];
+                const int nat = io.iperm[io.qbase + (int64_t)kb * io.qstride + row];
                 if (nat >= 0) io.mu[(int64_t)r * io.ncoarse + nat] = out;
             }
         }
     }
 }
 
-__global__ void k_perm_in(int ncoarse, int npad, const int32_t* perm, int nrhs, const double* G, double* gp) {
+__global__ void k_perm_in(int ncoarse, int npad, const int32_t* perm, const int32_t* iperm, int nrhs,
+                          const double* G, double* gp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i < npad && i >= ncoarse) gp[(int64_t)r * npad + i] = 0.0;
+    if (i < npad && iperm[i] < 0) gp[(int64_t)r * npad + i] = 0.0;  // padding position
     if (i >= ncoarse) return;
     gp[(int64_t)r * npad + perm[i]] = G[(int64_t)r * ncoarse + i];
 }
@@ -729,13 +741,20 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
     }
     AFD_HIP_TRY(hipMalloc((void**)&c.Ediag, npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.work, PP * sizeof(double)));
+    if (b.m >= 1 && b.K - 2 >= b.m) {  // the second chain of the factorisation (default priority)
+        AFD_HIP_TRY(hipMalloc((void**)&c.work2, PP * sizeof(double)));
+        AFD_HIP_TRY(hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking));
+        AFD_HIP_TRY(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+        AFD_HIP_TRY(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    }
     AFD_HIP_TRY(hipMalloc((void**)&c.dropped_dev, (npad + 1) * sizeof(int32_t)));
     AFD_HIP_TRY(hipMalloc((void**)&c.gperm, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.xperm, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.cvec, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.perm, b.ncoarse * sizeof(int32_t)));
     AFD_HIP_TRY(hipMalloc((void**)&c.iperm, npad * sizeof(int32_t)));
-    // ordering: axes of fewest blocks fastest
+    // ordering: axes of fewest blocks fastest (a banded matrix), then the
+    // super-blocks in the two-ended order
     std::vector<int32_t> perm(b.ncoarse);
     const int a0 = b.perm[0], a1 = b.perm[1], a2 = b.perm[2];
     for (int bk = 0; bk < b.nb[2]; ++bk)
@@ -744,7 +763,7 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
                 const int bb[3] = {bi, bj, bk};
                 const int nat = bi + b.nb[0] * (bj + b.nb[1] * bk);
                 const int ord = bb[a0] + b.nb[a0] * (bb[a1] + b.nb[a1] * bb[a2]);
-                for (int m = 0; m < 6; ++m) perm[6 * nat + m] = 6 * ord + m;
+                for (int m = 0; m < 6; ++m) perm[6 * nat + m] = twist_position(6 * ord + m, b.P, b.K, b.m);
             }
     AFD_HIP_TRY(hipMemcpyAsync(c.perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     c.iperm_host.assign(npad, -1);
@@ -755,7 +774,13 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
 }
 
 void coarse_free(Coarse& c) {
-    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.LinvT, &c.T, &c.U, &c.Ediag, &c.work, &c.gperm, &c.xperm, &c.cvec};
+    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.LinvT, &c.T, &c.U, &c.Ediag, &c.work, &c.work2, &c.gperm, &c.xperm,
+                       &c.cvec};
+    if (c.s2) (void)hipStreamDestroy(c.s2);
+    if (c.ev_fork) (void)hipEventDestroy(c.ev_fork);
+    if (c.ev_join) (void)hipEventDestroy(c.ev_join);
+    c.s2 = nullptr;
+    c.ev_fork = c.ev_join = nullptr;
     for (double** a : arrs)
         if (*a) {
             (void)hipFree(*a);
@@ -826,6 +851,8 @@ int coarse_direct(Coarse& c, const Grid& g, const double* rho, const uint8_t* nm
     p.inv_scale = b.inv_scale;
     p.P = b.P;
     p.ncoarse = b.ncoarse;
+    p.K = b.K;
+    p.m = b.m;
     p.perm = c.perm;
     p.rho = rho;
     p.nm = nmask;
@@ -858,6 +885,8 @@ int coarse_scatter_probe(Coarse& c, const double* G, int color, int mode, hipStr
     for (int a = 0; a < 3; ++a) p.nb[a] = b.nb[a];
     p.P = b.P;
     p.ncoarse = b.ncoarse;
+    p.K = b.K;
+    p.m = b.m;
     p.perm = c.perm;
     hipLaunchKernelGGL(k_scatter_probe, dim3((b.ncoarse + 255) / 256), dim3(256), 0, s, p, G, color, mode, c.D, c.B);
     AFD_HIP_TRY(hipGetLastError());
@@ -869,7 +898,7 @@ int coarse_factor(Coarse& c, hipStream_t s) {
     const int P = b.P, K = b.K;
     const int64_t PP = (int64_t)P * P;
     const int npad = K * P;
-    hipLaunchKernelGGL(k_init_coarse, dim3((npad + 255) / 256), dim3(256), 0, s, K, P, b.ncoarse, c.D);
+    hipLaunchKernelGGL(k_init_coarse, dim3((npad + 255) / 256), dim3(256), 0, s, K, P, c.iperm, c.D);
     hipLaunchKernelGGL(k_extract_diag, dim3((npad + 255) / 256), dim3(256), 0, s, K, P, c.D, c.Ediag);
     AFD_HIP_TRY(hipMemsetAsync(c.Linv, 0, PP * K * sizeof(double), s));
     AFD_HIP_TRY(hipMemsetAsync(c.T, 0, PP * K * sizeof(double), s));
@@ -879,25 +908,40 @@ int coarse_factor(Coarse& c, hipStream_t s) {
     // (Linv_k lower triangular); the Schur update then touches only the
     // leading w x w corner of D_{k+1}, T_k = Linv_k C_{k-1} only its last w
     // columns and U_k = Linv_k^T C_k^T only its first w columns.
+    //   In the two-ended order (twist_position) position m starts chain B and
+    // has no predecessor; the middle (position K-1) is also coupled to chain
+    // A's end (position m-1) by X = E(K-1, m-1), held in B[m-1], which is zero
+    // outside its LAST w rows and last w columns: C_X = X Linv_{m-1}^T has the
+    // same window, its Schur update touches the trailing w x w corner of the
+    // middle block, T_X = Linv_{K-1} C_X (kept in T[m], free since position m
+    // has no predecessor) its last w columns, and U_X = Linv_{m-1}^T C_X^T
+    // (kept in U[m-1]) its last w columns.
     const int w = std::min(b.w, P), o = P - w;
-    for (int k = 0; k < K; ++k) {
+    const int m = b.m;
+    double* Cx = m >= 1 ? blkptr(c.B, m - 1, P) + (int64_t)o * P + o : nullptr;  // C_X[o:P, o:P]
+    // one position: Schur update(s), Cholesky, inverse, chain matrices
+    auto position = [&](int k, hipStream_t st, double* work) -> int {
         double* Dk = blkptr(c.D, k, P);
         double* Li = blkptr(c.Linv, k, P);
-        if (k > 0) {  // D_k[0:w, 0:w] -= C_{k-1} C_{k-1}^T  (C stored in B[k-1])
+        const bool pred = k > 0 && k != m;        // coupled to position k - 1
+        const bool mid_x = k == K - 1 && m >= 1;  // the middle, also coupled to position m - 1
+        if (pred) {  // D_k[0:w, 0:w] -= C_{k-1} C_{k-1}^T  (C stored in B[k-1])
             const double* Ck = blkptr(c.B, k - 1, P) + o;
-            AFD_TRY(gemm(w, w, w, -1.0, Ck, P, 0, Ck, P, 1, 1.0, Dk, P, s));
+            AFD_TRY(gemm(w, w, w, -1.0, Ck, P, 0, Ck, P, 1, 1.0, Dk, P, st));
         }
+        if (mid_x)  // D_k[o:P, o:P] -= C_X C_X^T
+            AFD_TRY(gemm(w, w, w, -1.0, Cx, P, 0, Cx, P, 1, 1.0, Dk + (int64_t)o * P + o, P, st));
         // dense blocked Cholesky of D_k, tile inverses into Linv's diagonal tiles
         for (int j0 = 0; j0 < P; j0 += NB) {
             const int nb = std::min(NB, P - j0);
-            hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, s, Dk, Li, P, j0, nb, c.Ediag + (int64_t)k * P,
+            hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(256), 0, st, Dk, Li, P, j0, nb, c.Ediag + (int64_t)k * P,
                                c.dropped_dev + (int64_t)k * P);
             const int rows = P - j0 - nb;
             if (rows > 0) {
-                hipLaunchKernelGGL(k_panel, dim3((rows + 63) / 64), dim3(256), 0, s, Dk, Li, P, j0, nb);
+                hipLaunchKernelGGL(k_panel, dim3((rows + 63) / 64), dim3(256), 0, st, Dk, Li, P, j0, nb);
                 AFD_TRY(gemm(rows, rows, nb, -1.0, Dk + (int64_t)(j0 + nb) * P + j0, P, 0,
                              Dk + (int64_t)(j0 + nb) * P + j0, P, 1, 1.0, Dk + (int64_t)(j0 + nb) * P + j0 + nb, P,
-                             s));
+                             st));
             }
         }
         AFD_HIP_TRY(hipGetLastError());
@@ -908,29 +952,55 @@ int coarse_factor(Coarse& c, hipStream_t s) {
             const int nb = std::min(NB, P - i0);
             const int tiles = (i0 + GT - 1) / GT;
             const int S = std::max(1, std::min({(P - nb) / nb, 256 / tiles, i0 / 128}));
-            AFD_TRY(gemm_split(nb, i0, i0, 1.0, Dk + (int64_t)i0 * P, P, 0, Li, P, 0, c.work, P, c.work + (int64_t)nb * P,
-                               P, S, s));
-            AFD_TRY(gemm(nb, i0, nb, -1.0, Li + (int64_t)i0 * P + i0, P, 0, c.work, P, 0, 0.0, Li + (int64_t)i0 * P,
-                         P, s));
+            AFD_TRY(gemm_split(nb, i0, i0, 1.0, Dk + (int64_t)i0 * P, P, 0, Li, P, 0, work, P, work + (int64_t)nb * P,
+                               P, S, st));
+            AFD_TRY(gemm(nb, i0, nb, -1.0, Li + (int64_t)i0 * P + i0, P, 0, work, P, 0, 0.0, Li + (int64_t)i0 * P,
+                         P, st));
         }
-        hipLaunchKernelGGL(k_zero_dropped, dim3((P + 255) / 256, P), dim3(256), 0, s, Li, P,
+        hipLaunchKernelGGL(k_zero_dropped, dim3((P + 255) / 256, P), dim3(256), 0, st, Li, P,
                            c.dropped_dev + (int64_t)k * P);
-        hipLaunchKernelGGL(k_transpose, dim3((P + 31) / 32, (P + 31) / 32), dim3(32, 8), 0, s, P, Li,
+        hipLaunchKernelGGL(k_transpose, dim3((P + 31) / 32, (P + 31) / 32), dim3(32, 8), 0, st, P, Li,
                            blkptr(c.LinvT, k, P));
-        if (k > 0) {  // T_k[:, o:P] = Linv_k[:, 0:w] C_{k-1}[0:w, o:P]
-            AFD_TRY(gemm(P, w, w, 1.0, Li, P, 0, blkptr(c.B, k - 1, P) + o, P, 0, 0.0, blkptr(c.T, k, P) + o, P, s));
+        if (pred) {  // T_k[:, o:P] = Linv_k[:, 0:w] C_{k-1}[0:w, o:P]
+            AFD_TRY(gemm(P, w, w, 1.0, Li, P, 0, blkptr(c.B, k - 1, P) + o, P, 0, 0.0, blkptr(c.T, k, P) + o, P, st));
         }
-        if (k < K - 1) {
+        if (mid_x)  // T_X[:, o:P] = Linv_k[:, o:P] C_X[o:P, o:P], into T[m]
+            AFD_TRY(gemm(P, w, w, 1.0, Li + o, P, 0, Cx, P, 0, 0.0, blkptr(c.T, m, P) + o, P, st));
+        if (k == m - 1) {
+            // C_X = X[o:P, o:P] Linv_k[o:P, o:P]^T (in work, then back into B[m-1]);
+            // U_X[:, o:P] = Linv_k[o:P, :]^T C_X^T, into U[m-1]
+            AFD_TRY(gemm(w, w, w, 1.0, Cx, P, 0, Li + (int64_t)o * P + o, P, 1, 0.0, work, P, st));
+            AFD_HIP_TRY(hipMemcpy2DAsync(Cx, P * sizeof(double), work, P * sizeof(double), w * sizeof(double), w,
+                                         hipMemcpyDeviceToDevice, st));
+            AFD_TRY(gemm(P, w, w, 1.0, Li + (int64_t)o * P, P, 1, Cx, P, 1, 0.0, blkptr(c.U, k, P) + o, P, st));
+        } else if (k < K - 1) {
             // C_k[0:w, o:P] = B_k[0:w, o:P] Linv_k[o:P, o:P]^T (in work, then back into B[k])
             double* Bk = blkptr(c.B, k, P);
-            AFD_TRY(gemm(w, w, w, 1.0, Bk + o, P, 0, Li + (int64_t)o * P + o, P, 1, 0.0, c.work, P, s));
-            AFD_HIP_TRY(hipMemcpy2DAsync(Bk + o, P * sizeof(double), c.work, P * sizeof(double), w * sizeof(double), w,
-                                         hipMemcpyDeviceToDevice, s));
+            AFD_TRY(gemm(w, w, w, 1.0, Bk + o, P, 0, Li + (int64_t)o * P + o, P, 1, 0.0, work, P, st));
+            AFD_HIP_TRY(hipMemcpy2DAsync(Bk + o, P * sizeof(double), work, P * sizeof(double), w * sizeof(double), w,
+                                         hipMemcpyDeviceToDevice, st));
             // U_k[:, 0:w] = Linv_k[o:P, :]^T C_k[0:w, o:P]^T
-            AFD_TRY(gemm(P, w, w, 1.0, Li + (int64_t)o * P, P, 1, Bk + o, P, 1, 0.0, blkptr(c.U, k, P), P, s));
+            AFD_TRY(gemm(P, w, w, 1.0, Li + (int64_t)o * P, P, 1, Bk + o, P, 1, 0.0, blkptr(c.U, k, P), P, st));
         }
+        return AFD_OK;
+    };
+    // chains A (positions 0..m-1) and B (m..K-2) are independent until the
+    // middle: B runs on a second stream (its own work buffer) beside A
+    const bool two = m >= 1 && K - 2 >= m && c.s2 && c.work2;
+    if (two) {
+        AFD_HIP_TRY(hipEventRecord(c.ev_fork, s));
+        AFD_HIP_TRY(hipStreamWaitEvent(c.s2, c.ev_fork, 0));
+        for (int q = 0; q < std::max(m, K - 1 - m); ++q) {  // enqueued alternately, so both start at once
+            if (q < m) AFD_TRY(position(q, s, c.work));
+            if (m + q <= K - 2) AFD_TRY(position(m + q, c.s2, c.work2));
+        }
+        AFD_HIP_TRY(hipEventRecord(c.ev_join, c.s2));
+        AFD_HIP_TRY(hipStreamWaitEvent(s, c.ev_join, 0));
+    } else {
+        for (int k = 0; k < K - 1; ++k) AFD_TRY(position(k, s, c.work));
     }
-    hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, c.dropped_dev, b.ncoarse, c.dropped_dev + npad);
+    AFD_TRY(position(K - 1, s, c.work));
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(256), 0, s, c.dropped_dev, npad, c.dropped_dev + npad);
     AFD_HIP_TRY(hipGetLastError());
     int32_t nd = 0;
     AFD_HIP_TRY(hipMemcpyAsync(&nd, c.dropped_dev + npad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -954,42 +1024,63 @@ int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t
     const int npad = K * P;
     // coupling blocks E(k, k-1) are zero outside their last w columns, E(k, k+1)
     // outside their first w columns (half bandwidth w <= P), so the chain
-    // products only stream that window
-    const int w = std::min(b.w, P);
+    // products only stream that window.  Two-ended order (twist_position):
+    // chains A (positions 0..m-1) and B (m..K-2) run side by side, one launch
+    // per pair of steps, and meet the middle (K-1), which also couples to
+    // position m-1 through T_X (in T[m]) and U_X (in U[m-1]), last-w windows.
+    const int w = std::min(b.w, P), o = P - w;
+    const int m = b.m;
+    const int la = std::max(m - 1, 0), lb = std::max(K - 2 - m, 0);  // chain steps of A and B
     const unsigned rb = (unsigned)((P + 3) / 4);
-    GemvIO none{c.iperm, b.ncoarse, nullptr, -1, nullptr, -1, 0};
+    GemvIO none{c.iperm, b.ncoarse, nullptr, -1, nullptr, -1, 0, P};
+    // one launch of chain steps: positions pa (if >= 0) and pb (if >= 0), each
+    // v[pos] -= M[pos] v[pos + from] over the window [c0, c1), in place
+    auto chain = [&](const TM* M, double* v, int pa, int pb, int from, int c0, int c1, GemvIO io) {
+        const int p0 = pa >= 0 ? pa : pb;
+        const int nb = (pa >= 0 && pb >= 0) ? 2 : 1;
+        const int64_t d = nb == 2 ? (int64_t)(pb - pa) : 0;
+        io.qbase = p0 * P;
+        io.qstride = (int)(d * P);
+        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, nb), dim3(256), 0, s, P, M + (int64_t)p0 * PP, d * PP,
+                           v + (int64_t)(p0 + from) * P, d * P, v + (int64_t)p0 * P, d * P, -1.0, v + (int64_t)p0 * P,
+                           d * P, nrhs, (int64_t)npad, 0, c0, c1, io);
+    };
 
-    // c_k = Linv_k g_k, all k (g in the banded ordering); x_0 = c_0
-    hipLaunchKernelGGL(k_perm_in, dim3((npad + 255) / 256, nrhs), dim3(256), 0, s, b.ncoarse, npad, c.perm, nrhs, G,
-                       c.gperm);
-    GemvIO in = none;
-    in.y2 = c.xperm;
-    in.dual_k = 0;
+    // x_k = Linv_k g_k, all positions (g in the banded ordering)
+    hipLaunchKernelGGL(k_perm_in, dim3((npad + 255) / 256, nrhs), dim3(256), 0, s, b.ncoarse, npad, c.perm, c.iperm,
+                       nrhs, G, c.gperm);
     hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, K), dim3(256), 0, s, P, Linv, PP, c.gperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 1, 0, P, in);
-    // x_k = c_k - T_k x_{k-1}
-    for (int k = 1; k < K; ++k)
-        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(T, k, P), (int64_t)0,
-                           c.xperm + (int64_t)(k - 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.xperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, P - w, P, none);
-    // c'_k = Linv_k^T x_k, all k; mu_{K-1} = c'_{K-1} (kept and scattered)
+                       (const double*)nullptr, (int64_t)0, 1.0, c.xperm, (int64_t)P, nrhs, (int64_t)npad, 1, 0, P,
+                       none);
+    // x_k -= T_k x_{k-1} along both chains, then the middle
+    for (int q = 1; q <= std::max(la, lb); ++q)
+        chain(T, c.xperm, q <= la ? q : -1, q <= lb ? m + q : -1, -1, o, P, none);
+    if (K >= 2) chain(T, c.xperm, -1, K - 1, -1, o, P, none);
+    if (m >= 1) {  // x_{K-1} -= T_X x_{m-1}
+        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(T, m, P), (int64_t)0,
+                           c.xperm + (int64_t)(m - 1) * P, (int64_t)0, c.xperm + (int64_t)(K - 1) * P, (int64_t)0,
+                           -1.0, c.xperm + (int64_t)(K - 1) * P, (int64_t)0, nrhs, (int64_t)npad, 0, o, P, none);
+    }
+    // mu_k = Linv_k^T x_k, all positions; mu_{K-1} is final (scattered)
     GemvIO last = none;
-    last.y2 = c.gperm;
-    last.dual_k = K - 1;
     last.mu = MU;
     last.mu_k = K - 1;
     hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, K), dim3(256), 0, s, P, LinvT, PP, c.xperm, (int64_t)P,
-                       (const double*)nullptr, (int64_t)0, 1.0, c.cvec, (int64_t)P, nrhs, (int64_t)npad, 2, 0, P,
+                       (const double*)nullptr, (int64_t)0, 1.0, c.gperm, (int64_t)P, nrhs, (int64_t)npad, 2, 0, P,
                        last);
-    // mu_k = c'_k - U_k mu_{k+1}, scattered to natural order as produced
-    for (int k = K - 2; k >= 0; --k) {
-        GemvIO sc = none;
-        sc.mu = MU;
-        sc.qbase = k * P;
-        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(U, k, P), (int64_t)0,
-                           c.gperm + (int64_t)(k + 1) * P, (int64_t)0, c.cvec + (int64_t)k * P, (int64_t)0, -1.0,
-                           c.gperm + (int64_t)k * P, (int64_t)0, nrhs, (int64_t)npad, 0, 0, w, sc);
+    // mu_k -= U_k mu_{k+1} away from the middle, scattered to natural order as produced
+    GemvIO sc = none;
+    sc.mu = MU;
+    if (K >= 2) chain(U, c.gperm, -1, K - 2, 1, 0, w, sc);
+    if (m >= 1) {  // mu_{m-1} -= U_X mu_{K-1}
+        GemvIO sx = sc;
+        sx.qbase = (m - 1) * P;
+        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(U, m - 1, P), (int64_t)0,
+                           c.gperm + (int64_t)(K - 1) * P, (int64_t)0, c.gperm + (int64_t)(m - 1) * P, (int64_t)0,
+                           -1.0, c.gperm + (int64_t)(m - 1) * P, (int64_t)0, nrhs, (int64_t)npad, 0, o, P, sx);
     }
+    for (int q = 1; q <= std::max(la, lb); ++q)
+        chain(U, c.gperm, q <= la ? m - 1 - q : -1, q <= lb ? K - 2 - q : -1, 1, 0, w, sc);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -1018,12 +1109,9 @@ int coarse_to_dense_host(Coarse& c, double* E, hipStream_t s) {
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             const int pi = perm[i], pj = perm[j];
-            const int ki = pi / P, kj = pj / P;
-            double v = 0.0;
-            if (ki == kj) v = D[((int64_t)ki * P + pi % P) * P + pj % P];
-            else if (ki == kj + 1) v = B[((int64_t)kj * P + pi % P) * P + pj % P];
-            else if (kj == ki + 1) v = B[((int64_t)ki * P + pj % P) * P + pi % P];
-            E[(int64_t)i * n + j] = v;
+            const double* at = coarse_slot(D.data(), B.data(), P, K, b.m, pi, pj);
+            if (!at) at = coarse_slot(D.data(), B.data(), P, K, b.m, pj, pi);  // kept as the transpose
+            E[(int64_t)i * n + j] = at ? *at : 0.0;
         }
     return AFD_OK;
 }

@@ -92,7 +92,7 @@ uint64_t footprint_of(const afd_mesh_desc& d, int nrhs, int precision) {
         const int nc = 6 * nb[0] * nb[1] * nb[2];
         const int P = afd::choose_coarse_P(nc, w);
         const int K = (nc + P - 1) / P;
-        b += (uint64_t)P * P * K * 8 * 6 + (uint64_t)P * P * 8 + (uint64_t)K * P * 8 * 14;
+        b += (uint64_t)P * P * K * 8 * 6 + (uint64_t)P * P * 8 * 2 + (uint64_t)K * P * 8 * 14;
         b += (uint64_t)P * P * K * 4 * 4;                             // FP32 copies of the solve matrices
     }
     (void)nrhs;

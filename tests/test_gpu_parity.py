@@ -369,7 +369,10 @@ def coarse_P(monkeypatch):
     return set_p
 
 
-@pytest.mark.parametrize("P", [64, 320])  # 64 -> max(64, w) = 192: K = 4; 320: K = 3 with a ragged last block
+# 64 -> max(64, w) = 192: K = 4; 320: K = 3 with a ragged last block; 448: K = 2; 768: K = 1.  The
+# super-blocks run in the two-ended order (chain A, chain B reversed, the middle last), so these cover
+# both chains empty, chain A empty, one block per chain and a two-block chain B
+@pytest.mark.parametrize("P", [64, 320, 448, 768])
 def test_coarse_several_superblocks_match_oracle(ctx, coarse_P, P):
     dims, block = (16, 8, 8), (2, 2, 2)
     coarse_P(P)
