@@ -87,9 +87,9 @@ inline int twist_position(int q, int P, int K, int m) {
 
 // Super-block size of the block-tridiagonal coarse factor: any multiple of 64
 // that is >= the half bandwidth w is valid.  A coarse solve (two-ended order,
-// see twist_position) is 2 floor((K-2)/2) + 7 dependent launches: the paired
+// see twist_position) is 2 floor((K-2)/2) + 5 dependent launches: the paired
 // chain steps (P x w matrix-vector products; the coupling blocks are zero
-// outside a w-column window), the middle block's two couplings each way, the
+// outside a w-column window), one launch for the middle block each way, the
 // permutation and two batched passes over the K triangular inverses (K P^2 / 2
 // entries each).  Cost model fitted to measured solves on MI355X: ~6 us per
 // dependent launch plus the streamed bytes at ~4.5 TB/s.  Pick the P of least
@@ -110,7 +110,7 @@ inline int choose_coarse_P(int ncoarse, int w) {
         if (P > nc64) P = nc64;
         const int K = (ncoarse + P - 1) / P;
         const double bytes = 2.0 * (K - 1) * P * std::min(P, w) * 8.0 + 2.0 * K * (double)P * P * 4.0;
-        const double t = (K >= 2 ? 2.0 * ((K - 2) / 2) + 7.0 : 3.0) * lat + bytes / bw;
+        const double t = (K >= 2 ? 2.0 * ((K - 2) / 2) + 5.0 : 3.0) * lat + bytes / bw;
         if (t < best_t - 1e-12) {
             best_t = t;
             best = P;

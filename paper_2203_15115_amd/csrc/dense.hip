@@ -616,6 +616,11 @@ struct GemvIO {
     int mu_k;              // batch to scatter (-1: every batch)
     int qbase;             // position of row 0 of batch 0
     int qstride;           // positions from one batch to the next
+    // batch 1's own column window [c0b, c1b) (if c1b > 0); with M2 (single
+    // batch) a second product M2 x2 over that window added to the same rows
+    int c0b, c1b;
+    const void* M2;
+    const double* x2;
 };
 // per-lane 16-byte loads of the streamed matrix: 2 FP64 or 4 FP32 elements
 template <typename TM>
@@ -646,12 +651,10 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const TM* M, int64_t mstrid
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= P) return;
-    const TM* m = M + kb * mstride + (int64_t)row * P;
     x += kb * xstride;
     double acc[4] = {0, 0, 0, 0};
-    const int j0 = tri == 2 ? row : (tri == 1 ? 0 : c0);
-    const int j1 = tri == 1 ? row + 1 : (tri == 2 ? P : c1);
-    {
+    // acc += m[j0:j1] . xv[j0:j1] for every right-hand side
+    auto window = [&](const TM* m, const double* xv, int j0, int j1) {
         // aligned groups of N (P, the block offsets and the vector strides are
         // multiples of 4), four 16-byte loads per lane in flight; group members
         // outside [j0, j1) count zero
@@ -666,22 +669,27 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const TM* M, int64_t mstrid
                     if (j >= j1 || j + e < j0 || j + e >= j1) mv[u][e] = 0.0;
             }
             for (int r = 0; r < nrhs; ++r) {
-                const double* xr = x + r * vstride;
+                const double* xr = xv + r * vstride;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int j = jj + 64 * N * u;
                     if (j < j1) {
 #pragma unroll
                         for (int e = 0; e < N; e += 2) {
-                            const double2 xv = *reinterpret_cast<const double2*>(xr + j + e);
-                            acc[r] = fma(mv[u][e], xv.x, acc[r]);
-                            acc[r] = fma(mv[u][e + 1], xv.y, acc[r]);
+                            const double2 xx = *reinterpret_cast<const double2*>(xr + j + e);
+                            acc[r] = fma(mv[u][e], xx.x, acc[r]);
+                            acc[r] = fma(mv[u][e + 1], xx.y, acc[r]);
                         }
                     }
                 }
             }
         }
-    }
+    };
+    const bool own = kb == 1 && io.c1b > 0;
+    const int j0 = tri == 2 ? row : (tri == 1 ? 0 : (own ? io.c0b : c0));
+    const int j1 = tri == 1 ? row + 1 : (tri == 2 ? P : (own ? io.c1b : c1));
+    window(M + kb * mstride + (int64_t)row * P, x, j0, j1);
+    if (io.M2) window(static_cast<const TM*>(io.M2) + (int64_t)row * P, io.x2, io.c0b, io.c1b);
     for (int r = 0; r < nrhs; ++r) {
         double v = acc[r];
 #pragma unroll
@@ -1027,7 +1035,8 @@ int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t
     // products only stream that window.  Two-ended order (twist_position):
     // chains A (positions 0..m-1) and B (m..K-2) run side by side, one launch
     // per pair of steps, and meet the middle (K-1), which also couples to
-    // position m-1 through T_X (in T[m]) and U_X (in U[m-1]), last-w windows.
+    // position m-1 through T_X (in T[m]) and U_X (in U[m-1]), last-w windows;
+    // the middle's two products share one launch each way.
     const int w = std::min(b.w, P), o = P - w;
     const int m = b.m;
     const int la = std::max(m - 1, 0), lb = std::max(K - 2 - m, 0);  // chain steps of A and B
@@ -1055,11 +1064,14 @@ int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t
     // x_k -= T_k x_{k-1} along both chains, then the middle
     for (int q = 1; q <= std::max(la, lb); ++q)
         chain(T, c.xperm, q <= la ? q : -1, q <= lb ? m + q : -1, -1, o, P, none);
-    if (K >= 2) chain(T, c.xperm, -1, K - 1, -1, o, P, none);
-    if (m >= 1) {  // x_{K-1} -= T_X x_{m-1}
-        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(T, m, P), (int64_t)0,
-                           c.xperm + (int64_t)(m - 1) * P, (int64_t)0, c.xperm + (int64_t)(K - 1) * P, (int64_t)0,
-                           -1.0, c.xperm + (int64_t)(K - 1) * P, (int64_t)0, nrhs, (int64_t)npad, 0, o, P, none);
+    if (K >= 2) {  // the middle: x_{K-1} -= T_{K-1} x_{K-2} + T_X x_{m-1}, one launch
+        GemvIO mid = none;
+        if (m >= 1) {
+            mid.M2 = blkptr(T, m, P);
+            mid.x2 = c.xperm + (int64_t)(m - 1) * P;
+            mid.c0b = o, mid.c1b = P;
+        }
+        chain(T, c.xperm, -1, K - 1, -1, o, P, mid);
     }
     // mu_k = Linv_k^T x_k, all positions; mu_{K-1} is final (scattered)
     GemvIO last = none;
@@ -1071,13 +1083,16 @@ int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t
     // mu_k -= U_k mu_{k+1} away from the middle, scattered to natural order as produced
     GemvIO sc = none;
     sc.mu = MU;
-    if (K >= 2) chain(U, c.gperm, -1, K - 2, 1, 0, w, sc);
-    if (m >= 1) {  // mu_{m-1} -= U_X mu_{K-1}
-        GemvIO sx = sc;
-        sx.qbase = (m - 1) * P;
-        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, 1), dim3(256), 0, s, P, blkptr(U, m - 1, P), (int64_t)0,
-                           c.gperm + (int64_t)(K - 1) * P, (int64_t)0, c.gperm + (int64_t)(m - 1) * P, (int64_t)0,
-                           -1.0, c.gperm + (int64_t)(m - 1) * P, (int64_t)0, nrhs, (int64_t)npad, 0, o, P, sx);
+    if (K >= 2) {  // from the middle: mu_{K-2} -= U_{K-2} mu_{K-1} and mu_{m-1} -= U_X mu_{K-1}, one launch
+        const int nb = m >= 1 ? 2 : 1;
+        const int64_t d = m >= 1 ? (int64_t)(m - 1) - (K - 2) : 0;  // position step to the second output
+        GemvIO hd = sc;
+        hd.qbase = (K - 2) * P;
+        hd.qstride = (int)(d * P);
+        hd.c0b = o, hd.c1b = P;  // U_X's window
+        hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, nb), dim3(256), 0, s, P, blkptr(U, K - 2, P), d * PP,
+                           c.gperm + (int64_t)(K - 1) * P, (int64_t)0, c.gperm + (int64_t)(K - 2) * P, d * P, -1.0,
+                           c.gperm + (int64_t)(K - 2) * P, d * P, nrhs, (int64_t)npad, 0, 0, w, hd);
     }
     for (int q = 1; q <= std::max(la, lb); ++q)
         chain(U, c.gperm, q <= la ? m - 1 - q : -1, q <= lb ? K - 2 - q : -1, 1, 0, w, sc);
