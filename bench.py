@@ -409,6 +409,17 @@ def main():
                      "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] == -1 else None,
                      "kernel": KERNEL_NAMES[tune["fp64"]["variant"]], "bytes_per_launch": alg},
     }
+    # the opt-in coarse solve over FP32 copies of the FP64 factor's solve
+    # matrices (FP64 vectors and accumulation), same steps
+    afdcg.afd_mesh_coarse_precision(mesh, afdcg.AFD_FP32)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st32 = [step() for _ in range(args.steps)][-1]
+    torch.cuda.synchronize()
+    out["coarse_fp32_copies"] = {"ms_per_step": round((time.perf_counter() - t0) / max(1, args.steps) * 1e3, 3),
+                                 "time_to_1e-8_s": round(st32.t_setup + st32.t_iter, 5),
+                                 "iterations": st32.iterations, "rel_residual_true": st32.rel_residual_true}
     secs = [x for x in args.sections.split(",") if x]
     afdcg.afd_mesh_destroy(mesh)
     mesh = None

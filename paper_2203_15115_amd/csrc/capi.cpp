@@ -115,10 +115,13 @@ bool dir_fused() {
 // stream FP32 copies of the coarse solve matrices, with FP64 vectors and
 // accumulation (AFD_COARSE_F32=0: the FP64 factor)
 int g_coarse_f32 = -1;
+// FP32 copies of the coarse solve matrices are opt-in (AFD_COARSE_F32=1 for the
+// process, afd_mesh_coarse_precision per mesh): by default the coarse solve
+// streams the FP64 factor
 bool coarse_f32_enabled() {
     if (g_coarse_f32 < 0) {
         const char* e = getenv("AFD_COARSE_F32");
-        g_coarse_f32 = (e && *e == '0') ? 0 : 1;
+        g_coarse_f32 = (e && *e == '1') ? 1 : 0;
     }
     return g_coarse_f32 == 1;
 }
