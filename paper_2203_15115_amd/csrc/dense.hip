@@ -469,7 +469,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double f[6][24];      // rho_e Ke uI
     __shared__ double Mk[8][36];     // node k's share: sum_c f[a][3k+c] vJ[b][3k+c], at [k][6a+b]
     const int t = threadIdx.x;
-    const int I = blockIdx.x;
+    // workgroups go round-robin over the 8 XCDs: give each XCD a contiguous
+    // range of blocks, so neighbours (overlapping element boxes) share an L2
+    const int I = (blockIdx.x % 8) * (gridDim.x / 8) + min((int)(blockIdx.x % 8), (int)(gridDim.x % 8)) +
+                  (int)(blockIdx.x / 8);
     const int ib[3] = {I % p.nb[0], (I / p.nb[0]) % p.nb[1], I / (p.nb[0] * p.nb[1])};
     double ci[3];
     int e0[3], e1[3], lo[3], hi[3];

@@ -235,10 +235,18 @@ __device__ __forceinline__ void node_block(const BlkP& p, int n, int bb[3], doub
 // (V2 optional).  One wavefront per block (a block has 512-729 nodes), so the
 // six sums reduce with shuffles in a fixed order and no barriers.
 constexpr int RWG = 64;
+// Workgroups are dispatched round-robin over the 8 XCDs (one L2 each): dispatch
+// index b -> block so that every XCD gets a contiguous range of blocks, and x
+// neighbours, whose node rows share cache lines, share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % 8, k = b / 8;
+    const int base = nb / 8, rem = nb % 8;
+    return x * base + min(x, rem) + k;
+}
 template <typename T>
 __global__ __launch_bounds__(RWG) void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, const T* V,
                                                   const T* V2, double* G) {
-    const int blk = blockIdx.x;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bi = blk % p.nb[0], bj = (blk / p.nb[0]) % p.nb[1], bk = blk / (p.nb[0] * p.nb[1]);
     int lo[3], hi[3];
     block_range(p, 0, bi, lo[0], hi[0]);
