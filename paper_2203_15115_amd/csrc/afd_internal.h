@@ -211,10 +211,17 @@ int launch_precond_f32(const Grid& g, const KeHaar& kh, const float* rinv32, int
                        hipStream_t s);
 int launch_restrict(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V, double* G,
                     hipStream_t s);
+// G = W^T (V - V2); optionally also gperm[r][perm[i]] = G[r][i] (npad per
+// right-hand side: the coarse solve's permuted input, see coarse_solve) and
+// the CG beta/convergence update of sc from bpart (k_scalar_beta's work)
 int launch_restrict_diff(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V,
-                         const double* V2, double* G, hipStream_t s);
+                         const double* V2, double* G, hipStream_t s, const int32_t* perm = nullptr,
+                         double* gperm = nullptr, int64_t npad = 0, CgScalars* sc = nullptr,
+                         const double* bpart = nullptr, int bnpart = 0);
 int launch_restrict_diff_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V,
-                             const float* V2, double* G, hipStream_t s);
+                             const float* V2, double* G, hipStream_t s, const int32_t* perm = nullptr,
+                             double* gperm = nullptr, int64_t npad = 0, CgScalars* sc = nullptr,
+                             const double* bpart = nullptr, int bnpart = 0);
 int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V, double* G,
                         hipStream_t s);
 int launch_prolong(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, double* V,
@@ -273,7 +280,10 @@ int coarse_direct(Coarse& c, const Grid& g, const double* rho, const uint8_t* nm
 int coarse_factor(Coarse& c, hipStream_t s);
 int coarse_make_f32(Coarse& c, hipStream_t s);  // FP32 copies of the solve matrices (after coarse_factor)
 // mu = E^-1 g; f32: stream the FP32 copies (requires valid32), vectors and accumulation stay FP64
-int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, bool f32 = false);
+// g_in_perm: G's permuted copy is already in c.gperm (written by the
+// restriction), so the permutation launch is skipped
+int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, bool f32 = false,
+                 bool g_in_perm = false);
 int coarse_to_dense_host(Coarse& c, double* E_host, hipStream_t s);  // before factor only
 
 // post.hip

@@ -352,16 +352,23 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     // deflated preconditioner (equal to the Saad form, where W^T r = 0, in
     // exact arithmetic; it removes any rounding drift of W^T r, which the
     // FP32 inner solve of the mixed form needs)
-    auto coarse_of_z = [&]() -> int {
+    // The restriction also writes the coarse solve's permuted input (no
+    // permutation launch) and, inside the iteration (with_beta), does the CG
+    // beta/convergence update that follows the x/r update (no launch of its own).
+    auto coarse_of_z = [&](bool with_beta) -> int {
         if (!m->deflate) return AFD_OK;
+        const int64_t npad = (int64_t)m->blk.K * m->blk.P;
+        CgScalars* bsc = with_beta ? sc : nullptr;
         if constexpr (sizeof(T) == 8) {
             AFD_TRY(launch_apply(a, m->kh, 0, nrhs, Z, AZ, s));
-            AFD_TRY(launch_restrict_diff(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s));
+            AFD_TRY(launch_restrict_diff(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s, m->coarse.perm,
+                                         m->coarse.gperm, npad, bsc, w.partV, VEC_NPART));
         } else {
             AFD_TRY(launch_apply(a, m->kh, 1, nrhs, Z, AZ, s));
-            AFD_TRY(launch_restrict_diff_f32(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s));
+            AFD_TRY(launch_restrict_diff_f32(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s, m->coarse.perm,
+                                             m->coarse.gperm, npad, bsc, w.partV, VEC_NPART));
         }
-        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32);
+        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32, true);
     };
     // p' = beta p + M^-1 r - W mu (Pnew), then q = A p' with the p'.q partials;
     // AFD_DIR_FUSED=1 selects the single fused register-staged kernel instead
@@ -380,7 +387,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     if (m->deflate) {
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_precond(m->g, m->kh, m->rinv, nrhs, R, Z, s));
         else AFD_TRY(launch_precond_f32(m->g, m->kh, m->rinv32, nrhs, R, Z, s));
-        AFD_TRY(coarse_of_z());
+        AFD_TRY(coarse_of_z(false));
     }
     if constexpr (sizeof(T) == 8) AFD_TRY(launch_fill_f64(nrhs * ndof, 0.0, (double*)P0, s));
     else AFD_TRY(launch_fill_f32(nrhs * ndof, 0.0f, (float*)P0, s));
@@ -397,8 +404,8 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             else
                 AFD_TRY(launch_cg_update_f32(m->g, m->kh, m->rinv32, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr,
                                              w.partV, VEC_NPART, s));
-            AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
-            AFD_TRY(coarse_of_z());
+            if (!m->deflate || m->blk.nblk < nrhs) AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
+            AFD_TRY(coarse_of_z(m->deflate && m->blk.nblk >= nrhs));
             AFD_TRY(direction(P0, P1));
             std::swap(P0, P1);
         }

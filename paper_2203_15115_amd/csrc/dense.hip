@@ -760,6 +760,7 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
     }
     AFD_HIP_TRY(hipMalloc((void**)&c.dropped_dev, (npad + 1) * sizeof(int32_t)));
     AFD_HIP_TRY(hipMalloc((void**)&c.gperm, 4 * npad * sizeof(double)));
+    AFD_HIP_TRY(hipMemsetAsync(c.gperm, 0, 4 * npad * sizeof(double), s));  // padding positions stay zero
     AFD_HIP_TRY(hipMalloc((void**)&c.xperm, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.cvec, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.perm, b.ncoarse * sizeof(int32_t)));
@@ -1028,7 +1029,7 @@ int coarse_factor(Coarse& c, hipStream_t s) {
 
 template <typename TM>
 int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, const TM* Linv, const TM* LinvT,
-                   const TM* T, const TM* U) {
+                   const TM* T, const TM* U, bool g_in_perm) {
     const Blocks& b = c.blk;
     const int P = b.P, K = b.K;
     const int64_t PP = (int64_t)P * P;
@@ -1058,9 +1059,12 @@ int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t
                            d * P, nrhs, (int64_t)npad, 0, c0, c1, io);
     };
 
-    // x_k = Linv_k g_k, all positions (g in the banded ordering)
-    hipLaunchKernelGGL(k_perm_in, dim3((npad + 255) / 256, nrhs), dim3(256), 0, s, b.ncoarse, npad, c.perm, c.iperm,
-                       nrhs, G, c.gperm);
+    // x_k = Linv_k g_k, all positions (g in the banded ordering; padding
+    // positions of gperm are zero: set at allocation and by k_perm_in, and the
+    // solve leaves them zero since padding rows of the factor are identity)
+    if (!g_in_perm)
+        hipLaunchKernelGGL(k_perm_in, dim3((npad + 255) / 256, nrhs), dim3(256), 0, s, b.ncoarse, npad, c.perm,
+                           c.iperm, nrhs, G, c.gperm);
     hipLaunchKernelGGL(k_gemv<TM>, dim3(rb, K), dim3(256), 0, s, P, Linv, PP, c.gperm, (int64_t)P,
                        (const double*)nullptr, (int64_t)0, 1.0, c.xperm, (int64_t)P, nrhs, (int64_t)npad, 1, 0, P,
                        none);
@@ -1103,15 +1107,15 @@ int coarse_solve_t(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t
     return AFD_OK;
 }
 
-int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, bool f32) {
+int coarse_solve(Coarse& c, int nrhs, const double* G, double* MU, hipStream_t s, bool f32, bool g_in_perm) {
     if (f32) {
         if (!c.valid32) {
             set_error("coarse: FP32 solve without the FP32 copies");
             return AFD_E_INVALID_ARG;
         }
-        return coarse_solve_t<float>(c, nrhs, G, MU, s, c.Linv32, c.LinvT32, c.T32, c.U32);
+        return coarse_solve_t<float>(c, nrhs, G, MU, s, c.Linv32, c.LinvT32, c.T32, c.U32, g_in_perm);
     }
-    return coarse_solve_t<double>(c, nrhs, G, MU, s, c.Linv, c.LinvT, c.T, c.U);
+    return coarse_solve_t<double>(c, nrhs, G, MU, s, c.Linv, c.LinvT, c.T, c.U, g_in_perm);
 }
 
 int coarse_to_dense_host(Coarse& c, double* E, hipStream_t s) {

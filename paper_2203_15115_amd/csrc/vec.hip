@@ -243,9 +243,50 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     const int base = nb / 8, rem = nb % 8;
     return x * base + min(x, rem) + k;
 }
+// Optional riders of the restriction inside the CG iteration (each saves a
+// launch of its own): the permuted copy of G the coarse solve starts from
+// (gperm[r][perm[i]] = G[r][i]), and the CG step's beta/convergence update
+// (k_scalar_beta's work) for right-hand side r = blockIdx.x < nrhs, on one
+// wavefront of the workgroup (partials summed in a fixed order).
+struct RestrictRiders {
+    const int32_t* perm = nullptr;
+    double* gperm = nullptr;
+    int64_t npad = 0;
+    CgScalars* sc = nullptr;
+    const double* bpart = nullptr;
+    int bnpart = 0;
+};
+
+__device__ __forceinline__ void beta_step(CgScalars* sc, const double* part, int npart, int r) {
+    if (sc[r].done) return;  // same address for the whole wavefront
+    double rz = 0.0, rr = 0.0;
+    for (int i = threadIdx.x; i < npart; i += RWG) {
+        rz += part[(int64_t)(r * 2 + 0) * npart + i];
+        rr += part[(int64_t)(r * 2 + 1) * npart + i];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        rz += __shfl_down(rz, off, 64);
+        rr += __shfl_down(rr, off, 64);
+    }
+    if (threadIdx.x == 0) {
+        CgScalars st = sc[r];
+        st.iters += 1;
+        st.rz_new = rz;
+        st.rr = rr;
+        st.beta = rz / st.rz;
+        st.rz = rz;
+        if (!isfinite(rr)) st.done = 2;
+        else if (rr <= st.tol2) st.done = 1;
+        else if (st.iters >= st.max_iter) st.done = 3;
+        sc[r] = st;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(RWG) void k_restrict(BlkP p, const uint8_t* nm, int nrhs, int64_t ndof, const T* V,
-                                                  const T* V2, double* G) {
+                                                  const T* V2, double* G, RestrictRiders rd) {
+    if (rd.sc && (int)blockIdx.x < nrhs) beta_step(rd.sc, rd.bpart, rd.bnpart, blockIdx.x);
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int bi = blk % p.nb[0], bj = (blk / p.nb[0]) % p.nb[1], bk = blk / (p.nb[0] * p.nb[1]);
     int lo[3], hi[3];
@@ -313,7 +354,10 @@ __global__ __launch_bounds__(RWG) void k_restrict(BlkP p, const uint8_t* nm, int
             double s = m[a];
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) s += __shfl_down(s, off, 64);
-            if (threadIdx.x == 0) G[(int64_t)r * p.ncoarse + 6 * blk + a] = s;
+            if (threadIdx.x == 0) {
+                G[(int64_t)r * p.ncoarse + 6 * blk + a] = s;
+                if (rd.gperm) rd.gperm[r * rd.npad + rd.perm[6 * blk + a]] = s;
+            }
         }
     }
 }
@@ -549,7 +593,7 @@ int launch_cg_update_f32(const Grid& g, const KeHaar& kh, const float* rinv32, C
 int launch_restrict(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V, double* G,
                     hipStream_t s) {
     hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
-                       (const double*)nullptr, G);
+                       (const double*)nullptr, G, RestrictRiders{});
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -605,15 +649,31 @@ int launch_fill_f32(int64_t n, float v, float* a, hipStream_t s) {
 }
 
 int launch_restrict_diff(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* V,
-                         const double* V2, double* G, hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
+                         const double* V2, double* G, hipStream_t s, const int32_t* perm, double* gperm, int64_t npad,
+                         CgScalars* sc, const double* bpart, int bnpart) {
+    RestrictRiders rd;
+    rd.perm = perm, rd.gperm = gperm, rd.npad = npad, rd.sc = sc, rd.bpart = bpart, rd.bnpart = bnpart;
+    if (sc && b.nblk < nrhs) {
+        set_error("restrict: fewer blocks than right-hand sides for the fused scalar update");
+        return AFD_E_INVALID_ARG;
+    }
+    hipLaunchKernelGGL((k_restrict<double>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G,
+                       rd);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
 
 int launch_restrict_diff_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V,
-                             const float* V2, double* G, hipStream_t s) {
-    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G);
+                             const float* V2, double* G, hipStream_t s, const int32_t* perm, double* gperm,
+                             int64_t npad, CgScalars* sc, const double* bpart, int bnpart) {
+    RestrictRiders rd;
+    rd.perm = perm, rd.gperm = gperm, rd.npad = npad, rd.sc = sc, rd.bpart = bpart, rd.bnpart = bnpart;
+    if (sc && b.nblk < nrhs) {
+        set_error("restrict: fewer blocks than right-hand sides for the fused scalar update");
+        return AFD_E_INVALID_ARG;
+    }
+    hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V, V2, G,
+                       rd);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -621,7 +681,7 @@ int launch_restrict_diff_f32(const Grid& g, const Blocks& b, const uint8_t* nmas
 int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const float* V, double* G,
                         hipStream_t s) {
     hipLaunchKernelGGL((k_restrict<float>), dim3(b.nblk), dim3(RWG), 0, s, blkp(g, b), nmask, nrhs, g.ndof, V,
-                       (const float*)nullptr, G);
+                       (const float*)nullptr, G, RestrictRiders{});
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
