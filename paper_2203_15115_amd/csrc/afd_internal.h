@@ -258,7 +258,6 @@ struct Coarse {
     std::vector<int32_t> iperm_host;  // staging of iperm (lives until the copy has run)
     double* gperm = nullptr; // [4][K*P]
     double* xperm = nullptr; // [4][K*P]
-    double* cvec = nullptr;  // [4][K*P]
     // FP32 copies of Linv, LinvT, T and U for the FP32 inner solves of the
     // mixed form (made on demand after a factorisation; FP64 accumulation)
     float* Linv32 = nullptr;

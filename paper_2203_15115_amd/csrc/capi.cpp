@@ -426,7 +426,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             (uintptr_t)P1, (uintptr_t)Q, (uintptr_t)Z, (uintptr_t)AZ, (uintptr_t)sc, (uintptr_t)w.G,
             (uintptr_t)w.MU, (uintptr_t)w.partM, (uintptr_t)w.partV, (uintptr_t)m->npartM, (uintptr_t)c.Linv,
             (uintptr_t)c.LinvT, (uintptr_t)c.T, (uintptr_t)c.U, (uintptr_t)c.perm, (uintptr_t)c.iperm,
-            (uintptr_t)c.gperm, (uintptr_t)c.xperm, (uintptr_t)c.cvec, (uintptr_t)c.blk.P, (uintptr_t)c.blk.K,
+            (uintptr_t)c.gperm, (uintptr_t)c.xperm, (uintptr_t)c.blk.P, (uintptr_t)c.blk.K,
             (uintptr_t)c.Linv32, (uintptr_t)c.LinvT32, (uintptr_t)c.T32, (uintptr_t)c.U32,
             (uintptr_t)(use_coarse_f32(m) && c.valid32),
             (uintptr_t)(m->tune_variant[0] + 8), (uintptr_t)(m->tune_variant[1] + 8), (uintptr_t)m->tune_zc[0],

@@ -762,7 +762,6 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
     AFD_HIP_TRY(hipMalloc((void**)&c.gperm, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMemsetAsync(c.gperm, 0, 4 * npad * sizeof(double), s));  // padding positions stay zero
     AFD_HIP_TRY(hipMalloc((void**)&c.xperm, 4 * npad * sizeof(double)));
-    AFD_HIP_TRY(hipMalloc((void**)&c.cvec, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMalloc((void**)&c.perm, b.ncoarse * sizeof(int32_t)));
     AFD_HIP_TRY(hipMalloc((void**)&c.iperm, npad * sizeof(int32_t)));
     // ordering: axes of fewest blocks fastest (a banded matrix), then the
@@ -786,8 +785,7 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
 }
 
 void coarse_free(Coarse& c) {
-    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.LinvT, &c.T, &c.U, &c.Ediag, &c.work, &c.work2, &c.gperm, &c.xperm,
-                       &c.cvec};
+    double** arrs[] = {&c.D, &c.B, &c.Linv, &c.LinvT, &c.T, &c.U, &c.Ediag, &c.work, &c.work2, &c.gperm, &c.xperm};
     if (c.s2) (void)hipStreamDestroy(c.s2);
     if (c.ev_fork) (void)hipEventDestroy(c.ev_fork);
     if (c.ev_join) (void)hipEventDestroy(c.ev_join);
