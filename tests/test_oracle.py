@@ -285,3 +285,49 @@ def test_coarse_matrix_structure():
     assert nb == [2, 2, 2]
     assert np.allclose(E, E.T, atol=1e-14)
     assert np.linalg.eigvalsh(E).min() > 0       # clamped: positive definite
+
+
+# ------------------------------------------------------------- casting (Sec. 3.7)
+def test_casting_projection_worked_line():
+    # a line of 8 elements along x, parting plane before element 3, worked by hand:
+    # j < 3 takes the running maximum from j = 0: 3, max(3,1) = 3, max(3,4) = 4;
+    # j >= 3 takes it from the far end: 6, max(6,2) = 6, 9, 9, 9
+    from oracle.casting import cast_project
+    phi = [3, 1, 4, 1, 5, 9, 2, 6]
+    want = [3, 3, 4, 9, 9, 9, 6, 6]
+    assert list(cast_project(phi, (8, 1, 1), 0, 3)) == want
+    # the same line laid along y and along z
+    assert list(cast_project(phi, (1, 8, 1), 1, 3)) == want
+    assert list(cast_project(phi, (1, 1, 8), 2, 3)) == want
+    # one-sided castings: the whole line on one side of the plane
+    assert list(cast_project(phi, (8, 1, 1), 0, 0)) == [9, 9, 9, 9, 9, 9, 6, 6]
+    assert list(cast_project(phi, (8, 1, 1), 0, 8)) == [3, 3, 4, 4, 5, 9, 9, 9]
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_casting_projection_is_the_least_monotone_majorant(axis):
+    # characterisation independent of the running-maximum formula: along every
+    # line the result (i) is >= phi, (ii) does not increase away from the
+    # parting plane on either side, and (iii) equals phi at some element between
+    # it and the far end of its side -- so every field with (i) and (ii) is >= it
+    from oracle.casting import cast_project
+    rng = np.random.default_rng(40 + axis)
+    dims = (5, 4, 6)
+    n = dims[axis]
+    for p in range(n + 1):
+        phi = rng.integers(0, 7, size=int(np.prod(dims))).astype(float)  # ties on purpose
+        g = cast_project(phi, dims, axis, p)
+        f3 = np.moveaxis(phi.reshape(dims[::-1]), 2 - axis, -1).reshape(-1, n)
+        g3 = np.moveaxis(g.reshape(dims[::-1]), 2 - axis, -1).reshape(-1, n)
+        assert np.all(g3 >= f3)
+        for fl, gl in zip(f3, g3):
+            for j in range(n):
+                if j >= p:
+                    if j + 1 < n:
+                        assert gl[j] >= gl[j + 1]
+                    assert gl[j] in set(fl[j:])
+                else:
+                    if j >= 1:
+                        assert gl[j] >= gl[j - 1]
+                    assert gl[j] in set(fl[:j + 1])
+        assert np.array_equal(cast_project(g, dims, axis, p), g)  # idempotent
