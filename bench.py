@@ -409,6 +409,22 @@ def main():
                      "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] == -1 else None,
                      "kernel": KERNEL_NAMES[tune["fp64"]["variant"]], "bytes_per_launch": alg},
     }
+    # casting projection (Sec. 3.7) of the energy field of the last step: one
+    # launch reads and writes one FP64 value per element
+    cs = torch.empty_like(S)
+    cast = {}
+    for axis, parting in ((2, 0), (0, p.dims[0] // 2)):
+        for _ in range(20):
+            afdcg.afd_casting(ctx, p.dims, S, axis, parting, cs)
+        ev0.record(stream)
+        for _ in range(200):
+            afdcg.afd_casting(ctx, p.dims, S, axis, parting, cs)
+        ev1.record(stream)
+        ev1.synchronize()
+        t_c = ev0.elapsed_time(ev1) * 1e-3 / 200
+        cast[f"axis{axis}"] = {"parting": parting, "us": round(t_c * 1e6, 2),
+                               "gbs": round(2 * 8 * p.nelem / t_c / 1e9, 1)}
+    out["casting"] = cast
     # the opt-in coarse solve over FP32 copies of the FP64 factor's solve
     # matrices (FP64 vectors and accumulation), same steps
     afdcg.afd_mesh_coarse_precision(mesh, afdcg.AFD_FP32)

@@ -235,6 +235,20 @@ int afd_sensitivity(afd_mesh* mesh, int32_t nrhs, const double* U,
 int afd_threshold(afd_context* ctx, const double* s, int64_t n, double vol_frac,
                   uint8_t* solid, int32_t* order, double* tau_host);
 
+/* Casting constraint (Sec. 3.7): out = the least element field >= phi that
+ * does not increase away from the parting plane along the casting axis, so
+ * that a topology extracted from it (afd_threshold) has no cavity a mould
+ * drawn along the axis cannot reach.  dims = elements per axis (x fastest:
+ * element ex + dims[0] (ey + dims[1] ez)); axis 0, 1 or 2; the parting plane
+ * lies before element index parting along the axis (0..dims[axis]; 0 or
+ * dims[axis]: one-sided casting).  Along every line of elements parallel to
+ * the axis this is the running maximum from each far end toward the plane.
+ * phi and out are device arrays of dims[0]*dims[1]*dims[2] doubles (finite
+ * values); out may equal phi.  Exact (maxima only).  AFD_E_INVALID_ARG for a
+ * bad axis, dims or parting. */
+int afd_casting(afd_context* ctx, const int32_t dims[3], const double* phi, int32_t axis, int32_t parting,
+                double* out);
+
 /* ---- the whole solve ---------------------------------------------------- */
 /* Solves A U[r] = F[r] for r < nrhs (1..4) by deflated Jacobi-PCG (Sec. 3.5),
  * FP64 or FP32-inner/FP64-refined per opts->precision (the coarse factor is

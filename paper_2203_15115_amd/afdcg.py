@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVALID_ARG", -2: "E_NO_DEVICE", -
 
 EXPORTED = [
     "afd_context_create", "afd_context_destroy", "afd_last_error", "afd_context_sync", "afd_context_use_graphs",
-    "afd_mesh_coarse_precision",
+    "afd_mesh_coarse_precision", "afd_casting",
     "afd_mesh_create", "afd_mesh_destroy", "afd_mesh_sizes", "afd_mesh_set_scale", "afd_mesh_set_fixed",
     "afd_mesh_footprint", "afd_mesh_ke", "afd_apply_K", "afd_apply_K_mfma", "afd_mesh_autotune", "afd_mesh_apply_config",
     "afd_jacobi",
@@ -119,6 +119,7 @@ def lib():
             "afd_coarse_solve": (C.c_int, [vp, i32, vp, vp]),
             "afd_sensitivity": (C.c_int, [vp, i32, vp, i32, vp, vp]),
             "afd_threshold": (C.c_int, [vp, vp, i64, dbl, vp, vp, C.POINTER(dbl)]),
+            "afd_casting": (C.c_int, [vp, C.POINTER(i32), vp, i32, i32, vp]),
             "afd_solve": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, vp, vp, vp, vp, vp]),
             "afd_server_create": (C.c_int, [vp, C.c_uint64, i32, C.POINTER(vp)]),
             "afd_server_submit": (C.c_int, [vp, C.POINTER(afd_request), C.POINTER(afd_result),
@@ -282,6 +283,11 @@ def afd_threshold(ctx, s, n, vol_frac, solid, order=None):
     check(lib().afd_threshold(ctx, _ptr(s), n, float(vol_frac), _ptr(solid), _ptr(order), C.byref(tau)),
           "afd_threshold")
     return tau.value
+
+
+def afd_casting(ctx, dims, phi, axis, parting, out):
+    d = (C.c_int32 * 3)(*[int(x) for x in dims])
+    check(lib().afd_casting(ctx, d, _ptr(phi), int(axis), int(parting), _ptr(out)), "afd_casting")
 
 
 def make_opts(rtol=1e-8, max_iter=20000, precision=AFD_FP64, inner_rtol=1e-4, check_every=16,

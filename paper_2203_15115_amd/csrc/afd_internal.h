@@ -288,6 +288,8 @@ int coarse_to_dense_host(Coarse& c, double* E_host, hipStream_t s);  // before f
 // post.hip
 int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int nfields, const double* const* Ua,
                        const double* const* Ub, double* S, hipStream_t s);
+// casting projection of an element field on a dims grid (see afd_casting)
+int launch_cast(const int dims[3], int axis, int parting, const double* phi, double* out, hipStream_t s);
 int threshold_gpu(const double* s, int64_t n, double vol_frac, uint8_t* solid, int32_t* order, double* tau_host,
                   hipStream_t st);
 

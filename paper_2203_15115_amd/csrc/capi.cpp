@@ -958,6 +958,22 @@ int afd_threshold(afd_context* c, const double* s, int64_t n, double vol_frac, u
     return threshold_gpu(s, n, vol_frac, solid, order, tau, c->stream);
 }
 
+int afd_casting(afd_context* c, const int32_t dims[3], const double* phi, int32_t axis, int32_t parting,
+                double* out) {
+    AFD_TRY(check_ctx(c));
+    if (!dims || !phi || !out || axis < 0 || axis > 2) {
+        set_error("casting: null argument or axis outside 0..2");
+        return AFD_E_INVALID_ARG;
+    }
+    const int d[3] = {dims[0], dims[1], dims[2]};
+    if (d[0] < 1 || d[1] < 1 || d[2] < 1 || (int64_t)d[0] * d[1] * d[2] >= (int64_t(1) << 31) || parting < 0 ||
+        parting > d[axis]) {
+        set_error("casting: dims must be >= 1 (fewer than 2^31 elements), parting in 0..dims[axis]");
+        return AFD_E_INVALID_ARG;
+    }
+    return launch_cast(d, axis, parting, phi, out, c->stream);
+}
+
 int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* F, double* U, double* J, double* S,
               afd_solve_stats* st) {
     if (!m || !o || !F || !U || nrhs < 1 || nrhs > 4) {

@@ -194,6 +194,38 @@ __global__ void k_scatter(int64_t n, const uint64_t* kin, const int32_t* iin, ui
     }
 }
 
+// Casting projection (Sec. 3.7): one thread per line of elements parallel to
+// the casting axis, a running maximum from each far end toward the parting
+// plane (elements j >= parting from the last one down, j < parting from the
+// first one up).  Lines across the axis are consecutive threads, so for the y
+// and z axes a wavefront reads 64 consecutive elements per step; along x each
+// thread walks its own contiguous row.  Maxima are exact: bit-identical to any
+// other evaluation order.
+__global__ void k_cast(int nx, int ny, int nz, int axis, int parting, const double* phi, double* out) {
+    const int L = blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t base, stride;
+    int n, lines;
+    if (axis == 0) {
+        lines = ny * nz, n = nx, stride = 1, base = (int64_t)nx * L;
+    } else if (axis == 1) {
+        lines = nx * nz, n = ny, stride = nx;
+        base = (int64_t)(L % nx) + (int64_t)nx * ny * (L / nx);
+    } else {
+        lines = nx * ny, n = nz, stride = (int64_t)nx * ny, base = L;
+    }
+    if (L >= lines) return;
+    double run = -INFINITY;
+    for (int j = n - 1; j >= parting; --j) {
+        run = fmax(run, phi[base + j * stride]);
+        out[base + j * stride] = run;
+    }
+    run = -INFINITY;
+    for (int j = 0; j < parting; ++j) {
+        run = fmax(run, phi[base + j * stride]);
+        out[base + j * stride] = run;
+    }
+}
+
 __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* solid, int32_t* order_out) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -203,6 +235,14 @@ __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* s
 }
 
 }  // namespace
+
+int launch_cast(const int dims[3], int axis, int parting, const double* phi, double* out, hipStream_t s) {
+    const int lines = axis == 0 ? dims[1] * dims[2] : (axis == 1 ? dims[0] * dims[2] : dims[0] * dims[1]);
+    hipLaunchKernelGGL(k_cast, dim3((lines + 255) / 256), dim3(256), 0, s, dims[0], dims[1], dims[2], axis, parting,
+                       phi, out);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
 
 int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int nfields, const double* const* Ua,
                        const double* const* Ub, double* S, hipStream_t s) {

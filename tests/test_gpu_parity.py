@@ -752,3 +752,53 @@ def test_server_rejects_over_budget(ctx):
         assert ei.value.code == afdcg.AFD_E_OVER_BUDGET
     finally:
         afdcg.afd_server_destroy(srv)
+
+
+# ------------------------------------------------------------- casting (Sec. 3.7)
+# x lines are scanned 64 elements per step: 64, 65 and 130 cross the step boundaries
+@pytest.mark.parametrize("dims", [(1, 1, 1), (7, 5, 3), (16, 9, 12), (64, 2, 3), (65, 3, 2), (130, 3, 2),
+                                  (192, 96, 96)])
+def test_casting_matches_oracle(ctx, dims):
+    from oracle.casting import cast_project
+    rng = np.random.default_rng(sum(dims))
+    n = int(np.prod(dims))
+    phi = rng.standard_normal(n)
+    phi[rng.random(n) < 0.2] = 0.5  # repeated values
+    P = dev(phi)
+    cases = [(a, p) for a in range(3) for p in sorted({0, 1, dims[a] // 2, dims[a] - 1, dims[a]} - {-1})]
+    if n > 10 ** 6:
+        cases = [(0, 0), (1, dims[1] // 3), (2, dims[2])]  # the full workload size: one case per axis
+    for axis, p in cases:
+        out = torch.empty_like(P)
+        afdcg.afd_casting(ctx, dims, P, axis, p, out)
+        assert np.array_equal(host(out), cast_project(phi, dims, axis, p)), (axis, p)
+    Q = P.clone()  # in place
+    afdcg.afd_casting(ctx, dims, Q, 2, dims[2] // 2, Q)
+    assert np.array_equal(host(Q), cast_project(phi, dims, 2, dims[2] // 2))
+    out = torch.empty_like(P)
+    for axis, p in ((3, 0), (-1, 0), (0, dims[0] + 1), (1, -1)):
+        with pytest.raises(afdcg.AfdError):
+            afdcg.afd_casting(ctx, dims, P, axis, p, out)
+
+
+def test_casting_topology_has_no_cavity(ctx):
+    # one-sided casting drawn toward +z (parting plane at z = 0): along every
+    # z line of the thresholded topology, no void lies between the plane and a
+    # solid element (ties in the projected field fall to the lower index, i.e.
+    # nearer the plane)
+    dims = (12, 10, 14)
+    n = int(np.prod(dims))
+    phi = np.random.default_rng(5).standard_normal(n)
+    P = dev(phi)
+    out = torch.empty_like(P)
+    afdcg.afd_casting(ctx, dims, P, 2, 0, out)
+    solid = torch.empty(n, dtype=torch.uint8, device="cuda")
+    afdcg.afd_threshold(ctx, out, n, 0.4, solid)
+    sv = host(solid).reshape(dims[2], dims[1], dims[0])  # [z][y][x]
+    for y in range(dims[1]):
+        for x in range(dims[0]):
+            col = sv[:, y, x]
+            top = np.nonzero(col)[0]
+            if top.size:
+                assert col[:top.max() + 1].all(), (x, y, col)
+    assert abs(int(sv.sum()) - math.ceil(0.4 * n)) == 0
