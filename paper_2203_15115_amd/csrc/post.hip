@@ -194,35 +194,91 @@ __global__ void k_scatter(int64_t n, const uint64_t* kin, const int32_t* iin, ui
     }
 }
 
-// Casting projection (Sec. 3.7): one thread per line of elements parallel to
-// the casting axis, a running maximum from each far end toward the parting
+// Casting projection (Sec. 3.7): a running maximum along every line of
+// elements parallel to the casting axis, from each far end toward the parting
 // plane (elements j >= parting from the last one down, j < parting from the
-// first one up).  Lines across the axis are consecutive threads, so for the y
-// and z axes a wavefront reads 64 consecutive elements per step; along x each
-// thread walks its own contiguous row.  Maxima are exact: bit-identical to any
-// other evaluation order.
-__global__ void k_cast(int nx, int ny, int nz, int axis, int parting, const double* phi, double* out) {
-    const int L = blockIdx.x * blockDim.x + threadIdx.x;
+// first one up).  Maxima are exact: any evaluation order gives the same bits.
+// Along y and z (strided lines): a workgroup takes 64 consecutive lines (one
+// wavefront reads 64 consecutive elements per step) and cuts each side of
+// every line into 4 chunks, one wavefront per chunk: the chunk maxima go
+// through LDS, then each chunk runs its maximum from the carry of the chunks
+// farther out (every element is read twice, written once; the lines alone
+// are too few to fill the GPU).
+constexpr int CCH = 4;
+__global__ __launch_bounds__(256) void k_cast_yz(int nx, int ny, int nz, int axis, int parting, const double* phi,
+                                                 double* out) {
+    __shared__ double cmax[2][CCH][64];
+    const int li = threadIdx.x & 63, c = threadIdx.x >> 6;
+    const int L = blockIdx.x * 64 + li;
     int64_t base, stride;
     int n, lines;
-    if (axis == 0) {
-        lines = ny * nz, n = nx, stride = 1, base = (int64_t)nx * L;
-    } else if (axis == 1) {
+    if (axis == 1) {
         lines = nx * nz, n = ny, stride = nx;
         base = (int64_t)(L % nx) + (int64_t)nx * ny * (L / nx);
     } else {
         lines = nx * ny, n = nz, stride = (int64_t)nx * ny, base = L;
     }
-    if (L >= lines) return;
-    double run = -INFINITY;
-    for (int j = n - 1; j >= parting; --j) {
+    const bool valid = L < lines;
+    // this chunk of each side: side + runs j = hi..lo downward, side - j = lo2..hi2 upward
+    const int cl = (n - parting + CCH - 1) / CCH, hi = n - 1 - c * cl, lo = max(parting, hi - cl + 1);
+    const int cl2 = (parting + CCH - 1) / CCH, lo2 = c * cl2, hi2 = min(parting - 1, lo2 + cl2 - 1);
+    double m = -INFINITY, m2 = -INFINITY;
+    if (valid) {
+        for (int j = hi; j >= lo; --j) m = fmax(m, phi[base + j * stride]);
+        for (int j = lo2; j <= hi2; ++j) m2 = fmax(m2, phi[base + j * stride]);
+    }
+    cmax[0][c][li] = m;
+    cmax[1][c][li] = m2;
+    __syncthreads();
+    if (!valid) return;
+    double run = -INFINITY, run2 = -INFINITY;
+    for (int k = 0; k < c; ++k) {
+        run = fmax(run, cmax[0][k][li]);
+        run2 = fmax(run2, cmax[1][k][li]);
+    }
+    for (int j = hi; j >= lo; --j) {
         run = fmax(run, phi[base + j * stride]);
         out[base + j * stride] = run;
     }
-    run = -INFINITY;
-    for (int j = 0; j < parting; ++j) {
-        run = fmax(run, phi[base + j * stride]);
-        out[base + j * stride] = run;
+    for (int j = lo2; j <= hi2; ++j) {
+        run2 = fmax(run2, phi[base + j * stride]);
+        out[base + j * stride] = run2;
+    }
+}
+
+// Along x (contiguous lines) one wavefront per line: 64 consecutive elements
+// per step, a running maximum across the lanes by shuffles (log2 64 steps) on
+// top of the carry from the previous step.
+__global__ void k_cast_x(int nx, int lines, int parting, const double* phi, double* out) {
+    const int lane = threadIdx.x & 63;
+    const int L = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (L >= lines) return;
+    const int64_t base = (int64_t)nx * L;
+    double carry = -INFINITY;
+    for (int j0 = nx - 1; j0 >= parting; j0 -= 64) {  // side j >= parting, from the far end
+        const int j = j0 - lane;
+        double v = j >= parting ? phi[base + j] : -INFINITY;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double o = __shfl_up(v, off, 64);
+            if (lane >= off) v = fmax(v, o);
+        }
+        v = fmax(v, carry);
+        if (j >= parting) out[base + j] = v;
+        carry = __shfl(v, 63, 64);
+    }
+    carry = -INFINITY;
+    for (int j0 = 0; j0 < parting; j0 += 64) {  // side j < parting, from the first element
+        const int j = j0 + lane;
+        double v = j < parting ? phi[base + j] : -INFINITY;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double o = __shfl_up(v, off, 64);
+            if (lane >= off) v = fmax(v, o);
+        }
+        v = fmax(v, carry);
+        if (j < parting) out[base + j] = v;
+        carry = __shfl(v, 63, 64);
     }
 }
 
@@ -238,8 +294,11 @@ __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* s
 
 int launch_cast(const int dims[3], int axis, int parting, const double* phi, double* out, hipStream_t s) {
     const int lines = axis == 0 ? dims[1] * dims[2] : (axis == 1 ? dims[0] * dims[2] : dims[0] * dims[1]);
-    hipLaunchKernelGGL(k_cast, dim3((lines + 255) / 256), dim3(256), 0, s, dims[0], dims[1], dims[2], axis, parting,
-                       phi, out);
+    if (axis == 0)
+        hipLaunchKernelGGL(k_cast_x, dim3((lines + 3) / 4), dim3(256), 0, s, dims[0], lines, parting, phi, out);
+    else
+        hipLaunchKernelGGL(k_cast_yz, dim3((lines + 63) / 64), dim3(256), 0, s, dims[0], dims[1], dims[2], axis,
+                           parting, phi, out);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
