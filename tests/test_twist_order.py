@@ -94,8 +94,9 @@ def windowed_solve(E, g, P, w):
     return np.concatenate(mu)[perm], K
 
 
+# includes w = P (the coupling windows then cover whole super-blocks)
 @pytest.mark.parametrize("n,w,P", [(40, 8, 48), (100, 20, 48), (130, 30, 32), (200, 30, 32), (324, 60, 64),
-                                   (500, 40, 48), (768, 60, 64)])
+                                   (500, 40, 48), (768, 60, 64), (256, 32, 32), (300, 48, 48)])
 def test_two_ended_block_cholesky_solves(n, w, P):
     rng = np.random.default_rng(n + w + P)
     E = np.zeros((n, n))
