@@ -331,3 +331,111 @@ def test_casting_projection_is_the_least_monotone_majorant(axis):
                         assert gl[j] >= gl[j - 1]
                     assert gl[j] in set(fl[:j + 1])
         assert np.array_equal(cast_project(g, dims, axis, p), g)  # idempotent
+
+
+# ------------------------------------------------------------- constrained operator
+def _dense_operator(apply, n):
+    """Matrix of a linear map given only as a function, column by column."""
+    A = np.zeros((n, n))
+    e = np.zeros(n)
+    for i in range(n):
+        e[i] = 1.0
+        A[:, i] = apply(e)
+        e[i] = 0.0
+    return A
+
+
+def test_apply_constrained_is_the_extended_free_block():
+    # the operator the solver iterates with: K_ff on free DOFs (fixed inputs
+    # count as zero), the identity on fixed DOFs.  Pinned against the dense
+    # assembled matrix, and by the properties a wrong masking would break:
+    # symmetry, identity rows AND columns on fixed DOFs, A u = f for the direct
+    # solution, positive definiteness with a clamped face
+    dims = (4, 3, 2)
+    rho = _rand_rho(dims, 21)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    n = K.shape[0]
+    rng = np.random.default_rng(22)
+    fixed = (rng.random(n) < 0.2).astype(np.uint8)
+    A = _dense_operator(lambda u: fem.apply_constrained(K, fixed, u), n)
+    assert np.max(np.abs(A - A.T)) <= 1e-15 * np.max(np.abs(A))
+    fx = np.flatnonzero(fixed)
+    fr = np.flatnonzero(fixed == 0)
+    assert np.array_equal(A[fx][:, fx], np.eye(fx.size))
+    assert not A[fx][:, fr].any() and not A[fr][:, fx].any()
+    Kd = K.toarray()
+    assert np.max(np.abs(A[np.ix_(fr, fr)] - Kd[np.ix_(fr, fr)])) <= 1e-15 * np.max(np.abs(Kd))
+    # the direct solution satisfies A u = f (f is zero on fixed DOFs, u too)
+    fixed_c = wl.clamp_x0(dims)
+    f = wl.edge_load(dims, "bottom") + 0.5 * wl.point_load(dims, wl.node_id(dims, 2, 1, 2))
+    u = solvers.solve_direct(K, fixed_c, f)
+    assert np.max(np.abs(fem.apply_constrained(K, fixed_c, u) - f)) <= 1e-12 * np.max(np.abs(f))
+    Ac = _dense_operator(lambda v: fem.apply_constrained(K, fixed_c, v), n)
+    assert np.linalg.eigvalsh(Ac).min() > 0
+
+
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (1.0, 2.0, 0.5)])
+def test_apply_at_nodes_equals_assembled_operator_everywhere(h):
+    # the per-node oracle of the full-size apply, at EVERY node of a ragged mesh
+    # with scattered fixed DOFs, against the assembled constrained operator
+    dims = (5, 3, 4)
+    rho = _rand_rho(dims, 23)
+    Ke = fem.ke_gauss(h, 1.0, 0.3)
+    K = fem.assemble(dims, rho, Ke)
+    n = K.shape[0]
+    rng = np.random.default_rng(24)
+    fixed = (rng.random(n) < 0.15).astype(np.uint8)
+    u = rng.standard_normal(n)
+    nodes = np.arange(wl.n_nodes(dims))
+    got = fem.apply_at_nodes(dims, rho, Ke, u, nodes, fixed)
+    want = fem.apply_constrained(K, fixed, u).reshape(-1, 3)
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+    # unconstrained: no response to a rigid motion at any node
+    X = fem.node_coords(dims, h)
+    x, y, z = X.T
+    rot = np.stack([0.3 + 0.7 * y - 0.2 * z, -0.1 - 0.7 * x + 0.5 * z, 0.25 + 0.2 * x - 0.5 * y], axis=1)
+    got0 = fem.apply_at_nodes(dims, rho, Ke, rot.ravel(), nodes)
+    assert np.max(np.abs(got0)) <= 1e-13 * np.max(np.abs(Ke)) * np.max(np.abs(rot))
+
+
+def test_coarse_matrix_order_from_hand_built_motions():
+    # E(6I+a, 6J+b) = w_Ia^T K_ff w_Jb with every column built here from the
+    # physics of a rigid motion (translation e_a, rotation e_a x (x - c) about
+    # the centre c of the block's node range, coordinates in element units over
+    # the largest block edge), zero on fixed DOFs, block I = bi + nbx (bj + nby bk):
+    # pins the block and mode order the GPU coarse matrix is compared in
+    dims, block = (8, 4, 4), (4, 4, 4)          # two blocks along x
+    rho = _rand_rho(dims, 25)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    fixed = wl.clamp_x0(dims)
+    E, nb = solvers.coarse_matrix(K, fixed, dims, block)
+    assert nb == [2, 1, 1] and E.shape == (12, 12)
+    nx, ny, nz = dims
+    centres = {0: (1.5, 2.0, 2.0), 1: (6.0, 2.0, 2.0)}   # node ranges 0..3 and 4..8 along x, 0..4 in y, z
+    cols = []
+    for I in range(2):
+        c = np.array(centres[I])
+        for a in range(6):
+            w = np.zeros(3 * wl.n_nodes(dims))
+            for k in range(nz + 1):
+                for j in range(ny + 1):
+                    for i in range(nx + 1):
+                        if min(i // 4, 1) != I:
+                            continue
+                        if a < 3:
+                            d = np.eye(3)[a]
+                        else:
+                            d = np.cross(np.eye(3)[a - 3], (np.array([i, j, k]) - c) / 4.0)
+                        nid = wl.node_id(dims, i, j, k)
+                        w[3 * nid:3 * nid + 3] = d
+            w[fixed == 1] = 0.0
+            cols.append(w)
+    W = np.stack(cols, axis=1)
+    Kd = K.toarray()
+    keep = (fixed == 0).astype(float)
+    Eref = W.T @ (Kd * keep[:, None] * keep[None, :]) @ W
+    assert np.max(np.abs(E - Eref)) <= 1e-13 * np.max(np.abs(Eref))
+    # block 1 (no fixed DOF) is coupled to block 0 only through the shared elements:
+    # its rigid motions cost energy only there, so E(1, 1) is not zero but far
+    # smaller than the clamped block's
+    assert np.trace(E[6:, 6:]) < np.trace(E[:6, :6])
