@@ -11,6 +11,13 @@ away from the plane (toward +a), on the side j < p it may not increase toward
 line of elements parallel to a, the running maximum taken from each far end
 toward the plane.  Taking the maximum (never lowering a value) keeps every
 element at least as high in the ranking as before.
+
+The projected field is constant along plateaus (runs of equal running
+maxima).  A topology cut through a plateau has no cavity only if the plateau
+is cut nearer-to-the-plane first, so the extraction ranks equal values by the
+distance of the element from the parting plane along the axis
+(parting_distance: j - p on the side j >= p, p - 1 - j on the side j < p)
+before the element index.
 """
 from __future__ import annotations
 
@@ -30,3 +37,15 @@ def cast_project(phi, dims, axis, parting):
     if parting > 0:  # side j < p: running maximum from j = 0 up to p - 1
         g[..., :parting] = np.maximum.accumulate(g[..., :parting], axis=-1)
     return np.moveaxis(g, -1, npax).reshape(-1)
+
+
+def parting_distance(dims, axis, parting):
+    """Per element (x fastest), the number of elements between it and the
+    parting plane along the casting axis: j - p for j >= p, p - 1 - j for j < p."""
+    nx, ny, nz = (int(d) for d in dims)
+    n = (nx, ny, nz)[axis]
+    if not 0 <= parting <= n:
+        raise ValueError("parting index outside 0..n_axis")
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pos = (i, j, k)[axis]
+    return np.where(pos >= parting, pos - parting, parting - 1 - pos).reshape(-1).astype(np.int32)

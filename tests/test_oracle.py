@@ -273,6 +273,30 @@ def test_threshold_bruteforce(n, vf):
         assert np.all(s[solid == 1] >= tau) and np.all(s[solid == 0] <= tau)
 
 
+@pytest.mark.parametrize("n,vf", [(7, 0.5), (50, 0.3), (333, 0.475)])
+def test_threshold_tie_key_bruteforce(n, vf):
+    # a secondary key ranks equal values (ascending) before the index
+    rng = np.random.default_rng(n + 1)
+    s = rng.integers(0, 4, n).astype(float) * 0.5
+    tie = rng.integers(0, 5, n)
+    solid, tau = post.threshold(s, vf, tie)
+    ranked = sorted(range(n), key=lambda e: (-s[e], tie[e], e))
+    assert list(post.rank_order(s, tie)) == ranked
+    keep = math.ceil(vf * n)
+    want = np.zeros(n, dtype=np.uint8)
+    want[ranked[:keep]] = 1
+    assert np.array_equal(solid, want)
+    assert tau == s[ranked[keep - 1]]
+
+
+def test_signed_zeros_rank_as_equal_values():
+    # -0.0 and +0.0 are the same number: ranked by index among themselves
+    s = np.array([0.0, -0.0, 1.0, -0.0, 0.0, -1.0])
+    assert list(post.rank_order(s)) == [2, 0, 1, 3, 4, 5]
+    solid, tau = post.threshold(s, 0.5)
+    assert list(solid) == [1, 1, 1, 0, 0, 0] and tau == 0.0
+
+
 def test_coarse_matrix_structure():
     dims = (8, 4, 4)
     block = (4, 2, 2)
@@ -331,6 +355,64 @@ def test_casting_projection_is_the_least_monotone_majorant(axis):
                         assert gl[j] >= gl[j - 1]
                     assert gl[j] in set(fl[:j + 1])
         assert np.array_equal(cast_project(g, dims, axis, p), g)  # idempotent
+
+
+def test_parting_distance_worked_line():
+    # 8 elements, plane before element 3: 2 1 0 | 0 1 2 3 4
+    from oracle.casting import parting_distance
+    assert list(parting_distance((8, 1, 1), 0, 3)) == [2, 1, 0, 0, 1, 2, 3, 4]
+    assert list(parting_distance((1, 1, 8), 2, 0)) == list(range(8))
+    assert list(parting_distance((1, 8, 1), 1, 8)) == list(range(7, -1, -1))
+    with pytest.raises(ValueError):
+        parting_distance((4, 1, 1), 0, 5)
+
+
+def test_casting_plateau_cut_nearer_the_plane_first():
+    # all equal values on a line with the plane in the middle: a cut keeping 4
+    # of 8 elements keeps the 4 nearest the plane (2 on each side), not the 4
+    # lowest indices (which would leave voids between the plane and solid)
+    from oracle.casting import cast_project, parting_distance
+    phi = np.full(8, 2.0)
+    g = cast_project(phi, (8, 1, 1), 0, 4)
+    solid, _ = post.threshold(g, 0.5, parting_distance((8, 1, 1), 0, 4))
+    assert list(solid) == [0, 0, 1, 1, 1, 1, 0, 0]
+    solid_idx, _ = post.threshold(g, 0.5)
+    assert list(solid_idx) == [1, 1, 1, 1, 0, 0, 0, 0]
+
+
+def _has_cavity(solid, dims, axis, parting):
+    # along a line, a void between the plane and a solid element on either side
+    n = dims[axis]
+    lines = np.moveaxis(solid.reshape(dims[::-1]), 2 - axis, -1).reshape(-1, n)
+    for ln in lines:
+        hi = ln[parting:]
+        if hi.any() and not hi[:np.nonzero(hi)[0].max() + 1].all():
+            return True
+        lo = ln[:parting][::-1]
+        if lo.any() and not lo[:np.nonzero(lo)[0].max() + 1].all():
+            return True
+    return False
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_casting_topology_has_no_cavity(axis):
+    # the thresholded topology of a cast-projected field, ties cut by the
+    # distance to the plane, has no cavity for any parting plane; the
+    # index-only cut does leave cavities when the plane is inside the grid
+    from oracle.casting import cast_project, parting_distance
+    dims = (12, 10, 14)
+    n = dims[axis]
+    rng = np.random.default_rng(70 + axis)
+    idx_cavities = 0
+    for p in (0, 1, n // 2, n - 1, n):
+        for seed in range(4):
+            phi = rng.standard_normal(int(np.prod(dims)))
+            phi[rng.random(phi.size) < 0.3] = 0.0
+            g = cast_project(phi, dims, axis, p)
+            solid, _ = post.threshold(g, 0.4, parting_distance(dims, axis, p))
+            assert not _has_cavity(solid, dims, axis, p), (p, seed)
+            idx_cavities += _has_cavity(post.threshold(g, 0.4)[0], dims, axis, p)
+    assert idx_cavities > 0
 
 
 # ------------------------------------------------------------- constrained operator
