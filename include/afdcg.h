@@ -86,11 +86,19 @@ typedef struct {
     const int32_t* pairs; /* host array of 2*npairs RHS indices (a,b)            */
     int32_t npairs;       /* mutual-energy fields requested                      */
     int32_t max_refine;   /* MIXED: outer refinement sweeps (<=0: 30)            */
+    const double* x0;     /* start, nrhs x n_dof (host or device per mem_kind;
+                             values on fixed DOFs are ignored) or NULL: the
+                             deflated start W E^-1 W^T f.  FP64 starts from
+                             x0 + W E^-1 W^T (f - A x0); MIXED refines from x0.
+                             A warm start from a nearby solution (Sec. 3.2: the
+                             fixed-point loop re-solves after small topology
+                             changes) needs few iterations                      */
 } afd_solve_opts;
 
 typedef struct {
     int32_t iterations;       /* total CG iterations (inner, for MIXED)           */
-    int32_t refinements;      /* MIXED: outer sweeps                              */
+    int32_t refinements;      /* MIXED: outer sweeps; FP64: restarts on the true
+                                 residual                                         */
     int32_t status;           /* AFD_OK or the failure of this right-hand side    */
     int32_t coarse_dropped;   /* coarse columns dropped as rank-deficient         */
     double rel_residual_true; /* ||f - A u|| / ||f|| recomputed in FP64 at exit    */
@@ -230,24 +238,35 @@ int afd_sensitivity(afd_mesh* mesh, int32_t nrhs, const double* U,
 /* Topology at volume fraction vol_frac in [0,1] (Eq. 3.6, Sec. 3.2): the
  * ceil(vol_frac*n) elements first in the order (s descending, index
  * ascending) are solid (solid[e] = 1, else 0); *tau_host receives s of the
- * last solid element (+inf if none).  order (optional, may be NULL) receives
- * the full ranking as int32 element indices.  s, solid, order: device. */
-int afd_threshold(afd_context* ctx, const double* s, int64_t n, double vol_frac,
+ * last solid element (+inf if none).  Values compare as numbers (-0.0 ranks
+ * as +0.0).  tie (optional, may be NULL): an int32 key >= 0 per element that
+ * ranks equal values before the index, order (s descending, tie ascending,
+ * index ascending) -- for a field from afd_casting pass its dist output, so
+ * that plateaus are cut nearer the parting plane first and the topology has
+ * no cavity (Sec. 3.7).  order (optional, may be NULL) receives the full
+ * ranking as int32 element indices.  s, tie, solid, order: device.
+ * Synchronous (returns after the ranking); allocates a work space of ~24 B
+ * per element for the call. */
+int afd_threshold(afd_context* ctx, const double* s, const int32_t* tie, int64_t n, double vol_frac,
                   uint8_t* solid, int32_t* order, double* tau_host);
 
 /* Casting constraint (Sec. 3.7): out = the least element field >= phi that
  * does not increase away from the parting plane along the casting axis, so
- * that a topology extracted from it (afd_threshold) has no cavity a mould
- * drawn along the axis cannot reach.  dims = elements per axis (x fastest:
- * element ex + dims[0] (ey + dims[1] ez)); axis 0, 1 or 2; the parting plane
- * lies before element index parting along the axis (0..dims[axis]; 0 or
- * dims[axis]: one-sided casting).  Along every line of elements parallel to
- * the axis this is the running maximum from each far end toward the plane.
- * phi and out are device arrays of dims[0]*dims[1]*dims[2] doubles (finite
- * values); out may equal phi.  Exact (maxima only).  AFD_E_INVALID_ARG for a
- * bad axis, dims or parting. */
+ * that a topology extracted from it (afd_threshold with dist as the tie key)
+ * has no cavity a mould drawn along the axis cannot reach.  dims = elements
+ * per axis (x fastest: element ex + dims[0] (ey + dims[1] ez)); axis 0, 1 or
+ * 2; the parting plane lies before element index parting along the axis
+ * (0..dims[axis]; 0 or dims[axis]: one-sided casting).  Along every line of
+ * elements parallel to the axis this is the running maximum from each far
+ * end toward the plane.  phi and out are device arrays of
+ * dims[0]*dims[1]*dims[2] doubles (finite values); out may equal phi.  Exact
+ * (maxima only; a zero is written as +0.0).  dist (optional device int32
+ * array of the same size, may be NULL) receives each element's distance from
+ * the plane in elements along the axis (j - parting on the side j >= parting,
+ * parting - 1 - j before it).  AFD_E_INVALID_ARG for a bad axis, dims or
+ * parting. */
 int afd_casting(afd_context* ctx, const int32_t dims[3], const double* phi, int32_t axis, int32_t parting,
-                double* out);
+                double* out, int32_t* dist);
 
 /* ---- the whole solve ---------------------------------------------------- */
 /* Solves A U[r] = F[r] for r < nrhs (1..4) by deflated Jacobi-PCG (Sec. 3.5),
@@ -258,8 +277,15 @@ int afd_casting(afd_context* ctx, const int32_t dims[3], const double* phi, int3
  * the energy fields of afd_sensitivity (opts->pairs).  F, U, J, S are host or device per
  * opts->mem_kind.  F must be zero on fixed DOFs (AFD_E_INVALID_ARG
  * otherwise when F is on the host).  stats (host, may be NULL) receives nrhs
- * records.  Returns AFD_OK when every column converged, else the first
- * failing column's status (U holds the last iterate). */
+ * records.  A column succeeds when the true FP64 residual of the returned
+ * U[r], ||F[r] - A U[r]|| / ||F[r]|| recomputed at exit, is <= rtol: the FP64
+ * iteration stops on its recursive residual at 0.99 rtol and restarts from
+ * its iterate (up to 3 times) while the true residual is above rtol; the
+ * mixed form refines on the true residual.  Returns AFD_OK when every column
+ * succeeded, else the first failing column's status: AFD_E_NOT_CONVERGED when
+ * max_iter, the restarts or the refinement sweeps ran out above rtol (a target
+ * below the FP64 attainable accuracy of the problem ends so), AFD_E_BREAKDOWN;
+ * U then holds the last iterate. */
 int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
               const double* F, double* U, double* J, double* S, afd_solve_stats* stats);
 
@@ -270,7 +296,7 @@ typedef struct {
     const uint8_t* fixed;     /* host, n_dof               */
     const double* F;          /* host, nrhs * n_dof        */
     int32_t nrhs;
-    afd_solve_opts opts;      /* mem_kind ignored (host)   */
+    afd_solve_opts opts;      /* mem_kind ignored (host); pairs and x0 (host) copied */
 } afd_request;
 
 typedef struct {

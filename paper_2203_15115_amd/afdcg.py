@@ -57,7 +57,8 @@ class afd_mesh_desc(C.Structure):
 class afd_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("inner_rtol", C.c_double), ("check_every", C.c_int32), ("mem_kind", C.c_int32),
-                ("pairs", C.POINTER(C.c_int32)), ("npairs", C.c_int32), ("max_refine", C.c_int32)]
+                ("pairs", C.POINTER(C.c_int32)), ("npairs", C.c_int32), ("max_refine", C.c_int32),
+                ("x0", C.c_void_p)]
 
 
 class afd_solve_stats(C.Structure):
@@ -118,8 +119,8 @@ def lib():
             "afd_coarse_matrix": (C.c_int, [vp, vp]),
             "afd_coarse_solve": (C.c_int, [vp, i32, vp, vp]),
             "afd_sensitivity": (C.c_int, [vp, i32, vp, i32, vp, vp]),
-            "afd_threshold": (C.c_int, [vp, vp, i64, dbl, vp, vp, C.POINTER(dbl)]),
-            "afd_casting": (C.c_int, [vp, C.POINTER(i32), vp, i32, i32, vp]),
+            "afd_threshold": (C.c_int, [vp, vp, vp, i64, dbl, vp, vp, C.POINTER(dbl)]),
+            "afd_casting": (C.c_int, [vp, C.POINTER(i32), vp, i32, i32, vp, vp]),
             "afd_solve": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, vp, vp, vp, vp, vp]),
             "afd_server_create": (C.c_int, [vp, C.c_uint64, i32, C.POINTER(vp)]),
             "afd_server_submit": (C.c_int, [vp, C.POINTER(afd_request), C.POINTER(afd_result),
@@ -278,25 +279,26 @@ def afd_sensitivity(mesh, nrhs, U, pairs, S):
           "afd_sensitivity")
 
 
-def afd_threshold(ctx, s, n, vol_frac, solid, order=None):
+def afd_threshold(ctx, s, n, vol_frac, solid, order=None, tie=None):
     tau = C.c_double()
-    check(lib().afd_threshold(ctx, _ptr(s), n, float(vol_frac), _ptr(solid), _ptr(order), C.byref(tau)),
-          "afd_threshold")
+    check(lib().afd_threshold(ctx, _ptr(s), _ptr(tie), n, float(vol_frac), _ptr(solid), _ptr(order),
+                              C.byref(tau)), "afd_threshold")
     return tau.value
 
 
-def afd_casting(ctx, dims, phi, axis, parting, out):
+def afd_casting(ctx, dims, phi, axis, parting, out, dist=None):
     d = (C.c_int32 * 3)(*[int(x) for x in dims])
-    check(lib().afd_casting(ctx, d, _ptr(phi), int(axis), int(parting), _ptr(out)), "afd_casting")
+    check(lib().afd_casting(ctx, d, _ptr(phi), int(axis), int(parting), _ptr(out), _ptr(dist)), "afd_casting")
 
 
 def make_opts(rtol=1e-8, max_iter=20000, precision=AFD_FP64, inner_rtol=1e-4, check_every=16,
-              mem_kind=AFD_MEM_HOST, pairs=(), max_refine=30):
+              mem_kind=AFD_MEM_HOST, pairs=(), max_refine=30, x0=None):
+    """x0: start (numpy array or torch tensor per mem_kind, nrhs x n_dof) or None."""
     npairs = len(pairs)
     arr = (C.c_int32 * max(1, 2 * npairs))(*[int(v) for p in pairs for v in p])
     o = afd_solve_opts(float(rtol), int(max_iter), int(precision), float(inner_rtol), int(check_every),
-                       int(mem_kind), C.cast(arr, C.POINTER(C.c_int32)), npairs, int(max_refine))
-    o._keep = arr  # keep the pair array alive with the struct
+                       int(mem_kind), C.cast(arr, C.POINTER(C.c_int32)), npairs, int(max_refine), _ptr(x0))
+    o._keep = (arr, x0)  # keep the pair array and the start alive with the struct
     return o
 
 

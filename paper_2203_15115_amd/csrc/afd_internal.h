@@ -32,6 +32,9 @@ struct Status {
         if (_s != AFD_OK) return _s;    \
     } while (0)
 
+// AFD_OK or AFD_E_INVALID_ARG (with the message set) for a mesh description
+int validate_desc(const afd_mesh_desc& d);
+
 // ------------------------------------------------------------ element data
 // The element matrix in the tensor-product Haar basis.  Per axis, a node pair
 // (v0, v1) maps to (s, d) = (v0 + v1, v1 - v0); in that basis the isotropic
@@ -145,9 +148,6 @@ struct MatvecArgs {
 };
 struct DcgArgs {
     const double* rinv;      // nnode: 1 / sum of rho over the node's elements
-    Blocks blk;
-    int deflate;
-    const double* mu;        // [nrhs][ncoarse] (null if !deflate)
     CgScalars* sc;           // [nrhs]
     double* partial;         // [(rhs*2 + which) * npart + i]
     int npart;
@@ -175,12 +175,8 @@ int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, cons
                  hipStream_t s);
 int launch_residual(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* F,
                     const double* X, double* R, hipStream_t s);
-int launch_dir_apply(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* Pold,
-                     double* Pnew, const double* R, double* Q, hipStream_t s);
 int launch_residual_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
                         const float* F, const float* X, float* R, hipStream_t s);
-int launch_dir_apply_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
-                         const float* Pold, float* Pnew, const float* R, float* Q, hipStream_t s);
 int launch_apply_mfma(const MatvecArgs& a, const double* ke576_dev, int nrhs, const double* U, double* Y,
                       hipStream_t s);
 
@@ -226,6 +222,10 @@ int launch_restrict_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, in
                         hipStream_t s);
 int launch_prolong(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, double* V,
                    hipStream_t s);
+// X[r] += W MU[r] on free DOFs and X[r] = 0 on fixed DOFs (MU null: masking
+// only); X[r] = 0 where sc[r].done (sc may be null)
+int launch_prolong_add(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU,
+                       const CgScalars* sc, double* X, hipStream_t s);
 int launch_prolong_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU, float* V,
                        hipStream_t s);
 int launch_probe_vector(const Grid& g, const Blocks& b, const uint8_t* nmask, int color, int mode, double* V,
@@ -290,7 +290,13 @@ int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int n
                        const double* const* Ub, double* S, hipStream_t s);
 // casting projection of an element field on a dims grid (see afd_casting)
 int launch_cast(const int dims[3], int axis, int parting, const double* phi, double* out, hipStream_t s);
-int threshold_gpu(const double* s, int64_t n, double vol_frac, uint8_t* solid, int32_t* order, double* tau_host,
-                  hipStream_t st);
+int launch_parting_distance(const int dims[3], int axis, int parting, int32_t* dist, hipStream_t s);
+// ranking and threshold (see afd_threshold): threshold_run on a caller-given
+// device work space of threshold_work_bytes(n); threshold_gpu allocates it
+size_t threshold_work_bytes(int64_t n);
+int threshold_run(const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid, int32_t* order,
+                  double* tau_host, void* work, hipStream_t st);
+int threshold_gpu(const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid, int32_t* order,
+                  double* tau_host, hipStream_t st);
 
 }  // namespace afd

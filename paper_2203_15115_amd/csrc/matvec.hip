@@ -15,13 +15,12 @@
 //    corners of layer k-1 (carried in registers) plus the lower corners of
 //    layer k, and the plane is written once.
 //
-// Modes: APPLY (Y = A U), RESID (R = F - A X, with partial sums of r.M^-1 r and
-// r.r) and DIR (the deflated CG direction P' = beta P + M^-1 R - W mu formed
-// while staging, Q = A P', partial sums of p'.q).
+// Modes: APPLY (Y = A U) and RESID (R = F - A X, with partial sums of r.M^-1 r
+// and r.r).
 //
 // Kernels (same tiles, element arithmetic and summation order):
-//  * k_matvec: register-staged planes, every mode (the residual and fused
-//    direction forms, and apply variant 0);
+//  * k_matvec: register-staged planes, both modes (the residual form, and apply
+//    variant 0);
 //  * k_apply_tm: plain apply with tile-major densities and fixity words and
 //    every input staged by global_load_lds DMA (variants 2 and 3);
 //  * k_apply_bl: the same staging by untyped buffer loads, out-of-range lanes
@@ -41,7 +40,7 @@ constexpr int TX = 16, TY = 16, NT = TX * TY;  // element tile (threads)
 constexpr int PX = TX + 1, PY = TY + 1;        // node plane in LDS
 constexpr int PLANE = PX * PY * 3;
 
-enum { APPLY = 0, RESID = 1, DIR = 2 };
+enum { APPLY = 0, RESID = 1 };
 
 template <typename T>
 struct KH {
@@ -98,21 +97,14 @@ struct MvParams {
     int ndof;
     const T* rho;
     const uint8_t* nmask;
-    const T* U;     // APPLY: input; RESID: X; DIR: P (old)
-    T* Y;           // APPLY: output; RESID: R; DIR: Q
-    const T* F;     // RESID: F; DIR: R (residual)
-    T* Pn;          // DIR: new direction (owned nodes written)
+    const T* U;     // APPLY: input; RESID: X
+    T* Y;           // APPLY: output; RESID: R
+    const T* F;     // RESID: F
     int variant;             // plain-apply kernel variant
     const T* rho_t;          // tile-major densities (plain apply)
     const uint16_t* fm_t;    // tile-major face fixity words (plain apply)
     const double* rinv;  // per node 1/sum rho (double)
     const float* rinv32;
-    // deflation
-    int deflate;
-    int b[3], nb[3];
-    double inv_scale;
-    const double* mu;
-    int ncoarse;
     CgScalars* sc;
     double* partial;  // [(rhs*2 + which) * npart + i]
     int npart;
@@ -285,14 +277,10 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
     const int Z1 = min(Z0 + P.zc, P.nz + 1);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
-    const int roff = rhs * P.ndof;
+    const int64_t roff = (int64_t)rhs * P.ndof;  // nrhs * ndof may exceed 2^31
     const T* U = P.U + roff;
     T* Y = P.Y + roff;
     const T* F = (MODE != APPLY) ? P.F + roff : nullptr;
-    T* Pn = (MODE == DIR) ? P.Pn + roff : nullptr;
-    const double* mu = (MODE == DIR && P.deflate) ? P.mu + rhs * P.ncoarse : nullptr;
-    double beta = 0.0;
-    if constexpr (MODE == DIR) beta = P.sc[rhs].beta;
 
     const int gi = X0 + lx, gj = Y0 + ly;  // this thread's element (ex, ey) and owned node (i, j)
     const bool own = lx >= 1 && ly >= 1 && gi <= nx && gj <= ny;
@@ -301,45 +289,19 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
 
     // node slots this thread stages: fixed (i, j), so set up once
     int soff[NSLOT];     // plane offset, -1 outside the mesh / unused
-    int sblk[NSLOT];     // DIR: bi + nbx*bj
-    double sxx[NSLOT], syy[NSLOT];
 #pragma unroll
     for (int q = 0; q < NSLOT; ++q) {
         const int n = t + q * NT;
         soff[q] = -1;
-        sblk[q] = 0;
-        sxx[q] = syy[q] = 0.0;
         if (n < PNODES) {
             const int row = n / PX, li = n - row * PX;
             const int i = X0 + li, j = Y0 + row;
-            if (i >= 0 && i <= nx && j >= 0 && j <= ny) {
-                soff[q] = i + sy * j;
-                if constexpr (MODE == DIR) {
-                    if (P.deflate) {
-                        const int bi = min(i / P.b[0], P.nb[0] - 1), bj = min(j / P.b[1], P.nb[1] - 1);
-                        const int lo0 = bi * P.b[0], hi0 = (bi == P.nb[0] - 1) ? nx : lo0 + P.b[0] - 1;
-                        const int lo1 = bj * P.b[1], hi1 = (bj == P.nb[1] - 1) ? ny : lo1 + P.b[1] - 1;
-                        sblk[q] = bi + P.nb[0] * bj;
-                        sxx[q] = (i - 0.5 * (lo0 + hi0)) * P.inv_scale;
-                        syy[q] = (j - 0.5 * (lo1 + hi1)) * P.inv_scale;
-                    }
-                }
-            }
+            if (i >= 0 && i <= nx && j >= 0 && j <= ny) soff[q] = i + sy * j;
         }
     }
-    // global loads of plane gk into registers (masked; DIR forms the direction)
+    // global loads of plane gk into registers (masked)
     auto fetch = [&](int gk, T reg[NSLOT][3]) {
         const bool pv_ok = gk >= 0 && gk <= nz;
-        int bkoff = 0;
-        double zz = 0.0;
-        if constexpr (MODE == DIR) {
-            if (mu && pv_ok) {
-                const int bk = min(gk / P.b[2], P.nb[2] - 1);
-                const int lo2 = bk * P.b[2], hi2 = (bk == P.nb[2] - 1) ? nz : lo2 + P.b[2] - 1;
-                bkoff = P.nb[0] * P.nb[1] * bk;
-                zz = (gk - 0.5 * (lo2 + hi2)) * P.inv_scale;
-            }
-        }
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
 #pragma unroll
@@ -347,28 +309,10 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
             if (soff[q] >= 0 && pv_ok) {
                 const int node = soff[q] + sz * gk;
                 const int m = P.nmask[node];
-                if constexpr (MODE == DIR) {
-                    const double ri = rinv_of(P, node);
-                    double w[3] = {0.0, 0.0, 0.0};
-                    if (mu) {
-                        const double* mm = mu + 6 * (sblk[q] + bkoff);
-                        const double x = sxx[q], y = syy[q];
-                        w[0] = mm[0] + mm[4] * zz - mm[5] * y;
-                        w[1] = mm[1] - mm[3] * zz + mm[5] * x;
-                        w[2] = mm[2] + mm[3] * y - mm[4] * x;
-                    }
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double pv = beta * (double)U[3 * node + c] +
-                                          ri / (double)kh.kdiag[c] * (double)F[3 * node + c] - w[c];
-                        reg[q][c] = ((m >> c) & 1) ? T(0) : (T)pv;
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const T v = U[3 * node + c];
-                        reg[q][c] = ((m >> c) & 1) ? T(0) : v;
-                    }
+                for (int c = 0; c < 3; ++c) {
+                    const T v = U[3 * node + c];
+                    reg[q][c] = ((m >> c) & 1) ? T(0) : v;
                 }
             }
         }
@@ -398,7 +342,6 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
 
     T bf[4][3];                // transformed lower face of the current layer
     T ctop[4][3];              // transformed upper-face output of the previous layer
-    T own_prev[3];             // DIR: p' at the owned node, plane k
     double acc0 = 0.0, acc1 = 0.0;
     T reg[NSLOT][3];
 #pragma unroll
@@ -412,8 +355,6 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
     put(1, reg);
     __syncthreads();
     read_face(0, bf);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) own_prev[c] = bf[0][c];
     face_fwd<T>(bf);
     T rho_cur = rho_at(Z0 - 1);
     int buf = 1;  // buffer holding plane k+1
@@ -438,16 +379,6 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
         }
         T tf[4][3];
         read_face(buf, tf);
-        T own_next[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) own_next[c] = tf[0][c];
-        if constexpr (MODE == DIR) {  // owned nodes of plane k+1 write the new direction
-            if (own && k + 1 >= Z0 && k + 1 < Z1) {
-                const int a = 3 * (own_node + sz * (k + 1));
-#pragma unroll
-                for (int c = 0; c < 3; ++c) Pn[a + c] = tf[0][c];
-            }
-        }
         face_fwd<T>(tf);
         T yb[4][3], yt[4][3];
         element_haar<T, CUB>(kh, rho_cur, bf, tf, yb, yt);
@@ -481,22 +412,16 @@ __global__ __launch_bounds__(NT) void k_matvec(MvParams<T> P, KH<T> kh) {
                 const bool fx = (m >> c) & 1;
                 if constexpr (MODE == APPLY) {
                     pend[c] = fx ? U[a] : yv;
-                } else if constexpr (MODE == RESID) {
+                } else {  // RESID
                     const T rv = fx ? T(0) : (T)(F[a] - yv);
                     pend[c] = rv;
                     const double z = rinv_of(P, node) / (double)kh.kdiag[c] * (double)rv;
                     acc0 += (double)rv * z;
                     acc1 += (double)rv * (double)rv;
-                } else {  // DIR: q = A p' (p' = 0 on fixed DOFs, so q = 0 there)
-                    const T qv = fx ? T(0) : yv;
-                    pend[c] = qv;
-                    acc0 += (double)own_prev[c] * (double)qv;
                 }
             }
             pend_a = 3 * node;
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) own_prev[c] = own_next[c];
         // stage plane k+2 into the buffer that held plane k (read last layer)
         if (more) put(buf ^ 1, reg);
         buf ^= 1;
@@ -812,7 +737,7 @@ __global__ __launch_bounds__(NT) void k_apply_tm(MvParams<T> P, KH<T> kh) {
     const int Z1 = min(Z0 + P.zc, P.nz + 1);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
-    const int roff = rhs * P.ndof;
+    const int64_t roff = (int64_t)rhs * P.ndof;  // nrhs * ndof may exceed 2^31
     const T* U = P.U + roff;
     T* Y = P.Y + roff;
     const uint32_t* Udw = reinterpret_cast<const uint32_t*>(U);
@@ -1068,7 +993,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int Z1 = min(Z0 + P.zc, P.nz + 1);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
-    const int roff = rhs * P.ndof;
+    const int64_t roff = (int64_t)rhs * P.ndof;  // nrhs * ndof may exceed 2^31
     const T* U = P.U + roff;
     T* Y = P.Y + roff;
     const T* Rt = P.rho_t + (size_t)tile * nz * NT;
@@ -1247,22 +1172,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
 }
 
-int g_zc_override = -1;
-int g_variant = -1;
-
 // plain-apply kernel: 0 register staging; 2 / 3 the tile-major DMA kernel with
 // 1 / 2 layers per step; 4 / 6 the buffer-load kernel with a prefetch distance
-// of 2 / 1 layers (AFD_APPLY_KERNEL; the autotuner picks per mesh)
+// of 2 / 1 layers (6 is the default; the autotuner or afd_mesh_apply_config
+// pick another per mesh)
 bool valid_variant(int v) { return v == 0 || v == 2 || v == 3 || v == 4 || v == 6; }
-int apply_variant() {
-    if (g_variant < 0) {
-        const char* e = getenv("AFD_APPLY_KERNEL");
-        int v = e ? atoi(e) : 6;
-        if (!valid_variant(v)) v = 6;
-        g_variant = v;
-    }
-    return g_variant;
-}
+constexpr int DEFAULT_VARIANT = 6;
+int apply_variant() { return DEFAULT_VARIANT; }
 // buffer-load kernels address a node plane with 32-bit byte offsets
 template <typename T>
 int usable_variant(int v, const Grid& g) {
@@ -1292,10 +1208,6 @@ int g_slots[8][2];  // resident 256-thread workgroups per (apply variant, FP32) 
 void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, int& zc, int& nchunk) {
     tx = (g.nx + 1 + (TX - 2)) / (TX - 1);  // ceil((nx+1)/15)
     ty = (g.ny + 1 + (TY - 2)) / (TY - 1);
-    if (g_zc_override < 0) {
-        const char* e = getenv("AFD_MATVEC_ZC");
-        g_zc_override = e ? atoi(e) : 0;
-    }
     if (!valid_variant(variant)) variant = apply_variant();
     if (g_slots[variant][fp32] <= 0) {
         int dev = 0, cus = 256, per = fp32 ? 4 : 2;
@@ -1308,8 +1220,6 @@ void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, 
     const int planes = g.nz + 1;
     if (zc_req > 0) {
         zc = zc_req;
-    } else if (g_zc_override > 0) {
-        zc = g_zc_override;
     } else {
         int want = g_slots[variant][fp32] / (tx * ty);
         if (want < 1) want = 1;
@@ -1440,14 +1350,6 @@ int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, cons
 template <typename T>
 static void set_dcg(MvParams<T>& p, const DcgArgs& d) {
     p.rinv = d.rinv;
-    p.deflate = d.deflate;
-    for (int i = 0; i < 3; ++i) {
-        p.b[i] = d.blk.b[i];
-        p.nb[i] = d.blk.nb[i];
-    }
-    p.inv_scale = d.blk.inv_scale;
-    p.mu = d.mu;
-    p.ncoarse = d.blk.ncoarse;
     p.sc = d.sc;
     p.partial = d.partial;
     p.npart = d.npart;
@@ -1461,17 +1363,6 @@ int launch_residual(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int
     p.Y = R;
     p.F = F;
     return launch<double, RESID>(p, kh, nrhs, s);
-}
-
-int launch_dir_apply(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* Pold,
-                     double* Pnew, const double* R, double* Q, hipStream_t s) {
-    MvParams<double> p = base_params<double>(a);
-    set_dcg(p, d);
-    p.U = Pold;
-    p.Pn = Pnew;
-    p.F = R;
-    p.Y = Q;
-    return launch<double, DIR>(p, kh, nrhs, s);
 }
 
 template <typename T>
@@ -1525,18 +1416,6 @@ int launch_residual_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d,
     p.Y = R;
     p.F = F;
     return launch<float, RESID>(p, kh, nrhs, s);
-}
-
-int launch_dir_apply_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
-                         const float* Pold, float* Pnew, const float* R, float* Q, hipStream_t s) {
-    MvParams<float> p = base_params<float>(a);
-    set_dcg(p, d);
-    p.rinv32 = rinv32;
-    p.U = Pold;
-    p.Pn = Pnew;
-    p.F = R;
-    p.Y = Q;
-    return launch<float, DIR>(p, kh, nrhs, s);
 }
 
 }  // namespace afd

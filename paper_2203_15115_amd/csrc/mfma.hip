@@ -55,8 +55,8 @@ __global__ __launch_bounds__(NT) void k_matvec_mfma(MfP P) {
     const int Z1 = min(Z0 + P.zc, P.nz + 1);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int64_t sy = nx + 1, sz = (int64_t)(nx + 1) * (ny + 1);
-    const double* U = P.U + rhs * P.ndof;
-    double* Y = P.Y + rhs * P.ndof;
+    const double* U = P.U + (int64_t)rhs * P.ndof;
+    double* Y = P.Y + (int64_t)rhs * P.ndof;
     const int gi = X0 + lx, gj = Y0 + ly;
     const bool own = lx >= 1 && ly >= 1 && gi <= nx && gj <= ny;
     const bool elem_xy = gi >= 0 && gi < nx && gj >= 0 && gj < ny;

@@ -96,15 +96,37 @@ constexpr int RS_T = 256;     // threads
 constexpr int RS_R = 8;       // rounds (keys per thread)
 constexpr int RS_TILE = RS_T * RS_R;
 
-// Orders doubles descending (NaN last among equal bit patterns is irrelevant
-// here), as an unsigned key ascending.
+// Orders doubles descending as an unsigned key ascending.  -0.0 is keyed as
+// +0.0 (equal numbers rank by the next key, not by their bit patterns).
+__device__ __forceinline__ uint64_t desc_key(double v) {
+    if (v == 0.0) v = 0.0;
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    b = (b >> 63) ? ~b : (b | 0x8000000000000000ull);  // ascending order of the double
+    return ~b;                                         // descending
+}
+
+// keys of s in element order, payload = element index
 __global__ void k_make_keys(int64_t n, const double* s, uint64_t* key, int32_t* idx) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint64_t b = (uint64_t)__double_as_longlong(s[i]);
-    b = (b >> 63) ? ~b : (b | 0x8000000000000000ull);  // ascending order of the double
-    key[i] = ~b;                                       // descending
+    key[i] = desc_key(s[i]);
     idx[i] = (int32_t)i;
+}
+
+// secondary (tie) keys in element order: sorted first, so that the stable
+// passes over s keep (tie, index) order among equal values
+__global__ void k_make_tie_keys(int64_t n, const int32_t* tie, uint64_t* key, int32_t* idx) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = (uint64_t)(uint32_t)tie[i];
+    idx[i] = (int32_t)i;
+}
+
+// keys of s in the current order of the payload
+__global__ void k_make_keys_perm(int64_t n, const double* s, const int32_t* idx, uint64_t* key) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = desc_key(s[idx[i]]);
 }
 
 __global__ void k_hist(int64_t n, const uint64_t* key, int shift, uint32_t* hist, int ntiles) {
@@ -197,7 +219,8 @@ __global__ void k_scatter(int64_t n, const uint64_t* kin, const int32_t* iin, ui
 // Casting projection (Sec. 3.7): a running maximum along every line of
 // elements parallel to the casting axis, from each far end toward the parting
 // plane (elements j >= parting from the last one down, j < parting from the
-// first one up).  Maxima are exact: any evaluation order gives the same bits.
+// first one up).  Maxima are exact: any evaluation order gives the same value
+// (a zero is stored as +0.0, whichever signed zero fmax returned).
 // Along y and z (strided lines): a workgroup takes 64 consecutive lines (one
 // wavefront reads 64 consecutive elements per step) and cuts each side of
 // every line into 4 chunks, one wavefront per chunk: the chunk maxima go
@@ -238,11 +261,11 @@ __global__ __launch_bounds__(256) void k_cast_yz(int nx, int ny, int nz, int axi
     }
     for (int j = hi; j >= lo; --j) {
         run = fmax(run, phi[base + j * stride]);
-        out[base + j * stride] = run;
+        out[base + j * stride] = run == 0.0 ? 0.0 : run;
     }
     for (int j = lo2; j <= hi2; ++j) {
         run2 = fmax(run2, phi[base + j * stride]);
-        out[base + j * stride] = run2;
+        out[base + j * stride] = run2 == 0.0 ? 0.0 : run2;
     }
 }
 
@@ -264,7 +287,7 @@ __global__ void k_cast_x(int nx, int lines, int parting, const double* phi, doub
             if (lane >= off) v = fmax(v, o);
         }
         v = fmax(v, carry);
-        if (j >= parting) out[base + j] = v;
+        if (j >= parting) out[base + j] = v == 0.0 ? 0.0 : v;
         carry = __shfl(v, 63, 64);
     }
     carry = -INFINITY;
@@ -277,9 +300,20 @@ __global__ void k_cast_x(int nx, int lines, int parting, const double* phi, doub
             if (lane >= off) v = fmax(v, o);
         }
         v = fmax(v, carry);
-        if (j < parting) out[base + j] = v;
+        if (j < parting) out[base + j] = v == 0.0 ? 0.0 : v;
         carry = __shfl(v, 63, 64);
     }
+}
+
+// distance of every element from the parting plane along the casting axis:
+// j - parting for j >= parting, parting - 1 - j below (the tie key that cuts
+// plateaus of the projected field nearer the plane first)
+__global__ void k_parting_distance(int nx, int ny, int nz, int axis, int parting, int32_t* dist) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nx * ny * nz) return;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int j = axis == 0 ? (int)(e % nx) : (axis == 1 ? (int)((e % sxy) / nx) : (int)(e / sxy));
+    dist[e] = j >= parting ? j - parting : parting - 1 - j;
 }
 
 __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* solid, int32_t* order_out) {
@@ -291,6 +325,14 @@ __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* s
 }
 
 }  // namespace
+
+int launch_parting_distance(const int dims[3], int axis, int parting, int32_t* dist, hipStream_t s) {
+    const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+    hipLaunchKernelGGL(k_parting_distance, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dims[0], dims[1],
+                       dims[2], axis, parting, dist);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
 
 int launch_cast(const int dims[3], int axis, int parting, const double* phi, double* out, hipStream_t s) {
     const int lines = axis == 0 ? dims[1] * dims[2] : (axis == 1 ? dims[0] * dims[2] : dims[0] * dims[1]);
@@ -329,67 +371,84 @@ int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int n
     return AFD_OK;
 }
 
-int threshold_gpu(const double* s, int64_t n, double vol_frac, uint8_t* solid, int32_t* order, double* tau_host,
-                  hipStream_t st) {
+size_t threshold_work_bytes(int64_t n) {
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    // k0, k1 (8 B), i0, i1 (4 B) per key, 256 counters per tile, 256 digit totals;
+    // each part rounded to 256 B
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return 2 * r((size_t)n * 8) + 2 * r((size_t)n * 4) + r((size_t)256 * ntiles * 4) + r(256 * 4);
+}
+
+int threshold_run(const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid, int32_t* order,
+                  double* tau_host, void* work, hipStream_t st) {
     if (n <= 0 || n > 0x7fffffff || !(vol_frac >= 0.0 && vol_frac <= 1.0)) {
         set_error("threshold: need 0 < n < 2^31 and 0 <= vol_frac <= 1");
         return AFD_E_INVALID_ARG;
     }
     const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
-    uint64_t *k0 = nullptr, *k1 = nullptr;
-    int32_t *i0 = nullptr, *i1 = nullptr;
-    uint32_t *hist = nullptr, *dtot = nullptr;
-    int rc = AFD_OK;
-    if (hipMalloc((void**)&k0, n * 8) != hipSuccess || hipMalloc((void**)&k1, n * 8) != hipSuccess ||
-        hipMalloc((void**)&i0, n * 4) != hipSuccess || hipMalloc((void**)&i1, n * 4) != hipSuccess ||
-        hipMalloc((void**)&hist, (size_t)256 * ntiles * 4) != hipSuccess ||
-        hipMalloc((void**)&dtot, 256 * 4) != hipSuccess) {
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char* p = (char*)work;
+    uint64_t* k0 = (uint64_t*)p;
+    p += r((size_t)n * 8);
+    uint64_t* k1 = (uint64_t*)p;
+    p += r((size_t)n * 8);
+    int32_t* i0 = (int32_t*)p;
+    p += r((size_t)n * 4);
+    int32_t* i1 = (int32_t*)p;
+    p += r((size_t)n * 4);
+    uint32_t* hist = (uint32_t*)p;
+    p += r((size_t)256 * ntiles * 4);
+    uint32_t* dtot = (uint32_t*)p;
+    const dim3 eg((unsigned)((n + 255) / 256));
+    auto pass = [&](int shift) {
+        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(RS_T), 0, st, n, k0, shift, hist, ntiles);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(256), dim3(256), 0, st, hist, ntiles, dtot);
+        hipLaunchKernelGGL(k_scan_digits, dim3(1), dim3(64), 0, st, dtot);
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(RS_T), 0, st, n, k0, i0, k1, i1, shift, hist, ntiles, dtot);
+        std::swap(k0, k1);
+        std::swap(i0, i1);
+    };
+    if (tie) {
+        // stable LSD passes: the tie key first, then the 8 bytes of the s key
+        hipLaunchKernelGGL(k_make_tie_keys, eg, dim3(256), 0, st, n, tie, k0, i0);
+        for (int b = 0; b < 4; ++b) pass(8 * b);
+        hipLaunchKernelGGL(k_make_keys_perm, eg, dim3(256), 0, st, n, s, i0, k0);
+    } else {
+        hipLaunchKernelGGL(k_make_keys, eg, dim3(256), 0, st, n, s, k0, i0);
+    }
+    for (int b = 0; b < 8; ++b) pass(8 * b);
+    int64_t keep = (int64_t)std::ceil(vol_frac * (double)n);
+    if (keep > n) keep = n;
+    if (keep < 0) keep = 0;
+    hipLaunchKernelGGL(k_mark, eg, dim3(256), 0, st, n, keep, i0, solid, order);
+    AFD_HIP_TRY(hipGetLastError());
+    if (tau_host) {
+        *tau_host = INFINITY;
+        if (keep > 0) {
+            int32_t e = 0;
+            AFD_HIP_TRY(hipMemcpyAsync(&e, i0 + keep - 1, 4, hipMemcpyDeviceToHost, st));
+            AFD_HIP_TRY(hipStreamSynchronize(st));
+            AFD_HIP_TRY(hipMemcpyAsync(tau_host, s + e, 8, hipMemcpyDeviceToHost, st));
+        }
+    }
+    AFD_HIP_TRY(hipStreamSynchronize(st));
+    return AFD_OK;
+}
+
+int threshold_gpu(const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid, int32_t* order,
+                  double* tau_host, hipStream_t st) {
+    if (n <= 0 || n > 0x7fffffff) {
+        set_error("threshold: need 0 < n < 2^31 and 0 <= vol_frac <= 1");
+        return AFD_E_INVALID_ARG;
+    }
+    void* work = nullptr;
+    if (hipMalloc(&work, threshold_work_bytes(n)) != hipSuccess) {
         set_error("threshold: out of device memory");
-        rc = AFD_E_OOM;
+        return AFD_E_OOM;
     }
-    if (rc == AFD_OK) {
-        hipLaunchKernelGGL(k_make_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, k0, i0);
-        for (int pass = 0; pass < 8; ++pass) {
-            const int shift = 8 * pass;
-            hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(RS_T), 0, st, n, k0, shift, hist, ntiles);
-            hipLaunchKernelGGL(k_scan_tiles, dim3(256), dim3(256), 0, st, hist, ntiles, dtot);
-            hipLaunchKernelGGL(k_scan_digits, dim3(1), dim3(64), 0, st, dtot);
-            hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(RS_T), 0, st, n, k0, i0, k1, i1, shift, hist, ntiles,
-                               dtot);
-            std::swap(k0, k1);
-            std::swap(i0, i1);
-        }
-        int64_t keep = (int64_t)std::ceil(vol_frac * (double)n);
-        if (keep > n) keep = n;
-        if (keep < 0) keep = 0;
-        hipLaunchKernelGGL(k_mark, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, keep, i0, solid, order);
-        if (hipGetLastError() != hipSuccess) {
-            set_error("threshold: kernel launch failed");
-            rc = AFD_E_HIP;
-        }
-        if (rc == AFD_OK && tau_host) {
-            *tau_host = INFINITY;
-            if (keep > 0) {
-                int32_t e = 0;
-                if (hipMemcpyAsync(&e, i0 + keep - 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                    hipStreamSynchronize(st) != hipSuccess ||
-                    hipMemcpyAsync(tau_host, s + e, 8, hipMemcpyDeviceToHost, st) != hipSuccess) {
-                    set_error("threshold: copy failed");
-                    rc = AFD_E_HIP;
-                }
-            }
-        }
-        if (hipStreamSynchronize(st) != hipSuccess && rc == AFD_OK) {
-            set_error("threshold: stream sync failed");
-            rc = AFD_E_HIP;
-        }
-    }
-    (void)hipFree(k0);
-    (void)hipFree(k1);
-    (void)hipFree(i0);
-    (void)hipFree(i1);
-    (void)hipFree(hist);
-    (void)hipFree(dtot);
+    const int rc = threshold_run(s, tie, n, vol_frac, solid, order, tau_host, work, st);
+    if (rc != AFD_OK) (void)hipStreamSynchronize(st);  // no kernel may still use the work space
+    (void)hipFree(work);
     return rc;
 }
 

@@ -33,7 +33,7 @@ double clock_s() {
 struct Req {
     uint64_t ticket;
     afd_mesh_desc desc;
-    std::vector<double> rho, F;
+    std::vector<double> rho, F, x0;
     std::vector<uint8_t> fixed;
     std::vector<int32_t> pairs;
     int nrhs;
@@ -121,6 +121,7 @@ void run_job(afd_server* S, int si) {
         afd_solve_opts o = r.opts;
         o.mem_kind = AFD_MEM_HOST;
         o.pairs = r.pairs.empty() ? nullptr : r.pairs.data();
+        o.x0 = r.x0.empty() ? nullptr : r.x0.data();
         double* Uout = res->U;
         if (!Uout) {
             U.resize(r.F.size());
@@ -137,6 +138,11 @@ void run_job(afd_server* S, int si) {
     res->status = rc;
     {
         std::lock_guard<std::mutex> lk(S->mu);
+        // a slot without a mesh (never created, or freed above) holds no memory
+        if (!sl.mesh) {
+            S->used -= sl.mesh_bytes;
+            sl.mesh_bytes = 0;
+        }
         S->status[r.ticket] = rc;
         sl.job.reset();
         sl.busy = false;
@@ -188,25 +194,27 @@ void sched_loop(afd_server* S) {
                 }
             }
             if (pick < 0) {
-                // evict idle resident meshes to make room, then retry when a slot frees
+                // evict the idle resident meshes to make room: their charges are
+                // released under the lock, the meshes are freed (hipFree) outside
+                // it, by this thread, before any slot is given new work; then retry
+                std::vector<afd_mesh*> evict;
+                bool released = false;
                 for (auto& s : S->slots)
-                    if (!s.busy && s.mesh) {
-                        afd_mesh_destroy(s.mesh);
+                    if (!s.busy && s.mesh_bytes > 0) {
+                        if (s.mesh) evict.push_back(s.mesh);
                         s.mesh = nullptr;
                         S->used -= s.mesh_bytes;
                         s.mesh_bytes = 0;
+                        released = true;
                     }
-                bool fits = false;
-                for (size_t i = 0; i < S->slots.size(); ++i)
-                    if (!S->slots[i].busy && S->used + head.bytes <= S->budget) {
-                        pick = (int)i;
-                        fits = true;
-                        break;
-                    }
-                if (!fits) {
-                    S->cv_sched.wait(lk);  // wait for a running request to finish
+                if (released) {
+                    lk.unlock();
+                    for (afd_mesh* mh : evict) afd_mesh_destroy(mh);
+                    lk.lock();
                     continue;
                 }
+                S->cv_sched.wait(lk);  // nothing idle to evict: wait for a running request to finish
+                continue;
             }
         }
         Slot& s = S->slots[pick];
@@ -267,11 +275,18 @@ int afd_server_create(afd_context* ctx, uint64_t budget, int32_t max_slots, afd_
 
 int afd_server_submit(afd_server* S, const afd_request* q, afd_result* res, uint64_t* ticket) {
     if (!S || !q || !res || !ticket || !q->rho || !q->fixed || !q->F || q->nrhs < 1 || q->nrhs > 4 ||
-        q->desc.nx < 1 || q->desc.ny < 1 || q->desc.nz < 1 || q->opts.npairs < 0 ||
-        (q->opts.npairs > 0 && !q->opts.pairs)) {
+        q->opts.npairs < 0 || q->nrhs + q->opts.npairs > 16 || (q->opts.npairs > 0 && !q->opts.pairs) ||
+        !(q->opts.rtol > 0) || q->opts.max_iter < 1 ||
+        (q->opts.precision != AFD_FP64 && q->opts.precision != AFD_MIXED)) {
         afd::set_error("server_submit: bad request");
         return AFD_E_INVALID_ARG;
     }
+    for (int p = 0; p < 2 * q->opts.npairs; ++p)
+        if (q->opts.pairs[p] < 0 || q->opts.pairs[p] >= q->nrhs) {
+            afd::set_error("server_submit: pair index out of range");
+            return AFD_E_INVALID_ARG;
+        }
+    AFD_TRY(afd::validate_desc(q->desc));
     const afd_mesh_desc& d = q->desc;
     const int64_t ne = (int64_t)d.nx * d.ny * d.nz, nd = 3 * (int64_t)(d.nx + 1) * (d.ny + 1) * (d.nz + 1);
     auto r = std::make_unique<Req>();
@@ -279,7 +294,8 @@ int afd_server_submit(afd_server* S, const afd_request* q, afd_result* res, uint
     r->rho.assign(q->rho, q->rho + ne);
     r->fixed.assign(q->fixed, q->fixed + nd);
     r->F.assign(q->F, q->F + nd * q->nrhs);
-    r->pairs.assign(q->opts.pairs, q->opts.pairs + 2 * q->opts.npairs);
+    if (q->opts.npairs > 0) r->pairs.assign(q->opts.pairs, q->opts.pairs + 2 * q->opts.npairs);
+    if (q->opts.x0) r->x0.assign(q->opts.x0, q->opts.x0 + nd * q->nrhs);
     r->nrhs = q->nrhs;
     r->opts = q->opts;
     r->res = res;

@@ -388,6 +388,29 @@ __global__ void k_prolong(BlkP p, const uint8_t* nm, int nrhs, int64_t nnode, co
     v[2] = (mk & 4) ? T(0) : (T)(m[2] + m[3] * x[1] - m[4] * x[0]);
 }
 
+// X[r] += W MU[r] on free DOFs, X[r] = 0 on fixed DOFs (the coarse correction
+// of a warm start, x0 = x + W E^-1 W^T (b - A x)); MU null: only the masking
+// A right-hand side already marked done (a zero b) gets X[r] = 0.
+__global__ void k_prolong_add(BlkP p, const uint8_t* nm, int64_t nnode, const double* MU, const CgScalars* sc,
+                              double* X) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;  // 3 nnode < 2^31 (checked at mesh creation)
+    if (n >= nnode) return;
+    const int r = blockIdx.y;
+    const uint8_t mk = sc && sc[r].done ? 7 : nm[n];
+    double* v = X + (int64_t)r * 3 * nnode + 3 * (int64_t)n;
+    double d[3] = {0.0, 0.0, 0.0};
+    if (MU) {
+        int bb[3];
+        double x[3];
+        node_block(p, n, bb, x);
+        const double* mu = MU + (int64_t)r * p.ncoarse + 6 * (bb[0] + p.nb[0] * (bb[1] + p.nb[1] * bb[2]));
+        d[0] = mu[0] + mu[4] * x[2] - mu[5] * x[1];
+        d[1] = mu[1] - mu[3] * x[2] + mu[5] * x[0];
+        d[2] = mu[2] + mu[3] * x[1] - mu[4] * x[0];
+    }
+    for (int c = 0; c < 3; ++c) v[c] = ((mk >> c) & 1) ? 0.0 : v[c] + d[c];
+}
+
 // p' = beta p + M^-1 r - W mu (zero on fixed DOFs), the direction update of
 // the deflated PCG; one thread per node, skipped for converged right-hand sides
 template <typename T>
@@ -602,6 +625,14 @@ int launch_prolong(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrh
                    hipStream_t s) {
     hipLaunchKernelGGL((k_prolong<double>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, nrhs,
                        g.nnode, MU, V, -1, 0);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_prolong_add(const Grid& g, const Blocks& b, const uint8_t* nmask, int nrhs, const double* MU,
+                       const CgScalars* sc, double* X, hipStream_t s) {
+    hipLaunchKernelGGL(k_prolong_add, dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, g.nnode, MU,
+                       sc, X);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
