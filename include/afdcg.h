@@ -250,6 +250,19 @@ int afd_sensitivity(afd_mesh* mesh, int32_t nrhs, const double* U,
 int afd_threshold(afd_context* ctx, const double* s, const int32_t* tie, int64_t n, double vol_frac,
                   uint8_t* solid, int32_t* order, double* tau_host);
 
+/* afd_threshold for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, results and synchronisation, but the ranking's work space
+ * is a static device array of the library (49 MiB, held on every GPU the
+ * library runs on until the process ends), so the call makes no hipMalloc,
+ * hipFree or other allocating call.  n must be <= AFD_THRESHOLD_NOALLOC_MAX
+ * (AFD_E_INVALID_ARG otherwise).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (two threads, or streams of two contexts)
+ * race and must be serialised by the caller. */
+#define AFD_THRESHOLD_NOALLOC_MAX 2097152
+int afd_threshold_noalloc(afd_context* ctx, const double* s, const int32_t* tie, int64_t n, double vol_frac,
+                          uint8_t* solid, int32_t* order, double* tau_host);
+
 /* Casting constraint (Sec. 3.7): out = the least element field >= phi that
  * does not increase away from the parting plane along the casting axis, so
  * that a topology extracted from it (afd_threshold with dist as the tie key)

@@ -42,7 +42,7 @@ EXPORTED = [
     "afd_jacobi",
     "afd_dot",
     "afd_restrict", "afd_prolong", "afd_coarse_setup", "afd_coarse_matrix", "afd_coarse_solve",
-    "afd_sensitivity", "afd_threshold", "afd_solve", "afd_server_create", "afd_server_submit",
+    "afd_sensitivity", "afd_threshold", "afd_threshold_noalloc", "afd_solve", "afd_server_create", "afd_server_submit",
     "afd_server_poll", "afd_server_wait", "afd_server_clock", "afd_server_destroy",
 ]
 
@@ -120,6 +120,7 @@ def lib():
             "afd_coarse_solve": (C.c_int, [vp, i32, vp, vp]),
             "afd_sensitivity": (C.c_int, [vp, i32, vp, i32, vp, vp]),
             "afd_threshold": (C.c_int, [vp, vp, vp, i64, dbl, vp, vp, C.POINTER(dbl)]),
+            "afd_threshold_noalloc": (C.c_int, [vp, vp, vp, i64, dbl, vp, vp, C.POINTER(dbl)]),
             "afd_casting": (C.c_int, [vp, C.POINTER(i32), vp, i32, i32, vp, vp]),
             "afd_solve": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, vp, vp, vp, vp, vp]),
             "afd_server_create": (C.c_int, [vp, C.c_uint64, i32, C.POINTER(vp)]),
@@ -283,6 +284,16 @@ def afd_threshold(ctx, s, n, vol_frac, solid, order=None, tie=None):
     tau = C.c_double()
     check(lib().afd_threshold(ctx, _ptr(s), _ptr(tie), n, float(vol_frac), _ptr(solid), _ptr(order),
                               C.byref(tau)), "afd_threshold")
+    return tau.value
+
+
+AFD_THRESHOLD_NOALLOC_MAX = 2097152
+
+
+def afd_threshold_noalloc(ctx, s, n, vol_frac, solid, order=None, tie=None):
+    tau = C.c_double()
+    check(lib().afd_threshold_noalloc(ctx, _ptr(s), _ptr(tie), n, float(vol_frac), _ptr(solid), _ptr(order),
+                                      C.byref(tau)), "afd_threshold_noalloc")
     return tau.value
 
 

@@ -298,5 +298,12 @@ int threshold_run(const double* s, const int32_t* tie, int64_t n, double vol_fra
                   double* tau_host, void* work, hipStream_t st);
 int threshold_gpu(const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid, int32_t* order,
                   double* tau_host, hipStream_t st);
+// the allocation-free form: the work space is a static device array of
+// THRESHOLD_NOALLOC_BYTES (threshold_work_bytes(AFD_THRESHOLD_NOALLOC_MAX))
+// whose per-device address threshold_scratch_init takes (device current)
+constexpr size_t THRESHOLD_NOALLOC_BYTES = 51381248;
+int threshold_scratch_init(int device);
+int threshold_noalloc(int device, const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid,
+                      int32_t* order, double* tau_host, hipStream_t st);
 
 }  // namespace afd

@@ -520,6 +520,14 @@ int afd_context_create(int device, void* hip_stream, afd_context** out) {
         set_error("device allocation failed");
         return AFD_E_OOM;
     }
+    // device address of this GPU's static work space of afd_threshold_noalloc
+    const int rc = threshold_scratch_init(device);
+    if (rc != AFD_OK) {
+        (void)hipFree(c->scratch);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return rc;
+    }
     *out = c;
     return AFD_OK;
 }
@@ -957,6 +965,16 @@ int afd_threshold(afd_context* c, const double* s, const int32_t* tie, int64_t n
         return AFD_E_INVALID_ARG;
     }
     return threshold_gpu(s, tie, n, vol_frac, solid, order, tau, c->stream);
+}
+
+int afd_threshold_noalloc(afd_context* c, const double* s, const int32_t* tie, int64_t n, double vol_frac,
+                          uint8_t* solid, int32_t* order, double* tau) {
+    AFD_TRY(check_ctx(c));
+    if (!s || !solid) {
+        set_error("threshold_noalloc: null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    return threshold_noalloc(c->device, s, tie, n, vol_frac, solid, order, tau, c->stream);
 }
 
 int afd_casting(afd_context* c, const int32_t dims[3], const double* phi, int32_t axis, int32_t parting,

@@ -4,6 +4,7 @@
 // (Eq. 3.6 with the cutting value set by the target volume, Sec. 3.2).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "afd_internal.h"
@@ -433,6 +434,59 @@ int threshold_run(const double* s, const int32_t* tie, int64_t n, double vol_fra
     }
     AFD_HIP_TRY(hipStreamSynchronize(st));
     return AFD_OK;
+}
+
+// ---- the allocation-free ranking (afd_threshold_noalloc) ----------------
+// Its work space is one file-scope device array, `scratch`, sized for
+// AFD_THRESHOLD_NOALLOC_MAX keys; every GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): the device
+// address of each GPU's copy is taken once per device, with that device
+// current, when a context is created on it, and kept here.
+static __device__ __align__(256) char scratch[THRESHOLD_NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+static void* g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+int threshold_scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) {
+        set_error("threshold scratch: device index beyond 63");
+        return AFD_E_NO_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return AFD_OK;
+    void* ptr = nullptr;
+    AFD_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));  // the current device's copy
+    if (!ptr) {
+        set_error("threshold scratch: no device address");
+        return AFD_E_HIP;
+    }
+    g_scratch_ptr[device] = ptr;
+    return AFD_OK;
+}
+
+int threshold_noalloc(int device, const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid,
+                      int32_t* order, double* tau_host, hipStream_t st) {
+    static_assert(THRESHOLD_NOALLOC_BYTES >= 2 * (8 << 21) + 2 * (4 << 21) + 256 * 1024 * 4 + 1024,
+                  "scratch smaller than the work space of AFD_THRESHOLD_NOALLOC_MAX keys");
+    if (n <= 0 || n > AFD_THRESHOLD_NOALLOC_MAX) {
+        set_error("threshold_noalloc: need 0 < n <= AFD_THRESHOLD_NOALLOC_MAX (2097152)");
+        return AFD_E_INVALID_ARG;
+    }
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device >= 0 && device < MAX_DEVICES) ptr = g_scratch_ptr[device];
+    }
+    if (!ptr) {
+        set_error("threshold_noalloc: scratch address not set up for this device");
+        return AFD_E_HIP;
+    }
+    if (threshold_work_bytes(n) > THRESHOLD_NOALLOC_BYTES) {
+        set_error("threshold_noalloc: work space beyond the scratch array");
+        return AFD_E_INVALID_ARG;
+    }
+    return threshold_run(s, tie, n, vol_frac, solid, order, tau_host, ptr, st);
 }
 
 int threshold_gpu(const double* s, const int32_t* tie, int64_t n, double vol_frac, uint8_t* solid, int32_t* order,
