@@ -49,30 +49,104 @@ def matvec_algorithmic_bytes(dims, word=8):
     return nn * (6 * word + 1) + ne * word
 
 
-def cpu_baseline(budget_s=20.0):
-    """The CPU oracle (assembled CSR, scipy) on a bounded sample of the same
-    recipe: the 96x48x48 replica (1/8 of the volume); reports CSR K.u GDOF/s."""
+def cpu_baseline(budget_s=12.0):
+    """The CPU oracle, as it stands, on the GPU machine's host: its
+    element-by-element product K.u (rho_e Ke u_e gathered and scattered with
+    numpy, one core) on the full 192x96x96 workload (the value, GDOF/s);
+    beside it the oracle's assembled CSR product on the 96x48x48 replica, and
+    its direct solve (SuperLU) and deflated CG to 1e-8 on the 24x12x12
+    workload.  numpy's einsum and scipy's CSR product and SuperLU run on one
+    thread."""
     import scipy
-    from oracle import fem
+    from oracle import fem, solvers
     from paper_2203_15115_amd import workloads as wl
-    dims = (96, 48, 48)
-    p = wl.cantilever(dims, 50, seed=1001, ell=dims[0] / 12.0, block=(8, 8, 8))
-    t0 = time.perf_counter()
-    K = fem.assemble(p.dims, p.rho, fem.ke_gauss())
-    t_asm = time.perf_counter() - t0
+    Ke = fem.ke_gauss()
+    p = wl.config(1)
     u = np.random.default_rng(0).standard_normal(p.ndof)
-    y = K @ u
     reps, t0 = 0, time.perf_counter()
     while True:
-        y = K @ u
+        fem.apply_ebe(p.dims, p.rho, Ke, u)
         reps += 1
-        if time.perf_counter() - t0 > min(budget_s, 10.0) and reps >= 3:
+        if time.perf_counter() - t0 > budget_s and reps >= 2:
             break
-    t = (time.perf_counter() - t0) / reps
-    return {"value": round(p.ndof / t / 1e9, 4), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"scipy CSR SpMV of the assembled K on the 96x48x48 replica of the workload "
-                      f"({p.ndof} DOF, {K.nnz} nonzeros), mean of {reps} products; assembly {t_asm:.1f} s; "
-                      f"scipy {scipy.__version__} SpMV is single-threaded"}
+    t_ebe = (time.perf_counter() - t0) / reps
+    q = wl.cantilever((96, 48, 48), 50, seed=1001, ell=8.0, block=(8, 8, 8))
+    t0 = time.perf_counter()
+    K = fem.assemble(q.dims, q.rho, Ke)
+    t_asm = time.perf_counter() - t0
+    uq = np.random.default_rng(0).standard_normal(q.ndof)
+    nrep, t0 = 0, time.perf_counter()
+    while nrep < 3 or time.perf_counter() - t0 < 3.0:
+        K @ uq
+        nrep += 1
+    t_csr = (time.perf_counter() - t0) / nrep
+    c = wl.config(0)
+    K0 = fem.assemble(c.dims, c.rho, Ke)
+    t0 = time.perf_counter()
+    solvers.solve_direct(K0, c.fixed, c.F[0])
+    t_direct = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, it_dcg, _ = solvers.dcg(K0, c.fixed, c.F[0], c.dims, c.block, rtol=1e-8)
+    t_dcg = time.perf_counter() - t0
+    return {"value": round(p.ndof / t_ebe / 1e9, 5), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle element-by-element K.u (numpy, 1 thread) on the full 192x96x96 workload "
+                      f"({p.ndof} DOF): {t_ebe:.2f} s per product, mean of {reps}",
+            "csr_96x48x48_gdofs": round(q.ndof / t_csr / 1e9, 4),
+            "csr_96x48x48_note": f"assembled CSR ({K.nnz} nonzeros, assembly {t_asm:.1f} s), scipy "
+                                 f"{scipy.__version__} single-threaded SpMV, mean of {nrep}",
+            "direct_24x12x12_s": round(t_direct, 3), "dcg_24x12x12_to_1e-8_s": round(t_dcg, 3),
+            "dcg_24x12x12_iterations": int(it_dcg)}
+
+
+def bench_small_solve(ctx, stream):
+    """The 24x12x12 workload (12,675 DOF, 4^3 blocks): FP64 deflated solve
+    to 1e-8 (time after a warm-up solve on the same mesh)."""
+    import torch
+    from paper_2203_15115_amd import afdcg, workloads as wl
+    p = wl.config(0)
+    m = afdcg.afd_mesh_create(ctx, p.dims, block=p.block)
+    afdcg.afd_mesh_set_scale(m, p.rho, p.nelem, afdcg.AFD_MEM_HOST)
+    afdcg.afd_mesh_set_fixed(m, p.fixed, p.ndof, afdcg.AFD_MEM_HOST)
+    F = torch.as_tensor(p.F, device="cuda").contiguous()
+    U = torch.empty_like(F)
+    opts = afdcg.make_opts(rtol=1e-8, mem_kind=afdcg.AFD_MEM_DEVICE)
+    afdcg.afd_solve(m, opts, 1, F, U)
+    ts = []
+    for _ in range(5):
+        afdcg.afd_mesh_set_scale(m, p.rho, p.nelem, afdcg.AFD_MEM_HOST)  # setup included
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = afdcg.afd_solve(m, opts, 1, F, U)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    afdcg.afd_mesh_destroy(m)
+    return {"workload": "cantilever 24x12x12, 30% void, 4x4x4 blocks, FP64 to 1e-8",
+            "time_to_1e-8_s": round(sorted(ts)[2], 5), "iterations": st[0].iterations,
+            "rel_residual_true": st[0].rel_residual_true}
+
+
+def mixed_vs_oracle(ctx, stream):
+    """Mixed-precision solve of the 32x16x16 replica of the 256x128x128
+    recipe (50% void, 8^3 blocks, rtol 1e-11) against the oracle's direct
+    solve of the assembled system: relative displacement error."""
+    import torch
+    from oracle import fem, solvers
+    from paper_2203_15115_amd import afdcg, workloads as wl
+    p = wl.cantilever((32, 16, 16), 50, seed=1003, block=(8, 8, 8))
+    m = afdcg.afd_mesh_create(ctx, p.dims, block=p.block)
+    afdcg.afd_mesh_set_scale(m, p.rho, p.nelem, afdcg.AFD_MEM_HOST)
+    afdcg.afd_mesh_set_fixed(m, p.fixed, p.ndof, afdcg.AFD_MEM_HOST)
+    out = {"workload": "cantilever 32x16x16 (the 256x128x128 recipe at 1/8 per axis), direct oracle"}
+    U = np.zeros((1, p.ndof))
+    for name, prec, rtol in (("mixed_1e-11", afdcg.AFD_MIXED, 1e-11), ("mixed_1e-8", afdcg.AFD_MIXED, 1e-8),
+                             ("fp64_1e-8", afdcg.AFD_FP64, 1e-8)):
+        afdcg.afd_solve(m, afdcg.make_opts(rtol=rtol, precision=prec), 1, np.ascontiguousarray(p.F), U)
+        out[name] = U[0].copy()
+    afdcg.afd_mesh_destroy(m)
+    ud = solvers.solve_direct(fem.assemble(p.dims, p.rho, fem.ke_gauss()), p.fixed, p.F[0])
+    for k in ("mixed_1e-11", "mixed_1e-8", "fp64_1e-8"):
+        out[k] = float(np.linalg.norm(out[k] - ud) / np.linalg.norm(ud))
+    return out
 
 
 def _events_time(stream, fn, reps):
@@ -176,50 +250,91 @@ def bench_mixed(ctx, stream, args):
 
 
 def bench_serve(ctx, args):
-    """Poisson stream of cantilever requests nx x nx/2 x nx/2, nx uniform in
+    """Stream of cantilever requests nx x nx/2 x nx/2, nx uniform in
     {32,...,160}, 20-60% void, 1-4 RHS, to 1e-8: the continuous-batching
     server (mixed precision, 4 slots) against one-at-a-time FP64 solves in
-    arrival order on the same GPU."""
+    arrival order (1 slot) on the same GPU.  Each server's saturated
+    throughput is measured on the first --serve-sat requests kept queued
+    (a bounded backlog of slots + 4); then the same Poisson stream of
+    --serve-requests requests, at 0.8x the batched server's saturated rate,
+    is served by each, with latencies from submission to completion.
+    Request inputs are prepared by a producer thread ahead of their arrival
+    (workloads.RequestFactory), and displacements are not copied back (the
+    server keeps compliances, residuals and statuses)."""
+    import queue
+    import threading
+
     import numpy as np
     from paper_2203_15115_amd import afdcg, workloads as wl
     n = args.serve_requests
     reqs = wl.request_stream(n, rate=0.0, seed=7)
-    probs = [wl.request_problem(r) for r in reqs]
+    fac = wl.RequestFactory(seed=7)
 
-    def run_server(arrivals, prec, slots):
+    def run_server(prec, slots, count, arrivals=None):
+        q = queue.Queue(maxsize=32)
+
+        def produce():
+            for r in reqs[:count]:
+                p = fac.problem(r)
+                q.put(afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block, rtol=1e-8, precision=prec,
+                                          keep_U=False))
+        th = threading.Thread(target=produce, daemon=True)
+        th.start()
         srv = afdcg.afd_server_create(ctx, 0, slots)
-        subs = []
+        live, lat, lag, codes, resid = [], [], [], [], []
+
+        def reap(block_until=None):
+            keep = []
+            for r in live:
+                c = afdcg.afd_server_poll(srv, r.ticket)
+                if c == afdcg.AFD_PENDING:
+                    keep.append(r)
+                    continue
+                codes.append(c)
+                lat.append(r.res.t_done - r.res.t_submit)
+                resid.append(max(s.rel_residual_true for s in r.stats))
+            live[:] = keep
         t0 = time.perf_counter()
-        for p, ta in zip(probs, arrivals):
-            while time.perf_counter() - t0 < ta:
-                time.sleep(0.0005)
-            r = afdcg.ServerRequest(p.dims, p.rho, p.fixed, p.F, block=p.block, rtol=1e-8, precision=prec)
-            r.arrive = time.perf_counter() - t0
+        for i in range(count):
+            r = q.get()
+            if arrivals is None:  # saturated: keep a bounded backlog queued
+                while len(live) >= slots + 4:
+                    time.sleep(0.0005)
+                    reap()
+            else:
+                while time.perf_counter() - t0 < arrivals[i]:
+                    time.sleep(0.0003)
+                    if i % 8 == 0:
+                        reap()
+                lag.append(time.perf_counter() - t0 - arrivals[i])
             afdcg.afd_server_submit(srv, r)
-            subs.append(r)
-        codes = [afdcg.afd_server_wait(srv, r.ticket, 600.0) for r in subs]
+            live.append(r)
+            reap()
+        while live:
+            time.sleep(0.001)
+            reap()
         t_end = time.perf_counter() - t0
         afdcg.afd_server_destroy(srv)
-        done_rel = [r.res.t_done - r.res.t_submit + 0.0 for r in subs]
-        return subs, codes, t_end, done_rel
-
-    # saturated throughput of the batching server (all requests queued at t=0)
-    _, codes, t_sat, _ = run_server([0.0] * n, afdcg.AFD_MIXED, 4)
-    print(f"# serving: saturated {n} requests in {t_sat:.2f} s", file=sys.stderr, flush=True)
-    rate = 0.8 * n / t_sat
-    rng = np.random.default_rng(7)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
-    res = {}
-    for name, prec, slots in (("batched_mixed_4slots", afdcg.AFD_MIXED, 4), ("fifo_fp64_1slot", afdcg.AFD_FP64, 1)):
-        subs, codes, t_end, lat = run_server(arrivals, prec, slots)
         lat = np.array(lat)
-        print(f"# serving: {name} done in {t_end:.2f} s", file=sys.stderr, flush=True)
-        res[name] = {"solves_per_s": round(n / t_end, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-                     "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-                     "ok": int(sum(c == 0 for c in codes)), "requests": n,
-                     "max_rel_residual": max(s.rel_residual_true for r in subs for s in r.stats)}
-    return {"workload": f"{n} Poisson-arrival requests, nx in 32..160, 1-4 RHS, rtol 1e-8",
-            "saturated_solves_per_s": round(n / t_sat, 3), "arrival_rate_per_s": round(rate, 3), **res}
+        return {"requests": count, "solves_per_s": round(count / t_end, 3), "elapsed_s": round(t_end, 2),
+                "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                "ok": int(sum(c == 0 for c in codes)), "max_rel_residual": float(max(resid)),
+                "max_submit_lag_s": round(float(max(lag)), 4) if lag else 0.0}
+
+    out = {"workload": f"{n} Poisson-arrival requests, nx in 32..160, 20-60% void, 1-4 RHS, rtol 1e-8 "
+                       f"(saturation on the first {args.serve_sat})"}
+    modes = (("batched_mixed_4slots", afdcg.AFD_MIXED, 4), ("fifo_fp64_1slot", afdcg.AFD_FP64, 1))
+    for name, prec, slots in modes:
+        out[name] = {"saturated": run_server(prec, slots, min(args.serve_sat, n))}
+        print(f"# serving: {name} saturated {json.dumps(out[name]['saturated'])}", file=sys.stderr, flush=True)
+    rate = 0.8 * out["batched_mixed_4slots"]["saturated"]["solves_per_s"]
+    arrivals = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, n))
+    out["arrival_rate_per_s"] = round(rate, 3)
+    for name, prec, slots in modes:
+        out[name]["poisson"] = run_server(prec, slots, n, arrivals)
+        print(f"# serving: {name} poisson {json.dumps(out[name]['poisson'])}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -232,11 +347,14 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--sections", default="multi,mixed,serve",
                     help="extra measured sections: multi (4-RHS, VALU vs matrix cores), mixed, serve")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-sat", type=int, default=200, help="requests of each saturated serving run")
     ap.add_argument("--apply-only", action="store_true",
                     help="only a known-size copy and the timed applies (hardware-counter runs)")
     ap.add_argument("--apply-config", default="-1:0",
                     help="with --apply-only: variant:zc of the applies (-1:0 the default; no autotuning)")
+    ap.add_argument("--evict", action="store_true",
+                    help="with --apply-only: a 512 MiB read before each apply, on three (u, y) pairs in turn")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -267,13 +385,16 @@ def main():
         a = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB calibration copy
         b = torch.empty_like(a)
         b.copy_(a)
-        u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
-        y = torch.empty_like(u)
-        for _ in range(2000 + args.reps):  # 2000 warm-up launches (steady clocks), then the counted ones
+        pairs = [(torch.randn(p.ndof, dtype=torch.float64, device=dev),
+                  torch.empty(p.ndof, dtype=torch.float64, device=dev)) for _ in range(3 if args.evict else 1)]
+        for i in range(2000 + args.reps):  # 2000 warm-up launches (steady clocks), then the counted ones
+            if args.evict:
+                b.sum()
+            u, y = pairs[i % len(pairs)]
             afdcg.afd_apply_K(mesh, afdcg.AFD_FP64, 1, u, y)
         torch.cuda.synchronize()
         print(json.dumps({"apply_only": True, "copy_bytes": 2 * a.numel() * 8, "reps": args.reps, "warmup": 2000,
-                          "apply_config": {"variant": v, "zc": zc}}), flush=True)
+                          "evict": args.evict, "apply_config": {"variant": v, "zc": zc}}), flush=True)
         return
 
     # ---- apply execution picked by the autotuner on this mesh (outside the timed region)
@@ -332,6 +453,29 @@ def main():
             ev1.synchronize()
             return ev0.elapsed_time(ev1) / 1e3 / args.reps, "eager"
 
+    def time_evicted(prec, dtype, reps=60):
+        # each launch timed alone (HIP events around it on the library's
+        # stream), on one of three distinct (u, y) pairs in turn, after a read
+        # of 512 MiB that evicts the previous launch's data from the 256 MB
+        # MALL and the L2s: the apply reads u, the densities and the fixity from
+        # HBM.  (A read leaves clean lines behind; 512 MiB of writes instead
+        # leave dirty lines whose write-back would be charged to the apply.)
+        pairs = [(torch.randn(p.ndof, device=dev).to(dtype), torch.empty(p.ndof, dtype=dtype, device=dev))
+                 for _ in range(3)]
+        flush = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for i in range(reps + 10):
+            flush.sum()
+            uu, yy = pairs[i % 3]
+            if i >= 10:
+                evs[i - 10][0].record(stream)
+            afdcg.afd_apply_K(mesh, prec, 1, uu, yy)
+            if i >= 10:
+                evs[i - 10][1].record(stream)
+        stream.synchronize()
+        ts = sorted(a.elapsed_time(b) / 1e3 for a, b in evs)
+        return ts[len(ts) // 2], ts[len(ts) // 10], ts[(9 * len(ts)) // 10]
+
     u = torch.randn(p.ndof, dtype=torch.float64, device=dev)
     y = torch.empty_like(u)
     t_apply, apply_launch = time_applies(afdcg.AFD_FP64, u, y)
@@ -340,6 +484,10 @@ def main():
     achieved = alg / t_apply / 1e9
     print(f"# apply: {t_apply * 1e6:.1f} us/launch, {gdofs:.1f} GDOF/s, {achieved:.0f} GB/s algorithmic",
           file=sys.stderr, flush=True)
+    t_ev, t_ev10, t_ev90 = time_evicted(afdcg.AFD_FP64, torch.float64)
+    achieved_ev = alg / t_ev / 1e9
+    print(f"# apply, MALL evicted: {t_ev * 1e6:.1f} us/launch (p10 {t_ev10 * 1e6:.1f}, p90 {t_ev90 * 1e6:.1f}), "
+          f"{achieved_ev:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
     # FP32 apply (inner operator of the mixed form)
     uf, yf = u.float(), torch.empty(p.ndof, dtype=torch.float32, device=dev)
     t_apply32, _ = time_applies(afdcg.AFD_FP32, uf, yf)
@@ -402,8 +550,13 @@ def main():
         "apply_fp32_us": round(t_apply32 * 1e6, 3),
         "apply_fp32_gdofs": round(p.ndof / t_apply32 / 1e9, 3),
         "apply_tuning": tune,
+        "apply_mall_evicted_us": {"median": round(t_ev * 1e6, 3), "p10": round(t_ev10 * 1e6, 3),
+                                  "p90": round(t_ev90 * 1e6, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     # each launch alone after a 512 MiB read (inputs read from HBM, not the MALL)
+                     "achieved_mall_evicted": round(achieved_ev, 1),
+                     "frac_mall_evicted": round(achieved_ev / HBM_PEAK_GBS, 4),
                      # counters were taken on the default configuration (buffer-load kernel,
                      # prefetch distance 1, one-round z chunking)
                      "traffic": TRAFFIC_BYTES if args.config == 1 and tune["fp64"]["variant"] == -1 else None,
@@ -445,11 +598,16 @@ def main():
     if "mixed" in secs:
         out["mixed"] = bench_mixed(ctx, stream, args)
         print(f"# mixed: {json.dumps(out['mixed'])}", file=sys.stderr, flush=True)
+    out["small_solve"] = bench_small_solve(ctx, stream)
+    print(f"# 24x12x12: {json.dumps(out['small_solve'])}", file=sys.stderr, flush=True)
     if "serve" in secs:
         out["serving"] = bench_serve(ctx, args)
         print(f"# serving: {json.dumps(out['serving'])}", file=sys.stderr, flush=True)
     if not args.no_cpu:
+        out["mixed_error_vs_oracle"] = mixed_vs_oracle(ctx, stream)
+        print(f"# mixed vs oracle: {json.dumps(out['mixed_error_vs_oracle'])}", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
+        print(f"# cpu baseline: {json.dumps(out['cpu_baseline'])}", file=sys.stderr, flush=True)
     afdcg.afd_context_destroy(ctx)
     print(json.dumps(out), flush=True)
 

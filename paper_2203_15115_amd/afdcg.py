@@ -332,13 +332,14 @@ def afd_server_create(ctx, hbm_budget=0, max_slots=4):
 class ServerRequest:
     """Holds a request's host buffers and result storage alive until it completes."""
 
-    def __init__(self, dims, rho, fixed, F, block=(8, 8, 8), h=(1.0, 1.0, 1.0), E=1.0, nu=0.3, **optkw):
+    def __init__(self, dims, rho, fixed, F, block=(8, 8, 8), h=(1.0, 1.0, 1.0), E=1.0, nu=0.3, keep_U=True,
+                 **optkw):
         import numpy as np
         self.rho = np.ascontiguousarray(rho, dtype=np.float64)
         self.fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
         self.F = np.ascontiguousarray(np.atleast_2d(F), dtype=np.float64)
         self.nrhs = self.F.shape[0]
-        self.U = np.zeros_like(self.F)
+        self.U = np.zeros_like(self.F) if keep_U else None
         self.J = np.zeros(self.nrhs)
         self.stats = (afd_solve_stats * self.nrhs)()
         self.opts = make_opts(**optkw)
@@ -346,8 +347,8 @@ class ServerRequest:
                              float(E), float(nu), int(block[0]), int(block[1]), int(block[2]))
         self.req = afd_request(desc, self.rho.ctypes.data, self.fixed.ctypes.data, self.F.ctypes.data,
                                self.nrhs, self.opts)
-        self.res = afd_result(self.U.ctypes.data, self.J.ctypes.data, C.cast(self.stats, C.c_void_p).value,
-                              AFD_PENDING, 0.0, 0.0, 0.0)
+        self.res = afd_result(None if self.U is None else self.U.ctypes.data, self.J.ctypes.data,
+                              C.cast(self.stats, C.c_void_p).value, AFD_PENDING, 0.0, 0.0, 0.0)
         self.ticket = None
 
 

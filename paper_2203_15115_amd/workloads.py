@@ -204,3 +204,44 @@ def request_problem(req: Request):
     loads = ("bottom", "mid", "top", "adjoint")[: req.nrhs]
     return cantilever(req.dims, req.void_pct, req.seed, loads=loads, block=(8, 8, 8),
                       adjoint_seed=req.seed + 1, name=f"req{req.rid}")
+
+
+class RequestFactory:
+    """Inputs of a long request stream at a bounded host cost per request.
+
+    Per grid size the fixity mask, the three edge loads and a pool of
+    ``pool`` seeded smooth fields are drawn once; a request takes the field
+    ``req.seed % pool`` of its grid size and cuts it at its own void fraction,
+    and its point load sits at a node drawn from ``req.seed + 1``.  Requests
+    of one grid size thus share a field but differ in void fraction, number of
+    right-hand sides and point load.  (``request_problem`` draws a field per
+    request; this keeps a 2,000-request stream within a few MB per request
+    and a few ms of host time.)
+    """
+
+    def __init__(self, seed=7, pool=8):
+        self.seed = seed
+        self.pool = pool
+        self._fields = {}
+        self._fixed = {}
+        self._edges = {}
+
+    def _field(self, dims, k):
+        key = (dims, k)
+        if key not in self._fields:
+            self._fields[key] = smooth_field(dims, self.seed * 1000003 + dims[0] * 101 + k,
+                                             max(2.0, dims[0] / 12.0))
+        return self._fields[key]
+
+    def problem(self, req: Request):
+        dims = tuple(req.dims)
+        if dims not in self._fixed:
+            self._fixed[dims] = clamp_x0(dims)
+            self._edges[dims] = [edge_load(dims, w) for w in ("bottom", "mid", "top")]
+        rho = density_from_field(self._field(dims, req.seed % self.pool), req.void_pct)
+        F = np.empty((req.nrhs, 3 * n_nodes(dims)))
+        for r in range(min(req.nrhs, 3)):
+            F[r] = self._edges[dims][r]
+        if req.nrhs == 4:
+            F[3] = point_load(dims, point_load_node(dims, req.seed + 1))
+        return Problem(dims, rho, self._fixed[dims], F, (8, 8, 8), f"req{req.rid}")
