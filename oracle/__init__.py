@@ -17,6 +17,8 @@ It computes the plain definitions the method reaches:
   (Eq. 3.6 with the cutting value set by the target volume, Sec. 3.2).
 
 Modules: ``fem`` (element matrix, mesh indexing, assembly), ``solvers``
-(direct, Jacobi-PCG, deflated PCG), ``post`` (compliance, sensitivity, ranking).
+(direct, Jacobi-PCG, deflated PCG), ``post`` (compliance, sensitivity, ranking),
+``casting`` (the casting projection of Sec. 3.7), ``levelset`` (the augmented
+topological level-set loop of Sec. 3.2-3.4 and 3.8 on direct solves).
 """
 from . import fem, solvers, post  # noqa: F401

@@ -1,0 +1,232 @@
+"""Oracle of the augmented topological level-set loop (Sec. 3.2-3.4, 3.6,
+3.8, Fig. 6-7).  TEST INFRASTRUCTURE ONLY.
+
+The loop traces the Pareto curve of minimum volume from the full design
+domain downward.  At a target volume fraction v it iterates a fixed point
+(Fig. 6): finite element solve over the current topology, topological
+sensitivity fields, the augmented topological level-set, and the topology at
+v extracted from it.  The constraints g_i <= 0 enter through the augmented
+Lagrangian multipliers mu_i and penalties gamma_i (Eq. 3.11-3.12, 3.17-3.18).
+Once a topology has converged, v is lowered by dv; when a hard constraint is
+violated (or the fixed point does not settle), the loop returns to the last
+converged feasible topology and halves dv, and it stops when dv falls below
+dv_min (Sec. 3.8 steps 1-9).
+
+Readings of the paper used here (it leaves these open):
+
+* g_i = Q_i / (alpha_i Q_i0) - 1 for a constraint Q_i <= alpha_i Q_i0
+  (Eq. 3.21), Q_i0 its value on the full domain; the compliance Q = J is the
+  sum of f_k . u_k over the load cases, its field the sum of the element
+  strain energies rho_e u_e^T Ke u_e (the element route of Sec. 3.1).
+* Augmented level set (Eq. 3.17-3.18, the product in Eq. 3.18 read as
+  (mu_i + gamma_i g_i) T_gi): T_L = sum_i w_i T_gi with
+  w_i = max(mu_i + gamma_i g_i, 0) and T_gi = T_Qi / (alpha_i Q_i0).  The
+  objective's term T_phi (volume) is the same at every point, so it shifts
+  the field without reordering it and is left out; if every w_i is 0 the
+  constraint fields are taken with weight 1 each.
+* Multiplier and penalty updates after every solve k (k = 0 on the full
+  domain), from the values before the update: mu <- max(mu + gamma g_k, 0);
+  gamma is kept at k = 0 and otherwise updated by Eq. 3.12 as printed, with
+  min(g_k, 0) <= varsigma min(g_{k-1}, 0) keeping it and else
+  gamma <- max(eta gamma, k^2).
+* Step 7's convergence: two successive solves at the same target v whose
+  compliances differ by less than conv_tol (1%) of the earlier one; the
+  full domain (v = 1) counts as converged; max_fp solves at one target
+  without convergence count as a divergence (step 9).
+* Step 9: back to the last converged feasible topology (volume v_b), dv
+  halved, next target v_b - dv, extracted from that topology's level set;
+  termination when dv < dv_min or the next target would be <= 0.
+* Topology at v (Eq. 3.6): the ceil(v nE) elements of highest T_L (ties by
+  index; with the casting constraint of Sec. 3.7 the projected field, ties by
+  the distance to the parting plane, then index); void elements get the
+  ersatz scale.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import fem, post, solvers
+from .casting import cast_project, parting_distance
+
+FEA_FIXED_POINT = 0   # a fixed-point solve at the current target
+FEA_CONVERGED = 1     # converged: the target is lowered by dv
+FEA_VIOLATED = 2      # a hard constraint violated: dv halved, back to the last converged design
+FEA_DIVERGED = 3      # max_fp solves without convergence: treated as a violation
+FEA_TERMINATED = 4    # dv < dv_min or no volume left: the loop ends after this solve
+
+
+def al_update(mu, gamma, g_new, g_old, k, varsigma=0.25, eta=10.0):
+    """One multiplier / penalty update after solve k (Eq. 3.11, 3.12).
+
+    g_old is None at k = 0.  Both updates use the values before the update."""
+    mu_next = max(mu + gamma * g_new, 0.0)
+    if g_old is None or min(g_new, 0.0) <= varsigma * min(g_old, 0.0):
+        gamma_next = gamma
+    else:
+        gamma_next = max(eta * gamma, float(k) ** 2)
+    return mu_next, gamma_next
+
+
+def weights(mu, gamma, g):
+    """w_i = max(mu_i + gamma_i g_i, 0), all 1 when every w_i is 0 (Eq. 3.18)."""
+    w = [max(m + c * x, 0.0) for m, c, x in zip(mu, gamma, g)]
+    if all(x == 0.0 for x in w):
+        w = [1.0] * len(w)
+    return w
+
+
+def combined_field(fields, coef):
+    """sum_i coef_i fields_i, accumulated in the order of the fields."""
+    out = coef[0] * fields[0]
+    for c, f in zip(coef[1:], fields[1:]):
+        out = out + c * f
+    return out
+
+
+@dataclasses.dataclass
+class Params:
+    alpha_J: float = 3.0       # J <= alpha_J J0 (Eq. 3.22)
+    dv0: float = 0.025         # first volume step (Sec. 4.2)
+    dv_min: float = 0.025 / 16
+    mu0: float = 100.0         # Sec. 3.8 step 1
+    gamma0: float = 10.0
+    varsigma: float = 0.25     # Eq. 3.12
+    eta: float = 10.0
+    conv_tol: float = 0.01     # step 7: change in compliance
+    max_fp: int = 8
+    max_fea: int = 400
+    void_scale: float = 1e-3
+    cast_axis: int = -1        # casting constraint (Sec. 3.7): axis, or -1 for none
+    cast_parting: int = 0
+
+
+@dataclasses.dataclass
+class Record:
+    fea: int
+    event: int
+    v: float          # target volume fraction of the analysed topology
+    nsolid: int
+    J: float
+    g: float
+    mu: float         # after the update
+    gamma: float
+    dv: float         # step after this solve's decision
+
+
+def extract(field, vol, dims, p: Params):
+    """Solid mask (uint8) at volume fraction vol from a level-set field."""
+    if p.cast_axis >= 0:
+        f = cast_project(field, dims, p.cast_axis, p.cast_parting)
+        solid, _ = post.threshold(f, vol, parting_distance(dims, p.cast_axis, p.cast_parting))
+    else:
+        solid, _ = post.threshold(field, vol)
+    return solid
+
+
+def density(solid, p: Params):
+    return np.where(solid == 1, 1.0, p.void_scale)
+
+
+def fea(dims, solid, fixed, F, Ke, p: Params):
+    """Displacements of every load case on the topology, by direct solves."""
+    K = fem.assemble(dims, density(solid, p), Ke)
+    return np.stack([solvers.solve_direct(K, fixed, F[r]) for r in range(F.shape[0])])
+
+
+def compliance_field(dims, solid, Ke, U, p: Params):
+    rho = density(solid, p)
+    return sum(post.element_energy(dims, rho, Ke, U[r]) for r in range(U.shape[0]))
+
+
+class Loop:
+    """The loop as a state machine: ``first()`` gives the full domain; after
+    each solve, ``after_solve(solid, J, field)`` records it and returns the
+    next topology to analyse (None at the end).  ``run`` drives it with the
+    oracle's direct solves."""
+
+    def __init__(self, dims, p: Params):
+        self.dims = tuple(dims)
+        self.p = p
+        self.n = int(np.prod(dims))
+        self.mu, self.gamma = p.mu0, p.gamma0
+        self.dv = p.dv0
+        self.k = 0
+        self.J0 = None
+        self.g_prev = None
+        self.v = 1.0               # target of the topology being analysed
+        self.fp = 0                # solves at the current target
+        self.J_prev_same = None    # compliance of the previous solve at this target
+        self.best = None           # (solid, v, J, field) of the last converged feasible design
+        self.history = []
+
+    def first(self):
+        return np.ones(self.n, dtype=np.uint8)
+
+    def after_solve(self, solid, J, field_J):
+        p = self.p
+        k, v = self.k, self.v
+        if k == 0:
+            self.J0 = J
+        g = J / (p.alpha_J * self.J0) - 1.0
+        mu, gamma = al_update(self.mu, self.gamma, g, self.g_prev, k, p.varsigma, p.eta)
+        self.mu, self.gamma, self.g_prev = mu, gamma, g
+        self.fp += 1
+        if g > 0.0:
+            event = FEA_VIOLATED
+        elif k == 0 or self._converged(J):
+            event = FEA_CONVERGED
+        elif self.fp >= p.max_fp:
+            event = FEA_DIVERGED
+        else:
+            event = FEA_FIXED_POINT
+        nxt = None
+        if event in (FEA_VIOLATED, FEA_DIVERGED):
+            # step 9: back to the last converged feasible design with half the step
+            self.dv *= 0.5
+            if self.dv < p.dv_min or self.best[1] - self.dv <= 0.0:
+                event = FEA_TERMINATED
+            else:
+                self._target(self.best[1] - self.dv)
+                nxt = extract(self.best[3], self.v, self.dims, p)
+        else:
+            # steps 5-6: the augmented level set and the topology extracted from it
+            w = weights([mu], [gamma], [g])
+            field = combined_field([field_J], [w[0] / (p.alpha_J * self.J0)])
+            if event == FEA_CONVERGED:  # step 8: the next target
+                self.best = (solid.copy(), v, J, field)
+                if v - self.dv <= 0.0:
+                    event = FEA_TERMINATED
+                else:
+                    self._target(v - self.dv)
+                    nxt = extract(field, self.v, self.dims, p)
+            else:
+                self.J_prev_same = J
+                nxt = extract(field, v, self.dims, p)
+        self.history.append(Record(k, event, v, int(solid.sum()), J, g, mu, gamma, self.dv))
+        self.k += 1
+        if self.k >= p.max_fea:
+            nxt = None
+        return nxt
+
+    def _converged(self, J):
+        return self.J_prev_same is not None and abs(J - self.J_prev_same) < self.p.conv_tol * self.J_prev_same
+
+    def _target(self, v):
+        self.v = v
+        self.fp = 0
+        self.J_prev_same = None
+
+    def run(self, fixed, F, Ke=None):
+        """The whole loop with direct solves; returns the last converged
+        feasible design (solid, v, J) and the history."""
+        Ke = fem.ke_gauss() if Ke is None else Ke
+        solid = self.first()
+        while solid is not None:
+            U = fea(self.dims, solid, fixed, F, Ke, self.p)
+            J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
+            solid = self.after_solve(solid, J, compliance_field(self.dims, solid, Ke, U, self.p))
+        b = self.best
+        return (b[0], b[1], b[2]), self.history

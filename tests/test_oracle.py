@@ -521,3 +521,93 @@ def test_coarse_matrix_order_from_hand_built_motions():
     # its rigid motions cost energy only there, so E(1, 1) is not zero but far
     # smaller than the clamped block's
     assert np.trace(E[6:, 6:]) < np.trace(E[:6, :6])
+
+
+# ------------------------------------------------------------- level-set loop (Sec. 3.3-3.4, 3.8)
+def test_al_update_hand_checked_sequence():
+    # mu <- max(mu + gamma g, 0); gamma kept when min(g_k, 0) <= 0.25 min(g_{k-1}, 0),
+    # else max(10 gamma, k^2) (Eq. 3.11-3.12 as printed), both from the old values.
+    # Worked by hand from mu = 100, gamma = 10:
+    #   k=0 g=-2/3 : mu 100 - 20/3 = 280/3, gamma 10 (no previous g)
+    #   k=1 g=-1/2 : -1/2 <= -1/6 keeps gamma; mu 280/3 - 5 = 265/3
+    #   k=2 g=-1/10: -1/10 > -1/8 -> gamma max(100, 4) = 100; mu 265/3 - 1 = 262/3
+    #   k=3 g=1/20 : 0 > -1/40 -> gamma max(1000, 9) = 1000; mu 262/3 + 100/20 = 277/3
+    #   k=4 g=1/50 : 0 <= 0 keeps gamma; mu 277/3 + 20 = 337/3
+    #   k=5 g=-9/10: -9/10 <= 0 keeps gamma; mu max(337/3 - 900, 0) = 0
+    from oracle.levelset import al_update
+    mu, gamma, prev = 100.0, 10.0, None
+    want = [(280 / 3, 10.0), (265 / 3, 10.0), (262 / 3, 100.0), (277 / 3, 1000.0), (337 / 3, 1000.0), (0.0, 1000.0)]
+    for k, g in enumerate([-2 / 3, -1 / 2, -1 / 10, 1 / 20, 1 / 50, -9 / 10]):
+        mu, gamma = al_update(mu, gamma, g, prev, k)
+        prev = g
+        assert abs(mu - want[k][0]) <= 1e-12 * max(1.0, want[k][0]) and gamma == want[k][1], (k, mu, gamma)
+    # the k^2 branch: a small penalty late in the run
+    assert al_update(5.0, 1.0, -0.01, -0.5, 20) == (4.99, 400.0)
+
+
+def test_augmented_weights():
+    from oracle.levelset import combined_field, weights
+    assert weights([100.0, 3.0], [10.0, 10.0], [-0.5, -0.5]) == [95.0, 0.0]
+    assert weights([0.0], [10.0], [-0.2]) == [1.0]  # no active weight: the field itself
+    f = [np.array([1.0, 2.0]), np.array([10.0, -1.0])]
+    assert list(combined_field(f, [2.0, 0.5])) == [7.0, 3.5]
+
+
+def _loop_run(dims, p, F_which=("bottom",)):
+    from oracle import levelset as ls
+    fixed = wl.clamp_x0(dims)
+    F = np.stack([wl.edge_load(dims, w) for w in F_which])
+    loop = ls.Loop(dims, p)
+    return loop.run(fixed, F)
+
+
+def test_levelset_loop_invariants():
+    # Pareto tracing under J <= 3 J0 on a 12x6x6 cantilever (direct solves)
+    from oracle import levelset as ls
+    dims = (12, 6, 6)
+    n = int(np.prod(dims))
+    p = ls.Params(alpha_J=3.0)
+    (best, v_best, J_best), h = _loop_run(dims, p)
+    J0 = h[0].J
+    assert h[0].v == 1.0 and h[0].nsolid == n and h[0].event == ls.FEA_CONVERGED
+    assert abs(h[0].g - (1 / 3 - 1)) < 1e-15
+    assert h[-1].event == ls.FEA_TERMINATED and h[-1].dv < p.dv_min
+    conv = [r for r in h if r.event == ls.FEA_CONVERGED]
+    assert all(r.g <= 0 for r in conv)                                  # converged designs are feasible
+    assert all(a.v > b.v for a, b in zip(conv, conv[1:]))                # the Pareto trace descends
+    assert conv[-1].v == v_best and conv[-1].J == J_best and J_best <= 3 * J0
+    assert int(best.sum()) == conv[-1].nsolid
+    for r in h[1:]:
+        assert r.nsolid == math.ceil(r.v * n - 1e-9), r                  # topology at its target volume
+    for a, b in zip(h, h[1:]):
+        assert b.dv <= a.dv                                              # the step only shrinks ...
+        if b.event in (ls.FEA_VIOLATED, ls.FEA_DIVERGED, ls.FEA_TERMINATED) and b.dv < a.dv:
+            assert b.dv == a.dv / 2                                      # ... by halving
+        if b.event == ls.FEA_VIOLATED:
+            assert b.g > 0
+        if a.event == ls.FEA_FIXED_POINT and a.v == b.v and b.event != ls.FEA_VIOLATED:
+            # step 7: converged iff the compliance moved by less than 1%
+            assert (b.event == ls.FEA_CONVERGED) == (abs(b.J - a.J) < 0.01 * a.J)
+    assert any(r.event == ls.FEA_VIOLATED for r in h)                    # the hard constraint bound the run
+
+
+def test_levelset_loop_with_casting_has_no_cavity():
+    # every topology the loop analyses under the casting constraint (parting
+    # plane in the middle of z) is free of cavities along z
+    from oracle import levelset as ls
+    dims = (12, 6, 6)
+    p = ls.Params(alpha_J=2.0, cast_axis=2, cast_parting=3)
+    fixed = wl.clamp_x0(dims)
+    F = wl.edge_load(dims, "bottom")[None]
+    loop = ls.Loop(dims, p)
+    seen = []
+    orig = loop.after_solve
+
+    def spy(solid, J, field):
+        seen.append(solid.copy())
+        return orig(solid, J, field)
+    loop.after_solve = spy
+    (best, v, J), h = loop.run(fixed, F)
+    assert len(seen) == len(h) > 5 and J <= 2 * h[0].J
+    for s in seen:
+        assert not _has_cavity(s, dims, 2, 3)
