@@ -281,6 +281,16 @@ int afd_threshold_noalloc(afd_context* ctx, const double* s, const int32_t* tie,
 int afd_casting(afd_context* ctx, const int32_t dims[3], const double* phi, int32_t axis, int32_t parting,
                 double* out, int32_t* dist);
 
+/* The augmented topological level set (Eq. 3.17-3.18): out[e] =
+ * sum_t coef[t] * (sum_{r < rows[t]} fields[t][r * n + e]), terms and rows
+ * added left to right without fused multiply-adds (so it is the double the
+ * plain expression gives).  fields: HOST array of nterms (1..4) DEVICE
+ * pointers, group t holding rows[t] fields of n values (e.g. the strain
+ * energies of the load cases: their sum is the compliance sensitivity);
+ * rows, coef: HOST.  out: device, n doubles. */
+int afd_combine_fields(afd_context* ctx, int64_t n, int32_t nterms, const double* const* fields,
+                       const int32_t* rows, const double* coef, double* out);
+
 /* ---- the whole solve ---------------------------------------------------- */
 /* Solves A U[r] = F[r] for r < nrhs (1..4) by deflated Jacobi-PCG (Sec. 3.5),
  * FP64 or FP32-inner/FP64-refined per opts->precision (the coarse factor is
@@ -301,6 +311,68 @@ int afd_casting(afd_context* ctx, const int32_t dims[3], const double* phi, int3
  * U then holds the last iterate. */
 int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
               const double* F, double* U, double* J, double* S, afd_solve_stats* stats);
+
+/* ---- the optimisation loop (Sec. 3.2-3.4, 3.6, 3.8; Fig. 6-7) ------------ */
+/* Pareto tracing of minimum volume from the full design domain downward
+ * under the hard constraint J <= alpha_J J0 (Eq. 3.21-3.22; J the sum of the
+ * load cases' compliances, J0 its value on the full domain).  Per solve k:
+ * the finite element solves of every load case (afd_solve, warm-started from
+ * the previous displacements), g = J / (alpha_J J0) - 1, the multiplier and
+ * penalty updates mu <- max(mu + gamma g, 0) and Eq. 3.12 (gamma kept at
+ * k = 0), then
+ *  - g > 0 (hard constraint violated), or max_fp solves at one target
+ *    without convergence: back to the last converged feasible design
+ *    (volume v_b), dv halved, next target v_b - dv (stop when dv < dv_min);
+ *  - else the augmented level set T_L = w T_J / (alpha_J J0),
+ *    w = max(mu + gamma g, 0) (1 when 0), T_J the sum of the element
+ *    strain-energy fields; converged when the compliance moved by less than
+ *    conv_tol since the previous solve at the same target (the full domain
+ *    counts as converged), and then the target drops by dv (stop at <= 0);
+ *  - the next topology: the ceil(v nE) elements of highest T_L (with the
+ *    casting constraint, Sec. 3.7: of the projected field, ties cut nearer
+ *    the parting plane first), void elements at void_scale.
+ * The mesh's fixity is used and its densities are overwritten (on return
+ * they are those of the last solved topology).  F: HOST, nload (1..4) x n_dof,
+ * zero on fixed DOFs.  solid: HOST, n_elem, receives the last converged
+ * feasible design.  hist: HOST, hist_cap records (*n_hist receives the count;
+ * the loop also stops after hist_cap or max_fea solves); topo_hist: HOST,
+ * optional (NULL), hist_cap x n_elem, receives the topology of every solve.
+ * Returns AFD_OK when the loop ended by its rules or its solve budget, else
+ * the failing call's status (the history up to it is kept).  Allocates its
+ * device work space for the call. */
+#define AFD_LS_FIXED_POINT 0   /* another fixed-point solve at the same target    */
+#define AFD_LS_CONVERGED   1   /* converged (and feasible): the target drops by dv */
+#define AFD_LS_VIOLATED    2   /* hard constraint violated: dv halved, step back   */
+#define AFD_LS_DIVERGED    3   /* no convergence within max_fp: as a violation     */
+#define AFD_LS_TERMINATED  4   /* the loop ended after this solve                  */
+typedef struct {
+    double alpha_J;            /* >= 1                                          */
+    double dv0, dv_min;        /* Sec. 4.2: 0.025; stop below dv_min             */
+    double mu0, gamma0;        /* Sec. 3.8 step 1: 100, 10                       */
+    double varsigma, eta;      /* Eq. 3.12: 0.25, 10                             */
+    double conv_tol;           /* step 7: 0.01                                   */
+    int32_t max_fp, max_fea;   /* solves per target before a divergence; total   */
+    double void_scale;         /* ersatz scale of void elements (e.g. 1e-3)      */
+    int32_t cast_axis;         /* casting constraint: 0..2, or -1 for none       */
+    int32_t cast_parting;      /* parting plane index along cast_axis            */
+    afd_solve_opts solve;      /* the solves (mem_kind, pairs, x0 are set by the loop) */
+} afd_levelset_opts;
+typedef struct {
+    int32_t fea;               /* solve index                                    */
+    int32_t event;             /* AFD_LS_*                                       */
+    int32_t nsolid;            /* solid elements of the solved topology          */
+    int32_t iterations;        /* CG iterations of the solve (summed over loads) */
+    double v;                  /* target volume fraction of the solved topology  */
+    double J, g;               /* compliance and constraint value               */
+    double mu, gamma;          /* after this solve's update                      */
+    double dv;                 /* volume step after this solve's decision        */
+    double t_fea, t_total;     /* seconds: this solve (afd_solve, all load
+                                  cases) and the whole step (solve, fields,
+                                  level set, extraction, bookkeeping)           */
+} afd_levelset_record;
+int afd_levelset_run(afd_mesh* mesh, const afd_levelset_opts* opts, int32_t nload, const double* F,
+                     uint8_t* solid, afd_levelset_record* hist, int32_t hist_cap, int32_t* n_hist,
+                     uint8_t* topo_hist);
 
 /* ---- serving ------------------------------------------------------------ */
 typedef struct {

@@ -161,6 +161,7 @@ class Loop:
         self.J_prev_same = None    # compliance of the previous solve at this target
         self.best = None           # (solid, v, J, field) of the last converged feasible design
         self.history = []
+        self.last_extract = None   # (field, volume fraction) of the last extraction
 
     def first(self):
         return np.ones(self.n, dtype=np.uint8)
@@ -190,6 +191,7 @@ class Loop:
                 event = FEA_TERMINATED
             else:
                 self._target(self.best[1] - self.dv)
+                self.last_extract = (self.best[3], self.v)
                 nxt = extract(self.best[3], self.v, self.dims, p)
         else:
             # steps 5-6: the augmented level set and the topology extracted from it
@@ -201,9 +203,11 @@ class Loop:
                     event = FEA_TERMINATED
                 else:
                     self._target(v - self.dv)
+                    self.last_extract = (field, self.v)
                     nxt = extract(field, self.v, self.dims, p)
             else:
                 self.J_prev_same = J
+                self.last_extract = (field, v)
                 nxt = extract(field, v, self.dims, p)
         self.history.append(Record(k, event, v, int(solid.sum()), J, g, mu, gamma, self.dv))
         self.k += 1

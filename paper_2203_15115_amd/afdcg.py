@@ -42,7 +42,8 @@ EXPORTED = [
     "afd_jacobi",
     "afd_dot",
     "afd_restrict", "afd_prolong", "afd_coarse_setup", "afd_coarse_matrix", "afd_coarse_solve",
-    "afd_sensitivity", "afd_threshold", "afd_threshold_noalloc", "afd_solve", "afd_server_create", "afd_server_submit",
+    "afd_sensitivity", "afd_threshold", "afd_threshold_noalloc", "afd_solve", "afd_combine_fields",
+    "afd_levelset_run", "afd_server_create", "afd_server_submit",
     "afd_server_poll", "afd_server_wait", "afd_server_clock", "afd_server_destroy",
 ]
 
@@ -70,6 +71,22 @@ class afd_solve_stats(C.Structure):
 class afd_tune_report(C.Structure):
     _fields_ = [("variant", C.c_int32), ("zc", C.c_int32), ("us", C.c_double), ("default_us", C.c_double),
                 ("ncandidates", C.c_int32)]
+
+
+class afd_levelset_opts(C.Structure):
+    _fields_ = [("alpha_J", C.c_double), ("dv0", C.c_double), ("dv_min", C.c_double), ("mu0", C.c_double),
+                ("gamma0", C.c_double), ("varsigma", C.c_double), ("eta", C.c_double), ("conv_tol", C.c_double),
+                ("max_fp", C.c_int32), ("max_fea", C.c_int32), ("void_scale", C.c_double),
+                ("cast_axis", C.c_int32), ("cast_parting", C.c_int32), ("solve", afd_solve_opts)]
+
+
+class afd_levelset_record(C.Structure):
+    _fields_ = [("fea", C.c_int32), ("event", C.c_int32), ("nsolid", C.c_int32), ("iterations", C.c_int32),
+                ("v", C.c_double), ("J", C.c_double), ("g", C.c_double), ("mu", C.c_double),
+                ("gamma", C.c_double), ("dv", C.c_double), ("t_fea", C.c_double), ("t_total", C.c_double)]
+
+
+AFD_LS_FIXED_POINT, AFD_LS_CONVERGED, AFD_LS_VIOLATED, AFD_LS_DIVERGED, AFD_LS_TERMINATED = 0, 1, 2, 3, 4
 
 
 class afd_request(C.Structure):
@@ -123,6 +140,9 @@ def lib():
             "afd_threshold_noalloc": (C.c_int, [vp, vp, vp, i64, dbl, vp, vp, C.POINTER(dbl)]),
             "afd_casting": (C.c_int, [vp, C.POINTER(i32), vp, i32, i32, vp, vp]),
             "afd_solve": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, vp, vp, vp, vp, vp]),
+            "afd_combine_fields": (C.c_int, [vp, i64, i32, vp, vp, vp, vp]),
+            "afd_levelset_run": (C.c_int, [vp, C.POINTER(afd_levelset_opts), i32, vp, vp, vp, i32,
+                                           C.POINTER(i32), vp]),
             "afd_server_create": (C.c_int, [vp, C.c_uint64, i32, C.POINTER(vp)]),
             "afd_server_submit": (C.c_int, [vp, C.POINTER(afd_request), C.POINTER(afd_result),
                                             C.POINTER(C.c_uint64)]),
@@ -321,6 +341,43 @@ def afd_solve(mesh, opts, nrhs, F, U, J=None, S=None, raise_on_error=True):
     if raise_on_error:
         check(code, "afd_solve")
     return code, list(st)
+
+
+def afd_combine_fields(ctx, n, groups, coef, out):
+    """groups: sequence of (device tensor of rows x n, rows) pairs; coef: one value per group."""
+    k = len(groups)
+    ptrs = (C.c_void_p * k)(*[_ptr(g) for g, _ in groups])
+    rows = (C.c_int32 * k)(*[int(r) for _, r in groups])
+    cf = (C.c_double * k)(*[float(c) for c in coef])
+    check(lib().afd_combine_fields(ctx, n, k, C.cast(ptrs, C.c_void_p), C.cast(rows, C.c_void_p),
+                                   C.cast(cf, C.c_void_p), _ptr(out)), "afd_combine_fields")
+
+
+def make_levelset_opts(alpha_J=3.0, dv0=0.025, dv_min=0.025 / 16, mu0=100.0, gamma0=10.0, varsigma=0.25, eta=10.0,
+                       conv_tol=0.01, max_fp=8, max_fea=400, void_scale=1e-3, cast_axis=-1, cast_parting=0,
+                       **solvekw):
+    so = make_opts(**solvekw)
+    o = afd_levelset_opts(float(alpha_J), float(dv0), float(dv_min), float(mu0), float(gamma0), float(varsigma),
+                          float(eta), float(conv_tol), int(max_fp), int(max_fea), float(void_scale), int(cast_axis),
+                          int(cast_parting), so)
+    o._keep = so._keep
+    return o
+
+
+def afd_levelset_run(mesh, opts, F, nelem, hist_cap=400, with_topologies=False, raise_on_error=True):
+    """Returns (status, solid uint8 array, [afd_levelset_record], topologies or None)."""
+    import numpy as np
+    F = np.ascontiguousarray(np.atleast_2d(F), dtype=np.float64)
+    solid = np.zeros(nelem, dtype=np.uint8)
+    hist = (afd_levelset_record * hist_cap)()
+    n = C.c_int32()
+    topo = np.zeros((hist_cap, nelem), dtype=np.uint8) if with_topologies else None
+    code = lib().afd_levelset_run(mesh, C.byref(opts), F.shape[0], _ptr(F), _ptr(solid), C.cast(hist, C.c_void_p),
+                                  hist_cap, C.byref(n), _ptr(topo))
+    if raise_on_error:
+        check(code, "afd_levelset_run")
+    recs = list(hist)[: n.value]
+    return code, solid, recs, (topo[: n.value] if topo is not None else None)
 
 
 def afd_server_create(ctx, hbm_budget=0, max_slots=4):

@@ -34,6 +34,11 @@ struct Status {
 
 // AFD_OK or AFD_E_INVALID_ARG (with the message set) for a mesh description
 int validate_desc(const afd_mesh_desc& d);
+// the mesh's context, the context's stream and the mesh description
+afd_context* mesh_context(const afd_mesh* m);
+hipStream_t context_stream(const afd_context* c);
+const afd_mesh_desc& mesh_desc(const afd_mesh* m);
+int mesh_dof_mask(const afd_mesh* m, uint8_t* host);  // the fixity per DOF, copied to the host
 
 // ------------------------------------------------------------ element data
 // The element matrix in the tensor-product Haar basis.  Per axis, a node pair
@@ -291,6 +296,11 @@ int launch_sensitivity(const Grid& g, const KeHaar& kh, const double* rho, int n
 // casting projection of an element field on a dims grid (see afd_casting)
 int launch_cast(const int dims[3], int axis, int parting, const double* phi, double* out, hipStream_t s);
 int launch_parting_distance(const int dims[3], int axis, int parting, int32_t* dist, hipStream_t s);
+// out = sum_t coef[t] * (sum of the rows[t] rows of fields[t]), left to right, no FMA (t < 4)
+int launch_combine(int64_t n, int nterms, const double* const* fields, const int* rows, const double* coef,
+                   double* out, hipStream_t s);
+// rho[e] = solid[e] ? 1 : void_scale
+int launch_density(int64_t n, const uint8_t* solid, double void_scale, double* rho, hipStream_t s);
 // ranking and threshold (see afd_threshold): threshold_run on a caller-given
 // device work space of threshold_work_bytes(n); threshold_gpu allocates it
 size_t threshold_work_bytes(int64_t n);

@@ -115,6 +115,17 @@ struct afd_mesh {
     int npartM = 0;
 };
 
+namespace afd {
+afd_context* mesh_context(const afd_mesh* m) { return m->ctx; }
+hipStream_t context_stream(const afd_context* c) { return c->stream; }
+const afd_mesh_desc& mesh_desc(const afd_mesh* m) { return m->desc; }
+int mesh_dof_mask(const afd_mesh* m, uint8_t* host) {
+    AFD_HIP_TRY(hipMemcpyAsync(host, m->dofmask, m->g.ndof, hipMemcpyDeviceToHost, m->ctx->stream));
+    AFD_HIP_TRY(hipStreamSynchronize(m->ctx->stream));
+    return AFD_OK;
+}
+}  // namespace afd
+
 namespace {
 
 // The deflated iterations (FP64 and the FP32 inner solves of the mixed form)
@@ -975,6 +986,16 @@ int afd_threshold_noalloc(afd_context* c, const double* s, const int32_t* tie, i
         return AFD_E_INVALID_ARG;
     }
     return threshold_noalloc(c->device, s, tie, n, vol_frac, solid, order, tau, c->stream);
+}
+
+int afd_combine_fields(afd_context* c, int64_t n, int32_t nterms, const double* const* fields, const int32_t* rows,
+                       const double* coef, double* out) {
+    AFD_TRY(check_ctx(c));
+    if (!fields || !rows || !coef || !out) {
+        set_error("combine_fields: null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    return launch_combine(n, nterms, fields, rows, coef, out, c->stream);
 }
 
 int afd_casting(afd_context* c, const int32_t dims[3], const double* phi, int32_t axis, int32_t parting,

@@ -317,6 +317,37 @@ __global__ void k_parting_distance(int nx, int ny, int nz, int axis, int parting
     dist[e] = j >= parting ? j - parting : parting - 1 - j;
 }
 
+// ---- the augmented topological level set (Eq. 3.17-3.18) -------------
+// out = sum_t coef[t] * (sum over the rows of group t of its fields), with
+// the terms and the rows added in order and no fused multiply-add, so that the
+// result is the same double as the plain expression evaluated left to right
+constexpr int MAX_TERMS = 4;
+struct CombineP {
+    const double* f[MAX_TERMS];  // group t: rows f[t][r * n + e], r < rows[t]
+    int rows[MAX_TERMS];
+    double coef[MAX_TERMS];
+    int nterms;
+};
+__global__ void k_combine(int64_t n, CombineP p, double* out) {
+#pragma clang fp contract(off)
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double acc = 0.0;
+    for (int t = 0; t < p.nterms; ++t) {
+        double s = p.f[t][e];
+        for (int r = 1; r < p.rows[t]; ++r) s = s + p.f[t][(int64_t)r * n + e];
+        const double term = p.coef[t] * s;
+        acc = t == 0 ? term : acc + term;
+    }
+    out[e] = acc;
+}
+
+// element densities of a topology: 1 for solid, the ersatz scale for void
+__global__ void k_density(int64_t n, const uint8_t* solid, double void_scale, double* rho) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) rho[e] = solid[e] ? 1.0 : void_scale;
+}
+
 __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* solid, int32_t* order_out) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -326,6 +357,35 @@ __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* s
 }
 
 }  // namespace
+
+int launch_combine(int64_t n, int nterms, const double* const* fields, const int* rows, const double* coef,
+                   double* out, hipStream_t s) {
+    if (nterms < 1 || nterms > MAX_TERMS || n < 1) {
+        set_error("combine: 1..4 terms and n >= 1");
+        return AFD_E_INVALID_ARG;
+    }
+    CombineP p;
+    memset(&p, 0, sizeof(p));
+    p.nterms = nterms;
+    for (int t = 0; t < nterms; ++t) {
+        if (!fields[t] || rows[t] < 1) {
+            set_error("combine: null field or empty group");
+            return AFD_E_INVALID_ARG;
+        }
+        p.f[t] = fields[t];
+        p.rows[t] = rows[t];
+        p.coef[t] = coef[t];
+    }
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, p, out);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
+
+int launch_density(int64_t n, const uint8_t* solid, double void_scale, double* rho, hipStream_t s) {
+    hipLaunchKernelGGL(k_density, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, solid, void_scale, rho);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
+}
 
 int launch_parting_distance(const int dims[3], int axis, int parting, int32_t* dist, hipStream_t s) {
     const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];

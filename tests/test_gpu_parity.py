@@ -957,3 +957,67 @@ def test_casting_topology_has_no_cavity(ctx, axis):
         assert np.array_equal(got, want), p
         assert not _has_cavity(got, dims, axis, p), p
         assert int(got.sum()) == math.ceil(0.4 * n)
+
+
+# ------------------------------------------------------------- level-set loop (Sec. 3.2-3.4, 3.8)
+def _levelset_lockstep(ctx, dims, loads, block, params, cast=(-1, 0)):
+    # the GPU loop against the oracle's, step by step: every topology the GPU
+    # solves is re-solved by the oracle (direct solve of the assembled system),
+    # which then takes the same decision (event, target, step, mu, gamma) and
+    # extracts the same next topology (outside the tie band of its cut)
+    from oracle import levelset as ls
+    fixed = wl.clamp_x0(dims)
+    F = np.stack(loads)
+    n = wl.n_elems(dims)
+    p = ls.Params(cast_axis=cast[0], cast_parting=cast[1], **params)
+    m = make_mesh(ctx, dims, np.ones(n), fixed, block=block)
+    o = afdcg.make_levelset_opts(cast_axis=cast[0], cast_parting=cast[1], rtol=1e-11, **params)
+    code, solid, hist, topo = afdcg.afd_levelset_run(m, o, F, n, hist_cap=300, with_topologies=True)
+    afdcg.afd_mesh_destroy(m)
+    assert code == afdcg.AFD_OK and hist[-1].event == afdcg.AFD_LS_TERMINATED
+    Ke = fem.ke_gauss()
+    loop = ls.Loop(dims, p)
+    nxt = loop.first()
+    mismatched = 0
+    for k, rec in enumerate(hist):
+        s_k = topo[k]
+        diff = np.flatnonzero(s_k != nxt)
+        if diff.size:  # only inside the tie band of the oracle's cut
+            fld, vol = loop.last_extract
+            if cast[0] >= 0:
+                from oracle.casting import cast_project
+                fld = cast_project(fld, dims, cast[0], cast[1])
+            keep = math.ceil(vol * n)
+            tau = np.sort(fld)[::-1][keep - 1]
+            assert np.all(np.abs(fld[diff] - tau) <= 1e-6 * np.max(np.abs(fld))), (k, diff)
+            mismatched += diff.size
+        U = ls.fea(dims, s_k, fixed, F, Ke, p)
+        J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
+        nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p))
+        o_rec = loop.history[-1]
+        assert abs(rec.J - J) <= 1e-8 * J, (k, rec.J, J)
+        assert (rec.event, rec.v, rec.dv, rec.nsolid) == (o_rec.event, o_rec.v, o_rec.dv, o_rec.nsolid), (k, rec, o_rec)
+        assert abs(rec.mu - o_rec.mu) <= 1e-8 * max(1.0, o_rec.mu) and rec.gamma == o_rec.gamma, (k, rec, o_rec)
+    assert len(loop.history) == len(hist) and loop.history[-1].event == ls.FEA_TERMINATED
+    assert np.array_equal(solid, loop.best[0])  # the last converged feasible design
+    return hist, solid, loop.best[0], mismatched
+
+
+def test_levelset_loop_matches_oracle(ctx):
+    # two load cases (bottom edge and an off-centre point load: no mirror ties), J <= 2.5 J0
+    dims = (16, 8, 8)
+    loads = [wl.edge_load(dims, "bottom"), wl.point_load(dims, wl.node_id(dims, 16, 2, 8))]
+    hist, solid, b_solid, mism = _levelset_lockstep(ctx, dims, loads, (4, 4, 4), dict(alpha_J=2.5))
+    conv = [r for r in hist if r.event == afdcg.AFD_LS_CONVERGED]
+    assert conv[-1].g <= 0 and int(solid.sum()) == conv[-1].nsolid
+    assert any(r.event == afdcg.AFD_LS_VIOLATED for r in hist)
+    assert mism <= 2 * len(hist)
+    print(f"level-set loop 16x8x8: {len(hist)} solves, final volume {conv[-1].v:.4f}, J/J0 "
+          f"{conv[-1].J / hist[0].J:.3f}, {mism} elements inside tie bands")
+
+
+def test_levelset_loop_with_casting_matches_oracle(ctx):
+    dims = (16, 8, 8)
+    loads = [wl.point_load(dims, wl.node_id(dims, 16, 3, 0))]
+    hist, solid, b_solid, mism = _levelset_lockstep(ctx, dims, loads, (4, 4, 4), dict(alpha_J=2.0), cast=(2, 4))
+    assert not _has_cavity(solid, dims, 2, 4)
