@@ -281,6 +281,21 @@ int afd_threshold_noalloc(afd_context* ctx, const double* s, const int32_t* tie,
 int afd_casting(afd_context* ctx, const int32_t dims[3], const double* phi, int32_t axis, int32_t parting,
                 double* out, int32_t* dist);
 
+/* p-norm von Mises stress (the stress constraint of Eq. 3.21 / 3.23 and the
+ * adjoint field of Eq. 3.3) of nrhs (1..4) displacement fields U (device,
+ * [nrhs][n_dof]) on the mesh's current densities: element stresses at the
+ * voxel centre sigma_e = rho_e D B_c u_e, von Mises vm_e, and
+ * *pn_host = (sum_r sum_e vm_{e,r}^p)^(1/p) over every element and field
+ * (p >= 2, e.g. 8).  vm (optional device [nrhs][n_elem]) receives vm_e.  B
+ * (optional device [nrhs][n_dof]) receives the adjoint right-hand sides
+ * d pn / d U[r] = pn^(1-p) sum_e vm_e^(p-2) rho_e B_c^T D V sigma_e (V the
+ * von Mises quadratic form), zero on fixed DOFs: afd_solve of B gives the
+ * adjoint fields lambda_r, and the mutual energies of (U[r], lambda_r)
+ * (afd_sensitivity pairs) are the stress sensitivity field.  Synchronous;
+ * allocates a work space of up to 48 B per element per field. */
+int afd_stress_pnorm(afd_mesh* mesh, int32_t nrhs, const double* U, double p, double* vm, double* pn_host,
+                     double* B);
+
 /* The augmented topological level set (Eq. 3.17-3.18): out[e] =
  * sum_t coef[t] * (sum_{r < rows[t]} fields[t][r * n + e]), terms and rows
  * added left to right without fused multiply-adds (so it is the double the
@@ -315,7 +330,11 @@ int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
 /* ---- the optimisation loop (Sec. 3.2-3.4, 3.6, 3.8; Fig. 6-7) ------------ */
 /* Pareto tracing of minimum volume from the full design domain downward
  * under the hard constraint J <= alpha_J J0 (Eq. 3.21-3.22; J the sum of the
- * load cases' compliances, J0 its value on the full domain).  Per solve k:
+ * load cases' compliances, J0 its value on the full domain) and optionally
+ * sigma_PN <= alpha_sigma sigma_PN0 (Eq. 3.23, afd_stress_pnorm; its adjoint
+ * solve per step, g_s, mu_s, gamma_s by the same rules, and the term
+ * w_s T_sigma / (alpha_sigma sigma_PN0) of the level set, T_sigma the mutual
+ * energies of the load cases and their adjoint fields).  Per solve k:
  * the finite element solves of every load case (afd_solve, warm-started from
  * the previous displacements), g = J / (alpha_J J0) - 1, the multiplier and
  * penalty updates mu <- max(mu + gamma g, 0) and Eq. 3.12 (gamma kept at
@@ -331,6 +350,9 @@ int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
  *  - the next topology: the ceil(v nE) elements of highest T_L (with the
  *    casting constraint, Sec. 3.7: of the projected field, ties cut nearer
  *    the parting plane first), void elements at void_scale.
+ * With damping the topology is extracted from the mean of the solve's level
+ * set and the level set its topology was extracted from (a fixed point that
+ * would alternate between two topologies settles).
  * The mesh's fixity is used and its densities are overwritten (on return
  * they are those of the last solved topology).  F: HOST, nload (1..4) x n_dof,
  * zero on fixed DOFs.  solid: HOST, n_elem, receives the last converged
@@ -355,6 +377,12 @@ typedef struct {
     double void_scale;         /* ersatz scale of void elements (e.g. 1e-3)      */
     int32_t cast_axis;         /* casting constraint: 0..2, or -1 for none       */
     int32_t cast_parting;      /* parting plane index along cast_axis            */
+    double alpha_sigma;        /* stress constraint sigma_PN <= alpha_sigma
+                                  sigma_PN0 (Eq. 3.23), <= 0: none; needs
+                                  nload <= 2                                     */
+    double pnorm_p;            /* p of the stress p-norm (>= 2, e.g. 8)          */
+    int32_t damping;           /* 1: extract from the mean of the solve's level
+                                  set and the one its topology came from         */
     afd_solve_opts solve;      /* the solves (mem_kind, pairs, x0 are set by the loop) */
 } afd_levelset_opts;
 typedef struct {
@@ -369,6 +397,8 @@ typedef struct {
     double t_fea, t_total;     /* seconds: this solve (afd_solve, all load
                                   cases) and the whole step (solve, fields,
                                   level set, extraction, bookkeeping)           */
+    double S, g_s, mu_s, gamma_s; /* stress p-norm, its constraint value, its
+                                  multiplier and penalty (0 without it)         */
 } afd_levelset_record;
 int afd_levelset_run(afd_mesh* mesh, const afd_levelset_opts* opts, int32_t nload, const double* F,
                      uint8_t* solid, afd_levelset_record* hist, int32_t hist_cap, int32_t* n_hist,

@@ -36,6 +36,11 @@ Readings of the paper used here (it leaves these open):
 * Step 9: back to the last converged feasible topology (volume v_b), dv
   halved, next target v_b - dv, extracted from that topology's level set;
   termination when dv < dv_min or the next target would be <= 0.
+* With the p-norm stress constraint sigma_PN <= alpha_sigma sigma_PN0
+  (Eq. 3.23, see stress.py) a second term joins: g_s, its own mu_s and
+  gamma_s (same rules, same start values), T_L = w_J T_J / (alpha_J J0) +
+  w_s T_sigma / (alpha_sigma sigma_PN0); a violated stress constraint is a
+  hard violation like the compliance one.
 * Topology at v (Eq. 3.6): the ceil(v nE) elements of highest T_L (ties by
   index; with the casting constraint of Sec. 3.7 the projected field, ties by
   the distance to the parting plane, then index); void elements get the
@@ -48,7 +53,7 @@ import math
 
 import numpy as np
 
-from . import fem, post, solvers
+from . import fem, post, solvers, stress
 from .casting import cast_project, parting_distance
 
 FEA_FIXED_POINT = 0   # a fixed-point solve at the current target
@@ -101,6 +106,9 @@ class Params:
     void_scale: float = 1e-3
     cast_axis: int = -1        # casting constraint (Sec. 3.7): axis, or -1 for none
     cast_parting: int = 0
+    alpha_sigma: float = 0.0   # sigma_PN <= alpha_sigma sigma_PN0 (Eq. 3.23); <= 0: no stress constraint
+    pnorm_p: float = 8.0
+    damping: bool = False      # extract from the mean of this level set and the one the topology came from
 
 
 @dataclasses.dataclass
@@ -114,6 +122,10 @@ class Record:
     mu: float         # after the update
     gamma: float
     dv: float         # step after this solve's decision
+    S: float = 0.0    # stress p-norm (0 without the stress constraint)
+    g_s: float = 0.0
+    mu_s: float = 0.0
+    gamma_s: float = 0.0
 
 
 def extract(field, vol, dims, p: Params):
@@ -141,6 +153,17 @@ def compliance_field(dims, solid, Ke, U, p: Params):
     return sum(post.element_energy(dims, rho, Ke, U[r]) for r in range(U.shape[0]))
 
 
+def stress_quantities(dims, solid, fixed, Ke, U, p: Params):
+    """sigma_PN over the load cases and its sensitivity field (the mutual
+    energies of the primal and adjoint fields), by direct adjoint solves."""
+    rho = density(solid, p)
+    S = stress.pnorm(U, dims, rho, p.pnorm_p)
+    B = stress.adjoint_rhs(U, dims, rho, fixed, p.pnorm_p)
+    K = fem.assemble(dims, rho, Ke)
+    Lam = np.stack([solvers.solve_direct(K, fixed, b) for b in B])
+    return S, stress.stress_field(dims, rho, Ke, U, Lam)
+
+
 class Loop:
     """The loop as a state machine: ``first()`` gives the full domain; after
     each solve, ``after_solve(solid, J, field)`` records it and returns the
@@ -152,30 +175,41 @@ class Loop:
         self.p = p
         self.n = int(np.prod(dims))
         self.mu, self.gamma = p.mu0, p.gamma0
+        self.mu_s, self.gamma_s = p.mu0, p.gamma0
         self.dv = p.dv0
         self.k = 0
         self.J0 = None
+        self.S0 = None
         self.g_prev = None
+        self.gs_prev = None
         self.v = 1.0               # target of the topology being analysed
         self.fp = 0                # solves at the current target
         self.J_prev_same = None    # compliance of the previous solve at this target
         self.best = None           # (solid, v, J, field) of the last converged feasible design
         self.history = []
         self.last_extract = None   # (field, volume fraction) of the last extraction
+        self.src = None            # the level set the topology being analysed was extracted from
 
     def first(self):
         return np.ones(self.n, dtype=np.uint8)
 
-    def after_solve(self, solid, J, field_J):
+    def after_solve(self, solid, J, field_J, S=None, field_S=None):
         p = self.p
         k, v = self.k, self.v
+        stress = p.alpha_sigma > 0
         if k == 0:
             self.J0 = J
+            self.S0 = S
         g = J / (p.alpha_J * self.J0) - 1.0
         mu, gamma = al_update(self.mu, self.gamma, g, self.g_prev, k, p.varsigma, p.eta)
         self.mu, self.gamma, self.g_prev = mu, gamma, g
+        g_s = 0.0
+        if stress:
+            g_s = S / (p.alpha_sigma * self.S0) - 1.0
+            self.mu_s, self.gamma_s = al_update(self.mu_s, self.gamma_s, g_s, self.gs_prev, k, p.varsigma, p.eta)
+            self.gs_prev = g_s
         self.fp += 1
-        if g > 0.0:
+        if g > 0.0 or g_s > 0.0:
             event = FEA_VIOLATED
         elif k == 0 or self._converged(J):
             event = FEA_CONVERGED
@@ -192,11 +226,19 @@ class Loop:
             else:
                 self._target(self.best[1] - self.dv)
                 self.last_extract = (self.best[3], self.v)
+                self.src = self.best[3]
                 nxt = extract(self.best[3], self.v, self.dims, p)
         else:
             # steps 5-6: the augmented level set and the topology extracted from it
-            w = weights([mu], [gamma], [g])
-            field = combined_field([field_J], [w[0] / (p.alpha_J * self.J0)])
+            if stress:
+                w = weights([mu, self.mu_s], [gamma, self.gamma_s], [g, g_s])
+                field = combined_field([field_J, field_S], [w[0] / (p.alpha_J * self.J0),
+                                                            w[1] / (p.alpha_sigma * self.S0)])
+            else:
+                w = weights([mu], [gamma], [g])
+                field = combined_field([field_J], [w[0] / (p.alpha_J * self.J0)])
+            if p.damping and self.src is not None:
+                field = 0.5 * (field + self.src)
             if event == FEA_CONVERGED:  # step 8: the next target
                 self.best = (solid.copy(), v, J, field)
                 if v - self.dv <= 0.0:
@@ -204,12 +246,16 @@ class Loop:
                 else:
                     self._target(v - self.dv)
                     self.last_extract = (field, self.v)
+                    self.src = field
                     nxt = extract(field, self.v, self.dims, p)
             else:
                 self.J_prev_same = J
                 self.last_extract = (field, v)
+                self.src = field
                 nxt = extract(field, v, self.dims, p)
-        self.history.append(Record(k, event, v, int(solid.sum()), J, g, mu, gamma, self.dv))
+        self.history.append(Record(k, event, v, int(solid.sum()), J, g, mu, gamma, self.dv,
+                                   S if stress else 0.0, g_s, self.mu_s if stress else 0.0,
+                                   self.gamma_s if stress else 0.0))
         self.k += 1
         if self.k >= p.max_fea:
             nxt = None
@@ -231,6 +277,11 @@ class Loop:
         while solid is not None:
             U = fea(self.dims, solid, fixed, F, Ke, self.p)
             J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
-            solid = self.after_solve(solid, J, compliance_field(self.dims, solid, Ke, U, self.p))
+            fJ = compliance_field(self.dims, solid, Ke, U, self.p)
+            if self.p.alpha_sigma > 0:
+                S, fS = stress_quantities(self.dims, solid, fixed, Ke, U, self.p)
+                solid = self.after_solve(solid, J, fJ, S, fS)
+            else:
+                solid = self.after_solve(solid, J, fJ)
         b = self.best
         return (b[0], b[1], b[2]), self.history

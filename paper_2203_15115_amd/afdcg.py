@@ -43,7 +43,7 @@ EXPORTED = [
     "afd_dot",
     "afd_restrict", "afd_prolong", "afd_coarse_setup", "afd_coarse_matrix", "afd_coarse_solve",
     "afd_sensitivity", "afd_threshold", "afd_threshold_noalloc", "afd_solve", "afd_combine_fields",
-    "afd_levelset_run", "afd_server_create", "afd_server_submit",
+    "afd_levelset_run", "afd_stress_pnorm", "afd_server_create", "afd_server_submit",
     "afd_server_poll", "afd_server_wait", "afd_server_clock", "afd_server_destroy",
 ]
 
@@ -77,13 +77,15 @@ class afd_levelset_opts(C.Structure):
     _fields_ = [("alpha_J", C.c_double), ("dv0", C.c_double), ("dv_min", C.c_double), ("mu0", C.c_double),
                 ("gamma0", C.c_double), ("varsigma", C.c_double), ("eta", C.c_double), ("conv_tol", C.c_double),
                 ("max_fp", C.c_int32), ("max_fea", C.c_int32), ("void_scale", C.c_double),
-                ("cast_axis", C.c_int32), ("cast_parting", C.c_int32), ("solve", afd_solve_opts)]
+                ("cast_axis", C.c_int32), ("cast_parting", C.c_int32), ("alpha_sigma", C.c_double),
+                ("pnorm_p", C.c_double), ("damping", C.c_int32), ("solve", afd_solve_opts)]
 
 
 class afd_levelset_record(C.Structure):
     _fields_ = [("fea", C.c_int32), ("event", C.c_int32), ("nsolid", C.c_int32), ("iterations", C.c_int32),
                 ("v", C.c_double), ("J", C.c_double), ("g", C.c_double), ("mu", C.c_double),
-                ("gamma", C.c_double), ("dv", C.c_double), ("t_fea", C.c_double), ("t_total", C.c_double)]
+                ("gamma", C.c_double), ("dv", C.c_double), ("t_fea", C.c_double), ("t_total", C.c_double),
+                ("S", C.c_double), ("g_s", C.c_double), ("mu_s", C.c_double), ("gamma_s", C.c_double)]
 
 
 AFD_LS_FIXED_POINT, AFD_LS_CONVERGED, AFD_LS_VIOLATED, AFD_LS_DIVERGED, AFD_LS_TERMINATED = 0, 1, 2, 3, 4
@@ -141,6 +143,7 @@ def lib():
             "afd_casting": (C.c_int, [vp, C.POINTER(i32), vp, i32, i32, vp, vp]),
             "afd_solve": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, vp, vp, vp, vp, vp]),
             "afd_combine_fields": (C.c_int, [vp, i64, i32, vp, vp, vp, vp]),
+            "afd_stress_pnorm": (C.c_int, [vp, i32, vp, dbl, vp, C.POINTER(dbl), vp]),
             "afd_levelset_run": (C.c_int, [vp, C.POINTER(afd_levelset_opts), i32, vp, vp, vp, i32,
                                            C.POINTER(i32), vp]),
             "afd_server_create": (C.c_int, [vp, C.c_uint64, i32, C.POINTER(vp)]),
@@ -343,6 +346,13 @@ def afd_solve(mesh, opts, nrhs, F, U, J=None, S=None, raise_on_error=True):
     return code, list(st)
 
 
+def afd_stress_pnorm(mesh, nrhs, U, p=8.0, vm=None, B=None):
+    """Returns the p-norm of the von Mises stresses of the nrhs fields."""
+    pn = C.c_double()
+    check(lib().afd_stress_pnorm(mesh, nrhs, _ptr(U), float(p), _ptr(vm), C.byref(pn), _ptr(B)), "afd_stress_pnorm")
+    return pn.value
+
+
 def afd_combine_fields(ctx, n, groups, coef, out):
     """groups: sequence of (device tensor of rows x n, rows) pairs; coef: one value per group."""
     k = len(groups)
@@ -355,11 +365,11 @@ def afd_combine_fields(ctx, n, groups, coef, out):
 
 def make_levelset_opts(alpha_J=3.0, dv0=0.025, dv_min=0.025 / 16, mu0=100.0, gamma0=10.0, varsigma=0.25, eta=10.0,
                        conv_tol=0.01, max_fp=8, max_fea=400, void_scale=1e-3, cast_axis=-1, cast_parting=0,
-                       **solvekw):
+                       alpha_sigma=0.0, pnorm_p=8.0, damping=False, **solvekw):
     so = make_opts(**solvekw)
     o = afd_levelset_opts(float(alpha_J), float(dv0), float(dv_min), float(mu0), float(gamma0), float(varsigma),
                           float(eta), float(conv_tol), int(max_fp), int(max_fea), float(void_scale), int(cast_axis),
-                          int(cast_parting), so)
+                          int(cast_parting), float(alpha_sigma), float(pnorm_p), 1 if damping else 0, so)
     o._keep = so._keep
     return o
 

@@ -299,6 +299,9 @@ int launch_parting_distance(const int dims[3], int axis, int parting, int32_t* d
 // out = sum_t coef[t] * (sum of the rows[t] rows of fields[t]), left to right, no FMA (t < 4)
 int launch_combine(int64_t n, int nterms, const double* const* fields, const int* rows, const double* coef,
                    double* out, hipStream_t s);
+// p-norm von Mises stress of nrhs displacement fields (see afd_stress_pnorm)
+int stress_pnorm(const Grid& g, const double h[3], double E, double nu, const double* rho, const uint8_t* nmask,
+                 int nrhs, const double* U, double p, double* vm, double* pn_host, double* B, hipStream_t st);
 // rho[e] = solid[e] ? 1 : void_scale
 int launch_density(int64_t n, const uint8_t* solid, double void_scale, double* rho, hipStream_t s);
 // ranking and threshold (see afd_threshold): threshold_run on a caller-given

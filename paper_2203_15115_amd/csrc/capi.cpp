@@ -988,6 +988,16 @@ int afd_threshold_noalloc(afd_context* c, const double* s, const int32_t* tie, i
     return threshold_noalloc(c->device, s, tie, n, vol_frac, solid, order, tau, c->stream);
 }
 
+int afd_stress_pnorm(afd_mesh* m, int32_t nrhs, const double* U, double p, double* vm, double* pn, double* B) {
+    if (!m || !U || !pn) {
+        set_error("stress_pnorm: null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
+    return stress_pnorm(m->g, h, m->desc.E, m->desc.nu, m->rho, m->nmask, nrhs, U, p, vm, pn, B, m->ctx->stream);
+}
+
 int afd_combine_fields(afd_context* c, int64_t n, int32_t nterms, const double* const* fields, const int32_t* rows,
                        const double* coef, double* out) {
     AFD_TRY(check_ctx(c));

@@ -18,17 +18,20 @@ namespace {
 struct Dev {
     double* rho = nullptr;      // n_elem
     uint8_t* solid = nullptr;   // n_elem, topology to solve
-    double* S = nullptr;        // nload x n_elem energy fields
-    double* field = nullptr;    // n_elem, T_L of the last feasible solve
-    double* best = nullptr;     // n_elem, T_L of the last converged feasible design
+    double* S = nullptr;        // energy fields (see the layout in afd_levelset_run)
+    double* raw = nullptr;      // n_elem, T_L of this solve
+    double* cur = nullptr;      // n_elem, T_L after damping
+    double* src = nullptr;      // n_elem, the level set the solved topology was extracted from
+    double* best = nullptr;     // n_elem, level set of the last converged feasible design
     double* cast = nullptr;     // n_elem, projected field
     int32_t* dist = nullptr;    // n_elem, parting-plane distance
     double* F = nullptr;        // nload x n_dof
-    double* U = nullptr;        // nload x n_dof
+    double* UL = nullptr;       // nload x n_dof displacements, then (stress) nload x n_dof adjoint fields
+    double* B = nullptr;        // nload x n_dof adjoint right-hand sides (stress)
     double* J = nullptr;        // nload
     void release() {
-        for (void* p : {(void*)rho, (void*)solid, (void*)S, (void*)field, (void*)best, (void*)cast, (void*)dist,
-                        (void*)F, (void*)U, (void*)J})
+        for (void* p : {(void*)rho, (void*)solid, (void*)S, (void*)raw, (void*)cur, (void*)src, (void*)best,
+                        (void*)cast, (void*)dist, (void*)F, (void*)UL, (void*)B, (void*)J})
             if (p) (void)hipFree(p);
     }
 };
@@ -99,6 +102,16 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
                 }
             }
     }
+    const bool stress = o->alpha_sigma > 0.0;
+    if (stress && (nload > 2 || !(o->pnorm_p >= 2.0))) {
+        set_error("levelset: the stress constraint needs nload <= 2 and pnorm_p >= 2");
+        return AFD_E_INVALID_ARG;
+    }
+    // energy fields: without the stress constraint the nload strain-energy
+    // fields; with it the afd_sensitivity layout of [U_0..U_n-1, L_0..L_n-1]
+    // with the pairs (r, n + r): n strain energies, n adjoint self energies
+    // (unused), n mutual energies
+    const int nfields = stress ? 3 * nload : nload;
     Dev dv;
     auto fail = [&](int rc) {
         (void)hipStreamSynchronize(s);
@@ -106,18 +119,25 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         return rc;
     };
     int rc = AFD_OK;
-    if ((rc = alloc(&dv.rho, ne)) || (rc = alloc(&dv.solid, ne)) || (rc = alloc(&dv.S, (size_t)nload * ne)) ||
-        (rc = alloc(&dv.field, ne)) || (rc = alloc(&dv.best, ne)) || (rc = alloc(&dv.cast, ne)) ||
-        (rc = alloc(&dv.dist, ne)) || (rc = alloc(&dv.F, (size_t)nload * nd)) ||
-        (rc = alloc(&dv.U, (size_t)nload * nd)) || (rc = alloc(&dv.J, nload)))
+    if ((rc = alloc(&dv.rho, ne)) || (rc = alloc(&dv.solid, ne)) || (rc = alloc(&dv.S, (size_t)nfields * ne)) ||
+        (rc = alloc(&dv.raw, ne)) || (rc = alloc(&dv.cur, ne)) || (rc = alloc(&dv.src, ne)) ||
+        (rc = alloc(&dv.best, ne)) || (rc = alloc(&dv.cast, ne)) || (rc = alloc(&dv.dist, ne)) ||
+        (rc = alloc(&dv.F, (size_t)nload * nd)) || (rc = alloc(&dv.UL, (size_t)(stress ? 2 : 1) * nload * nd)) ||
+        (stress && (rc = alloc(&dv.B, (size_t)nload * nd))) || (rc = alloc(&dv.J, nload)))
         return fail(rc);
-    if (hipMemcpyAsync(dv.F, F, (size_t)nload * nd * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-        set_error("levelset: copy of F failed");
-        return fail(AFD_E_HIP);
-    }
-    // topology extraction at volume fraction v from a level-set field
+    auto copy = [&](void* dst, const void* src_, size_t bytes, hipMemcpyKind kind) -> int {
+        if (hipMemcpyAsync(dst, src_, bytes, kind, s) != hipSuccess) {
+            set_error("levelset: copy failed");
+            return AFD_E_HIP;
+        }
+        return AFD_OK;
+    };
+    if ((rc = copy(dv.F, F, (size_t)nload * nd * sizeof(double), hipMemcpyHostToDevice))) return fail(rc);
+    double* Lam = dv.UL + (size_t)nload * nd;
+    // topology extraction at volume fraction v from a level-set field, which
+    // becomes the source of the next solve's topology
     auto extract = [&](const double* fld, double v) -> int {
+        if (o->damping && fld != dv.src) AFD_TRY(copy(dv.src, fld, ne * sizeof(double), hipMemcpyDeviceToDevice));
         if (o->cast_axis >= 0) {
             AFD_TRY(afd_casting(ctx, dims, fld, o->cast_axis, o->cast_parting, dv.cast, dv.dist));
             return afd_threshold(ctx, dv.cast, dv.dist, ne, v, dv.solid, nullptr, nullptr);
@@ -126,31 +146,41 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
     };
     // the first topology: the full domain
     std::vector<uint8_t> solid_h(ne, 1), best_h(ne, 1);
-    if (hipMemcpyAsync(dv.solid, solid_h.data(), ne, hipMemcpyHostToDevice, s) != hipSuccess) {
-        set_error("levelset: copy failed");
-        return fail(AFD_E_HIP);
-    }
-    double mu = o->mu0, gamma = o->gamma0, step = o->dv0, v = 1.0, J0 = 0.0, g_prev = 0.0;
+    if ((rc = copy(dv.solid, solid_h.data(), ne, hipMemcpyHostToDevice))) return fail(rc);
+    double mu = o->mu0, gamma = o->gamma0, mu_s = o->mu0, gamma_s = o->gamma0, step = o->dv0, v = 1.0;
+    double J0 = 0.0, S0 = 0.0, g_prev = 0.0, gs_prev = 0.0;
     double J_prev_same = -1.0, v_best = 1.0;  // -1: no previous solve at this target
     int fp = 0;
-    std::vector<afd_solve_stats> st(nload);
+    bool have_src = false;
+    std::vector<afd_solve_stats> st(nload), st2(nload);
     std::vector<double> Jh(nload);
+    std::vector<int32_t> pairs(2 * nload);
+    for (int r = 0; r < nload; ++r) pairs[2 * r] = r, pairs[2 * r + 1] = nload + r;
     const int kmax = std::min(o->max_fea, hist_cap);
     for (int k = 0; k < kmax; ++k) {
         const double t0 = now_s();
-        // step 2: the solves over the current topology
+        // step 2: the solves over the current topology (warm-started)
         if ((rc = launch_density(ne, dv.solid, o->void_scale, dv.rho, s))) return fail(rc);
         if ((rc = afd_mesh_set_scale(m, dv.rho, ne, AFD_MEM_DEVICE))) return fail(rc);
         afd_solve_opts so = o->solve;
         so.mem_kind = AFD_MEM_DEVICE;
         so.pairs = nullptr;
         so.npairs = 0;
-        so.x0 = k > 0 ? dv.U : nullptr;  // warm start from the previous topology's displacements
-        if ((rc = afd_solve(m, &so, nload, dv.F, dv.U, dv.J, dv.S, st.data()))) return fail(rc);
-        if (hipMemcpyAsync(Jh.data(), dv.J, nload * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(solid_h.data(), dv.solid, ne, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            set_error("levelset: copy failed");
+        so.x0 = k > 0 ? dv.UL : nullptr;
+        if ((rc = afd_solve(m, &so, nload, dv.F, dv.UL, dv.J, stress ? nullptr : dv.S, st.data()))) return fail(rc);
+        double Sp = 0.0;
+        if (stress) {
+            // the stress p-norm, its adjoint right-hand sides and adjoint solves
+            if ((rc = afd_stress_pnorm(m, nload, dv.UL, o->pnorm_p, nullptr, &Sp, dv.B))) return fail(rc);
+            so.x0 = k > 0 ? Lam : nullptr;
+            if ((rc = afd_solve(m, &so, nload, dv.B, Lam, nullptr, nullptr, st2.data()))) return fail(rc);
+            if ((rc = afd_sensitivity(m, 2 * nload, dv.UL, nload, pairs.data(), dv.S))) return fail(rc);
+        }
+        if ((rc = copy(Jh.data(), dv.J, nload * sizeof(double), hipMemcpyDeviceToHost)) ||
+            (rc = copy(solid_h.data(), dv.solid, ne, hipMemcpyDeviceToHost)))
+            return fail(rc);
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            set_error("levelset: stream sync failed");
             return fail(AFD_E_HIP);
         }
         const double t1 = now_s();
@@ -158,20 +188,26 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         int iters = 0;
         for (int r = 0; r < nload; ++r) {
             J += Jh[r];
-            iters += st[r].iterations;
+            iters += st[r].iterations + (stress ? st2[r].iterations : 0);
         }
         int nsolid = 0;
         for (int64_t e = 0; e < ne; ++e) nsolid += solid_h[e];
         if (topo_hist) memcpy(topo_hist + (size_t)k * ne, solid_h.data(), ne);
-        // step 3: constraint value and the multiplier / penalty updates
-        if (k == 0) J0 = J;
+        // step 3: constraint values and the multiplier / penalty updates
+        if (k == 0) J0 = J, S0 = Sp;
         const double g = J / (o->alpha_J * J0) - 1.0;
         al_update(mu, gamma, g, g_prev, k, o->varsigma, o->eta);
         g_prev = g;
+        double g_s = 0.0;
+        if (stress) {
+            g_s = Sp / (o->alpha_sigma * S0) - 1.0;
+            al_update(mu_s, gamma_s, g_s, gs_prev, k, o->varsigma, o->eta);
+            gs_prev = g_s;
+        }
         ++fp;
         const bool converged = J_prev_same >= 0.0 && std::fabs(J - J_prev_same) < o->conv_tol * J_prev_same;
         int event;
-        if (g > 0.0) event = AFD_LS_VIOLATED;                     // step 4
+        if (g > 0.0 || g_s > 0.0) event = AFD_LS_VIOLATED;      // step 4
         else if (k == 0 || converged) event = AFD_LS_CONVERGED;  // step 7
         else if (fp >= o->max_fp) event = AFD_LS_DIVERGED;
         else event = AFD_LS_FIXED_POINT;
@@ -188,23 +224,28 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
                 fp = 0;
                 J_prev_same = -1.0;
                 if ((rc = extract(dv.best, v))) return fail(rc);
+                have_src = true;
             }
         } else {
             // steps 5-6: the augmented level set and the topology at the target
-            double w = std::max(mu + gamma * g, 0.0);
-            if (w == 0.0) w = 1.0;
-            const double coef = w / (o->alpha_J * J0);
-            const double* grp[1] = {dv.S};
-            const int32_t rows[1] = {nload};
-            if ((rc = afd_combine_fields(ctx, ne, 1, grp, rows, &coef, dv.field))) return fail(rc);
+            double w = std::max(mu + gamma * g, 0.0), w_s = std::max(mu_s + gamma_s * g_s, 0.0);
+            if (stress ? (w == 0.0 && w_s == 0.0) : w == 0.0) w = w_s = 1.0;
+            const double* grp[2] = {dv.S, dv.S + (size_t)2 * nload * ne};
+            const int32_t rows[2] = {nload, nload};
+            const double coef[2] = {w / (o->alpha_J * J0), stress ? w_s / (o->alpha_sigma * S0) : 0.0};
+            if ((rc = afd_combine_fields(ctx, ne, stress ? 2 : 1, grp, rows, coef, dv.raw))) return fail(rc);
+            double* cur = dv.raw;
+            if (o->damping && have_src) {  // the mean with the level set this topology came from
+                const double* g2[2] = {dv.raw, dv.src};
+                const int32_t r2[2] = {1, 1};
+                const double half[2] = {0.5, 0.5};
+                if ((rc = afd_combine_fields(ctx, ne, 2, g2, r2, half, dv.cur))) return fail(rc);
+                cur = dv.cur;
+            }
             if (event == AFD_LS_CONVERGED) {  // step 8
                 v_best = v;
                 best_h = solid_h;
-                if (hipMemcpyAsync(dv.best, dv.field, ne * sizeof(double), hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess) {
-                    set_error("levelset: copy failed");
-                    return fail(AFD_E_HIP);
-                }
+                if ((rc = copy(dv.best, cur, ne * sizeof(double), hipMemcpyDeviceToDevice))) return fail(rc);
                 if (v - step <= 0.0) {
                     event = AFD_LS_TERMINATED;
                     more = false;
@@ -212,11 +253,13 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
                     v -= step;
                     fp = 0;
                     J_prev_same = -1.0;
-                    if ((rc = extract(dv.field, v))) return fail(rc);
+                    if ((rc = extract(cur, v))) return fail(rc);
+                    have_src = true;
                 }
             } else {
                 J_prev_same = J;
-                if ((rc = extract(dv.field, v))) return fail(rc);
+                if ((rc = extract(cur, v))) return fail(rc);
+                have_src = true;
             }
         }
         afd_levelset_record& h = hist[k];
@@ -230,6 +273,10 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         h.mu = mu;
         h.gamma = gamma;
         h.dv = step;
+        h.S = Sp;
+        h.g_s = g_s;
+        h.mu_s = stress ? mu_s : 0.0;
+        h.gamma_s = stress ? gamma_s : 0.0;
         if (hipStreamSynchronize(s) != hipSuccess) {
             set_error("levelset: stream sync failed");
             return fail(AFD_E_HIP);

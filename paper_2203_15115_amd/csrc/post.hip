@@ -317,6 +317,118 @@ __global__ void k_parting_distance(int nx, int ny, int nz, int axis, int parting
     dist[e] = j >= parting ? j - parting : parting - 1 - j;
 }
 
+// ---- p-norm von Mises stress (Eq. 3.3, 3.23) --------------------------
+// Element stress at the voxel centre: in the Haar basis the centroid
+// gradient of component c along axis i is H[1 << i][c] / (4 h_i) (the mean of
+// the four edge differences along i), sigma = rho (lam tr(eps) I + 2 mu eps).
+struct StressP {
+    int nx, ny, nz;
+    int nrhs;
+    int64_t ndof;
+    double inv4h[3];
+    double lam, mu, p;
+    const double* U;     // [nrhs][ndof]
+    const double* rho;
+    double* vm;          // [nrhs][nE] or null
+    double* part;        // [nrhs][gridDim.x]: per-workgroup sums of vm^p
+    double* T;           // [nrhs][6][nE] or null: rho vm^(p-2) D V sigma (adjoint terms)
+};
+
+__global__ __launch_bounds__(256) void k_stress(StressP p) {
+    __shared__ double red[256 / 64];
+    const int nE = p.nx * p.ny * p.nz;  // < 2^31 (checked on the host)
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    double vp = 0.0;
+    if (e < nE) {
+        const int ex = e % p.nx, exy = e / p.nx, ey = exy % p.ny, ez = exy / p.ny;
+        const int sy = p.nx + 1, sz = (p.nx + 1) * (p.ny + 1);
+        const double* u0 = p.U + (int64_t)r * p.ndof;
+        double h[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int64_t nd = (ex + (a & 1)) + sy * (ey + ((a >> 1) & 1)) + (int64_t)sz * (ez + (a >> 2));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[a][c] = u0[3 * nd + c];
+        }
+        haar_fwd(h);
+        double g[3][3];  // g[i][c] = d u_c / d x_i at the centre
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g[i][c] = h[1 << i][c] * p.inv4h[i];
+        const double rho = p.rho[e];
+        const double exx = g[0][0], eyy = g[1][1], ezz = g[2][2];
+        const double tr = exx + eyy + ezz;
+        const double sxx = rho * (p.lam * tr + 2.0 * p.mu * exx), syy = rho * (p.lam * tr + 2.0 * p.mu * eyy),
+                     szz = rho * (p.lam * tr + 2.0 * p.mu * ezz);
+        const double tyz = rho * p.mu * (g[1][2] + g[2][1]), txz = rho * p.mu * (g[0][2] + g[2][0]),
+                     txy = rho * p.mu * (g[0][1] + g[1][0]);
+        const double q = sxx * sxx + syy * syy + szz * szz - sxx * syy - syy * szz - szz * sxx +
+                         3.0 * (tyz * tyz + txz * txz + txy * txy);
+        const double vm = sqrt(fmax(q, 0.0));
+        vp = pow(vm, p.p);
+        if (p.vm) p.vm[(int64_t)r * nE + e] = vm;
+        if (p.T) {
+            const double w = rho * pow(vm, p.p - 2.0);
+            const double a0 = sxx - 0.5 * (syy + szz), a1 = syy - 0.5 * (sxx + szz), a2 = szz - 0.5 * (sxx + syy);
+            const double ta = p.lam * (a0 + a1 + a2);
+            double* T = p.T + (int64_t)r * 6 * nE + e;
+            T[0] = w * (ta + 2.0 * p.mu * a0);
+            T[(int64_t)nE] = w * (ta + 2.0 * p.mu * a1);
+            T[2 * (int64_t)nE] = w * (ta + 2.0 * p.mu * a2);
+            T[3 * (int64_t)nE] = w * p.mu * 3.0 * tyz;
+            T[4 * (int64_t)nE] = w * p.mu * 3.0 * txz;
+            T[5 * (int64_t)nE] = w * p.mu * 3.0 * txy;
+        }
+    }
+    // fixed-order workgroup sum of vm^p
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) vp += __shfl_down(vp, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = vp;
+    __syncthreads();
+    if (threadIdx.x == 0) p.part[(int64_t)r * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// B[r] at node n: scale * sum over the node's elements of B_c,a^T t_e (a the
+// node's corner of element e), zero on fixed DOFs: the adjoint right-hand side
+__global__ void k_stress_rhs(StressP p, const uint8_t* nmask, double scale, double* B) {
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int nn = (nx + 1) * (ny + 1) * (nz + 1);
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int r = blockIdx.y;
+    const int nE = nx * ny * nz;
+    const int i = n % (nx + 1), ij = n / (nx + 1), j = ij % (ny + 1), k = ij / (ny + 1);
+    const double* T = p.T + (int64_t)r * 6 * nE;
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int dz = 0; dz < 2; ++dz) {
+        const int ez = k - 1 + dz;
+        if (ez < 0 || ez >= nz) continue;
+        for (int dy = 0; dy < 2; ++dy) {
+            const int ey = j - 1 + dy;
+            if (ey < 0 || ey >= ny) continue;
+            for (int dx = 0; dx < 2; ++dx) {
+                const int ex = i - 1 + dx;
+                if (ex < 0 || ex >= nx) continue;
+                const int e = ex + nx * (ey + ny * ez);
+                // the node is corner (1 - dx, 1 - dy, 1 - dz) of element e: sign +1 on the far side
+                const double gx = (dx ? -1.0 : 1.0) * p.inv4h[0], gy = (dy ? -1.0 : 1.0) * p.inv4h[1],
+                             gz = (dz ? -1.0 : 1.0) * p.inv4h[2];
+                const double txx = T[e], tyy = T[(int64_t)nE + e], tzz = T[2 * (int64_t)nE + e],
+                             tyz = T[3 * (int64_t)nE + e], txz = T[4 * (int64_t)nE + e], txy = T[5 * (int64_t)nE + e];
+                f[0] += gx * txx + gy * txy + gz * txz;
+                f[1] += gx * txy + gy * tyy + gz * tyz;
+                f[2] += gx * txz + gy * tyz + gz * tzz;
+            }
+        }
+    }
+    const uint8_t m = nmask[n];
+    double* b = B + (int64_t)r * p.ndof + 3 * (int64_t)n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[c] = ((m >> c) & 1) ? 0.0 : scale * f[c];
+}
+
 // ---- the augmented topological level set (Eq. 3.17-3.18) -------------
 // out = sum_t coef[t] * (sum over the rows of group t of its fields), with
 // the terms and the rows added in order and no fused multiply-add, so that the
@@ -357,6 +469,64 @@ __global__ void k_mark(int64_t n, int64_t keep, const int32_t* order, uint8_t* s
 }
 
 }  // namespace
+
+int stress_pnorm(const Grid& g, const double h[3], double E, double nu, const double* rho, const uint8_t* nmask,
+                 int nrhs, const double* U, double p, double* vm, double* pn_host, double* B, hipStream_t st) {
+    if (nrhs < 1 || nrhs > 4 || !(p >= 2.0) || !std::isfinite(p)) {
+        set_error("stress: nrhs 1..4 and p >= 2");
+        return AFD_E_INVALID_ARG;
+    }
+    if (g.nelem >= ((int64_t)1 << 31) || g.nnode >= ((int64_t)1 << 31)) {
+        set_error("stress: more than 2^31 elements or nodes");
+        return AFD_E_INVALID_ARG;
+    }
+    StressP P;
+    memset(&P, 0, sizeof(P));
+    P.nx = g.nx, P.ny = g.ny, P.nz = g.nz;
+    P.nrhs = nrhs;
+    P.ndof = g.ndof;
+    for (int a = 0; a < 3; ++a) P.inv4h[a] = 1.0 / (4.0 * h[a]);
+    P.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    P.mu = E / (2.0 * (1.0 + nu));
+    P.p = p;
+    P.U = U;
+    P.rho = rho;
+    P.vm = vm;
+    const unsigned nb = (unsigned)((g.nelem + 255) / 256);
+    double* work = nullptr;
+    const size_t part_n = (size_t)nrhs * nb, T_n = B ? (size_t)nrhs * 6 * g.nelem : 0;
+    if (hipMalloc((void**)&work, (part_n + T_n) * sizeof(double)) != hipSuccess) {
+        set_error("stress: out of device memory");
+        return AFD_E_OOM;
+    }
+    P.part = work;
+    P.T = B ? work + part_n : nullptr;
+    int rc = AFD_OK;
+    std::vector<double> part(part_n);
+    hipLaunchKernelGGL(k_stress, dim3(nb, nrhs), dim3(256), 0, st, P);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(part.data(), P.part, part_n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("stress: kernel or copy failed");
+        rc = AFD_E_HIP;
+    }
+    double sum = 0.0;
+    for (size_t i = 0; i < part_n; ++i) sum += part[i];
+    const double pn = std::pow(sum, 1.0 / p);
+    if (rc == AFD_OK && pn_host) *pn_host = pn;
+    if (rc == AFD_OK && B) {
+        const double scale = sum > 0.0 ? std::pow(pn, 1.0 - p) : 0.0;
+        hipLaunchKernelGGL(k_stress_rhs, dim3((unsigned)((g.nnode + 255) / 256), nrhs), dim3(256), 0, st, P, nmask,
+                           scale, B);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+            set_error("stress: adjoint right-hand side kernel failed");
+            rc = AFD_E_HIP;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(work);
+    return rc;
+}
 
 int launch_combine(int64_t n, int nterms, const double* const* fields, const int* rows, const double* coef,
                    double* out, hipStream_t s) {

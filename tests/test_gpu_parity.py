@@ -993,9 +993,15 @@ def _levelset_lockstep(ctx, dims, loads, block, params, cast=(-1, 0)):
             mismatched += diff.size
         U = ls.fea(dims, s_k, fixed, F, Ke, p)
         J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
-        nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p))
+        if p.alpha_sigma > 0:
+            S, fS = ls.stress_quantities(dims, s_k, fixed, Ke, U, p)
+            nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p), S, fS)
+            assert abs(rec.S - S) <= 1e-8 * S, (k, rec.S, S)
+        else:
+            nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p))
         o_rec = loop.history[-1]
         assert abs(rec.J - J) <= 1e-8 * J, (k, rec.J, J)
+        assert abs(rec.mu_s - o_rec.mu_s) <= 1e-8 * max(1.0, o_rec.mu_s) and rec.gamma_s == o_rec.gamma_s, k
         assert (rec.event, rec.v, rec.dv, rec.nsolid) == (o_rec.event, o_rec.v, o_rec.dv, o_rec.nsolid), (k, rec, o_rec)
         assert abs(rec.mu - o_rec.mu) <= 1e-8 * max(1.0, o_rec.mu) and rec.gamma == o_rec.gamma, (k, rec, o_rec)
     assert len(loop.history) == len(hist) and loop.history[-1].event == ls.FEA_TERMINATED
@@ -1021,3 +1027,73 @@ def test_levelset_loop_with_casting_matches_oracle(ctx):
     loads = [wl.point_load(dims, wl.node_id(dims, 16, 3, 0))]
     hist, solid, b_solid, mism = _levelset_lockstep(ctx, dims, loads, (4, 4, 4), dict(alpha_J=2.0), cast=(2, 4))
     assert not _has_cavity(solid, dims, 2, 4)
+
+
+# ------------------------------------------------------------- p-norm stress (Eq. 3.3, 3.23)
+@pytest.mark.parametrize("dims,h", [((6, 3, 3), (1.0, 1.0, 1.0)), ((19, 9, 8), (1.0, 2.0, 0.5)),
+                                    ((48, 24, 24), (1.0, 1.0, 1.0))])
+def test_stress_pnorm_matches_oracle(ctx, dims, h):
+    # von Mises at the element centres, the p-norm over two fields and the
+    # adjoint right-hand sides, against the oracle, on random displacements
+    from oracle import stress
+    E, nu = (2.5, 0.27) if h != (1.0, 1.0, 1.0) else (1.0, 0.3)
+    rho, fixed = rand_problem(dims, 31)
+    m = make_mesh(ctx, dims, rho, fixed, h=h, E=E, nu=nu)
+    nd, n = 3 * wl.n_nodes(dims), wl.n_elems(dims)
+    U = np.random.default_rng(32).standard_normal((2, nd))
+    vm = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    B = torch.empty((2, nd), dtype=torch.float64, device="cuda")
+    for p in (8.0, 2.0):
+        pn = afdcg.afd_stress_pnorm(m, 2, dev(U), p, vm, B)
+        vmh, Bh = host(vm), host(B)
+        want_vm = np.stack([stress.von_mises(stress.element_stress(dims, rho, u, h, E, nu)) for u in U])
+        assert np.max(np.abs(vmh - want_vm)) <= 1e-13 * np.max(want_vm)
+        assert abs(pn - stress.pnorm(U, dims, rho, p, h, E, nu)) <= 1e-12 * pn
+        want_B = stress.adjoint_rhs(U, dims, rho, fixed, p, h, E, nu)
+        assert np.max(np.abs(Bh - want_B)) <= 1e-11 * np.max(np.abs(want_B)), p
+        assert np.all(Bh[:, fixed == 1] == 0)
+    afdcg.afd_mesh_destroy(m)
+
+
+def test_stress_sensitivity_field_matches_oracle(ctx):
+    # the whole stress path on the GPU: primal solves, adjoint right-hand
+    # sides, adjoint solves, mutual energies; against the oracle's direct solves
+    from oracle import stress
+    dims = (16, 8, 8)
+    n, nd = wl.n_elems(dims), 3 * wl.n_nodes(dims)
+    rho = np.where(np.random.default_rng(40).random(n) < 0.3, 1e-3, 1.0)
+    fixed = wl.clamp_x0(dims)
+    F = np.stack([wl.edge_load(dims, "bottom"), wl.edge_load(dims, "mid")])
+    m = make_mesh(ctx, dims, rho, fixed, block=(4, 4, 4))
+    UL = torch.zeros((4, nd), dtype=torch.float64, device="cuda")
+    opts = afdcg.make_opts(rtol=1e-12, mem_kind=afdcg.AFD_MEM_DEVICE)
+    afdcg.afd_solve(m, opts, 2, dev(F), UL[:2])
+    B = torch.empty((2, nd), dtype=torch.float64, device="cuda")
+    pn = afdcg.afd_stress_pnorm(m, 2, UL[:2], 8.0, None, B)
+    afdcg.afd_solve(m, opts, 2, B.clone(), UL[2:])
+    S = torch.empty((6, n), dtype=torch.float64, device="cuda")
+    afdcg.afd_sensitivity(m, 4, UL, [(0, 2), (1, 3)], S)
+    Sh = host(S)
+    afdcg.afd_mesh_destroy(m)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    U = np.stack([solvers.solve_direct(K, fixed, f) for f in F])
+    assert abs(pn - stress.pnorm(U, dims, rho)) <= 1e-9 * pn
+    Bo = stress.adjoint_rhs(U, dims, rho, fixed)
+    Lam = np.stack([solvers.solve_direct(K, fixed, b) for b in Bo])
+    want = stress.stress_field(dims, rho, fem.ke_gauss(), U, Lam)
+    got = Sh[4] + Sh[5]
+    assert np.max(np.abs(got - want)) <= 1e-8 * np.max(np.abs(want))
+
+
+def test_levelset_loop_with_stress_matches_oracle(ctx):
+    # compliance and stress constraints, J <= 100 J0 (inactive) and
+    # sigma_PN <= 1.5 sigma_PN0, with damping; two edge loads
+    dims = (16, 8, 8)
+    loads = [wl.edge_load(dims, "bottom"), wl.edge_load(dims, "mid")]
+    hist, solid, b_solid, mism = _levelset_lockstep(
+        ctx, dims, loads, (4, 4, 4), dict(alpha_J=100.0, alpha_sigma=1.5, dv_min=0.025 / 4, damping=True))
+    conv = [r for r in hist if r.event == afdcg.AFD_LS_CONVERGED]
+    assert conv[-1].g_s <= 0 and conv[-1].S > 1.3 * hist[0].S  # the stress constraint bound the run
+    assert any(r.event == afdcg.AFD_LS_VIOLATED and r.g_s > 0 for r in hist)
+    print(f"stress-constrained loop 16x8x8: {len(hist)} solves, final volume {conv[-1].v:.4f}, "
+          f"S/S0 {conv[-1].S / hist[0].S:.3f}, J/J0 {conv[-1].J / hist[0].J:.3f}, {mism} elements in tie bands")

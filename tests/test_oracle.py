@@ -611,3 +611,108 @@ def test_levelset_loop_with_casting_has_no_cavity():
     assert len(seen) == len(h) > 5 and J <= 2 * h[0].J
     for s in seen:
         assert not _has_cavity(s, dims, 2, 3)
+
+
+# ------------------------------------------------------------- p-norm stress (Eq. 3.3, 3.23)
+def test_von_mises_special_cases_and_invariance():
+    from oracle.stress import von_mises
+    assert von_mises(np.array([[3.0, 0, 0, 0, 0, 0]]))[0] == 3.0               # uniaxial
+    assert abs(von_mises(np.array([[0, 0, 0, 0, 0, 2.0]]))[0] - 2 * np.sqrt(3)) < 1e-15  # pure shear
+    assert von_mises(np.array([[5.0, 5.0, 5.0, 0, 0, 0]]))[0] == 0.0           # hydrostatic
+    # invariant under rotations of the stress tensor
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        S = rng.standard_normal((3, 3))
+        S = S + S.T
+        Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        R = Q @ S @ Q.T
+        v = lambda T: np.array([[T[0, 0], T[1, 1], T[2, 2], T[1, 2], T[0, 2], T[0, 1]]])
+        assert abs(von_mises(v(S))[0] - von_mises(v(R))[0]) < 1e-12 * von_mises(v(S))[0]
+        # and equal to sqrt(3/2 |dev S|^2)
+        dev = S - np.trace(S) / 3 * np.eye(3)
+        assert abs(von_mises(v(S))[0] - np.sqrt(1.5 * np.sum(dev * dev))) < 1e-12 * von_mises(v(S))[0]
+
+
+def test_element_stress_of_a_linear_field():
+    # trilinear elements reproduce a linear displacement u = A x exactly: the
+    # centroid stress is lambda tr(eps) I + 2 mu eps with eps = sym(A), times rho
+    from oracle.stress import element_stress
+    dims, h, E, nu = (3, 2, 2), (1.0, 2.0, 0.5), 2.0, 0.27
+    A = np.random.default_rng(4).standard_normal((3, 3))
+    X = fem.node_coords(dims, h)
+    u = (X @ A.T).reshape(-1)
+    rho = np.random.default_rng(5).uniform(0.5, 2.0, wl.n_elems(dims))
+    sig = element_stress(dims, rho, u, h, E, nu)
+    lam, mu = fem.lame(E, nu)
+    eps = 0.5 * (A + A.T)
+    S = lam * np.trace(eps) * np.eye(3) + 2 * mu * eps
+    want = np.array([S[0, 0], S[1, 1], S[2, 2], S[1, 2], S[0, 2], S[0, 1]])
+    assert np.allclose(sig, rho[:, None] * want[None, :], rtol=1e-13, atol=1e-13)
+
+
+def _stress_problem(dims=(6, 3, 3)):
+    rng = np.random.default_rng(8)
+    rho = np.where(rng.random(wl.n_elems(dims)) < 0.3, 1e-3, 1.0)
+    fixed = wl.clamp_x0(dims)
+    F = np.stack([wl.edge_load(dims, "bottom"), wl.point_load(dims, wl.node_id(dims, dims[0], 1, dims[2]))])
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    U = np.stack([solvers.solve_direct(K, fixed, f) for f in F])
+    return dims, rho, fixed, F, K, U
+
+
+def test_adjoint_rhs_is_the_gradient_of_the_pnorm():
+    # central differences of sigma_PN along random directions of each load
+    # case's displacements (p = 8): the adjoint right-hand side is the gradient
+    from oracle.stress import adjoint_rhs, pnorm
+    dims, rho, fixed, F, K, U = _stress_problem()
+    B = adjoint_rhs(U, dims, rho, fixed, p=8.0)
+    rng = np.random.default_rng(9)
+    for k in range(2):
+        for _ in range(3):
+            d = rng.standard_normal(U.shape[1]) * (fixed == 0)
+            eps = 1e-6 * np.linalg.norm(U[k]) / np.linalg.norm(d)
+            Up, Um = U.copy(), U.copy()
+            Up[k] += eps * d
+            Um[k] -= eps * d
+            fd = (pnorm(Up, dims, rho) - pnorm(Um, dims, rho)) / (2 * eps)
+            assert abs(fd - B[k] @ d) <= 1e-6 * abs(fd), (k, fd, B[k] @ d)
+    assert np.all(B[:, fixed == 1] == 0)
+
+
+def test_stress_field_is_the_displacement_route_sensitivity():
+    # T_sigma(e) = sum_k rho_e lambda_k,e^T Ke u_k,e equals the derivative of
+    # sigma_PN (stresses evaluated with the old densities) through the
+    # displacements when element e's stiffness scale shrinks by a factor (1 - d)
+    from oracle.stress import adjoint_rhs, pnorm, stress_field
+    dims, rho, fixed, F, K, U = _stress_problem()
+    Ke = fem.ke_gauss()
+    B = adjoint_rhs(U, dims, rho, fixed)
+    Lam = np.stack([solvers.solve_direct(K, fixed, b) for b in B])
+    T = stress_field(dims, rho, Ke, U, Lam)
+    for e in (0, 7, 25, 53):
+        vals = []
+        for d in (1e-5, -1e-5):
+            r2 = rho.copy()
+            r2[e] *= 1 - d
+            K2 = fem.assemble(dims, r2, Ke)
+            U2 = np.stack([solvers.solve_direct(K2, fixed, f) for f in F])
+            vals.append(pnorm(U2, dims, rho))
+        fd = (vals[0] - vals[1]) / 2e-5
+        assert abs(fd - T[e]) <= 1e-5 * np.max(np.abs(T)), (e, fd, T[e])
+
+
+def test_levelset_loop_with_stress_invariants():
+    # J <= 100 J0 (inactive) and sigma_PN <= 1.5 sigma_PN0 with damping on a
+    # 12x6x6 cantilever: every converged design satisfies both constraints,
+    # the stress constraint is the one that binds, and the fixed points settle
+    from oracle import levelset as ls
+    dims = (12, 6, 6)
+    p = ls.Params(alpha_J=100.0, alpha_sigma=1.5, dv_min=0.025 / 4, damping=True)
+    (best, v, J), h = _loop_run(dims, p)
+    S0 = h[0].S
+    conv = [r for r in h if r.event == ls.FEA_CONVERGED]
+    assert all(r.g <= 0 and r.g_s <= 0 and r.S <= 1.5 * S0 for r in conv)
+    assert any(r.event == ls.FEA_VIOLATED and r.g_s > 0 and r.g <= 0 for r in h)
+    assert conv[-1].S > 1.3 * S0 and conv[-1].v < 0.6
+    assert not any(r.event == ls.FEA_DIVERGED for r in h)
+    assert abs(h[0].g_s - (1 / 1.5 - 1)) < 1e-15
