@@ -659,22 +659,42 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const TM* M, int64_t mstrid
     // acc += m[j0:j1] . xv[j0:j1] for every right-hand side
     auto window = [&](const TM* m, const double* xv, int j0, int j1) {
         // aligned groups of N (P, the block offsets and the vector strides are
-        // multiples of 4), four 16-byte loads per lane in flight; group members
-        // outside [j0, j1) count zero
-        for (int jj = (j0 & ~(N - 1)) + N * lane; jj < j1; jj += 256 * N) {
-            double mv[4][N];
+        // multiples of 4); group members outside [j0, j1) count zero.  A chunk
+        // is GU 16-byte loads per lane of the matrix and of the first
+        // right-hand side, all issued before the first is used, so that a row
+        // window of up to 64 * N * GU columns (1024 in FP64: every chain step's
+        // window) costs one memory latency instead of one per four loads
+        constexpr int GU = 8;
+        for (int jj = (j0 & ~(N - 1)) + N * lane; jj < j1; jj += 64 * N * GU) {
+            double mv[GU][N], xv0[GU][N];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < GU; ++u) {
                 const int j = jj + 64 * N * u;
-                if (j < j1) load_lane(m + j, mv[u]);
+                if (j < j1) {
+                    load_lane(m + j, mv[u]);
+#pragma unroll
+                    for (int e = 0; e < N; e += 2) {
+                        const double2 xx = *reinterpret_cast<const double2*>(xv + j + e);
+                        xv0[u][e] = xx.x;
+                        xv0[u][e + 1] = xx.y;
+                    }
+                }
 #pragma unroll
                 for (int e = 0; e < N; ++e)
                     if (j >= j1 || j + e < j0 || j + e >= j1) mv[u][e] = 0.0;
             }
-            for (int r = 0; r < nrhs; ++r) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int j = jj + 64 * N * u;
+                if (j < j1) {
+#pragma unroll
+                    for (int e = 0; e < N; ++e) acc[0] = fma(mv[u][e], xv0[u][e], acc[0]);
+                }
+            }
+            for (int r = 1; r < nrhs; ++r) {
                 const double* xr = xv + r * vstride;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < GU; ++u) {
                     const int j = jj + 64 * N * u;
                     if (j < j1) {
 #pragma unroll
