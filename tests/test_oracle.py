@@ -8,6 +8,7 @@ from fractions import Fraction
 import math
 
 import numpy as np
+import scipy.linalg as sla
 import pytest
 
 from oracle import fem, solvers, post
@@ -716,3 +717,78 @@ def test_levelset_loop_with_stress_invariants():
     assert conv[-1].S > 1.3 * S0 and conv[-1].v < 0.6
     assert not any(r.event == ls.FEA_DIVERGED for r in h)
     assert abs(h[0].g_s - (1 / 1.5 - 1)) < 1e-15
+
+
+# ------------------------------------------------------------- modal analysis (Eq. 3.4, 3.21)
+def test_mass_matrix_exact_and_quadrature():
+    from oracle.modal import me_exact, me_gauss
+    for h in ((1, 1, 1), (1, 2, Fraction(1, 2))):
+        Mx = np.array([[float(v) for v in row] for row in me_exact(h)])
+        assert np.max(np.abs(me_gauss(tuple(float(x) for x in h)) - Mx)) <= 1e-15 * np.max(Mx)
+        vol = float(h[0] * h[1] * h[2])
+        # one component of a unit translation carries the element's mass
+        t = np.zeros(24)
+        t[0::3] = 1.0
+        assert abs(t @ Mx @ t - vol) <= 1e-15 * vol
+    # per-component spectrum of the unit cube: products of the 1-D values 1/2, 1/6
+    M = np.array([[float(v) for v in row] for row in me_exact((1, 1, 1))])
+    ev = np.sort(np.linalg.eigvalsh(M[0::3, 0::3]))
+    want = np.sort([1 / 8] + [1 / 24] * 3 + [1 / 72] * 3 + [1 / 216])
+    assert np.allclose(ev, want, rtol=1e-14)
+
+
+def test_single_element_modes_and_scaling():
+    # a free element: six zero-energy modes, the rest positive; with the voxel
+    # edges scaled by s the eigenvalues scale by 1/s^2 (K ~ s, M ~ s^3)
+    from oracle.modal import me_gauss
+    lam1 = sla.eigh(fem.ke_gauss(), me_gauss(), eigvals_only=True)
+    assert np.sum(np.abs(lam1) < 1e-12) == 6 and np.all(lam1[6:] > 1e-3)
+    lam2 = sla.eigh(fem.ke_gauss((2.0, 2.0, 2.0)), me_gauss((2.0, 2.0, 2.0)), eigvals_only=True)
+    assert np.allclose(lam2[6:], lam1[6:] / 4, rtol=1e-12)
+
+
+def _modal_problem(dims, seed=50):
+    from oracle.modal import me_gauss
+    rho = np.where(np.random.default_rng(seed).random(wl.n_elems(dims)) < 0.3, 1e-3, 1.0)
+    fixed = wl.clamp_x0(dims)
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    M = fem.assemble(dims, rho, me_gauss())
+    return rho, fixed, K, M
+
+
+def test_lowest_modes_dense_and_lanczos_agree():
+    from oracle.modal import lowest_modes
+    dims = (12, 6, 6)  # 3,822 free DOFs: the shift-invert Lanczos branch
+    rho, fixed, K, M = _modal_problem(dims)
+    lam, Phi = lowest_modes(K, M, fixed, nev=3)
+    Kff, free = fem.constrained_operator(K, fixed)
+    Mff, _ = fem.constrained_operator(M, fixed)
+    lam_d = sla.eigh(Kff.toarray(), Mff.toarray(), eigvals_only=True, subset_by_index=[0, 2])
+    assert np.allclose(lam, lam_d, rtol=1e-10)
+    for i in range(3):
+        p = Phi[i]
+        assert abs(p @ (M @ p) - 1) < 1e-12 and np.all(p[fixed == 1] == 0)
+        res = Kff @ p[free] - lam[i] * (Mff @ p[free])
+        assert np.linalg.norm(res) <= 1e-8 * lam[i] * np.linalg.norm(Mff @ p[free])
+    assert abs(Phi[0] @ (M @ Phi[1])) < 1e-10
+
+
+def test_eigen_sensitivity_is_the_derivative():
+    # T_lambda(e) = rho_e phi^T (Ke - lambda Me) phi equals the drop of the
+    # lowest eigenvalue when element e's stiffness and mass shrink by (1 - d)
+    from oracle.modal import eigen_sensitivity, lowest_modes, me_gauss
+    dims = (6, 4, 2)  # unequal cross-section: bending in y and z well apart
+    rho, fixed, K, M = _modal_problem(dims, 51)
+    lam, Phi = lowest_modes(K, M, fixed, 2)
+    assert lam[1] > 1.05 * lam[0]  # a simple eigenvalue
+    Ke, Me = fem.ke_gauss(), me_gauss()
+    T = eigen_sensitivity(dims, rho, Ke, Me, lam[0], Phi[0])
+    for e in (0, 9, 31, 47):
+        vals = []
+        for d in (1e-5, -1e-5):
+            r2 = rho.copy()
+            r2[e] *= 1 - d
+            l2, _ = lowest_modes(fem.assemble(dims, r2, Ke), fem.assemble(dims, r2, Me), fixed, 1)
+            vals.append(l2[0])
+        fd = (vals[1] - vals[0]) / 2e-5
+        assert abs(fd - T[e]) <= 1e-6 * np.max(np.abs(T)), (e, fd, T[e])
