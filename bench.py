@@ -337,6 +337,32 @@ def bench_serve(ctx, args):
     return out
 
 
+def bench_modal(ctx, stream):
+    """The lowest eigenpair of the 128x64x64 cantilever (40% void, 8^3
+    blocks) by subspace iteration on 4 vectors with 4-column deflated inner
+    solves to 1e-10, with its eigenvalue sensitivity field (Eq. 3.4)."""
+    import torch
+    from paper_2203_15115_amd import afdcg, workloads as wl
+    p = wl.config(2)
+    m = afdcg.afd_mesh_create(ctx, p.dims, block=p.block)
+    afdcg.afd_mesh_set_scale(m, p.rho, p.nelem, afdcg.AFD_MEM_HOST)
+    afdcg.afd_mesh_set_fixed(m, p.fixed, p.ndof, afdcg.AFD_MEM_HOST)
+    afdcg.afd_coarse_setup(m)
+    Phi = torch.empty((1, p.ndof), dtype=torch.float64, device="cuda")
+    S = torch.empty((1, p.nelem), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    code, lam, st = afdcg.afd_modal(m, afdcg.make_opts(rtol=1e-10, check_every=32), 1, Phi, S, tol=1e-8,
+                                    max_iter=60, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    afdcg.afd_mesh_destroy(m)
+    return {"workload": "lowest eigenpair, cantilever 128x64x64, 40% void, 8x8x8 blocks, block of 4, inner "
+                        "solves to 1e-10, Ritz residual 1e-8", "status": code, "lambda": lam[0],
+            "time_s": round(dt, 4), "subspace_iterations": st.iterations, "cg_iterations": st.cg_iterations,
+            "rel_residual": st.rel_residual[0]}
+
+
 def bench_levelset(ctx, stream):
     """The augmented topological level-set loop (Sec. 3.8, Fig. 7) on a
     96x48x48 cantilever (221,184 elements, 680,775 DOF, 8^3 blocks) from the
@@ -390,8 +416,9 @@ def main():
     ap.add_argument("--reps", type=int, default=200, help="timed operator applies")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--config", type=int, default=1)
-    ap.add_argument("--sections", default="multi,mixed,levelset,serve",
-                    help="extra measured sections: multi (4-RHS, VALU vs matrix cores), mixed, levelset, serve")
+    ap.add_argument("--sections", default="multi,mixed,modal,levelset,small,serve",
+                    help="extra measured sections: multi (4-RHS, VALU vs matrix cores), mixed, modal, levelset, "
+                         "small (24x12x12 solve), serve")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-sat", type=int, default=200, help="requests of each saturated serving run")
     ap.add_argument("--apply-only", action="store_true",
@@ -643,11 +670,15 @@ def main():
     if "mixed" in secs:
         out["mixed"] = bench_mixed(ctx, stream, args)
         print(f"# mixed: {json.dumps(out['mixed'])}", file=sys.stderr, flush=True)
+    if "modal" in secs:
+        out["modal"] = bench_modal(ctx, stream)
+        print(f"# modal: {json.dumps(out['modal'])}", file=sys.stderr, flush=True)
     if "levelset" in secs:
         out["levelset"] = bench_levelset(ctx, stream)
         print(f"# level-set loop: {json.dumps(out['levelset'])}", file=sys.stderr, flush=True)
-    out["small_solve"] = bench_small_solve(ctx, stream)
-    print(f"# 24x12x12: {json.dumps(out['small_solve'])}", file=sys.stderr, flush=True)
+    if "small" in secs:
+        out["small_solve"] = bench_small_solve(ctx, stream)
+        print(f"# 24x12x12: {json.dumps(out['small_solve'])}", file=sys.stderr, flush=True)
     if "serve" in secs:
         out["serving"] = bench_serve(ctx, args)
         print(f"# serving: {json.dumps(out['serving'])}", file=sys.stderr, flush=True)

@@ -296,6 +296,34 @@ int afd_casting(afd_context* ctx, const int32_t dims[3], const double* phi, int3
 int afd_stress_pnorm(afd_mesh* mesh, int32_t nrhs, const double* U, double p, double* vm, double* pn_host,
                      double* B);
 
+/* ---- modal analysis (the eigenvalue constraint of Eq. 3.21; Eq. 3.4) ----- */
+/* Y[r] = M U[r] for r < nrhs (1..4): the consistent mass matrix of the voxel
+ * (unit density, int N^T N per component), each element's mass scaled by its
+ * stiffness scale rho_e, applied element by element on the free DOFs (fixed
+ * inputs taken as zero, 0 on fixed DOFs).  U, Y: device, FP64, [nrhs][n_dof]. */
+int afd_apply_M(afd_mesh* mesh, int32_t nrhs, const double* U, double* Y);
+
+typedef struct {
+    int32_t iterations;        /* subspace iterations                            */
+    int32_t cg_iterations;     /* CG iterations of all the inner solves          */
+    int32_t converged;         /* 1 when every Ritz residual met tol             */
+    double rel_residual[3];    /* ||K phi - lambda M phi|| / (lambda ||M phi||)  */
+    double t;                  /* seconds                                        */
+} afd_modal_stats;
+/* The nev (1..3) lowest eigenpairs of K phi = lambda M phi on the free DOFs
+ * (the free vibration problem whose lowest eigenvalue Eq. 3.21 constrains)
+ * by subspace iteration on a block of 4 vectors: each iteration one 4-column
+ * deflated solve K Y = M X (afd_solve with *inner's rtol and precision,
+ * warm-started from X / lambda) and a Rayleigh-Ritz projection, until every
+ * reported pair's Ritz residual is <= tol (AFD_E_NOT_CONVERGED after max_iter
+ * iterations; the outputs then hold the last Ritz pairs).  lambda_host: nev
+ * eigenvalues ascending; Phi: device [nev][n_dof], M-normalised (phi^T M phi
+ * = 1), sign arbitrary; S (optional device [nev][n_elem]): the eigenvalue
+ * sensitivity field of each pair, rho_e phi_e^T (K_e - lambda M_e) phi_e
+ * (Eq. 3.4 by the element route).  Synchronous; allocates 4 x 4 work vectors. */
+int afd_modal(afd_mesh* mesh, const afd_solve_opts* inner, int32_t nev, double tol, int32_t max_iter,
+              double* lambda_host, double* Phi, double* S, afd_modal_stats* stats);
+
 /* The augmented topological level set (Eq. 3.17-3.18): out[e] =
  * sum_t coef[t] * (sum_{r < rows[t]} fields[t][r * n + e]), terms and rows
  * added left to right without fused multiply-adds (so it is the double the

@@ -43,7 +43,7 @@ EXPORTED = [
     "afd_dot",
     "afd_restrict", "afd_prolong", "afd_coarse_setup", "afd_coarse_matrix", "afd_coarse_solve",
     "afd_sensitivity", "afd_threshold", "afd_threshold_noalloc", "afd_solve", "afd_combine_fields",
-    "afd_levelset_run", "afd_stress_pnorm", "afd_server_create", "afd_server_submit",
+    "afd_levelset_run", "afd_stress_pnorm", "afd_apply_M", "afd_modal", "afd_server_create", "afd_server_submit",
     "afd_server_poll", "afd_server_wait", "afd_server_clock", "afd_server_destroy",
 ]
 
@@ -89,6 +89,11 @@ class afd_levelset_record(C.Structure):
 
 
 AFD_LS_FIXED_POINT, AFD_LS_CONVERGED, AFD_LS_VIOLATED, AFD_LS_DIVERGED, AFD_LS_TERMINATED = 0, 1, 2, 3, 4
+
+
+class afd_modal_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("cg_iterations", C.c_int32), ("converged", C.c_int32),
+                ("rel_residual", C.c_double * 3), ("t", C.c_double)]
 
 
 class afd_request(C.Structure):
@@ -144,6 +149,9 @@ def lib():
             "afd_solve": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, vp, vp, vp, vp, vp]),
             "afd_combine_fields": (C.c_int, [vp, i64, i32, vp, vp, vp, vp]),
             "afd_stress_pnorm": (C.c_int, [vp, i32, vp, dbl, vp, C.POINTER(dbl), vp]),
+            "afd_apply_M": (C.c_int, [vp, i32, vp, vp]),
+            "afd_modal": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, dbl, i32, vp, vp, vp,
+                                    C.POINTER(afd_modal_stats)]),
             "afd_levelset_run": (C.c_int, [vp, C.POINTER(afd_levelset_opts), i32, vp, vp, vp, i32,
                                            C.POINTER(i32), vp]),
             "afd_server_create": (C.c_int, [vp, C.c_uint64, i32, C.POINTER(vp)]),
@@ -351,6 +359,21 @@ def afd_stress_pnorm(mesh, nrhs, U, p=8.0, vm=None, B=None):
     pn = C.c_double()
     check(lib().afd_stress_pnorm(mesh, nrhs, _ptr(U), float(p), _ptr(vm), C.byref(pn), _ptr(B)), "afd_stress_pnorm")
     return pn.value
+
+
+def afd_apply_M(mesh, nrhs, U, Y):
+    check(lib().afd_apply_M(mesh, nrhs, _ptr(U), _ptr(Y)), "afd_apply_M")
+
+
+def afd_modal(mesh, inner, nev, Phi, S=None, tol=1e-8, max_iter=60, raise_on_error=True):
+    """Returns (status, eigenvalues list, afd_modal_stats)."""
+    lam = (C.c_double * nev)()
+    st = afd_modal_stats()
+    code = lib().afd_modal(mesh, C.byref(inner), nev, float(tol), int(max_iter), C.cast(lam, C.c_void_p), _ptr(Phi),
+                           _ptr(S), C.byref(st))
+    if raise_on_error:
+        check(code, "afd_modal")
+    return code, list(lam), st
 
 
 def afd_combine_fields(ctx, n, groups, coef, out):

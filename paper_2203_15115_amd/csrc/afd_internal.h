@@ -302,6 +302,12 @@ int launch_combine(int64_t n, int nterms, const double* const* fields, const int
 // p-norm von Mises stress of nrhs displacement fields (see afd_stress_pnorm)
 int stress_pnorm(const Grid& g, const double h[3], double E, double nu, const double* rho, const uint8_t* nmask,
                  int nrhs, const double* U, double p, double* vm, double* pn_host, double* B, hipStream_t st);
+// modal.hip: consistent mass apply and the subspace-iteration eigen-solver (see afd_apply_M, afd_modal)
+int mass_apply(const Grid& g, const double h[3], const double* rho, const uint8_t* nmask, int nrhs, const double* U,
+               double* Y, hipStream_t s);
+int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const double* rho, const uint8_t* nmask,
+                   const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam_out, double* Phi,
+                   double* S, afd_modal_stats* st, hipStream_t s);
 // rho[e] = solid[e] ? 1 : void_scale
 int launch_density(int64_t n, const uint8_t* solid, double void_scale, double* rho, hipStream_t s);
 // ranking and threshold (see afd_threshold): threshold_run on a caller-given

@@ -988,6 +988,28 @@ int afd_threshold_noalloc(afd_context* c, const double* s, const int32_t* tie, i
     return threshold_noalloc(c->device, s, tie, n, vol_frac, solid, order, tau, c->stream);
 }
 
+int afd_apply_M(afd_mesh* m, int32_t nrhs, const double* U, double* Y) {
+    if (!m || !U || !Y) {
+        set_error("apply_M: null argument");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
+    return mass_apply(m->g, h, m->rho, m->nmask, nrhs, U, Y, m->ctx->stream);
+}
+
+int afd_modal(afd_mesh* m, const afd_solve_opts* inner, int32_t nev, double tol, int32_t max_iter, double* lam,
+              double* Phi, double* S, afd_modal_stats* st) {
+    if (!m) {
+        set_error("modal: null mesh");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    if (st) memset(st, 0, sizeof(*st));
+    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
+    return modal_subspace(m, m->g, h, m->rho, m->nmask, inner, nev, tol, max_iter, lam, Phi, S, st, m->ctx->stream);
+}
+
 int afd_stress_pnorm(afd_mesh* m, int32_t nrhs, const double* U, double p, double* vm, double* pn, double* B) {
     if (!m || !U || !pn) {
         set_error("stress_pnorm: null argument");

@@ -1097,3 +1097,58 @@ def test_levelset_loop_with_stress_matches_oracle(ctx):
     assert any(r.event == afdcg.AFD_LS_VIOLATED and r.g_s > 0 for r in hist)
     print(f"stress-constrained loop 16x8x8: {len(hist)} solves, final volume {conv[-1].v:.4f}, "
           f"S/S0 {conv[-1].S / hist[0].S:.3f}, J/J0 {conv[-1].J / hist[0].J:.3f}, {mism} elements in tie bands")
+
+
+# ------------------------------------------------------------- modal analysis (Eq. 3.4, 3.21)
+@pytest.mark.parametrize("dims,h", [((1, 1, 1), (1.0, 1.0, 1.0)), ((17, 16, 9), (1.0, 1.0, 1.0)),
+                                    ((19, 9, 8), (1.0, 2.0, 0.5))])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_apply_M_matches_oracle(ctx, dims, h, nrhs):
+    from oracle.modal import me_gauss
+    rho, fixed = rand_problem(dims, 60 + nrhs)
+    m = make_mesh(ctx, dims, rho, fixed, h=h)
+    Me = me_gauss(h)
+    M = fem.assemble(dims, rho, Me)
+    Mabs = fem.assemble(dims, rho, np.abs(Me))
+    nd = 3 * wl.n_nodes(dims)
+    U = np.random.default_rng(61).standard_normal((nrhs, nd))
+    Yd = torch.empty((nrhs, nd), dtype=torch.float64, device="cuda")
+    afdcg.afd_apply_M(m, nrhs, dev(U), Yd)
+    Y = host(Yd)
+    afdcg.afd_mesh_destroy(m)
+    fx = fixed != 0
+    for r in range(nrhs):
+        u = np.where(fx, 0.0, U[r])
+        want = np.where(fx, 0.0, M @ u)
+        bound = 64 * EPS64 * (Mabs @ np.abs(u)) + 1e-300
+        assert np.all(np.abs(Y[r] - want) <= bound), np.max(np.abs(Y[r] - want) / bound)
+
+
+@pytest.mark.parametrize("dims,block", [((12, 6, 4), (4, 2, 2)), ((24, 12, 8), (4, 4, 4))])
+def test_modal_matches_oracle(ctx, dims, block):
+    # the lowest eigenpairs by subspace iteration with deflated inner solves,
+    # against the oracle's dense / shift-invert Lanczos eigenpairs; the
+    # eigenvalue sensitivity fields against the oracle's
+    from oracle.modal import eigen_sensitivity, lowest_modes, me_gauss
+    n, nd = wl.n_elems(dims), 3 * wl.n_nodes(dims)
+    rho = np.where(np.random.default_rng(70).random(n) < 0.3, 1e-3, 1.0)
+    fixed = wl.clamp_x0(dims)
+    m = make_mesh(ctx, dims, rho, fixed, block=block)
+    Phi = torch.empty((2, nd), dtype=torch.float64, device="cuda")
+    S = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    code, lam, st = afdcg.afd_modal(m, afdcg.make_opts(rtol=1e-11), 2, Phi, S, tol=1e-10, max_iter=200)
+    afdcg.afd_mesh_destroy(m)
+    Ke, Me = fem.ke_gauss(), me_gauss()
+    K, M = fem.assemble(dims, rho, Ke), fem.assemble(dims, rho, Me)
+    lam_o, Phi_o = lowest_modes(K, M, fixed, 3)
+    assert lam_o[1] > 1.05 * lam_o[0] and lam_o[2] > 1.05 * lam_o[1]  # simple eigenvalues
+    P, Sh = host(Phi), host(S)
+    for j in range(2):
+        assert abs(lam[j] - lam_o[j]) <= 1e-10 * lam_o[j], (j, lam[j], lam_o[j])
+        assert st.rel_residual[j] <= 1e-9
+        sgn = np.sign(P[j] @ (M @ Phi_o[j]))
+        assert np.linalg.norm(P[j] - sgn * Phi_o[j]) <= 1e-7 * np.linalg.norm(Phi_o[j]), j
+        want = eigen_sensitivity(dims, rho, Ke, Me, lam_o[j], Phi_o[j])
+        assert np.max(np.abs(Sh[j] - want)) <= 1e-7 * np.max(np.abs(want)), j
+    print(f"modal {dims}: {st.iterations} subspace iterations, {st.cg_iterations} CG iterations, "
+          f"lambda {lam}, residuals {list(st.rel_residual)[:2]}")
