@@ -21,6 +21,7 @@ Modules: ``fem`` (element matrix, mesh indexing, assembly), ``solvers``
 ``casting`` (the casting projection of Sec. 3.7), ``levelset`` (the augmented
 topological level-set loop of Sec. 3.2-3.4 and 3.8 on direct solves),
 ``stress`` (the p-norm von Mises stress, its adjoint and field, Eq. 3.3),
-``modal`` (mass matrix, lowest eigenpairs and their sensitivity, Eq. 3.4).
+``modal`` (mass matrix, lowest eigenpairs and their sensitivity, Eq. 3.4),
+``buckling`` (geometric stiffness, load factors and their sensitivity, Eq. 3.5).
 """
 from . import fem, solvers, post  # noqa: F401

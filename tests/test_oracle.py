@@ -792,3 +792,83 @@ def test_eigen_sensitivity_is_the_derivative():
             vals.append(l2[0])
         fd = (vals[1] - vals[0]) / 2e-5
         assert abs(fd - T[e]) <= 1e-6 * np.max(np.abs(T)), (e, fd, T[e])
+
+
+# ------------------------------------------------------------- linear buckling (Eq. 3.5)
+def test_geometric_stiffness_quadrature_and_closed_forms():
+    from oracle.buckling import kg_element, kg_gauss
+    rng = np.random.default_rng(80)
+    h = (1.0, 2.0, 0.5)
+    S = rng.standard_normal((3, 3))
+    S = S + S.T
+    Kg = kg_element(S, h)
+    assert np.max(np.abs(Kg - kg_gauss(S, h))) <= 1e-14 * np.max(np.abs(Kg))
+    assert np.allclose(Kg, Kg.T, atol=1e-15)
+    X = fem.LOCAL * np.asarray(h)
+    for c in range(3):  # translations carry no geometric energy
+        t = np.zeros(24)
+        t[c::3] = 1.0
+        assert np.max(np.abs(Kg @ t)) <= 1e-13 * np.max(np.abs(Kg))
+    # u_y = theta x + phi y: int S_pq du_y/dx_p du_y/dx_q = (S_xx th^2 + 2 S_xy th ph + S_yy ph^2) V
+    th, ph = 0.7, -0.3
+    u = np.zeros(24)
+    u[1::3] = th * X[:, 0] + ph * X[:, 1]
+    V = h[0] * h[1] * h[2]
+    want = (S[0, 0] * th * th + 2 * S[0, 1] * th * ph + S[1, 1] * ph * ph) * V
+    assert abs(u @ Kg @ u - want) <= 1e-13 * abs(want)
+
+
+def _buckling_problem(dims):
+    from oracle import stress
+    rng = np.random.default_rng(81)
+    rho = np.where(rng.random(wl.n_elems(dims)) < 0.2, 1e-3, 1.0)
+    fixed = wl.clamp_x0(dims)
+    f = wl.edge_load(dims, "mid")
+    # an axial compression of the x = L face plus the transverse edge load
+    for j in range(dims[1] + 1):
+        for k in range(dims[2] + 1):
+            f[3 * wl.node_id(dims, dims[0], j, k)] -= 1.0 / ((dims[1] + 1) * (dims[2] + 1))
+    K = fem.assemble(dims, rho, fem.ke_gauss())
+    u = solvers.solve_direct(K, fixed, f)
+    sig = stress.element_stress(dims, rho, u)
+    return rho, fixed, f, K, u, sig
+
+
+def test_buckling_modes_dense_and_lanczos_agree():
+    from oracle.buckling import assemble_kg, buckling_modes
+    dims = (12, 6, 6)
+    rho, fixed, f, K, u, sig = _buckling_problem(dims)
+    Kg = assemble_kg(dims, sig)
+    lam, Phi = buckling_modes(K, Kg, fixed, 2)   # Lanczos branch (3,822 free DOFs)
+    Kff, free = fem.constrained_operator(K, fixed)
+    Gff, _ = fem.constrained_operator(Kg, fixed)
+    mu = sla.eigh(-Gff.toarray(), Kff.toarray(), eigvals_only=True)
+    want = np.sort(1.0 / mu[mu > 0])[:2]
+    assert np.allclose(lam, want, rtol=1e-9)
+    for i in range(2):
+        p = Phi[i][free]
+        assert abs(p @ (Kff @ p) - 1) < 1e-12
+        r = Kff @ p + lam[i] * (Gff @ p)
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(Kff @ p)
+
+
+def test_buckling_sensitivity_is_the_derivative():
+    # with the prebuckling stresses held (scaled with rho_e), T_P(e) is the
+    # drop of the smallest load factor when element e's scale shrinks by (1 - d)
+    from oracle.buckling import assemble_kg, buckling_modes, buckling_sensitivity
+    dims = (6, 3, 3)
+    rho, fixed, f, K, u, sig = _buckling_problem(dims)
+    Ke = fem.ke_gauss()
+    lam, Phi = buckling_modes(K, assemble_kg(dims, sig), fixed, 2)
+    assert lam[1] > 1.05 * lam[0]
+    T = buckling_sensitivity(dims, rho, Ke, sig, lam[0], Phi[0])
+    for e in (0, 7, 30, 53):
+        vals = []
+        for d in (1e-5, -1e-5):
+            r2 = rho.copy()
+            r2[e] *= 1 - d
+            s2 = sig * (r2 / rho)[:, None]
+            l2, _ = buckling_modes(fem.assemble(dims, r2, Ke), assemble_kg(dims, s2), fixed, 1)
+            vals.append(l2[0])
+        fd = (vals[1] - vals[0]) / 2e-5
+        assert abs(fd - T[e]) <= 1e-6 * np.max(np.abs(T)), (e, fd, T[e])
