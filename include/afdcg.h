@@ -324,6 +324,27 @@ typedef struct {
 int afd_modal(afd_mesh* mesh, const afd_solve_opts* inner, int32_t nev, double tol, int32_t max_iter,
               double* lambda_host, double* Phi, double* S, afd_modal_stats* stats);
 
+/* ---- linear buckling (Eq. 3.5; the buckling constraints of Eq. 3.21, 3.24) */
+/* Y[r] = K_sigma X[r] for r < nrhs (1..4): the geometric stiffness of the
+ * stress state of the displacement field U0 (device, one field), each
+ * element's stress taken at its centre (rho_e D B_c u_e, as in
+ * afd_stress_pnorm): K_sigma,e[(a,i),(b,j)] = delta_ij sum_pq S_pq
+ * int dN_a/dx_p dN_b/dx_q; on the free DOFs (fixed inputs taken as zero, 0 on
+ * fixed DOFs).  Synchronous; allocates 48 B per element for the call. */
+int afd_apply_Kg(afd_mesh* mesh, const double* U0, int32_t nrhs, const double* X, double* Y);
+/* The nev (1..3) smallest positive load factors lambda of
+ * (K + lambda K_sigma) phi = 0 for the stress state of U (device, the static
+ * solution under the applied loads; the critical load is lambda times them),
+ * by the subspace iteration of afd_modal on -K_sigma x = mu K x (largest mu,
+ * lambda = 1 / mu).  Phi: device [nev][n_dof], phi^T K phi = 1; S (optional
+ * device [nev][n_elem]): the load-factor sensitivity field of Eq. 3.5 by the
+ * element route with the prebuckling stresses held,
+ * lambda phi_e^T (rho_e K_e + lambda K_sigma,e) phi_e.  stats as afd_modal
+ * (residual ||K phi + lambda K_sigma phi|| / ||K phi||).  AFD_E_BREAKDOWN if
+ * fewer than nev positive load factors are found. */
+int afd_buckling(afd_mesh* mesh, const double* U, const afd_solve_opts* inner, int32_t nev, double tol,
+                 int32_t max_iter, double* lambda_host, double* Phi, double* S, afd_modal_stats* stats);
+
 /* The augmented topological level set (Eq. 3.17-3.18): out[e] =
  * sum_t coef[t] * (sum_{r < rows[t]} fields[t][r * n + e]), terms and rows
  * added left to right without fused multiply-adds (so it is the double the

@@ -43,7 +43,7 @@ EXPORTED = [
     "afd_dot",
     "afd_restrict", "afd_prolong", "afd_coarse_setup", "afd_coarse_matrix", "afd_coarse_solve",
     "afd_sensitivity", "afd_threshold", "afd_threshold_noalloc", "afd_solve", "afd_combine_fields",
-    "afd_levelset_run", "afd_stress_pnorm", "afd_apply_M", "afd_modal", "afd_server_create", "afd_server_submit",
+    "afd_levelset_run", "afd_stress_pnorm", "afd_apply_M", "afd_modal", "afd_apply_Kg", "afd_buckling", "afd_server_create", "afd_server_submit",
     "afd_server_poll", "afd_server_wait", "afd_server_clock", "afd_server_destroy",
 ]
 
@@ -150,6 +150,9 @@ def lib():
             "afd_combine_fields": (C.c_int, [vp, i64, i32, vp, vp, vp, vp]),
             "afd_stress_pnorm": (C.c_int, [vp, i32, vp, dbl, vp, C.POINTER(dbl), vp]),
             "afd_apply_M": (C.c_int, [vp, i32, vp, vp]),
+            "afd_apply_Kg": (C.c_int, [vp, vp, i32, vp, vp]),
+            "afd_buckling": (C.c_int, [vp, vp, C.POINTER(afd_solve_opts), i32, dbl, i32, vp, vp, vp,
+                                       C.POINTER(afd_modal_stats)]),
             "afd_modal": (C.c_int, [vp, C.POINTER(afd_solve_opts), i32, dbl, i32, vp, vp, vp,
                                     C.POINTER(afd_modal_stats)]),
             "afd_levelset_run": (C.c_int, [vp, C.POINTER(afd_levelset_opts), i32, vp, vp, vp, i32,
@@ -373,6 +376,21 @@ def afd_modal(mesh, inner, nev, Phi, S=None, tol=1e-8, max_iter=60, raise_on_err
                            _ptr(S), C.byref(st))
     if raise_on_error:
         check(code, "afd_modal")
+    return code, list(lam), st
+
+
+def afd_apply_Kg(mesh, U0, nrhs, X, Y):
+    check(lib().afd_apply_Kg(mesh, _ptr(U0), nrhs, _ptr(X), _ptr(Y)), "afd_apply_Kg")
+
+
+def afd_buckling(mesh, U, inner, nev, Phi, S=None, tol=1e-8, max_iter=60, raise_on_error=True):
+    """Returns (status, load factors list, afd_modal_stats)."""
+    lam = (C.c_double * nev)()
+    st = afd_modal_stats()
+    code = lib().afd_buckling(mesh, _ptr(U), C.byref(inner), nev, float(tol), int(max_iter), C.cast(lam, C.c_void_p),
+                              _ptr(Phi), _ptr(S), C.byref(st))
+    if raise_on_error:
+        check(code, "afd_buckling")
     return code, list(lam), st
 
 

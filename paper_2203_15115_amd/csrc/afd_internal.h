@@ -308,6 +308,12 @@ int mass_apply(const Grid& g, const double h[3], const double* rho, const uint8_
 int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const double* rho, const uint8_t* nmask,
                    const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam_out, double* Phi,
                    double* S, afd_modal_stats* st, hipStream_t s);
+// geometric stiffness of the centroid stresses of U0 (see afd_apply_Kg, afd_buckling)
+int geo_apply(const Grid& g, const double h[3], double E, double nu, const double* rho, const uint8_t* nmask,
+              const double* U0, int nrhs, const double* X, double* Y, hipStream_t s);
+int buckling_subspace(afd_mesh* mesh, const Grid& g, const double h[3], double E, double nu, const double* rho,
+                      const uint8_t* nmask, const double* U, const afd_solve_opts* inner, int nev, double tol,
+                      int max_iter, double* lam_out, double* Phi, double* S, afd_modal_stats* st, hipStream_t s);
 // rho[e] = solid[e] ? 1 : void_scale
 int launch_density(int64_t n, const uint8_t* solid, double void_scale, double* rho, hipStream_t s);
 // ranking and threshold (see afd_threshold): threshold_run on a caller-given

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "afd_internal.h"
+#include "voxel_dev.h"
 
 namespace afd {
 
@@ -102,20 +103,7 @@ __global__ void k_kinetic(KinP p, double* S) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[a][c] = ph[3 * nd + c];
     }
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int st = 1 << ax;
-#pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            if (n & st) continue;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double s = v[n][c] + v[n + st][c], d = v[n + st][c] - v[n][c];
-                v[n][c] = s;
-                v[n + st][c] = d;
-            }
-        }
-    }
+    haar_fwd(v);
     double kin = 0.0;
 #pragma unroll
     for (int al = 0; al < 8; ++al)
@@ -209,6 +197,145 @@ __global__ void k_start_block(int64_t nnode, const uint8_t* nmask, double* X) {
     }
 }
 
+// ---- linear buckling (Eq. 3.5) ---------------------------------------
+// element centroid stresses sig[6][nE] of a displacement field
+struct SigP {
+    int nx, ny, nz;
+    double inv4h[3];
+    double lam, mu;
+    const double* U;
+    const double* rho;
+};
+__global__ void k_elem_stress(SigP p, double* sig) {
+    const int nE = p.nx * p.ny * p.nz;  // < 2^31 (checked on the host)
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nE) return;
+    const int ex = e % p.nx, exy = e / p.nx, ey = exy % p.ny, ez = exy / p.ny;
+    const int sy = p.nx + 1, sz = (p.nx + 1) * (p.ny + 1);
+    double v[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int64_t nd = (ex + (a & 1)) + sy * (ey + ((a >> 1) & 1)) + (int64_t)sz * (ez + (a >> 2));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[a][c] = p.U[3 * nd + c];
+    }
+    haar_fwd(v);
+    double sg[6];
+    centroid_stress(v, p.inv4h, p.lam, p.mu, p.rho[e], sg);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sig[(int64_t)q * nE + e] = sg[q];
+}
+
+// The geometric stiffness of element e, K_sigma,e[(a,i),(b,j)] = delta_ij
+// sum_pq S_pq G^pq_ab, G^pq_ab = int dN_a/dx_p dN_b/dx_q (nodes in binary
+// order): with the symmetric stress, w_ab = sum_p S_pp Gd[p]_ab +
+// S_yz Go[0]_ab + S_xz Go[1]_ab + S_xy Go[2]_ab, Go = G^pq + G^qp.
+struct GeoP {
+    int nx, ny, nz;
+    int64_t ndof;
+    double Gd[3][8][8];
+    double Go[3][8][8];
+    const double* sig;     // [6][nE]
+    const uint8_t* nmask;
+};
+__device__ __forceinline__ double geo_w(const GeoP& p, const double S[6], int a, int b) {
+    return S[0] * p.Gd[0][a][b] + S[1] * p.Gd[1][a][b] + S[2] * p.Gd[2][a][b] + S[3] * p.Go[0][a][b] +
+           S[4] * p.Go[1][a][b] + S[5] * p.Go[2][a][b];
+}
+// Y[r] = scale * K_sigma U[r] on free DOFs (fixed inputs taken as zero), 0 on
+// fixed DOFs; one thread per node gathering its elements' rows in a fixed order
+__global__ void k_geo_apply(GeoP p, double scale, const double* U, double* Y) {
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int sy = nx + 1, sz = (nx + 1) * (ny + 1);
+    const int nn = sz * (nz + 1);
+    const int nE = nx * ny * nz;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int r = blockIdx.y;
+    const double* u = U + (int64_t)r * p.ndof;
+    const int i = n % sy, j = (n / sy) % (ny + 1), k = n / sz;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int dz = 0; dz < 2; ++dz) {
+        const int ez = k - 1 + dz;
+        if (ez < 0 || ez >= nz) continue;
+        for (int dy = 0; dy < 2; ++dy) {
+            const int ey = j - 1 + dy;
+            if (ey < 0 || ey >= ny) continue;
+            for (int dx = 0; dx < 2; ++dx) {
+                const int ex = i - 1 + dx;
+                if (ex < 0 || ex >= nx) continue;
+                const int e = ex + nx * (ey + ny * ez);
+                const int a = (1 - dx) + 2 * (1 - dy) + 4 * (1 - dz);  // this node's corner of e
+                double S[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) S[q] = p.sig[(int64_t)q * nE + e];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int m = (ex + (b & 1)) + sy * (ey + ((b >> 1) & 1)) + sz * (ez + (b >> 2));
+                    const uint8_t mk = p.nmask[m];
+                    const double w = geo_w(p, S, a, b);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] += ((mk >> c) & 1) ? 0.0 : w * u[3 * (int64_t)m + c];
+                }
+            }
+        }
+    }
+    const uint8_t mk = p.nmask[n];
+    double* y = Y + (int64_t)r * p.ndof + 3 * (int64_t)n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c] = ((mk >> c) & 1) ? 0.0 : scale * acc[c];
+}
+
+// G[f][e] = phi_e^T K_sigma,e phi_e (field f of Phi)
+__global__ void k_geo_energy(GeoP p, const double* Phi, double* G) {
+    const int nE = p.nx * p.ny * p.nz;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nE) return;
+    const int f = blockIdx.y;
+    const int ex = e % p.nx, exy = e / p.nx, ey = exy % p.ny, ez = exy / p.ny;
+    const int sy = p.nx + 1, sz = (p.nx + 1) * (p.ny + 1);
+    const double* ph = Phi + (int64_t)f * p.ndof;
+    double v[8][3], S[6];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int64_t nd = (ex + (a & 1)) + sy * (ey + ((a >> 1) & 1)) + (int64_t)sz * (ez + (a >> 2));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[a][c] = ph[3 * nd + c];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S[q] = p.sig[(int64_t)q * nE + e];
+    double acc = 0.0;
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+            const double w = geo_w(p, S, a, b);
+            acc += w * (v[a][0] * v[b][0] + v[a][1] * v[b][1] + v[a][2] * v[b][2]);
+        }
+    G[(int64_t)f * nE + e] = acc;
+}
+
+// G^pq_ab for the voxel, nodes in binary order
+void geo_tables(const double h[3], GeoP& p) {
+    auto one = [&](int ax, int p_, int q_, int ia, int ib) {
+        const double hh = h[ax];
+        if (ax == p_ && ax == q_) return (ia == ib ? 1.0 : -1.0) / hh;              // int phi_a' phi_b'
+        if (ax == p_) return (ia == 0 ? -0.5 : 0.5);                                  // int phi_a' phi_b
+        if (ax == q_) return (ib == 0 ? -0.5 : 0.5);                                  // int phi_a phi_b'
+        return hh * (ia == ib ? 2.0 : 1.0) / 6.0;                                     // int phi_a phi_b
+    };
+    auto G = [&](int p_, int q_, int a, int b) {
+        double v = 1.0;
+        for (int ax = 0; ax < 3; ++ax) v *= one(ax, p_, q_, (a >> ax) & 1, (b >> ax) & 1);
+        return v;
+    };
+    const int off[3][2] = {{1, 2}, {0, 2}, {0, 1}};  // yz, xz, xy
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+            for (int d = 0; d < 3; ++d) p.Gd[d][a][b] = G(d, d, a, b);
+            for (int o = 0; o < 3; ++o)
+                p.Go[o][a][b] = G(off[o][0], off[o][1], a, b) + G(off[o][1], off[o][0], a, b);
+        }
+}
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -269,38 +396,40 @@ int mass_apply(const Grid& g, const double h[3], const double* rho, const uint8_
     return AFD_OK;
 }
 
-int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const double* rho, const uint8_t* nmask,
-                   const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam_out, double* Phi,
-                   double* S, afd_modal_stats* st, hipStream_t s) {
-    if (nev < 1 || nev > BLK - 1 || !(tol > 0) || max_iter < 1 || !lam_out || !Phi || !inner) {
-        set_error("modal: nev 1..3, tol > 0, max_iter >= 1, non-null lambda, Phi, solve options");
-        return AFD_E_INVALID_ARG;
+namespace {
+
+// The largest eigenvalues mu of B x = mu K x (K positive definite on the free
+// DOFs; B = M for modes, -K_sigma for buckling) by subspace iteration on a
+// block of BLK vectors: Z = B X, Y = K^-1 Z (one BLK-column deflated solve,
+// warm-started from X mu), Rayleigh-Ritz (Kr = Y^T Z = Y^T K Y, Br = Y^T B Y;
+// Kr = L L^T, L^-1 Br L^-T = V diag(mu) V^T, Q = L^-T V), X = Y Q (K-orthonormal),
+// until the Ritz residuals ||B x - mu K x|| / (|mu| ||K x||) of the first nev
+// pairs (B X = (B Y) Q and K X = Z Q from the solves, formed as vectors) meet
+// tol.  X (BLK x n_dof, caller's) holds the Ritz vectors on return, mu the
+// Ritz values in descending order.
+struct Subspace {
+    afd_mesh* mesh;
+    int64_t nd;
+    hipStream_t s;
+    double *Y = nullptr, *Z = nullptr, *W = nullptr, *part = nullptr;
+    std::vector<double> hp;
+    int alloc() {
+        const size_t vec = (size_t)BLK * nd;
+        if (hipMalloc((void**)&Y, vec * 8) != hipSuccess || hipMalloc((void**)&Z, vec * 8) != hipSuccess ||
+            hipMalloc((void**)&W, vec * 8) != hipSuccess ||
+            hipMalloc((void**)&part, (size_t)GNB * BLK * BLK * 8) != hipSuccess) {
+            set_error("eigen: out of device memory");
+            return AFD_E_OOM;
+        }
+        hp.resize((size_t)GNB * BLK * BLK);
+        return AFD_OK;
     }
-    if (g.nelem >= ((int64_t)1 << 31)) {
-        set_error("modal: more than 2^31 elements");
-        return AFD_E_INVALID_ARG;
-    }
-    const double t0 = now_s();
-    const int64_t nd = g.ndof;
-    double *X = nullptr, *Y = nullptr, *Zk = nullptr, *Zm = nullptr, *part = nullptr;
-    const size_t vec = (size_t)BLK * nd;
-    if (hipMalloc((void**)&X, vec * 8) != hipSuccess || hipMalloc((void**)&Y, vec * 8) != hipSuccess ||
-        hipMalloc((void**)&Zk, vec * 8) != hipSuccess || hipMalloc((void**)&Zm, vec * 8) != hipSuccess ||
-        hipMalloc((void**)&part, (size_t)GNB * BLK * BLK * 8) != hipSuccess) {
-        for (double* q : {X, Y, Zk, Zm, part})
-            if (q) (void)hipFree(q);
-        set_error("modal: out of device memory");
-        return AFD_E_OOM;
-    }
-    int rc = AFD_OK;
-    auto done = [&](int code) {
+    void release() {
         (void)hipStreamSynchronize(s);
-        for (double* q : {X, Y, Zk, Zm, part}) (void)hipFree(q);
-        if (st) st->t = now_s() - t0;
-        return code;
-    };
-    std::vector<double> hp((size_t)GNB * BLK * BLK);
-    auto gram = [&](const double* A, const double* B, double G[BLK][BLK]) -> int {
+        for (double* q : {Y, Z, W, part})
+            if (q) (void)hipFree(q);
+    }
+    int gram(const double* A, const double* B, double G[BLK][BLK]) {
         hipLaunchKernelGGL(k_gram, dim3(GNB), dim3(GWG), 0, s, nd, BLK, A, B, part);
         AFD_HIP_TRY(hipGetLastError());
         AFD_HIP_TRY(hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, s));
@@ -311,8 +440,8 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
             G[q / BLK][q % BLK] = acc;
         }
         return AFD_OK;
-    };
-    auto lincomb = [&](const double* src, const double Q[BLK][BLK], double* dst) -> int {
+    }
+    int lincomb(const double* src, const double Q[BLK][BLK], double* dst) {
         LinP lp;
         lp.m = BLK;
         for (int i = 0; i < BLK; ++i)
@@ -320,10 +449,9 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
         hipLaunchKernelGGL(k_lincomb, dim3(2048), dim3(256), 0, s, nd, lp, src, dst);
         AFD_HIP_TRY(hipGetLastError());
         return AFD_OK;
-    };
-    // ||A_j - theta_j B_j|| / (theta_j ||B_j||) for the first nev columns, the
-    // residual vectors formed in R
-    auto residuals = [&](const double* A, const double* B, const double* th, double* R, double* out) -> int {
+    }
+    // out[j] = ||A_j - th_j B_j|| / (|th_j| ||B_j||), j < n, the vectors formed in R
+    int residuals(const double* A, const double* B, const double* th, double* R, int n, double* out) {
         ThP t;
         for (int j = 0; j < BLK; ++j) t.th[j] = th[j];
         hipLaunchKernelGGL(k_resid, dim3(2048), dim3(256), 0, s, nd, t, A, B, R);
@@ -331,59 +459,60 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
         double G1[BLK][BLK], G3[BLK][BLK];
         AFD_TRY(gram(R, R, G1));
         AFD_TRY(gram(B, B, G3));
-        for (int j = 0; j < nev; ++j) out[j] = std::sqrt(G1[j][j]) / (std::fabs(th[j]) * std::sqrt(G3[j][j]));
+        for (int j = 0; j < n; ++j) out[j] = std::sqrt(G1[j][j]) / (std::fabs(th[j]) * std::sqrt(G3[j][j]));
         return AFD_OK;
-    };
+    }
+};
+
+template <typename ApplyB>
+int subspace_largest(Subspace& sp, const Grid& g, const uint8_t* nmask, ApplyB applyB, const afd_solve_opts* inner,
+                     int nev, double tol, int max_iter, double* X, double mu[BLK], double res[BLK], int& it, int& cg,
+                     bool& conv) {
+    hipStream_t s = sp.s;
     hipLaunchKernelGGL(k_start_block, dim3((unsigned)((g.nnode + 255) / 256), BLK), dim3(256), 0, s, g.nnode, nmask,
                        X);
-    if (hipGetLastError() != hipSuccess) {
-        set_error("modal: start block kernel failed");
-        return done(AFD_E_HIP);
-    }
+    AFD_HIP_TRY(hipGetLastError());
     afd_solve_opts so = *inner;
     so.mem_kind = AFD_MEM_DEVICE;
     so.pairs = nullptr;
     so.npairs = 0;
     std::vector<afd_solve_stats> ss(BLK);
-    double theta[BLK] = {0, 0, 0, 0}, res[BLK] = {1, 1, 1, 1};
-    int it = 0, cg = 0;
-    bool conv = false;
+    for (int j = 0; j < BLK; ++j) mu[j] = 0.0, res[j] = 1.0;
+    it = 0, cg = 0, conv = false;
     while (it < max_iter && !conv) {
         ++it;
-        // Zk = M X; Y = K^-1 Zk, warm-started from X / theta (K^-1 M x = x / lambda for an eigenpair)
-        if ((rc = mass_apply(g, h, rho, nmask, BLK, X, Zk, s))) return done(rc);
+        // Z = B X; Y = K^-1 Z, warm-started from X mu (K^-1 B x = mu x for an eigenpair)
+        AFD_TRY(applyB(X, sp.Z));
         if (it > 1) {
             double D[BLK][BLK] = {};
-            for (int j = 0; j < BLK; ++j) D[j][j] = theta[j] > 0 ? 1.0 / theta[j] : 0.0;
-            if ((rc = lincomb(X, D, Y))) return done(rc);
-            so.x0 = Y;
+            for (int j = 0; j < BLK; ++j) D[j][j] = mu[j];
+            AFD_TRY(sp.lincomb(X, D, sp.Y));
+            so.x0 = sp.Y;
         } else {
             so.x0 = nullptr;
         }
-        if ((rc = afd_solve(mesh, &so, BLK, Zk, Y, nullptr, nullptr, ss.data()))) return done(rc);
+        AFD_TRY(afd_solve(sp.mesh, &so, BLK, sp.Z, sp.Y, nullptr, nullptr, ss.data()));
         for (int j = 0; j < BLK; ++j) cg += ss[j].iterations;
-        // Rayleigh-Ritz: Kr = Y^T K Y = Y^T Zk, Mr = Y^T M Y = Y^T Zm
-        double Kr[BLK][BLK], Mr[BLK][BLK];
-        if ((rc = gram(Y, Zk, Kr))) return done(rc);
-        if ((rc = mass_apply(g, h, rho, nmask, BLK, Y, Zm, s))) return done(rc);
-        if ((rc = gram(Y, Zm, Mr))) return done(rc);
+        double Kr[BLK][BLK], Br[BLK][BLK];
+        AFD_TRY(sp.gram(sp.Y, sp.Z, Kr));
+        AFD_TRY(applyB(sp.Y, sp.W));
+        AFD_TRY(sp.gram(sp.Y, sp.W, Br));
         for (int i = 0; i < BLK; ++i)  // symmetric parts (rounding and inexact solves)
             for (int j = i + 1; j < BLK; ++j) {
                 Kr[i][j] = Kr[j][i] = 0.5 * (Kr[i][j] + Kr[j][i]);
-                Mr[i][j] = Mr[j][i] = 0.5 * (Mr[i][j] + Mr[j][i]);
+                Br[i][j] = Br[j][i] = 0.5 * (Br[i][j] + Br[j][i]);
             }
-        // Mr = L L^T; C = L^-1 Kr L^-T = V diag(theta) V^T; Q = L^-T V (M-orthonormal Ritz vectors)
         double L[BLK][BLK] = {};
         for (int j = 0; j < BLK; ++j) {
-            double d = Mr[j][j];
+            double d = Kr[j][j];
             for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
             if (!(d > 0)) {
-                set_error("modal: the subspace lost rank (M-Gram matrix not positive definite)");
-                return done(AFD_E_BREAKDOWN);
+                set_error("eigen: the subspace lost rank (K-Gram matrix not positive definite)");
+                return AFD_E_BREAKDOWN;
             }
             L[j][j] = std::sqrt(d);
             for (int i = j + 1; i < BLK; ++i) {
-                double v = Mr[i][j];
+                double v = Kr[i][j];
                 for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
                 L[i][j] = v / L[j][j];
             }
@@ -401,7 +530,7 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
         for (int i = 0; i < BLK; ++i)
             for (int j = 0; j < BLK; ++j) {
                 double v = 0.0;
-                for (int k = 0; k < BLK; ++k) v += Li[i][k] * Kr[k][j];
+                for (int k = 0; k < BLK; ++k) v += Li[i][k] * Br[k][j];
                 T1[i][j] = v;
             }
         for (int i = 0; i < BLK; ++i)
@@ -413,7 +542,7 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
         double d[BLK], V[BLK][BLK];
         jacobi_eig(BLK, C, d, V);
         int ord[BLK] = {0, 1, 2, 3};
-        std::sort(ord, ord + BLK, [&](int a, int b) { return d[a] < d[b]; });
+        std::sort(ord, ord + BLK, [&](int a, int b) { return d[a] > d[b]; });
         double Q[BLK][BLK];
         for (int j = 0; j < BLK; ++j) {
             for (int i = 0; i < BLK; ++i) {
@@ -421,31 +550,85 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
                 for (int k = i; k < BLK; ++k) v += Li[k][i] * V[k][ord[j]];  // (L^-T V)[i][j]
                 Q[i][j] = v;
             }
-            theta[j] = d[ord[j]];
+            mu[j] = d[ord[j]];
         }
-        // X = Y Q; K X = Zk Q (from the solves) and M X = Zm Q give the Ritz residuals
-        if ((rc = lincomb(Y, Q, X)) || (rc = lincomb(Zk, Q, Y)) || (rc = lincomb(Zm, Q, Zk))) return done(rc);
-        if ((rc = residuals(Y, Zk, theta, Zm, res))) return done(rc);
+        // X = Y Q; B X = W Q into Y, K X = Z Q into W; residual vectors in Z
+        AFD_TRY(sp.lincomb(sp.Y, Q, X));
+        AFD_TRY(sp.lincomb(sp.W, Q, sp.Y));
+        AFD_TRY(sp.lincomb(sp.Z, Q, sp.W));
+        AFD_TRY(sp.residuals(sp.Y, sp.W, mu, sp.Z, nev, res));
         conv = true;
         for (int j = 0; j < nev; ++j) conv = conv && res[j] <= tol;
     }
-    // the reported residuals with the operator itself: ||K phi - lambda M phi|| / (lambda ||M phi||)
-    if ((rc = afd_apply_K(mesh, AFD_FP64, BLK, X, Y))) return done(rc);
-    if ((rc = mass_apply(g, h, rho, nmask, BLK, X, Zk, s))) return done(rc);
-    if ((rc = residuals(Y, Zk, theta, Zm, res))) return done(rc);
+    return AFD_OK;
+}
+
+}  // namespace
+
+int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const double* rho, const uint8_t* nmask,
+                   const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam_out, double* Phi,
+                   double* S, afd_modal_stats* st, hipStream_t s) {
+    if (nev < 1 || nev > BLK - 1 || !(tol > 0) || max_iter < 1 || !lam_out || !Phi || !inner) {
+        set_error("modal: nev 1..3, tol > 0, max_iter >= 1, non-null lambda, Phi, solve options");
+        return AFD_E_INVALID_ARG;
+    }
+    if (g.nelem >= ((int64_t)1 << 31)) {
+        set_error("modal: more than 2^31 elements");
+        return AFD_E_INVALID_ARG;
+    }
+    const double t0 = now_s();
+    Subspace sp{mesh, g.ndof, s};
+    double* X = nullptr;
+    int rc = sp.alloc();
+    if (rc == AFD_OK && hipMalloc((void**)&X, (size_t)BLK * g.ndof * 8) != hipSuccess) {
+        set_error("modal: out of device memory");
+        rc = AFD_E_OOM;
+    }
+    auto done = [&](int code) {
+        sp.release();
+        if (X) (void)hipFree(X);
+        if (st) st->t = now_s() - t0;
+        return code;
+    };
+    if (rc) return done(rc);
+    double mu[BLK], res[BLK];
+    int it = 0, cg = 0;
+    bool conv = false;
+    auto applyM = [&](const double* in, double* out) { return mass_apply(g, h, rho, nmask, BLK, in, out, s); };
+    if ((rc = subspace_largest(sp, g, nmask, applyM, inner, nev, tol, max_iter, X, mu, res, it, cg, conv)))
+        return done(rc);
+    // lambda = 1 / mu; phi = x / sqrt(mu) (M-normalised: x^T M x = mu x^T K x = mu)
+    double D[BLK][BLK] = {};
+    for (int j = 0; j < BLK; ++j) {
+        if (!(mu[j] > 0)) {
+            set_error("modal: a non-positive Ritz value (M or K not definite on the free DOFs)");
+            return done(AFD_E_BREAKDOWN);
+        }
+        D[j][j] = 1.0 / std::sqrt(mu[j]);
+    }
+    double lam[BLK];
+    for (int j = 0; j < BLK; ++j) lam[j] = 1.0 / mu[j];
+    if ((rc = sp.lincomb(X, D, X))) return done(rc);
+    // reported residuals with the operators: ||K phi - lambda M phi|| / (lambda ||M phi||)
+    if ((rc = afd_apply_K(mesh, AFD_FP64, BLK, X, sp.Y))) return done(rc);
+    if ((rc = mass_apply(g, h, rho, nmask, BLK, X, sp.W, s))) return done(rc);
+    if ((rc = sp.residuals(sp.Y, sp.W, lam, sp.Z, nev, res))) return done(rc);
     for (int j = 0; j < nev; ++j) {
-        lam_out[j] = theta[j];
+        lam_out[j] = lam[j];
         if (st) st->rel_residual[j] = res[j];
     }
-    AFD_HIP_TRY(hipMemcpyAsync(Phi, X, (size_t)nev * nd * 8, hipMemcpyDeviceToDevice, s));
+    if (hipMemcpyAsync(Phi, X, (size_t)nev * g.ndof * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("modal: copy failed");
+        return done(AFD_E_HIP);
+    }
     if (S) {  // T_lambda(e) = rho_e phi_e^T (K_e - lambda M_e) phi_e
         if ((rc = afd_sensitivity(mesh, nev, X, 0, nullptr, S))) return done(rc);
         KinP kp;
         memset(&kp, 0, sizeof(kp));
         kp.nx = g.nx, kp.ny = g.ny, kp.nz = g.nz;
-        kp.ndof = nd;
+        kp.ndof = g.ndof;
         kp.nf = nev;
-        for (int j = 0; j < nev; ++j) kp.lam[j] = theta[j];
+        for (int j = 0; j < nev; ++j) kp.lam[j] = lam[j];
         for (int al = 0; al < 8; ++al) {
             double m = 1.0;
             for (int ax = 0; ax < 3; ++ax) m *= h[ax] * (((al >> ax) & 1) ? 1.0 / 12.0 : 0.25);
@@ -465,7 +648,148 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
         st->converged = conv ? 1 : 0;
     }
     if (!conv) {
-        set_error("modal: the Ritz values did not settle within max_iter");
+        set_error("modal: the Ritz residuals did not meet tol within max_iter");
+        return done(AFD_E_NOT_CONVERGED);
+    }
+    return done(AFD_OK);
+}
+
+int geo_apply(const Grid& g, const double h[3], double E, double nu, const double* rho, const uint8_t* nmask,
+              const double* U0, int nrhs, const double* X, double* Y, hipStream_t s) {
+    if (nrhs < 1 || nrhs > BLK || !U0 || !X || !Y) {
+        set_error("apply_Kg: nrhs 1..4 and non-null U0, X, Y");
+        return AFD_E_INVALID_ARG;
+    }
+    if (g.nelem >= ((int64_t)1 << 31)) {
+        set_error("apply_Kg: more than 2^31 elements");
+        return AFD_E_INVALID_ARG;
+    }
+    double* sig = nullptr;
+    if (hipMalloc((void**)&sig, (size_t)6 * g.nelem * 8) != hipSuccess) {
+        set_error("apply_Kg: out of device memory");
+        return AFD_E_OOM;
+    }
+    SigP sp6;
+    sp6.nx = g.nx, sp6.ny = g.ny, sp6.nz = g.nz;
+    for (int a = 0; a < 3; ++a) sp6.inv4h[a] = 1.0 / (4.0 * h[a]);
+    sp6.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    sp6.mu = E / (2.0 * (1.0 + nu));
+    sp6.U = U0;
+    sp6.rho = rho;
+    hipLaunchKernelGGL(k_elem_stress, dim3((unsigned)((g.nelem + 255) / 256)), dim3(256), 0, s, sp6, sig);
+    GeoP gp;
+    memset(&gp, 0, sizeof(gp));
+    gp.nx = g.nx, gp.ny = g.ny, gp.nz = g.nz;
+    gp.ndof = g.ndof;
+    geo_tables(h, gp);
+    gp.sig = sig;
+    gp.nmask = nmask;
+    hipLaunchKernelGGL(k_geo_apply, dim3((unsigned)((g.nnode + 255) / 256), nrhs), dim3(256), 0, s, gp, 1.0, X, Y);
+    const hipError_t e = hipGetLastError();
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(sig);
+    if (e != hipSuccess) {
+        set_error("apply_Kg: kernel launch failed");
+        return AFD_E_HIP;
+    }
+    return AFD_OK;
+}
+
+int buckling_subspace(afd_mesh* mesh, const Grid& g, const double h[3], double E, double nu, const double* rho,
+                      const uint8_t* nmask, const double* U, const afd_solve_opts* inner, int nev, double tol,
+                      int max_iter, double* lam_out, double* Phi, double* S, afd_modal_stats* st, hipStream_t s) {
+    if (nev < 1 || nev > BLK - 1 || !(tol > 0) || max_iter < 1 || !lam_out || !Phi || !inner || !U) {
+        set_error("buckling: nev 1..3, tol > 0, max_iter >= 1, non-null U, lambda, Phi, solve options");
+        return AFD_E_INVALID_ARG;
+    }
+    if (g.nelem >= ((int64_t)1 << 31)) {
+        set_error("buckling: more than 2^31 elements");
+        return AFD_E_INVALID_ARG;
+    }
+    const double t0 = now_s();
+    Subspace sp{mesh, g.ndof, s};
+    double *X = nullptr, *sig = nullptr, *Gf = nullptr;
+    int rc = sp.alloc();
+    if (rc == AFD_OK && (hipMalloc((void**)&X, (size_t)BLK * g.ndof * 8) != hipSuccess ||
+                         hipMalloc((void**)&sig, (size_t)6 * g.nelem * 8) != hipSuccess ||
+                         (S && hipMalloc((void**)&Gf, (size_t)nev * g.nelem * 8) != hipSuccess))) {
+        set_error("buckling: out of device memory");
+        rc = AFD_E_OOM;
+    }
+    auto done = [&](int code) {
+        sp.release();
+        for (double* q : {X, sig, Gf})
+            if (q) (void)hipFree(q);
+        if (st) st->t = now_s() - t0;
+        return code;
+    };
+    if (rc) return done(rc);
+    // the prebuckling stresses, one per element (centroid)
+    SigP sp6;
+    sp6.nx = g.nx, sp6.ny = g.ny, sp6.nz = g.nz;
+    for (int a = 0; a < 3; ++a) sp6.inv4h[a] = 1.0 / (4.0 * h[a]);
+    sp6.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    sp6.mu = E / (2.0 * (1.0 + nu));
+    sp6.U = U;
+    sp6.rho = rho;
+    hipLaunchKernelGGL(k_elem_stress, dim3((unsigned)((g.nelem + 255) / 256)), dim3(256), 0, s, sp6, sig);
+    GeoP gp;
+    memset(&gp, 0, sizeof(gp));
+    gp.nx = g.nx, gp.ny = g.ny, gp.nz = g.nz;
+    gp.ndof = g.ndof;
+    geo_tables(h, gp);
+    gp.sig = sig;
+    gp.nmask = nmask;
+    const unsigned nb = (unsigned)((g.nnode + 255) / 256);
+    auto applyNegKg = [&](const double* in, double* out) -> int {
+        hipLaunchKernelGGL(k_geo_apply, dim3(nb, BLK), dim3(256), 0, s, gp, -1.0, in, out);
+        AFD_HIP_TRY(hipGetLastError());
+        return AFD_OK;
+    };
+    double mu[BLK], res[BLK];
+    int it = 0, cg = 0;
+    bool conv = false;
+    if ((rc = subspace_largest(sp, g, nmask, applyNegKg, inner, nev, tol, max_iter, X, mu, res, it, cg, conv)))
+        return done(rc);
+    double lam[BLK] = {0, 0, 0, 0};
+    for (int j = 0; j < nev; ++j) {
+        if (!(mu[j] > 0)) {
+            set_error("buckling: fewer positive load factors than requested (the loads put too little in compression)");
+            return done(AFD_E_BREAKDOWN);
+        }
+        lam[j] = 1.0 / mu[j];
+    }
+    // reported residuals: ||K phi + lambda K_sigma phi|| / ||K phi|| (phi^T K phi = 1)
+    if ((rc = afd_apply_K(mesh, AFD_FP64, BLK, X, sp.Y))) return done(rc);
+    if ((rc = applyNegKg(X, sp.W))) return done(rc);
+    for (int j = 0; j < nev; ++j) {
+        lam_out[j] = lam[j];
+    }
+    if ((rc = sp.residuals(sp.W, sp.Y, mu, sp.Z, nev, res))) return done(rc);
+    if (st)
+        for (int j = 0; j < nev; ++j) st->rel_residual[j] = res[j];
+    if (hipMemcpyAsync(Phi, X, (size_t)nev * g.ndof * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("buckling: copy failed");
+        return done(AFD_E_HIP);
+    }
+    if (S) {  // T_P(e) = lambda phi_e^T (rho_e K_e + lambda K_sigma,e) phi_e
+        if ((rc = afd_sensitivity(mesh, nev, X, 0, nullptr, S))) return done(rc);
+        hipLaunchKernelGGL(k_geo_energy, dim3((unsigned)((g.nelem + 255) / 256), nev), dim3(256), 0, s, gp, X, Gf);
+        AFD_HIP_TRY(hipGetLastError());
+        for (int j = 0; j < nev; ++j) {
+            const double* grp[2] = {S + (size_t)j * g.nelem, Gf + (size_t)j * g.nelem};
+            const int rows[2] = {1, 1};
+            const double coef[2] = {lam[j], lam[j] * lam[j]};
+            if ((rc = launch_combine(g.nelem, 2, grp, rows, coef, S + (size_t)j * g.nelem, s))) return done(rc);
+        }
+    }
+    if (st) {
+        st->iterations = it;
+        st->cg_iterations = cg;
+        st->converged = conv ? 1 : 0;
+    }
+    if (!conv) {
+        set_error("buckling: the Ritz residuals did not meet tol within max_iter");
         return done(AFD_E_NOT_CONVERGED);
     }
     return done(AFD_OK);

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "afd_internal.h"
+#include "voxel_dev.h"
 
 namespace afd {
 
@@ -22,23 +23,6 @@ struct SensP {
     const double* ub[MAXF];
     KeHaar kh;
 };
-
-__device__ __forceinline__ void haar_fwd(double v[8][3]) {
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int st = 1 << ax;
-#pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            if (n & st) continue;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double s = v[n][c] + v[n + st][c], d = v[n + st][c] - v[n][c];
-                v[n][c] = s;
-                v[n + st][c] = d;
-            }
-        }
-    }
-}
 
 // S[f][e] = rho_e * u_e^T Ke v_e = rho_e * (T u_e)^T Khat (T v_e)
 __global__ void k_sensitivity(SensP p, const double* rho, double* S) {
@@ -318,9 +302,7 @@ __global__ void k_parting_distance(int nx, int ny, int nz, int axis, int parting
 }
 
 // ---- p-norm von Mises stress (Eq. 3.3, 3.23) --------------------------
-// Element stress at the voxel centre: in the Haar basis the centroid
-// gradient of component c along axis i is H[1 << i][c] / (4 h_i) (the mean of
-// the four edge differences along i), sigma = rho (lam tr(eps) I + 2 mu eps).
+// Element stress at the voxel centre (centroid_stress).
 struct StressP {
     int nx, ny, nz;
     int nrhs;
@@ -352,18 +334,10 @@ __global__ __launch_bounds__(256) void k_stress(StressP p) {
             for (int c = 0; c < 3; ++c) h[a][c] = u0[3 * nd + c];
         }
         haar_fwd(h);
-        double g[3][3];  // g[i][c] = d u_c / d x_i at the centre
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) g[i][c] = h[1 << i][c] * p.inv4h[i];
         const double rho = p.rho[e];
-        const double exx = g[0][0], eyy = g[1][1], ezz = g[2][2];
-        const double tr = exx + eyy + ezz;
-        const double sxx = rho * (p.lam * tr + 2.0 * p.mu * exx), syy = rho * (p.lam * tr + 2.0 * p.mu * eyy),
-                     szz = rho * (p.lam * tr + 2.0 * p.mu * ezz);
-        const double tyz = rho * p.mu * (g[1][2] + g[2][1]), txz = rho * p.mu * (g[0][2] + g[2][0]),
-                     txy = rho * p.mu * (g[0][1] + g[1][0]);
+        double sg[6];
+        centroid_stress(h, p.inv4h, p.lam, p.mu, rho, sg);
+        const double sxx = sg[0], syy = sg[1], szz = sg[2], tyz = sg[3], txz = sg[4], txy = sg[5];
         const double q = sxx * sxx + syy * syy + szz * szz - sxx * syy - syy * szz - szz * sxx +
                          3.0 * (tyz * tyz + txz * txz + txy * txy);
         const double vm = sqrt(fmax(q, 0.0));

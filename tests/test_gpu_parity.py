@@ -1152,3 +1152,80 @@ def test_modal_matches_oracle(ctx, dims, block):
         assert np.max(np.abs(Sh[j] - want)) <= 1e-7 * np.max(np.abs(want)), j
     print(f"modal {dims}: {st.iterations} subspace iterations, {st.cg_iterations} CG iterations, "
           f"lambda {lam}, residuals {list(st.rel_residual)[:2]}")
+
+
+# ------------------------------------------------------------- linear buckling (Eq. 3.5)
+def _compressed_cantilever(dims, seed):
+    # an axial compression of the x = L face plus a transverse mid-edge load
+    rng = np.random.default_rng(seed)
+    rho = np.where(rng.random(wl.n_elems(dims)) < 0.2, 1e-3, 1.0)
+    fixed = wl.clamp_x0(dims)
+    f = wl.edge_load(dims, "mid")
+    for j in range(dims[1] + 1):
+        for k in range(dims[2] + 1):
+            f[3 * wl.node_id(dims, dims[0], j, k)] -= 1.0 / ((dims[1] + 1) * (dims[2] + 1))
+    return rho, fixed, f
+
+
+@pytest.mark.parametrize("dims,h", [((7, 5, 3), (1.0, 1.0, 1.0)), ((19, 9, 8), (1.0, 2.0, 0.5))])
+def test_apply_Kg_matches_oracle(ctx, dims, h):
+    from oracle import buckling, stress
+    E, nu = (2.5, 0.27) if h != (1.0, 1.0, 1.0) else (1.0, 0.3)
+    rho, fixed = rand_problem(dims, 90)
+    m = make_mesh(ctx, dims, rho, fixed, h=h, E=E, nu=nu)
+    nd = 3 * wl.n_nodes(dims)
+    rng = np.random.default_rng(91)
+    U0 = rng.standard_normal(nd)
+    X = rng.standard_normal((2, nd))
+    Yd = torch.empty((2, nd), dtype=torch.float64, device="cuda")
+    afdcg.afd_apply_Kg(m, dev(U0), 2, dev(X), Yd)
+    Y = host(Yd)
+    afdcg.afd_mesh_destroy(m)
+    sig = stress.element_stress(dims, rho, U0, h, E, nu)
+    Kg = buckling.assemble_kg(dims, sig, h)
+    fx = fixed != 0
+    # bound: 64 eps times the sum of |entries| |x| (entries built from |stress| and |G|)
+    Gt = buckling.grad_tables(h)
+    absG = np.abs(Gt)
+    dm = fem.dofmap(dims)
+    for r in range(2):
+        x = np.where(fx, 0.0, X[r])
+        want = np.where(fx, 0.0, Kg @ x)
+        w_abs = np.einsum("epq,pqab->eab", np.abs(np.stack([buckling.stress_tensor(s) for s in sig])), absG)
+        xe = np.abs(x[dm]).reshape(-1, 8, 3)
+        contrib = np.einsum("eab,ebc->eac", w_abs, xe).reshape(-1, 24)
+        bound = np.zeros(nd)
+        np.add.at(bound, dm.ravel(), contrib.ravel())
+        bound = 64 * EPS64 * bound + 1e-300
+        assert np.all(np.abs(Y[r] - want) <= bound), np.max(np.abs(Y[r] - want) / bound)
+
+
+# seeds picked so that the three lowest load factors are apart by 5% or more
+@pytest.mark.parametrize("dims,block,seed", [((12, 6, 4), (4, 2, 2), 93), ((20, 8, 6), (4, 4, 3), 92)])
+def test_buckling_matches_oracle(ctx, dims, block, seed):
+    from oracle import buckling, stress
+    n, nd = wl.n_elems(dims), 3 * wl.n_nodes(dims)
+    rho, fixed, f = _compressed_cantilever(dims, seed)
+    m = make_mesh(ctx, dims, rho, fixed, block=block)
+    U = torch.empty((1, nd), dtype=torch.float64, device="cuda")
+    afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-12, mem_kind=afdcg.AFD_MEM_DEVICE), 1, dev(f[None]), U)
+    Phi = torch.empty((2, nd), dtype=torch.float64, device="cuda")
+    S = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    code, lam, st = afdcg.afd_buckling(m, U, afdcg.make_opts(rtol=1e-11), 2, Phi, S, tol=1e-9, max_iter=300)
+    afdcg.afd_mesh_destroy(m)
+    Ke = fem.ke_gauss()
+    K = fem.assemble(dims, rho, Ke)
+    u = solvers.solve_direct(K, fixed, f)
+    sig = stress.element_stress(dims, rho, u)
+    lam_o, Phi_o = buckling.buckling_modes(K, buckling.assemble_kg(dims, sig), fixed, 3)
+    assert lam_o[1] > 1.05 * lam_o[0] and lam_o[2] > 1.05 * lam_o[1]
+    P, Sh = host(Phi), host(S)
+    for j in range(2):
+        assert abs(lam[j] - lam_o[j]) <= 1e-9 * lam_o[j], (j, lam[j], lam_o[j])
+        assert st.rel_residual[j] <= 1e-8
+        sgn = np.sign(P[j] @ (K @ Phi_o[j]))
+        assert np.linalg.norm(P[j] - sgn * Phi_o[j]) <= 1e-6 * np.linalg.norm(Phi_o[j]), j
+        want = buckling.buckling_sensitivity(dims, rho, Ke, sig, lam_o[j], Phi_o[j])
+        assert np.max(np.abs(Sh[j] - want)) <= 1e-6 * np.max(np.abs(want)), j
+    print(f"buckling {dims}: {st.iterations} subspace iterations, {st.cg_iterations} CG iterations, "
+          f"load factors {lam}, residuals {list(st.rel_residual)[:2]}")
