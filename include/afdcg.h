@@ -329,8 +329,11 @@ int afd_modal(afd_mesh* mesh, const afd_solve_opts* inner, int32_t nev, double t
  * stress state of the displacement field U0 (device, one field), each
  * element's stress taken at its centre (rho_e D B_c u_e, as in
  * afd_stress_pnorm): K_sigma,e[(a,i),(b,j)] = delta_ij sum_pq S_pq
- * int dN_a/dx_p dN_b/dx_q; on the free DOFs (fixed inputs taken as zero, 0 on
- * fixed DOFs).  Synchronous; allocates 48 B per element for the call. */
+ * int dN_a/dx_p dN_b/dx_q; elements whose scale rho_e is below 1/2 (the
+ * ersatz void) carry no stress and add nothing (their scaled stress over
+ * their soft strains would give spurious local modes near zero load); on the
+ * free DOFs (fixed inputs taken as zero, 0 on fixed DOFs).  Synchronous;
+ * allocates 48 B per element for the call. */
 int afd_apply_Kg(afd_mesh* mesh, const double* U0, int32_t nrhs, const double* X, double* Y);
 /* The nev (1..3) smallest positive load factors lambda of
  * (K + lambda K_sigma) phi = 0 for the stress state of U (device, the static

@@ -8,7 +8,11 @@ load.  Readings used here (the paper cites an assembly-free buckling method
 without giving it):
 
 * the element geometric stiffness uses the element's centroid stress (the
-  stress of stress.element_stress, constant over the element):
+  stress of stress.element_stress, constant over the element), and the
+  ersatz void (elements whose scale is below 1/2) carries none: its scaled
+  stress times its ~1/rho_e larger strains would otherwise give spurious
+  local modes at load factors near zero in the void, the pseudo-mode effect
+  of buckling on ersatz material (prebuckling_stress):
   K_sigma,e[(a,i),(b,j)] = delta_ij sum_pq S_pq int dN_a/dx_p dN_b/dx_q dV,
   S the 3x3 stress tensor; the integrals are products of the 1-D stiffness,
   mass and mixed integrals, as for Ke;
@@ -28,7 +32,15 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import fem
+from . import fem, stress
+
+
+def prebuckling_stress(dims, rho, u, h=(1.0, 1.0, 1.0), E=1.0, nu=0.3):
+    """(nE, 6) centroid stresses of the static field u, zero on void elements
+    (scale below 1/2)."""
+    sig = stress.element_stress(dims, rho, u, h, E, nu)
+    sig[np.asarray(rho) < 0.5] = 0.0
+    return sig
 
 
 def grad_tables(h=(1.0, 1.0, 1.0)):

@@ -198,7 +198,8 @@ __global__ void k_start_block(int64_t nnode, const uint8_t* nmask, double* X) {
 }
 
 // ---- linear buckling (Eq. 3.5) ---------------------------------------
-// element centroid stresses sig[6][nE] of a displacement field
+// element centroid stresses sig[6][nE] of a displacement field, zero on the
+// ersatz void (scale below 1/2)
 struct SigP {
     int nx, ny, nz;
     double inv4h[3];
@@ -221,9 +222,11 @@ __global__ void k_elem_stress(SigP p, double* sig) {
     }
     haar_fwd(v);
     double sg[6];
-    centroid_stress(v, p.inv4h, p.lam, p.mu, p.rho[e], sg);
+    const double re = p.rho[e];
+    centroid_stress(v, p.inv4h, p.lam, p.mu, re, sg);
+    // the ersatz void carries no prebuckling stress
 #pragma unroll
-    for (int q = 0; q < 6; ++q) sig[(int64_t)q * nE + e] = sg[q];
+    for (int q = 0; q < 6; ++q) sig[(int64_t)q * nE + e] = re < 0.5 ? 0.0 : sg[q];
 }
 
 // The geometric stiffness of element e, K_sigma,e[(a,i),(b,j)] = delta_ij

@@ -1181,7 +1181,8 @@ def test_apply_Kg_matches_oracle(ctx, dims, h):
     afdcg.afd_apply_Kg(m, dev(U0), 2, dev(X), Yd)
     Y = host(Yd)
     afdcg.afd_mesh_destroy(m)
-    sig = stress.element_stress(dims, rho, U0, h, E, nu)
+    sig = buckling.prebuckling_stress(dims, rho, U0, h, E, nu)
+    assert np.any(rho < 0.5)
     Kg = buckling.assemble_kg(dims, sig, h)
     fx = fixed != 0
     # bound: 64 eps times the sum of |entries| |x| (entries built from |stress| and |G|)
@@ -1201,7 +1202,7 @@ def test_apply_Kg_matches_oracle(ctx, dims, h):
 
 
 # seeds picked so that the three lowest load factors are apart by 5% or more
-@pytest.mark.parametrize("dims,block,seed", [((12, 6, 4), (4, 2, 2), 93), ((20, 8, 6), (4, 4, 3), 92)])
+@pytest.mark.parametrize("dims,block,seed", [((12, 6, 4), (4, 2, 2), 93), ((20, 8, 6), (4, 4, 3), 93)])
 def test_buckling_matches_oracle(ctx, dims, block, seed):
     from oracle import buckling, stress
     n, nd = wl.n_elems(dims), 3 * wl.n_nodes(dims)
@@ -1216,7 +1217,7 @@ def test_buckling_matches_oracle(ctx, dims, block, seed):
     Ke = fem.ke_gauss()
     K = fem.assemble(dims, rho, Ke)
     u = solvers.solve_direct(K, fixed, f)
-    sig = stress.element_stress(dims, rho, u)
+    sig = buckling.prebuckling_stress(dims, rho, u)
     lam_o, Phi_o = buckling.buckling_modes(K, buckling.assemble_kg(dims, sig), fixed, 3)
     assert lam_o[1] > 1.05 * lam_o[0] and lam_o[2] > 1.05 * lam_o[1]
     P, Sh = host(Phi), host(S)

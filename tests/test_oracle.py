@@ -820,6 +820,7 @@ def test_geometric_stiffness_quadrature_and_closed_forms():
 
 def _buckling_problem(dims):
     from oracle import stress
+    from oracle.buckling import prebuckling_stress
     rng = np.random.default_rng(81)
     rho = np.where(rng.random(wl.n_elems(dims)) < 0.2, 1e-3, 1.0)
     fixed = wl.clamp_x0(dims)
@@ -830,7 +831,8 @@ def _buckling_problem(dims):
             f[3 * wl.node_id(dims, dims[0], j, k)] -= 1.0 / ((dims[1] + 1) * (dims[2] + 1))
     K = fem.assemble(dims, rho, fem.ke_gauss())
     u = solvers.solve_direct(K, fixed, f)
-    sig = stress.element_stress(dims, rho, u)
+    sig = prebuckling_stress(dims, rho, u)
+    assert np.all(sig[rho < 0.5] == 0) and np.all(sig[rho >= 0.5] == stress.element_stress(dims, rho, u)[rho >= 0.5])
     return rho, fixed, f, K, u, sig
 
 
