@@ -161,8 +161,9 @@ int matvec_num_tiles(const Grid& g);
 // element counts of the tile-major side arrays of the plain apply: returns the
 // fixity-word count, *nrho the density count
 int64_t tile_layout_sizes(const Grid& g, int64_t* nrho);
-// default z chunk of a plain-apply kernel variant (zc_req > 0 forces it)
-void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int* zc, int* nchunk);
+// default z chunk of a plain-apply kernel variant for nrhs right-hand sides
+// (zc_req > 0 forces it)
+void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int nrhs, int* zc, int* nchunk);
 int launch_tile_rho(const Grid& g, const double* rho, double* rho_t, float* rho32_t, hipStream_t s);
 int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipStream_t s);
 // p' = beta p + M^-1 r - W mu (MU null: no deflation), zero on fixed DOFs

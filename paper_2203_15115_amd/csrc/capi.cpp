@@ -759,7 +759,7 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
     std::vector<Cand> cands;
     for (int v : {6, 4, 2, 3, 0}) {
         int zc = 0, nch = 0;
-        apply_tiling(m->g, f, v, 0, &zc, &nch);
+        apply_tiling(m->g, f, v, 0, nrhs, &zc, &nch);
         for (int mult : {2, 1, 4, 6, 8}) {  // chunks x mult / 2
             const int want = std::max(1, nch * mult / 2);
             const int planes = m->g.nz + 1;

@@ -1205,7 +1205,9 @@ int g_slots[8][2];  // resident 256-thread workgroups per (apply variant, FP32) 
 // z-chunking: as many chunks as fit in one round of resident workgroups of
 // the given kernel variant, so that no partly filled second round trails the
 // launch; at least 4 node planes per chunk.  zc_req > 0 forces the chunk.
-void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, int& zc, int& nchunk) {
+// z chunking: by default enough chunks for one round of workgroups over the
+// chip, counting the right-hand sides (grid.y) of the launch
+void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, int& zc, int& nchunk, int nrhs = 1) {
     tx = (g.nx + 1 + (TX - 2)) / (TX - 1);  // ceil((nx+1)/15)
     ty = (g.ny + 1 + (TY - 2)) / (TY - 1);
     if (!valid_variant(variant)) variant = apply_variant();
@@ -1221,7 +1223,7 @@ void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, 
     if (zc_req > 0) {
         zc = zc_req;
     } else {
-        int want = g_slots[variant][fp32] / (tx * ty);
+        int want = g_slots[variant][fp32] / (tx * ty * std::max(1, nrhs));
         if (want < 1) want = 1;
         const int maxc = (planes + 3) / 4;
         if (want > maxc) want = maxc;
@@ -1236,14 +1238,14 @@ void tiling(const Grid& g, int fp32, int variant, int zc_req, int& tx, int& ty, 
 // mesh); the fused solver modes keep the default tiling, which also sizes the
 // partial-sum buffers
 template <typename T>
-MvParams<T> base_params(const MatvecArgs& a, bool plain = false) {
+MvParams<T> base_params(const MatvecArgs& a, int nrhs, bool plain = false) {
     MvParams<T> p{};
     p.nx = a.g.nx;
     p.ny = a.g.ny;
     p.nz = a.g.nz;
     const int f = sizeof(T) == 4 ? 1 : 0;
     p.variant = usable_variant<T>(plain ? (a.apply_variant[f] >= 0 ? a.apply_variant[f] : apply_variant()) : 0, a.g);
-    tiling(a.g, f, plain ? p.variant : -1, plain ? a.apply_zc[f] : 0, p.tiles_x, p.tiles_y, p.zc, p.nchunk);
+    tiling(a.g, f, plain ? p.variant : -1, plain ? a.apply_zc[f] : 0, p.tiles_x, p.tiles_y, p.zc, p.nchunk, nrhs);
     p.ndof = (int)a.g.ndof;
     if constexpr (sizeof(T) == 8) {
         p.rho = a.rho;
@@ -1307,9 +1309,9 @@ int matvec_num_tiles(const Grid& g) {
     return best;
 }
 
-void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int* zc, int* nchunk) {
+void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int nrhs, int* zc, int* nchunk) {
     int tx, ty;
-    tiling(g, fp32, variant, zc_req, tx, ty, *zc, *nchunk);
+    tiling(g, fp32, variant, zc_req, tx, ty, *zc, *nchunk, nrhs);
 }
 
 int64_t tile_layout_sizes(const Grid& g, int64_t* nrho) {
@@ -1336,12 +1338,12 @@ int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipSt
 int launch_apply(const MatvecArgs& a, const KeHaar& kh, int fp32, int nrhs, const void* U, void* Y,
                  hipStream_t s) {
     if (fp32) {
-        MvParams<float> p = base_params<float>(a, true);
+        MvParams<float> p = base_params<float>(a, nrhs, true);
         p.U = (const float*)U;
         p.Y = (float*)Y;
         return launch<float, APPLY>(p, kh, nrhs, s);
     }
-    MvParams<double> p = base_params<double>(a, true);
+    MvParams<double> p = base_params<double>(a, nrhs, true);
     p.U = (const double*)U;
     p.Y = (double*)Y;
     return launch<double, APPLY>(p, kh, nrhs, s);
@@ -1357,7 +1359,7 @@ static void set_dcg(MvParams<T>& p, const DcgArgs& d) {
 
 int launch_residual(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int nrhs, const double* F,
                     const double* X, double* R, hipStream_t s) {
-    MvParams<double> p = base_params<double>(a);
+    MvParams<double> p = base_params<double>(a, nrhs);
     set_dcg(p, d);
     p.U = X;
     p.Y = R;
@@ -1372,7 +1374,7 @@ int launch_dot_t(const MatvecArgs& a, const KeHaar& khd, const DcgArgs& d, int n
         set_error("nrhs must be in 1..4");
         return AFD_E_INVALID_ARG;
     }
-    MvParams<T> p = base_params<T>(a);  // default tiling: the partial-sum buffer is sized for it
+    MvParams<T> p = base_params<T>(a, nrhs);  // default tiling: the partial-sum buffer is sized for it
     set_dcg(p, d);
     p.U = U;
     p.Y = Y;
@@ -1409,7 +1411,7 @@ int launch_apply_dot(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, in
 
 int launch_residual_f32(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, const float* rinv32, int nrhs,
                         const float* F, const float* X, float* R, hipStream_t s) {
-    MvParams<float> p = base_params<float>(a);
+    MvParams<float> p = base_params<float>(a, nrhs);
     set_dcg(p, d);
     p.rinv32 = rinv32;
     p.U = X;
