@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
@@ -126,6 +128,20 @@ inline int choose_coarse_P(int ncoarse, int w) {
         if (P == nc64) break;
     }
     return best;
+}
+
+// Device memory of the library.  Every allocation and free goes through
+// these, under one process-wide lock that the recording of an iteration graph
+// (stream capture and instantiation) also holds: hipFree synchronises the
+// device, and no allocation or free of one thread (a server slot creating or
+// dropping a mesh) may overlap a capture in another (a slot recording its
+// iterations), nor may two captures overlap.  Replays need no lock.
+std::recursive_mutex& device_memory_mutex();
+hipError_t dev_malloc_raw(void** p, size_t bytes);
+hipError_t dev_free(void* p);
+template <typename T>
+inline hipError_t dev_malloc(T** p, size_t bytes) {
+    return dev_malloc_raw(reinterpret_cast<void**>(p), bytes);
 }
 
 // Per-right-hand-side CG scalars, device resident.

@@ -47,6 +47,19 @@ int validate_desc(const afd_mesh_desc& d) {
     return AFD_OK;
 }
 
+std::recursive_mutex& device_memory_mutex() {
+    static std::recursive_mutex mu;
+    return mu;
+}
+hipError_t dev_malloc_raw(void** p, size_t bytes) {
+    std::lock_guard<std::recursive_mutex> lk(device_memory_mutex());
+    return hipMalloc(p, bytes);
+}
+hipError_t dev_free(void* p) {
+    std::lock_guard<std::recursive_mutex> lk(device_memory_mutex());
+    return hipFree(p);
+}
+
 }  // namespace afd
 
 using namespace afd;
@@ -81,6 +94,7 @@ struct IterGraph {
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> key;
     void release() {
+        std::lock_guard<std::recursive_mutex> lk(afd::device_memory_mutex());
         if (exec) (void)hipGraphExecDestroy(exec);
         exec = nullptr;
         key.clear();
@@ -157,7 +171,7 @@ int check_ctx(afd_context* c) {
 template <typename T>
 int dalloc(T** p, size_t n) {
     if (*p) return AFD_OK;
-    if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+    if (afd::dev_malloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
         *p = nullptr;
         set_error("device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
         return AFD_E_OOM;
@@ -166,7 +180,7 @@ int dalloc(T** p, size_t n) {
 }
 template <typename T>
 void dfree(T** p) {
-    if (*p) (void)hipFree(*p);
+    if (*p) (void)afd::dev_free(*p);
     *p = nullptr;
 }
 
@@ -459,6 +473,9 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             (uintptr_t)(m->tune_variant[0] + 8), (uintptr_t)(m->tune_variant[1] + 8), (uintptr_t)m->tune_zc[0],
             (uintptr_t)m->tune_zc[1]};
         if (!gr.exec || gr.key != key) {
+            // no allocation or free anywhere in the library, and no other
+            // recording, while this stream captures (see device_memory_mutex)
+            std::lock_guard<std::recursive_mutex> lk(afd::device_memory_mutex());
             gr.release();
             AFD_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             T *p0 = P0, *p1 = P1;
@@ -525,7 +542,7 @@ int afd_context_create(int device, void* hip_stream, afd_context** out) {
         }
         c->own_stream = true;
     }
-    if (hipMalloc((void**)&c->scratch, VEC_NPART * sizeof(double)) != hipSuccess) {
+    if (afd::dev_malloc((void**)&c->scratch, VEC_NPART * sizeof(double)) != hipSuccess) {
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         set_error("device allocation failed");
@@ -534,7 +551,7 @@ int afd_context_create(int device, void* hip_stream, afd_context** out) {
     // device address of this GPU's static work space of afd_threshold_noalloc
     const int rc = threshold_scratch_init(device);
     if (rc != AFD_OK) {
-        (void)hipFree(c->scratch);
+        (void)afd::dev_free(c->scratch);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return rc;
@@ -547,7 +564,7 @@ void afd_context_destroy(afd_context* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    if (c->scratch) (void)hipFree(c->scratch);
+    if (c->scratch) (void)afd::dev_free(c->scratch);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -738,8 +755,8 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
     const size_t word = f ? 4 : 8, n = (size_t)nrhs * m->g.ndof;
     void *U = nullptr, *Y = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipMalloc(&U, n * word) != hipSuccess || hipMalloc(&Y, n * word) != hipSuccess) {
-        if (U) (void)hipFree(U);
+    if (afd::dev_malloc(&U, n * word) != hipSuccess || afd::dev_malloc(&Y, n * word) != hipSuccess) {
+        if (U) (void)afd::dev_free(U);
         set_error("autotune: scratch allocation failed");
         return AFD_E_OOM;
     }
@@ -806,8 +823,8 @@ int afd_mesh_autotune(afd_mesh* m, int32_t precision, int32_t nrhs, afd_tune_rep
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(U);
-    (void)hipFree(Y);
+    (void)afd::dev_free(U);
+    (void)afd::dev_free(Y);
     if (rc != AFD_OK) return rc;
     // keep the default unless a candidate is clearly faster (timing noise is
     // a few percent between runs)

@@ -764,26 +764,26 @@ int coarse_alloc(Coarse& c, hipStream_t s) {
     size_t bytes = PP * b.K * sizeof(double);
     double** arrs[] = {&c.D, &c.B, &c.Linv, &c.LinvT, &c.T, &c.U};
     for (double** a : arrs) {
-        if (hipMalloc((void**)a, bytes) != hipSuccess) {
+        if (afd::dev_malloc((void**)a, bytes) != hipSuccess) {
             coarse_free(c);
             set_error("coarse: out of device memory");
             return AFD_E_OOM;
         }
     }
-    AFD_HIP_TRY(hipMalloc((void**)&c.Ediag, npad * sizeof(double)));
-    AFD_HIP_TRY(hipMalloc((void**)&c.work, PP * sizeof(double)));
+    AFD_HIP_TRY(afd::dev_malloc((void**)&c.Ediag, npad * sizeof(double)));
+    AFD_HIP_TRY(afd::dev_malloc((void**)&c.work, PP * sizeof(double)));
     if (b.m >= 1 && b.K - 2 >= b.m) {  // the second chain of the factorisation (default priority)
-        AFD_HIP_TRY(hipMalloc((void**)&c.work2, PP * sizeof(double)));
+        AFD_HIP_TRY(afd::dev_malloc((void**)&c.work2, PP * sizeof(double)));
         AFD_HIP_TRY(hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking));
         AFD_HIP_TRY(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
         AFD_HIP_TRY(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
     }
-    AFD_HIP_TRY(hipMalloc((void**)&c.dropped_dev, (npad + 1) * sizeof(int32_t)));
-    AFD_HIP_TRY(hipMalloc((void**)&c.gperm, 4 * npad * sizeof(double)));
+    AFD_HIP_TRY(afd::dev_malloc((void**)&c.dropped_dev, (npad + 1) * sizeof(int32_t)));
+    AFD_HIP_TRY(afd::dev_malloc((void**)&c.gperm, 4 * npad * sizeof(double)));
     AFD_HIP_TRY(hipMemsetAsync(c.gperm, 0, 4 * npad * sizeof(double), s));  // padding positions stay zero
-    AFD_HIP_TRY(hipMalloc((void**)&c.xperm, 4 * npad * sizeof(double)));
-    AFD_HIP_TRY(hipMalloc((void**)&c.perm, b.ncoarse * sizeof(int32_t)));
-    AFD_HIP_TRY(hipMalloc((void**)&c.iperm, npad * sizeof(int32_t)));
+    AFD_HIP_TRY(afd::dev_malloc((void**)&c.xperm, 4 * npad * sizeof(double)));
+    AFD_HIP_TRY(afd::dev_malloc((void**)&c.perm, b.ncoarse * sizeof(int32_t)));
+    AFD_HIP_TRY(afd::dev_malloc((void**)&c.iperm, npad * sizeof(int32_t)));
     // ordering: axes of fewest blocks fastest (a banded matrix), then the
     // super-blocks in the two-ended order
     std::vector<int32_t> perm(b.ncoarse);
@@ -813,19 +813,19 @@ void coarse_free(Coarse& c) {
     c.ev_fork = c.ev_join = nullptr;
     for (double** a : arrs)
         if (*a) {
-            (void)hipFree(*a);
+            (void)afd::dev_free(*a);
             *a = nullptr;
         }
     float** arrs32[] = {&c.Linv32, &c.LinvT32, &c.T32, &c.U32};
     for (float** a : arrs32)
         if (*a) {
-            (void)hipFree(*a);
+            (void)afd::dev_free(*a);
             *a = nullptr;
         }
     c.valid32 = false;
-    if (c.dropped_dev) (void)hipFree(c.dropped_dev);
-    if (c.perm) (void)hipFree(c.perm);
-    if (c.iperm) (void)hipFree(c.iperm);
+    if (c.dropped_dev) (void)afd::dev_free(c.dropped_dev);
+    if (c.perm) (void)afd::dev_free(c.perm);
+    if (c.iperm) (void)afd::dev_free(c.iperm);
     c.iperm = nullptr;
     c.dropped_dev = nullptr;
     c.perm = nullptr;
@@ -858,7 +858,7 @@ int coarse_make_f32(Coarse& c, hipStream_t s) {
     float** dst[] = {&c.Linv32, &c.LinvT32, &c.T32, &c.U32};
     const double* src[] = {c.Linv, c.LinvT, c.T, c.U};
     for (int i = 0; i < 4; ++i) {
-        if (!*dst[i] && hipMalloc((void**)dst[i], n * sizeof(float)) != hipSuccess) {
+        if (!*dst[i] && afd::dev_malloc((void**)dst[i], n * sizeof(float)) != hipSuccess) {
             set_error("coarse: out of device memory for the FP32 copies");
             return AFD_E_OOM;
         }

@@ -32,13 +32,13 @@ struct Dev {
     void release() {
         for (void* p : {(void*)rho, (void*)solid, (void*)S, (void*)raw, (void*)cur, (void*)src, (void*)best,
                         (void*)cast, (void*)dist, (void*)F, (void*)UL, (void*)B, (void*)J})
-            if (p) (void)hipFree(p);
+            if (p) (void)afd::dev_free(p);
     }
 };
 
 template <typename T>
 int alloc(T** p, size_t n) {
-    if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+    if (afd::dev_malloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
         afd::set_error("levelset: out of device memory");
         return AFD_E_OOM;
     }

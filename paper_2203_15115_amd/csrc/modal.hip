@@ -418,9 +418,9 @@ struct Subspace {
     std::vector<double> hp;
     int alloc() {
         const size_t vec = (size_t)BLK * nd;
-        if (hipMalloc((void**)&Y, vec * 8) != hipSuccess || hipMalloc((void**)&Z, vec * 8) != hipSuccess ||
-            hipMalloc((void**)&W, vec * 8) != hipSuccess ||
-            hipMalloc((void**)&part, (size_t)GNB * BLK * BLK * 8) != hipSuccess) {
+        if (afd::dev_malloc((void**)&Y, vec * 8) != hipSuccess || afd::dev_malloc((void**)&Z, vec * 8) != hipSuccess ||
+            afd::dev_malloc((void**)&W, vec * 8) != hipSuccess ||
+            afd::dev_malloc((void**)&part, (size_t)GNB * BLK * BLK * 8) != hipSuccess) {
             set_error("eigen: out of device memory");
             return AFD_E_OOM;
         }
@@ -430,7 +430,7 @@ struct Subspace {
     void release() {
         (void)hipStreamSynchronize(s);
         for (double* q : {Y, Z, W, part})
-            if (q) (void)hipFree(q);
+            if (q) (void)afd::dev_free(q);
     }
     int gram(const double* A, const double* B, double G[BLK][BLK]) {
         hipLaunchKernelGGL(k_gram, dim3(GNB), dim3(GWG), 0, s, nd, BLK, A, B, part);
@@ -583,13 +583,13 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
     Subspace sp{mesh, g.ndof, s};
     double* X = nullptr;
     int rc = sp.alloc();
-    if (rc == AFD_OK && hipMalloc((void**)&X, (size_t)BLK * g.ndof * 8) != hipSuccess) {
+    if (rc == AFD_OK && afd::dev_malloc((void**)&X, (size_t)BLK * g.ndof * 8) != hipSuccess) {
         set_error("modal: out of device memory");
         rc = AFD_E_OOM;
     }
     auto done = [&](int code) {
         sp.release();
-        if (X) (void)hipFree(X);
+        if (X) (void)afd::dev_free(X);
         if (st) st->t = now_s() - t0;
         return code;
     };
@@ -668,7 +668,7 @@ int geo_apply(const Grid& g, const double h[3], double E, double nu, const doubl
         return AFD_E_INVALID_ARG;
     }
     double* sig = nullptr;
-    if (hipMalloc((void**)&sig, (size_t)6 * g.nelem * 8) != hipSuccess) {
+    if (afd::dev_malloc((void**)&sig, (size_t)6 * g.nelem * 8) != hipSuccess) {
         set_error("apply_Kg: out of device memory");
         return AFD_E_OOM;
     }
@@ -690,7 +690,7 @@ int geo_apply(const Grid& g, const double h[3], double E, double nu, const doubl
     hipLaunchKernelGGL(k_geo_apply, dim3((unsigned)((g.nnode + 255) / 256), nrhs), dim3(256), 0, s, gp, 1.0, X, Y);
     const hipError_t e = hipGetLastError();
     (void)hipStreamSynchronize(s);
-    (void)hipFree(sig);
+    (void)afd::dev_free(sig);
     if (e != hipSuccess) {
         set_error("apply_Kg: kernel launch failed");
         return AFD_E_HIP;
@@ -713,16 +713,16 @@ int buckling_subspace(afd_mesh* mesh, const Grid& g, const double h[3], double E
     Subspace sp{mesh, g.ndof, s};
     double *X = nullptr, *sig = nullptr, *Gf = nullptr;
     int rc = sp.alloc();
-    if (rc == AFD_OK && (hipMalloc((void**)&X, (size_t)BLK * g.ndof * 8) != hipSuccess ||
-                         hipMalloc((void**)&sig, (size_t)6 * g.nelem * 8) != hipSuccess ||
-                         (S && hipMalloc((void**)&Gf, (size_t)nev * g.nelem * 8) != hipSuccess))) {
+    if (rc == AFD_OK && (afd::dev_malloc((void**)&X, (size_t)BLK * g.ndof * 8) != hipSuccess ||
+                         afd::dev_malloc((void**)&sig, (size_t)6 * g.nelem * 8) != hipSuccess ||
+                         (S && afd::dev_malloc((void**)&Gf, (size_t)nev * g.nelem * 8) != hipSuccess))) {
         set_error("buckling: out of device memory");
         rc = AFD_E_OOM;
     }
     auto done = [&](int code) {
         sp.release();
         for (double* q : {X, sig, Gf})
-            if (q) (void)hipFree(q);
+            if (q) (void)afd::dev_free(q);
         if (st) st->t = now_s() - t0;
         return code;
     };

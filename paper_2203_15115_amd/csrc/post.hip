@@ -469,7 +469,7 @@ int stress_pnorm(const Grid& g, const double h[3], double E, double nu, const do
     const unsigned nb = (unsigned)((g.nelem + 255) / 256);
     double* work = nullptr;
     const size_t part_n = (size_t)nrhs * nb, T_n = B ? (size_t)nrhs * 6 * g.nelem : 0;
-    if (hipMalloc((void**)&work, (part_n + T_n) * sizeof(double)) != hipSuccess) {
+    if (afd::dev_malloc((void**)&work, (part_n + T_n) * sizeof(double)) != hipSuccess) {
         set_error("stress: out of device memory");
         return AFD_E_OOM;
     }
@@ -498,7 +498,7 @@ int stress_pnorm(const Grid& g, const double h[3], double E, double nu, const do
         }
     }
     (void)hipStreamSynchronize(st);
-    (void)hipFree(work);
+    (void)afd::dev_free(work);
     return rc;
 }
 
@@ -700,13 +700,13 @@ int threshold_gpu(const double* s, const int32_t* tie, int64_t n, double vol_fra
         return AFD_E_INVALID_ARG;
     }
     void* work = nullptr;
-    if (hipMalloc(&work, threshold_work_bytes(n)) != hipSuccess) {
+    if (afd::dev_malloc(&work, threshold_work_bytes(n)) != hipSuccess) {
         set_error("threshold: out of device memory");
         return AFD_E_OOM;
     }
     const int rc = threshold_run(s, tie, n, vol_frac, solid, order, tau_host, work, st);
     if (rc != AFD_OK) (void)hipStreamSynchronize(st);  // no kernel may still use the work space
-    (void)hipFree(work);
+    (void)afd::dev_free(work);
     return rc;
 }
 

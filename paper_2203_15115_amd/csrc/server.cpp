@@ -261,11 +261,11 @@ int afd_server_create(afd_context* ctx, uint64_t budget, int32_t max_slots, afd_
             delete S;
             return rc;
         }
-        // slots create and free meshes (hipMalloc / hipFree, which synchronise
-        // the device) while other slots solve: a stream capture in progress on
-        // one slot must not see such implicit synchronisation, so slots launch
-        // their iterations one by one
-        (void)afd_context_use_graphs(s.ctx, 0);
+        // slots record and replay their iteration graphs like any context:
+        // the library's device allocations and frees (a slot creating or
+        // dropping a mesh) and graph recordings exclude one another through
+        // one process-wide lock, so no capture sees a device-synchronising
+        // free from another slot
     }
     for (int i = 0; i < max_slots; ++i) S->slots[i].th = std::thread(slot_loop, S, i);
     S->sched = std::thread(sched_loop, S);
