@@ -194,6 +194,26 @@ int afd_mesh_apply_config(afd_mesh* mesh, int32_t precision, int32_t variant, in
  * stopping test and the true residual stay FP64).  AFD_E_INVALID_ARG
  * otherwise. */
 int afd_mesh_coarse_precision(afd_mesh* mesh, int32_t precision);
+/* Execution form of the FP64 deflated PCG of afd_solve on this mesh (the
+ * iteration of Sec. 3.5 is the same in both forms, only its execution
+ * differs):
+ *   AFD_FORM_LAUNCHES   (the default) a chain of launches per iteration,
+ *                       recorded as HIP graphs in chunks of check_every
+ *                       iterations;
+ *   AFD_FORM_PERSISTENT one launch for the whole solve, one workgroup of 1024
+ *                       threads per right-hand side iterating until its
+ *                       stopping test, on one compute unit per right-hand
+ *                       side (for meshes of at most 65,536 elements whose
+ *                       coarse problem fits one super-block of at most 1024
+ *                       unknowns; afd_solve returns AFD_E_INVALID_ARG for a
+ *                       larger one).  Slower per solve than the chain at every
+ *                       size measured; it leaves the rest of the chip to
+ *                       concurrent work.
+ * The mixed form always runs the launch chain.  AFD_E_INVALID_ARG for other
+ * values. */
+#define AFD_FORM_LAUNCHES   0
+#define AFD_FORM_PERSISTENT 1
+int afd_mesh_solver_form(afd_mesh* mesh, int32_t form);
 
 /* Jacobi diagonal of A (Sec. 3.5: preconditioner formed assembly-free):
  * d[3n+c] = Ke_cc * sum of rho over the elements touching node n for a free

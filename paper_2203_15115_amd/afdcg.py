@@ -29,6 +29,8 @@ AFD_MEM_DEVICE = 1
 AFD_FP64 = 0
 AFD_MIXED = 1
 AFD_FP32 = 2
+AFD_FORM_LAUNCHES = 0
+AFD_FORM_PERSISTENT = 1
 
 STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVALID_ARG", -2: "E_NO_DEVICE", -3: "E_OOM",
                 -4: "E_OVER_BUDGET", -5: "E_NOT_CONVERGED", -6: "E_BREAKDOWN",
@@ -36,7 +38,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVALID_ARG", -2: "E_NO_DEVICE", -
 
 EXPORTED = [
     "afd_context_create", "afd_context_destroy", "afd_last_error", "afd_context_sync", "afd_context_use_graphs",
-    "afd_mesh_coarse_precision", "afd_casting",
+    "afd_mesh_coarse_precision", "afd_mesh_solver_form", "afd_casting",
     "afd_mesh_create", "afd_mesh_destroy", "afd_mesh_sizes", "afd_mesh_set_scale", "afd_mesh_set_fixed",
     "afd_mesh_footprint", "afd_mesh_ke", "afd_apply_K", "afd_apply_K_mfma", "afd_mesh_autotune", "afd_mesh_apply_config",
     "afd_jacobi",
@@ -124,6 +126,7 @@ def lib():
             "afd_context_sync": (C.c_int, [vp]),
             "afd_context_use_graphs": (C.c_int, [vp, i32]),
             "afd_mesh_coarse_precision": (C.c_int, [vp, i32]),
+            "afd_mesh_solver_form": (C.c_int, [vp, i32]),
             "afd_mesh_create": (C.c_int, [vp, C.POINTER(afd_mesh_desc), C.POINTER(vp)]),
             "afd_mesh_destroy": (None, [vp]),
             "afd_mesh_sizes": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
@@ -165,6 +168,11 @@ def lib():
             "afd_server_clock": (dbl, [vp]),
             "afd_server_destroy": (None, [vp]),
         }
+        # every exported call is declared: an undeclared one would pass
+        # pointers as C ints
+        missing = sorted(set(EXPORTED) - set(sig))
+        if missing:
+            raise RuntimeError(f"no ctypes prototype for {missing}")
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype = res
@@ -220,6 +228,10 @@ def afd_context_use_graphs(ctx, enable):
 
 def afd_mesh_coarse_precision(mesh, precision):
     check(lib().afd_mesh_coarse_precision(mesh, int(precision)), "afd_mesh_coarse_precision")
+
+
+def afd_mesh_solver_form(mesh, form):
+    check(lib().afd_mesh_solver_form(mesh, int(form)), "afd_mesh_solver_form")
 
 
 def afd_mesh_create(ctx, dims, h=(1.0, 1.0, 1.0), E=1.0, nu=0.3, block=(0, 0, 0)):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libafdcg.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["ke.cpp", "matvec.hip", "mfma.hip", "vec.hip", "dense.hip", "post.hip", "capi.cpp", "server.cpp", "levelset.cpp", "modal.hip"]
+SOURCES = ["ke.cpp", "matvec.hip", "mfma.hip", "vec.hip", "dense.hip", "post.hip", "capi.cpp", "server.cpp", "levelset.cpp", "modal.hip", "persist.hip"]
 ARCH = os.environ.get("AFD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of every kernel

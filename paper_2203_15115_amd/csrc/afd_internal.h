@@ -154,6 +154,16 @@ struct CgScalars {
     int32_t pad;
 };
 
+// persist.hip: the FP64 deflated PCG as one launch, one workgroup per
+// right-hand side (see afd_mesh_solver_form)
+constexpr int64_t PERSISTENT_MAX_ELEMS = 65536;  // largest mesh of the form
+bool persistent_fits(const Grid& g, const Blocks& b, bool deflate, int nrhs);
+int launch_dcg_persistent(const Grid& g, const Blocks& b, bool deflate, const KeHaar& kh, const double* rho,
+                          const uint8_t* nmask, const double* rinv, const double* Linv, const double* LinvT,
+                          const int32_t* perm, const int32_t* iperm, int nrhs, const double* F, double* X, double* R,
+                          double* P, double* Q, double* Z, double* Ye, CgScalars* sc, double rtol, int max_iter,
+                          bool warm, hipStream_t s);
+
 // --------------------------------------------------------------- launchers
 // matvec.hip
 struct MatvecArgs {

@@ -78,6 +78,7 @@ struct Work {
     // FP64 Krylov state [nrhs][ndof]
     double *X = nullptr, *R = nullptr, *P0 = nullptr, *P1 = nullptr, *Q = nullptr, *Z = nullptr, *AZ = nullptr;
     double *F = nullptr;   // device copy of F (host input)
+    double* Ye = nullptr;  // persistent form: per-element outputs of the apply [nrhs][24][nelem]
     double *S = nullptr;   // energies (host output)
     // FP32 inner state
     float *Xf = nullptr, *Rf = nullptr, *P0f = nullptr, *P1f = nullptr, *Qf = nullptr, *Zf = nullptr,
@@ -124,6 +125,7 @@ struct afd_mesh {
     int coarse_f32 = -1;             // coarse solve matrices streamed in FP32 (1) or FP64 (0); -1: default
     int tune_variant[2] = {-1, -1};  // autotuned plain-apply kernel per precision (FP64, FP32)
     int tune_zc[2] = {0, 0};
+    int solver_form = AFD_FORM_LAUNCHES;
     Coarse coarse;
     Work w;
     int npartM = 0;
@@ -186,7 +188,7 @@ void dfree(T** p) {
 
 void free_work(Work& w) {
     dfree(&w.X), dfree(&w.R), dfree(&w.P0), dfree(&w.P1), dfree(&w.Q), dfree(&w.Z), dfree(&w.AZ), dfree(&w.F),
-        dfree(&w.S);
+        dfree(&w.S), dfree(&w.Ye);
     dfree(&w.Xf), dfree(&w.Rf), dfree(&w.P0f), dfree(&w.P1f), dfree(&w.Qf), dfree(&w.Zf), dfree(&w.AZf),
         dfree(&w.Bf);
     dfree(&w.G), dfree(&w.MU), dfree(&w.sc), dfree(&w.outer), dfree(&w.partM), dfree(&w.partV), dfree(&w.Jdev);
@@ -209,6 +211,7 @@ int ensure_work(afd_mesh* m, int nrhs, int mixed) {
     AFD_TRY(dalloc(&w.Z, n));
     AFD_TRY(dalloc(&w.AZ, n));
     AFD_TRY(dalloc(&w.F, n));
+    if (persistent_fits(m->g, m->blk, m->deflate, 1)) AFD_TRY(dalloc(&w.Ye, (size_t)nr * 24 * m->g.nelem));
     if (mx) {
         AFD_TRY(dalloc(&w.Xf, n));
         AFD_TRY(dalloc(&w.Rf, n));
@@ -723,6 +726,7 @@ int afd_mesh_footprint(const afd_mesh* m, int32_t nrhs, int32_t precision, uint6
     const int64_t ntm = tile_layout_sizes(m->g, &ntr);
     b += (uint64_t)ntr * 12 + (uint64_t)ntm * 2;                         // tile-major apply inputs
     b += (uint64_t)nrhs * nd * 8 * 8;                                    // FP64 work vectors
+    if (persistent_fits(m->g, m->blk, m->deflate, 1)) b += (uint64_t)nrhs * ne * 24 * 8;  // persistent form
     if (precision == AFD_MIXED) b += (uint64_t)nrhs * nd * 4 * 8;        // FP32 inner vectors
     if (m->deflate) {
         const uint64_t PP = (uint64_t)m->blk.P * m->blk.P;
@@ -854,6 +858,15 @@ int afd_mesh_apply_config(afd_mesh* m, int32_t precision, int32_t variant, int32
     const int f = precision == AFD_FP32 ? 1 : 0;
     m->tune_variant[f] = variant;
     m->tune_zc[f] = zc;
+    return AFD_OK;
+}
+
+int afd_mesh_solver_form(afd_mesh* m, int32_t form) {
+    if (!m || (form != AFD_FORM_LAUNCHES && form != AFD_FORM_PERSISTENT)) {
+        set_error("solver_form: AFD_FORM_LAUNCHES or AFD_FORM_PERSISTENT");
+        return AFD_E_INVALID_ARG;
+    }
+    m->solver_form = form;
     return AFD_OK;
 }
 
@@ -1180,12 +1193,27 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
         // rtol after that has met the FP64 attainable accuracy of its problem
         // and is reported AFD_E_NOT_CONVERGED.
         constexpr int FP64_RESTARTS = 3;
+        // the execution form (the iteration is the same): the graph-recorded
+        // launch chain, or one launch per solve on request
+        const bool persistent = m->solver_form == AFD_FORM_PERSISTENT;
+        if (persistent && !(persistent_fits(m->g, m->blk, m->deflate, nrhs) && w.Ye)) {
+            set_error("solve: the persistent form needs at most " + std::to_string(PERSISTENT_MAX_ELEMS) +
+                      " elements and a coarse problem of one super-block");
+            return AFD_E_INVALID_ARG;
+        }
+        const Coarse& cf = m->coarse;
         std::vector<int> iters(nrhs, 0);
         for (int run = 0;; ++run) {
             int used = 0;
             for (int r = 0; r < nrhs; ++r) used = std::max(used, iters[r]);
-            AFD_TRY(dcg_run<double>(m, nrhs, w.F, w.X, w.R, w.P0, w.P1, w.Q, w.Z, w.AZ, w.sc, 0.99 * o->rtol,
-                                    std::max(1, o->max_iter - used), ce, nullptr, warm || run > 0));
+            if (persistent)
+                AFD_TRY(launch_dcg_persistent(m->g, m->blk, m->deflate, m->kh, m->rho, m->nmask, m->rinv, cf.Linv,
+                                              cf.LinvT, cf.perm, cf.iperm, nrhs, w.F, w.X, w.R, w.P0, w.Q, w.Z, w.Ye,
+                                              w.sc, 0.99 * o->rtol, std::max(1, o->max_iter - used), warm || run > 0,
+                                              s));
+            else
+                AFD_TRY(dcg_run<double>(m, nrhs, w.F, w.X, w.R, w.P0, w.P1, w.Q, w.Z, w.AZ, w.sc, 0.99 * o->rtol,
+                                        std::max(1, o->max_iter - used), ce, nullptr, warm || run > 0));
             AFD_HIP_TRY(hipMemcpyAsync(hsc.data(), w.sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
             AFD_TRY(true_residual());  // synchronises
             bool again = false;

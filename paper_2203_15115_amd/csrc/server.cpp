@@ -85,6 +85,7 @@ uint64_t footprint_of(const afd_mesh_desc& d, int nrhs, int precision) {
     const int64_t ntm = afd::tile_layout_sizes(g, &ntr);
     b += (uint64_t)ntr * 12 + (uint64_t)ntm * 2;
     if (precision == AFD_MIXED) b += (uint64_t)4 * nd * 4 * 8;
+    if (ne <= (uint64_t)afd::PERSISTENT_MAX_ELEMS) b += (uint64_t)4 * ne * 24 * 8;  // persistent form's element buffer
     if (d.bx > 0 && d.by > 0 && d.bz > 0) {
         int nb[3] = {(d.nx + d.bx - 1) / d.bx, (d.ny + d.by - 1) / d.by, (d.nz + d.bz - 1) / d.bz};
         std::sort(nb, nb + 3);

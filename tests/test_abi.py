@@ -38,3 +38,4 @@ def test_null_arguments_rejected_without_device():
     assert L.afd_mesh_create(None, None, None) in (afdcg.AFD_E_INVALID_ARG,)
     assert L.afd_solve(None, None, 1, None, None, None, None, None) == afdcg.AFD_E_INVALID_ARG
     assert L.afd_mesh_sizes(None, None, None, None, None) == afdcg.AFD_E_INVALID_ARG
+    assert L.afd_mesh_solver_form(None, afdcg.AFD_FORM_LAUNCHES) == afdcg.AFD_E_INVALID_ARG

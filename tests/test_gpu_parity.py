@@ -1230,3 +1230,89 @@ def test_buckling_matches_oracle(ctx, dims, block, seed):
         assert np.max(np.abs(Sh[j] - want)) <= 1e-6 * np.max(np.abs(want)), j
     print(f"buckling {dims}: {st.iterations} subspace iterations, {st.cg_iterations} CG iterations, "
           f"load factors {lam}, residuals {list(st.rel_residual)[:2]}")
+
+
+# ------------------------------------------------------------- persistent form of the solve
+def _form_solve(ctx, dims, rho, fixed, F, block, form, rtol, h=(1.0, 1.0, 1.0), E=1.0, nu=0.3, pairs=(),
+                max_iter=20000):
+    m = make_mesh(ctx, dims, rho, fixed, block=block, h=h, E=E, nu=nu)
+    afdcg.afd_mesh_solver_form(m, form)
+    nr, nd, ne = F.shape[0], 3 * wl.n_nodes(dims), wl.n_elems(dims)
+    U, J, S = np.zeros((nr, nd)), np.zeros(nr), np.zeros((nr + len(pairs), ne))
+    code, st = afdcg.afd_solve(m, afdcg.make_opts(rtol=rtol, max_iter=max_iter, pairs=pairs), nr,
+                               np.ascontiguousarray(F), U, J, S, raise_on_error=False)
+    afdcg.afd_mesh_destroy(m)
+    return code, U, J, S, st
+
+
+@pytest.mark.parametrize("dims,block,box,nrhs", [
+    ((24, 12, 12), (4, 4, 4), False, 1),   # the 24x12x12 workload's mesh and blocks
+    ((13, 7, 5), (4, 4, 3), False, 3),     # ragged last blocks, random fixity
+    ((16, 9, 6), (4, 3, 3), True, 2),      # unequal voxel edges (index-space motions are not rigid)
+    ((12, 6, 6), (0, 0, 0), False, 4),     # undeflated
+])
+def test_persistent_solve_matches_oracle_and_launch_chain(ctx, dims, block, box, nrhs):
+    h, E, nu = ((1.0, 2.0, 0.5), 2.5, 0.27) if box else ((1.0, 1.0, 1.0), 1.0, 0.3)
+    rng = np.random.default_rng(95 + nrhs)
+    if dims == (24, 12, 12):
+        p = wl.config(0)
+        rho, fixed, F = p.rho, p.fixed, p.F[:nrhs]
+    else:
+        rho = np.where(rng.random(wl.n_elems(dims)) < 0.3, 1e-3, 1.0)
+        fixed = wl.clamp_x0(dims)
+        fixed[rng.random(fixed.size) < 0.02] = 1
+        F = rng.standard_normal((nrhs, fixed.size))
+        F[:, fixed != 0] = 0.0
+    K = fem.assemble(dims, rho, fem.ke_gauss(h, E, nu))
+    pairs = ((0, nrhs - 1),) if nrhs > 1 else ()
+    code, U, J, S, st = _form_solve(ctx, dims, rho, fixed, F, block, afdcg.AFD_FORM_PERSISTENT, 1e-11, h, E, nu,
+                                    pairs)
+    code_l, U_l, J_l, S_l, st_l = _form_solve(ctx, dims, rho, fixed, F, block, afdcg.AFD_FORM_LAUNCHES, 1e-11,
+                                              h, E, nu, pairs)
+    assert code == afdcg.AFD_OK and code_l == afdcg.AFD_OK, (code, code_l)
+    for r in range(nrhs):
+        ud = solvers.solve_direct(K, fixed, F[r])
+        assert np.linalg.norm(U[r] - ud) <= 1e-8 * np.linalg.norm(ud), r
+        assert st[r].rel_residual_true <= 1e-11
+        assert abs(J[r] - F[r] @ ud) <= 1e-9 * abs(F[r] @ ud)
+        # the same iteration as the launch chain, with other summation orders
+        assert abs(st[r].iterations - st_l[r].iterations) <= 2 + st_l[r].iterations // 50, \
+            (r, st[r].iterations, st_l[r].iterations)
+        assert np.linalg.norm(U[r] - U_l[r]) <= 1e-9 * np.linalg.norm(U_l[r])
+    assert np.max(np.abs(S - S_l)) <= 1e-9 * np.max(np.abs(S_l))
+    # bitwise reproducible
+    code2, U2, _, _, st2 = _form_solve(ctx, dims, rho, fixed, F, block, afdcg.AFD_FORM_PERSISTENT, 1e-11, h, E, nu,
+                                       pairs)
+    assert np.array_equal(U, U2) and [s.iterations for s in st] == [s.iterations for s in st2]
+    print(f"persistent {dims} x{nrhs}: iterations {[s.iterations for s in st]} "
+          f"(launch chain {[s.iterations for s in st_l]})")
+
+
+def test_persistent_status_warm_start_and_limits(ctx, c0_direct):
+    p, K, ud = c0_direct
+    m = make_mesh(ctx, p.dims, p.rho, p.fixed, block=p.block)
+    afdcg.afd_mesh_solver_form(m, afdcg.AFD_FORM_PERSISTENT)
+    F = np.ascontiguousarray(p.F[:1])
+    # max_iter reached: AFD_E_NOT_CONVERGED with a finite last iterate
+    U = np.zeros((1, p.ndof))
+    code, st = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-10, max_iter=20), 1, F, U, raise_on_error=False)
+    assert code == afdcg.AFD_E_NOT_CONVERGED and st[0].iterations == 20 and np.all(np.isfinite(U))
+    # converged, then warm-started from the solution: done at once
+    code, st = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-10), 1, F, U)
+    assert code == afdcg.AFD_OK and np.linalg.norm(U[0] - ud) <= 1e-7 * np.linalg.norm(ud)
+    U2 = np.zeros_like(U)
+    code, st2 = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-10, x0=U.copy()), 1, F, U2)
+    assert code == afdcg.AFD_OK and st2[0].iterations <= 1
+    # a zero load: zero displacements, no iteration
+    code, st3 = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-10), 1, np.zeros_like(F), U2)
+    assert code == afdcg.AFD_OK and st3[0].iterations == 0 and not np.any(U2)
+    afdcg.afd_mesh_destroy(m)
+    # a mesh beyond the form: refused on the host
+    big = (96, 48, 48)
+    m = afdcg.afd_mesh_create(ctx, big, block=(8, 8, 8))
+    afdcg.afd_mesh_set_fixed(m, wl.clamp_x0(big), 3 * wl.n_nodes(big), afdcg.AFD_MEM_HOST)
+    afdcg.afd_mesh_solver_form(m, afdcg.AFD_FORM_PERSISTENT)
+    Fb = wl.edge_load(big, "bottom")[None]
+    code, _ = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-8), 1, Fb, np.zeros_like(Fb), raise_on_error=False)
+    assert code == afdcg.AFD_E_INVALID_ARG
+    afdcg.afd_mesh_destroy(m)
