@@ -41,6 +41,16 @@ Readings of the paper used here (it leaves these open):
   gamma_s (same rules, same start values), T_L = w_J T_J / (alpha_J J0) +
   w_s T_sigma / (alpha_sigma sigma_PN0); a violated stress constraint is a
   hard violation like the compliance one.
+* With the eigenvalue constraint lambda_1 >= alpha_lambda lambda_10 (Eq. 3.21;
+  lambda_1 the lowest eigenvalue of K phi = lambda M phi, see modal.py, void
+  elements scaled in mass as in stiffness) a further term joins with
+  g_l = 1 - lambda_1 / (alpha_lambda lambda_10), its own mu_l and gamma_l (same
+  rules, same start values) and the field T_lambda / (alpha_lambda
+  lambda_10), T_lambda(e) = rho_e phi_e^T (Ke - lambda_1 Me) phi_e the drop of
+  lambda_1 when element e loses its stiffness and mass (modal.py): like the
+  compliance and stress fields, the increase of g when e is removed.  A
+  violated eigenvalue constraint is a hard violation; step 7's convergence
+  test stays on the compliance.
 * Topology at v (Eq. 3.6): the ceil(v nE) elements of highest T_L (ties by
   index; with the casting constraint of Sec. 3.7 the projected field, ties by
   the distance to the parting plane, then index); void elements get the
@@ -53,7 +63,7 @@ import math
 
 import numpy as np
 
-from . import fem, post, solvers, stress
+from . import fem, modal, post, solvers, stress
 from .casting import cast_project, parting_distance
 
 FEA_FIXED_POINT = 0   # a fixed-point solve at the current target
@@ -109,6 +119,7 @@ class Params:
     alpha_sigma: float = 0.0   # sigma_PN <= alpha_sigma sigma_PN0 (Eq. 3.23); <= 0: no stress constraint
     pnorm_p: float = 8.0
     damping: bool = False      # extract from the mean of this level set and the one the topology came from
+    alpha_lambda: float = 0.0  # lambda_1 >= alpha_lambda lambda_10 (Eq. 3.21); <= 0: no eigenvalue constraint
 
 
 @dataclasses.dataclass
@@ -126,6 +137,10 @@ class Record:
     g_s: float = 0.0
     mu_s: float = 0.0
     gamma_s: float = 0.0
+    lam: float = 0.0  # lowest eigenvalue (0 without the eigenvalue constraint)
+    g_l: float = 0.0
+    mu_l: float = 0.0
+    gamma_l: float = 0.0
 
 
 def extract(field, vol, dims, p: Params):
@@ -164,6 +179,15 @@ def stress_quantities(dims, solid, fixed, Ke, U, p: Params):
     return S, stress.stress_field(dims, rho, Ke, U, Lam)
 
 
+def eigen_quantities(dims, solid, fixed, Ke, Me, p: Params):
+    """The lowest eigenvalue of the topology and its sensitivity field."""
+    rho = density(solid, p)
+    K = fem.assemble(dims, rho, Ke)
+    M = fem.assemble(dims, rho, Me)
+    lam, Phi = modal.lowest_modes(K, M, fixed, 1)
+    return float(lam[0]), modal.eigen_sensitivity(dims, rho, Ke, Me, lam[0], Phi[0])
+
+
 class Loop:
     """The loop as a state machine: ``first()`` gives the full domain; after
     each solve, ``after_solve(solid, J, field)`` records it and returns the
@@ -176,6 +200,9 @@ class Loop:
         self.n = int(np.prod(dims))
         self.mu, self.gamma = p.mu0, p.gamma0
         self.mu_s, self.gamma_s = p.mu0, p.gamma0
+        self.mu_l, self.gamma_l = p.mu0, p.gamma0
+        self.L0 = None
+        self.gl_prev = None
         self.dv = p.dv0
         self.k = 0
         self.J0 = None
@@ -193,13 +220,15 @@ class Loop:
     def first(self):
         return np.ones(self.n, dtype=np.uint8)
 
-    def after_solve(self, solid, J, field_J, S=None, field_S=None):
+    def after_solve(self, solid, J, field_J, S=None, field_S=None, lam=None, field_lam=None):
         p = self.p
         k, v = self.k, self.v
         stress = p.alpha_sigma > 0
+        eigen = p.alpha_lambda > 0
         if k == 0:
             self.J0 = J
             self.S0 = S
+            self.L0 = lam
         g = J / (p.alpha_J * self.J0) - 1.0
         mu, gamma = al_update(self.mu, self.gamma, g, self.g_prev, k, p.varsigma, p.eta)
         self.mu, self.gamma, self.g_prev = mu, gamma, g
@@ -208,8 +237,13 @@ class Loop:
             g_s = S / (p.alpha_sigma * self.S0) - 1.0
             self.mu_s, self.gamma_s = al_update(self.mu_s, self.gamma_s, g_s, self.gs_prev, k, p.varsigma, p.eta)
             self.gs_prev = g_s
+        g_l = 0.0
+        if eigen:
+            g_l = 1.0 - lam / (p.alpha_lambda * self.L0)
+            self.mu_l, self.gamma_l = al_update(self.mu_l, self.gamma_l, g_l, self.gl_prev, k, p.varsigma, p.eta)
+            self.gl_prev = g_l
         self.fp += 1
-        if g > 0.0 or g_s > 0.0:
+        if g > 0.0 or g_s > 0.0 or g_l > 0.0:
             event = FEA_VIOLATED
         elif k == 0 or self._converged(J):
             event = FEA_CONVERGED
@@ -230,13 +264,16 @@ class Loop:
                 nxt = extract(self.best[3], self.v, self.dims, p)
         else:
             # steps 5-6: the augmented level set and the topology extracted from it
+            # the active constraints in the order J, stress, eigenvalue
+            mus, gammas, gs, fields, scales = [mu], [gamma], [g], [field_J], [p.alpha_J * self.J0]
             if stress:
-                w = weights([mu, self.mu_s], [gamma, self.gamma_s], [g, g_s])
-                field = combined_field([field_J, field_S], [w[0] / (p.alpha_J * self.J0),
-                                                            w[1] / (p.alpha_sigma * self.S0)])
-            else:
-                w = weights([mu], [gamma], [g])
-                field = combined_field([field_J], [w[0] / (p.alpha_J * self.J0)])
+                mus.append(self.mu_s), gammas.append(self.gamma_s), gs.append(g_s)
+                fields.append(field_S), scales.append(p.alpha_sigma * self.S0)
+            if eigen:
+                mus.append(self.mu_l), gammas.append(self.gamma_l), gs.append(g_l)
+                fields.append(field_lam), scales.append(p.alpha_lambda * self.L0)
+            w = weights(mus, gammas, gs)
+            field = combined_field(fields, [wi / sc for wi, sc in zip(w, scales)])
             if p.damping and self.src is not None:
                 field = 0.5 * (field + self.src)
             if event == FEA_CONVERGED:  # step 8: the next target
@@ -255,7 +292,8 @@ class Loop:
                 nxt = extract(field, v, self.dims, p)
         self.history.append(Record(k, event, v, int(solid.sum()), J, g, mu, gamma, self.dv,
                                    S if stress else 0.0, g_s, self.mu_s if stress else 0.0,
-                                   self.gamma_s if stress else 0.0))
+                                   self.gamma_s if stress else 0.0, lam if eigen else 0.0, g_l,
+                                   self.mu_l if eigen else 0.0, self.gamma_l if eigen else 0.0))
         self.k += 1
         if self.k >= p.max_fea:
             nxt = None
@@ -273,15 +311,17 @@ class Loop:
         """The whole loop with direct solves; returns the last converged
         feasible design (solid, v, J) and the history."""
         Ke = fem.ke_gauss() if Ke is None else Ke
+        Me = modal.me_gauss()
         solid = self.first()
         while solid is not None:
             U = fea(self.dims, solid, fixed, F, Ke, self.p)
             J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
             fJ = compliance_field(self.dims, solid, Ke, U, self.p)
+            S = fS = lam = fL = None
             if self.p.alpha_sigma > 0:
                 S, fS = stress_quantities(self.dims, solid, fixed, Ke, U, self.p)
-                solid = self.after_solve(solid, J, fJ, S, fS)
-            else:
-                solid = self.after_solve(solid, J, fJ)
+            if self.p.alpha_lambda > 0:
+                lam, fL = eigen_quantities(self.dims, solid, fixed, Ke, Me, self.p)
+            solid = self.after_solve(solid, J, fJ, S, fS, lam, fL)
         b = self.best
         return (b[0], b[1], b[2]), self.history

@@ -604,9 +604,9 @@ def test_levelset_loop_with_casting_has_no_cavity():
     seen = []
     orig = loop.after_solve
 
-    def spy(solid, J, field):
+    def spy(solid, J, field, *rest):
         seen.append(solid.copy())
-        return orig(solid, J, field)
+        return orig(solid, J, field, *rest)
     loop.after_solve = spy
     (best, v, J), h = loop.run(fixed, F)
     assert len(seen) == len(h) > 5 and J <= 2 * h[0].J
@@ -717,6 +717,40 @@ def test_levelset_loop_with_stress_invariants():
     assert conv[-1].S > 1.3 * S0 and conv[-1].v < 0.6
     assert not any(r.event == ls.FEA_DIVERGED for r in h)
     assert abs(h[0].g_s - (1 / 1.5 - 1)) < 1e-15
+
+
+def _mid_span_load(dims):
+    # unit -z force shared by the bottom nodes of the line x = nx/2 (along y)
+    nx, ny, nz = dims
+    f = np.zeros(3 * wl.n_nodes(dims))
+    for j in range(ny + 1):
+        f[3 * wl.node_id(dims, nx // 2, j, 0) + 2] = -1.0 / (ny + 1)
+    return f
+
+
+def test_levelset_loop_with_eigen_invariants():
+    # J <= 3 J0 and lambda_1 >= lambda_10 with damping on a 10x5x5 cantilever
+    # loaded at mid-span: the first volume steps take mass-dominated material
+    # (T_lambda < 0, near the free end), so lambda_1 rises; later the
+    # eigenvalue bound is the one that stops a step; every converged design
+    # satisfies both constraints; mu_l / gamma_l follow Eq. 3.11-3.12
+    from oracle import levelset as ls
+    dims = (10, 5, 5)
+    p = ls.Params(alpha_J=3.0, alpha_lambda=1.0, damping=True, dv_min=0.025 / 4)
+    loop = ls.Loop(dims, p)
+    (best, v, J), h = loop.run(wl.clamp_x0(dims), _mid_span_load(dims)[None])
+    L0 = h[0].lam
+    assert L0 > 0 and h[0].g_l == 0.0
+    conv = [r for r in h if r.event == ls.FEA_CONVERGED]
+    assert all(r.g <= 0 and r.g_l <= 0 and r.lam >= L0 for r in conv)
+    assert conv[1].lam > conv[0].lam and conv[2].lam > conv[1].lam      # the field's sign
+    assert any(r.event == ls.FEA_VIOLATED and r.g_l > 0 and r.g <= 0 for r in h)  # the eigenvalue bound binds
+    mu, gamma, g_old = p.mu0, p.gamma0, None
+    for k, r in enumerate(h):
+        mu, gamma = ls.al_update(mu, gamma, r.g_l, g_old, k, p.varsigma, p.eta)
+        g_old = r.g_l
+        assert abs(mu - r.mu_l) <= 1e-12 * max(1.0, mu) and gamma == r.gamma_l, k
+    assert conv[-1].v < 0.85 and h[-1].event == ls.FEA_TERMINATED
 
 
 # ------------------------------------------------------------- modal analysis (Eq. 3.4, 3.21)
