@@ -422,6 +422,13 @@ int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
  *  - the next topology: the ceil(v nE) elements of highest T_L (with the
  *    casting constraint, Sec. 3.7: of the projected field, ties cut nearer
  *    the parting plane first), void elements at void_scale.
+ * With alpha_lambda > 0 the lowest eigenvalue joins as a hard constraint
+ * lambda_1 >= alpha_lambda lambda_10 (Eq. 3.21; afd_modal on each topology,
+ * void elements scaled in mass as in stiffness): g_l = 1 - lambda_1 /
+ * (alpha_lambda lambda_10), its own mu_l, gamma_l by the same rules, and the
+ * term w_l T_lambda / (alpha_lambda lambda_10) of the level set, T_lambda the
+ * eigenvalue field of afd_modal (Eq. 3.4: the drop of lambda_1 when an
+ * element loses stiffness and mass).
  * With damping the topology is extracted from the mean of the solve's level
  * set and the level set its topology was extracted from (a fixed point that
  * would alternate between two topologies settles).
@@ -456,6 +463,10 @@ typedef struct {
     int32_t damping;           /* 1: extract from the mean of the solve's level
                                   set and the one its topology came from         */
     afd_solve_opts solve;      /* the solves (mem_kind, pairs, x0 are set by the loop) */
+    double alpha_lambda;       /* eigenvalue constraint lambda_1 >= alpha_lambda
+                                  lambda_10, 0 < alpha_lambda <= 1; <= 0: none   */
+    double modal_tol;          /* Ritz residual of the eigenpair (e.g. 1e-9); its
+                                  inner solves take the rtol of `solve`          */
 } afd_levelset_opts;
 typedef struct {
     int32_t fea;               /* solve index                                    */
@@ -470,6 +481,8 @@ typedef struct {
                                   cases) and the whole step (solve, fields,
                                   level set, extraction, bookkeeping)           */
     double S, g_s, mu_s, gamma_s; /* stress p-norm, its constraint value, its
+                                  multiplier and penalty (0 without it)         */
+    double lam, g_l, mu_l, gamma_l; /* lowest eigenvalue, its constraint value,
                                   multiplier and penalty (0 without it)         */
 } afd_levelset_record;
 int afd_levelset_run(afd_mesh* mesh, const afd_levelset_opts* opts, int32_t nload, const double* F,

@@ -1,7 +1,8 @@
 // The augmented topological level-set loop (Sec. 3.2-3.4, 3.6, 3.8; Fig. 6-7):
-// Pareto tracing of minimum volume under a hard compliance constraint, as a
-// host state machine over the library's device steps (solve, energy fields,
-// combined level set, casting projection, ranking).  Every per-element step
+// Pareto tracing of minimum volume under a hard compliance constraint (and
+// optionally stress and eigenvalue constraints), as a host state machine over
+// the library's device steps (solve, energy fields, eigenpair, combined level
+// set, casting projection, ranking).  Every per-element step
 // runs on the GPU; the host keeps the scalars (J, g, mu, gamma, v, dv).
 #include <hip/hip_runtime.h>
 
@@ -29,9 +30,11 @@ struct Dev {
     double* UL = nullptr;       // nload x n_dof displacements, then (stress) nload x n_dof adjoint fields
     double* B = nullptr;        // nload x n_dof adjoint right-hand sides (stress)
     double* J = nullptr;        // nload
+    double* Phi = nullptr;      // n_dof, lowest mode (eigenvalue constraint)
+    double* SL = nullptr;       // n_elem, its eigenvalue field
     void release() {
         for (void* p : {(void*)rho, (void*)solid, (void*)S, (void*)raw, (void*)cur, (void*)src, (void*)best,
-                        (void*)cast, (void*)dist, (void*)F, (void*)UL, (void*)B, (void*)J})
+                        (void*)cast, (void*)dist, (void*)F, (void*)UL, (void*)B, (void*)J, (void*)Phi, (void*)SL})
             if (p) (void)afd::dev_free(p);
     }
 };
@@ -107,6 +110,11 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         set_error("levelset: the stress constraint needs nload <= 2 and pnorm_p >= 2");
         return AFD_E_INVALID_ARG;
     }
+    const bool eigen = o->alpha_lambda > 0.0;
+    if (eigen && !(o->alpha_lambda <= 1.0 && o->modal_tol > 0.0)) {
+        set_error("levelset: the eigenvalue constraint needs 0 < alpha_lambda <= 1 and modal_tol > 0");
+        return AFD_E_INVALID_ARG;
+    }
     // energy fields: without the stress constraint the nload strain-energy
     // fields; with it the afd_sensitivity layout of [U_0..U_n-1, L_0..L_n-1]
     // with the pairs (r, n + r): n strain energies, n adjoint self energies
@@ -123,7 +131,8 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         (rc = alloc(&dv.raw, ne)) || (rc = alloc(&dv.cur, ne)) || (rc = alloc(&dv.src, ne)) ||
         (rc = alloc(&dv.best, ne)) || (rc = alloc(&dv.cast, ne)) || (rc = alloc(&dv.dist, ne)) ||
         (rc = alloc(&dv.F, (size_t)nload * nd)) || (rc = alloc(&dv.UL, (size_t)(stress ? 2 : 1) * nload * nd)) ||
-        (stress && (rc = alloc(&dv.B, (size_t)nload * nd))) || (rc = alloc(&dv.J, nload)))
+        (stress && (rc = alloc(&dv.B, (size_t)nload * nd))) || (rc = alloc(&dv.J, nload)) ||
+        (eigen && ((rc = alloc(&dv.Phi, nd)) || (rc = alloc(&dv.SL, ne)))))
         return fail(rc);
     auto copy = [&](void* dst, const void* src_, size_t bytes, hipMemcpyKind kind) -> int {
         if (hipMemcpyAsync(dst, src_, bytes, kind, s) != hipSuccess) {
@@ -148,7 +157,8 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
     std::vector<uint8_t> solid_h(ne, 1), best_h(ne, 1);
     if ((rc = copy(dv.solid, solid_h.data(), ne, hipMemcpyHostToDevice))) return fail(rc);
     double mu = o->mu0, gamma = o->gamma0, mu_s = o->mu0, gamma_s = o->gamma0, step = o->dv0, v = 1.0;
-    double J0 = 0.0, S0 = 0.0, g_prev = 0.0, gs_prev = 0.0;
+    double mu_l = o->mu0, gamma_l = o->gamma0;
+    double J0 = 0.0, S0 = 0.0, L0 = 0.0, g_prev = 0.0, gs_prev = 0.0, gl_prev = 0.0;
     double J_prev_same = -1.0, v_best = 1.0;  // -1: no previous solve at this target
     int fp = 0;
     bool have_src = false;
@@ -176,6 +186,19 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
             if ((rc = afd_solve(m, &so, nload, dv.B, Lam, nullptr, nullptr, st2.data()))) return fail(rc);
             if ((rc = afd_sensitivity(m, 2 * nload, dv.UL, nload, pairs.data(), dv.S))) return fail(rc);
         }
+        double lam = 0.0;
+        int modal_cg = 0;
+        if (eigen) {
+            // the lowest eigenpair of the topology and its field (Eq. 3.4)
+            afd_solve_opts mo = o->solve;
+            mo.mem_kind = AFD_MEM_DEVICE;
+            mo.pairs = nullptr;
+            mo.npairs = 0;
+            mo.x0 = nullptr;
+            afd_modal_stats ms{};
+            if ((rc = afd_modal(m, &mo, 1, o->modal_tol, 200, &lam, dv.Phi, dv.SL, &ms))) return fail(rc);
+            modal_cg = ms.cg_iterations;
+        }
         if ((rc = copy(Jh.data(), dv.J, nload * sizeof(double), hipMemcpyDeviceToHost)) ||
             (rc = copy(solid_h.data(), dv.solid, ne, hipMemcpyDeviceToHost)))
             return fail(rc);
@@ -190,11 +213,12 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
             J += Jh[r];
             iters += st[r].iterations + (stress ? st2[r].iterations : 0);
         }
+        iters += modal_cg;
         int nsolid = 0;
         for (int64_t e = 0; e < ne; ++e) nsolid += solid_h[e];
         if (topo_hist) memcpy(topo_hist + (size_t)k * ne, solid_h.data(), ne);
         // step 3: constraint values and the multiplier / penalty updates
-        if (k == 0) J0 = J, S0 = Sp;
+        if (k == 0) J0 = J, S0 = Sp, L0 = lam;
         const double g = J / (o->alpha_J * J0) - 1.0;
         al_update(mu, gamma, g, g_prev, k, o->varsigma, o->eta);
         g_prev = g;
@@ -204,10 +228,16 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
             al_update(mu_s, gamma_s, g_s, gs_prev, k, o->varsigma, o->eta);
             gs_prev = g_s;
         }
+        double g_l = 0.0;
+        if (eigen) {
+            g_l = 1.0 - lam / (o->alpha_lambda * L0);
+            al_update(mu_l, gamma_l, g_l, gl_prev, k, o->varsigma, o->eta);
+            gl_prev = g_l;
+        }
         ++fp;
         const bool converged = J_prev_same >= 0.0 && std::fabs(J - J_prev_same) < o->conv_tol * J_prev_same;
         int event;
-        if (g > 0.0 || g_s > 0.0) event = AFD_LS_VIOLATED;      // step 4
+        if (g > 0.0 || g_s > 0.0 || g_l > 0.0) event = AFD_LS_VIOLATED;  // step 4
         else if (k == 0 || converged) event = AFD_LS_CONVERGED;  // step 7
         else if (fp >= o->max_fp) event = AFD_LS_DIVERGED;
         else event = AFD_LS_FIXED_POINT;
@@ -228,12 +258,23 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
             }
         } else {
             // steps 5-6: the augmented level set and the topology at the target
-            double w = std::max(mu + gamma * g, 0.0), w_s = std::max(mu_s + gamma_s * g_s, 0.0);
-            if (stress ? (w == 0.0 && w_s == 0.0) : w == 0.0) w = w_s = 1.0;
-            const double* grp[2] = {dv.S, dv.S + (size_t)2 * nload * ne};
-            const int32_t rows[2] = {nload, nload};
-            const double coef[2] = {w / (o->alpha_J * J0), stress ? w_s / (o->alpha_sigma * S0) : 0.0};
-            if ((rc = afd_combine_fields(ctx, ne, stress ? 2 : 1, grp, rows, coef, dv.raw))) return fail(rc);
+            // the active constraints in the order compliance, stress, eigenvalue
+            const double* grp[3];
+            int32_t rows[3];
+            double wgt[3], scale[3];
+            int nt = 0;
+            grp[nt] = dv.S, rows[nt] = nload, wgt[nt] = std::max(mu + gamma * g, 0.0), scale[nt++] = o->alpha_J * J0;
+            if (stress)
+                grp[nt] = dv.S + (size_t)2 * nload * ne, rows[nt] = nload,
+                wgt[nt] = std::max(mu_s + gamma_s * g_s, 0.0), scale[nt++] = o->alpha_sigma * S0;
+            if (eigen)
+                grp[nt] = dv.SL, rows[nt] = 1, wgt[nt] = std::max(mu_l + gamma_l * g_l, 0.0),
+                scale[nt++] = o->alpha_lambda * L0;
+            bool all_zero = true;
+            for (int i = 0; i < nt; ++i) all_zero = all_zero && wgt[i] == 0.0;
+            double coef[3];
+            for (int i = 0; i < nt; ++i) coef[i] = (all_zero ? 1.0 : wgt[i]) / scale[i];
+            if ((rc = afd_combine_fields(ctx, ne, nt, grp, rows, coef, dv.raw))) return fail(rc);
             double* cur = dv.raw;
             if (o->damping && have_src) {  // the mean with the level set this topology came from
                 const double* g2[2] = {dv.raw, dv.src};
@@ -277,6 +318,10 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         h.g_s = g_s;
         h.mu_s = stress ? mu_s : 0.0;
         h.gamma_s = stress ? gamma_s : 0.0;
+        h.lam = lam;
+        h.g_l = g_l;
+        h.mu_l = eigen ? mu_l : 0.0;
+        h.gamma_l = eigen ? gamma_l : 0.0;
         if (hipStreamSynchronize(s) != hipSuccess) {
             set_error("levelset: stream sync failed");
             return fail(AFD_E_HIP);

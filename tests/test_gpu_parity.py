@@ -976,6 +976,8 @@ def _levelset_lockstep(ctx, dims, loads, block, params, cast=(-1, 0)):
     afdcg.afd_mesh_destroy(m)
     assert code == afdcg.AFD_OK and hist[-1].event == afdcg.AFD_LS_TERMINATED
     Ke = fem.ke_gauss()
+    from oracle.modal import me_gauss
+    Me = me_gauss()
     loop = ls.Loop(dims, p)
     nxt = loop.first()
     mismatched = 0
@@ -993,13 +995,16 @@ def _levelset_lockstep(ctx, dims, loads, block, params, cast=(-1, 0)):
             mismatched += diff.size
         U = ls.fea(dims, s_k, fixed, F, Ke, p)
         J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
+        S = fS = lam = fL = None
         if p.alpha_sigma > 0:
             S, fS = ls.stress_quantities(dims, s_k, fixed, Ke, U, p)
-            nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p), S, fS)
             assert abs(rec.S - S) <= 1e-8 * S, (k, rec.S, S)
-        else:
-            nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p))
+        if p.alpha_lambda > 0:
+            lam, fL = ls.eigen_quantities(dims, s_k, fixed, Ke, Me, p)
+            assert abs(rec.lam - lam) <= 1e-8 * lam, (k, rec.lam, lam)
+        nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p), S, fS, lam, fL)
         o_rec = loop.history[-1]
+        assert abs(rec.mu_l - o_rec.mu_l) <= 1e-8 * max(1.0, o_rec.mu_l) and rec.gamma_l == o_rec.gamma_l, k
         assert abs(rec.J - J) <= 1e-8 * J, (k, rec.J, J)
         assert abs(rec.mu_s - o_rec.mu_s) <= 1e-8 * max(1.0, o_rec.mu_s) and rec.gamma_s == o_rec.gamma_s, k
         assert (rec.event, rec.v, rec.dv, rec.nsolid) == (o_rec.event, o_rec.v, o_rec.dv, o_rec.nsolid), (k, rec, o_rec)
@@ -1007,6 +1012,26 @@ def _levelset_lockstep(ctx, dims, loads, block, params, cast=(-1, 0)):
     assert len(loop.history) == len(hist) and loop.history[-1].event == ls.FEA_TERMINATED
     assert np.array_equal(solid, loop.best[0])  # the last converged feasible design
     return hist, solid, loop.best[0], mismatched
+
+
+def test_levelset_loop_with_eigen_constraint_matches_oracle(ctx):
+    # J <= 3 J0 and lambda_1 >= lambda_10 with damping, mid-span load: the
+    # eigenpair of every topology by subspace iteration on the GPU, by a
+    # dense eigensolver in the oracle; the eigenvalue bound stops a step; the
+    # unequal cross-section keeps the lowest eigenvalue simple (lambda_2 >=
+    # 1.22 lambda_1 along the run)
+    dims = (12, 6, 4)
+    f = np.zeros(3 * wl.n_nodes(dims))
+    for j in range(dims[1] + 1):
+        f[3 * wl.node_id(dims, dims[0] // 2, j, 0) + 2] = -1.0 / (dims[1] + 1)
+    params = dict(alpha_J=3.0, alpha_lambda=1.0, damping=True, dv_min=0.025 / 4)
+    hist, solid, b_solid, mism = _levelset_lockstep(ctx, dims, [f], (4, 4, 4), params)
+    conv = [r for r in hist if r.event == afdcg.AFD_LS_CONVERGED]
+    assert all(r.g <= 0 and r.g_l <= 0 for r in conv)
+    assert any(r.event == afdcg.AFD_LS_VIOLATED and r.g_l > 0 and r.g <= 0 for r in hist)
+    assert mism <= 2 * len(hist)
+    print(f"level-set loop with the eigenvalue bound 12x6x4: {len(hist)} solves, final volume {conv[-1].v:.4f}, "
+          f"lambda/lambda0 {conv[-1].lam / hist[0].lam:.3f}, {mism} elements inside tie bands")
 
 
 def test_levelset_loop_matches_oracle(ctx):

@@ -729,13 +729,14 @@ def _mid_span_load(dims):
 
 
 def test_levelset_loop_with_eigen_invariants():
-    # J <= 3 J0 and lambda_1 >= lambda_10 with damping on a 10x5x5 cantilever
-    # loaded at mid-span: the first volume steps take mass-dominated material
+    # J <= 3 J0 and lambda_1 >= lambda_10 with damping on a 12x6x4 cantilever
+    # (unequal cross-section: the lowest eigenvalue stays simple, lambda_2 >=
+    # 1.22 lambda_1 along the run) loaded at mid-span: the first volume steps take mass-dominated material
     # (T_lambda < 0, near the free end), so lambda_1 rises; later the
     # eigenvalue bound is the one that stops a step; every converged design
     # satisfies both constraints; mu_l / gamma_l follow Eq. 3.11-3.12
     from oracle import levelset as ls
-    dims = (10, 5, 5)
+    dims = (12, 6, 4)
     p = ls.Params(alpha_J=3.0, alpha_lambda=1.0, damping=True, dv_min=0.025 / 4)
     loop = ls.Loop(dims, p)
     (best, v, J), h = loop.run(wl.clamp_x0(dims), _mid_span_load(dims)[None])
