@@ -332,9 +332,20 @@ int stress_pnorm(const Grid& g, const double h[3], double E, double nu, const do
 // modal.hip: consistent mass apply and the subspace-iteration eigen-solver (see afd_apply_M, afd_modal)
 int mass_apply(const Grid& g, const double h[3], const double* rho, const uint8_t* nmask, int nrhs, const double* U,
                double* Y, hipStream_t s);
+// the subspace block of the eigen-solver between runs: 4 columns of n_dof
+// (device, owned by the caller), their Ritz values mu = 1 / lambda, and
+// whether they hold a run's result
+struct EigenBlock {
+    double* X = nullptr;
+    double mu[4] = {0.0, 0.0, 0.0, 0.0};
+    bool valid = false;
+};
 int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const double* rho, const uint8_t* nmask,
                    const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam_out, double* Phi,
-                   double* S, afd_modal_stats* st, hipStream_t s);
+                   double* S, afd_modal_stats* st, hipStream_t s, EigenBlock* block = nullptr);
+// afd_modal with a start block (see EigenBlock), for the optimisation loop
+int modal_with_block(afd_mesh* m, const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam,
+                     double* Phi, double* S, afd_modal_stats* st, EigenBlock* block);
 // geometric stiffness of the centroid stresses of U0 (see afd_apply_Kg, afd_buckling)
 int geo_apply(const Grid& g, const double h[3], double E, double nu, const double* rho, const uint8_t* nmask,
               const double* U0, int nrhs, const double* X, double* Y, hipStream_t s);

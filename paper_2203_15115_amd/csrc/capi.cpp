@@ -513,6 +513,23 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
 
 }  // namespace
 
+namespace afd {
+// afd_modal, optionally starting from (and handing back) the subspace block
+// of an earlier run
+int modal_with_block(afd_mesh* m, const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam,
+                     double* Phi, double* S, afd_modal_stats* st, EigenBlock* block) {
+    if (!m) {
+        set_error("modal: null mesh");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    if (st) memset(st, 0, sizeof(*st));
+    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
+    return modal_subspace(m, m->g, h, m->rho, m->nmask, inner, nev, tol, max_iter, lam, Phi, S, st, m->ctx->stream,
+                          block);
+}
+}  // namespace afd
+
 extern "C" {
 
 const char* afd_last_error(void) { return g_err.c_str(); }
@@ -1030,14 +1047,7 @@ int afd_apply_M(afd_mesh* m, int32_t nrhs, const double* U, double* Y) {
 
 int afd_modal(afd_mesh* m, const afd_solve_opts* inner, int32_t nev, double tol, int32_t max_iter, double* lam,
               double* Phi, double* S, afd_modal_stats* st) {
-    if (!m) {
-        set_error("modal: null mesh");
-        return AFD_E_INVALID_ARG;
-    }
-    AFD_TRY(check_ctx(m->ctx));
-    if (st) memset(st, 0, sizeof(*st));
-    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
-    return modal_subspace(m, m->g, h, m->rho, m->nmask, inner, nev, tol, max_iter, lam, Phi, S, st, m->ctx->stream);
+    return afd::modal_with_block(m, inner, nev, tol, max_iter, lam, Phi, S, st, nullptr);
 }
 
 int afd_apply_Kg(afd_mesh* m, const double* U0, int32_t nrhs, const double* X, double* Y) {

@@ -32,9 +32,11 @@ struct Dev {
     double* J = nullptr;        // nload
     double* Phi = nullptr;      // n_dof, lowest mode (eigenvalue constraint)
     double* SL = nullptr;       // n_elem, its eigenvalue field
+    double* XB = nullptr;       // 4 x n_dof, the eigen-solver's last Ritz block (start of the next one)
     void release() {
         for (void* p : {(void*)rho, (void*)solid, (void*)S, (void*)raw, (void*)cur, (void*)src, (void*)best,
-                        (void*)cast, (void*)dist, (void*)F, (void*)UL, (void*)B, (void*)J, (void*)Phi, (void*)SL})
+                        (void*)cast, (void*)dist, (void*)F, (void*)UL, (void*)B, (void*)J, (void*)Phi, (void*)SL,
+                        (void*)XB})
             if (p) (void)afd::dev_free(p);
     }
 };
@@ -132,7 +134,7 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         (rc = alloc(&dv.best, ne)) || (rc = alloc(&dv.cast, ne)) || (rc = alloc(&dv.dist, ne)) ||
         (rc = alloc(&dv.F, (size_t)nload * nd)) || (rc = alloc(&dv.UL, (size_t)(stress ? 2 : 1) * nload * nd)) ||
         (stress && (rc = alloc(&dv.B, (size_t)nload * nd))) || (rc = alloc(&dv.J, nload)) ||
-        (eigen && ((rc = alloc(&dv.Phi, nd)) || (rc = alloc(&dv.SL, ne)))))
+        (eigen && ((rc = alloc(&dv.Phi, nd)) || (rc = alloc(&dv.SL, ne)) || (rc = alloc(&dv.XB, 4 * nd)))))
         return fail(rc);
     auto copy = [&](void* dst, const void* src_, size_t bytes, hipMemcpyKind kind) -> int {
         if (hipMemcpyAsync(dst, src_, bytes, kind, s) != hipSuccess) {
@@ -163,6 +165,8 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
     int fp = 0;
     bool have_src = false;
     std::vector<afd_solve_stats> st(nload), st2(nload);
+    EigenBlock eig_block;  // each eigen-solve starts from the previous topology's Ritz block
+    eig_block.X = dv.XB;
     std::vector<double> Jh(nload);
     std::vector<int32_t> pairs(2 * nload);
     for (int r = 0; r < nload; ++r) pairs[2 * r] = r, pairs[2 * r + 1] = nload + r;
@@ -189,14 +193,16 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         double lam = 0.0;
         int modal_cg = 0;
         if (eigen) {
-            // the lowest eigenpair of the topology and its field (Eq. 3.4)
+            // the lowest eigenpair of the topology and its field (Eq. 3.4), the
+            // subspace iteration started from the previous topology's block
             afd_solve_opts mo = o->solve;
             mo.mem_kind = AFD_MEM_DEVICE;
             mo.pairs = nullptr;
             mo.npairs = 0;
             mo.x0 = nullptr;
             afd_modal_stats ms{};
-            if ((rc = afd_modal(m, &mo, 1, o->modal_tol, 200, &lam, dv.Phi, dv.SL, &ms))) return fail(rc);
+            if ((rc = modal_with_block(m, &mo, 1, o->modal_tol, 200, &lam, dv.Phi, dv.SL, &ms, &eig_block)))
+                return fail(rc);
             modal_cg = ms.cg_iterations;
         }
         if ((rc = copy(Jh.data(), dv.J, nload * sizeof(double), hipMemcpyDeviceToHost)) ||

@@ -470,23 +470,28 @@ struct Subspace {
 template <typename ApplyB>
 int subspace_largest(Subspace& sp, const Grid& g, const uint8_t* nmask, ApplyB applyB, const afd_solve_opts* inner,
                      int nev, double tol, int max_iter, double* X, double mu[BLK], double res[BLK], int& it, int& cg,
-                     bool& conv) {
+                     bool& conv, const EigenBlock* start) {
     hipStream_t s = sp.s;
-    hipLaunchKernelGGL(k_start_block, dim3((unsigned)((g.nnode + 255) / 256), BLK), dim3(256), 0, s, g.nnode, nmask,
-                       X);
-    AFD_HIP_TRY(hipGetLastError());
+    const bool warm = start && start->valid;
+    if (warm) {  // the block of an earlier run (e.g. of the previous topology of a loop)
+        AFD_HIP_TRY(hipMemcpyAsync(X, start->X, (size_t)BLK * g.ndof * 8, hipMemcpyDeviceToDevice, s));
+    } else {
+        hipLaunchKernelGGL(k_start_block, dim3((unsigned)((g.nnode + 255) / 256), BLK), dim3(256), 0, s, g.nnode,
+                           nmask, X);
+        AFD_HIP_TRY(hipGetLastError());
+    }
     afd_solve_opts so = *inner;
     so.mem_kind = AFD_MEM_DEVICE;
     so.pairs = nullptr;
     so.npairs = 0;
     std::vector<afd_solve_stats> ss(BLK);
-    for (int j = 0; j < BLK; ++j) mu[j] = 0.0, res[j] = 1.0;
+    for (int j = 0; j < BLK; ++j) mu[j] = warm ? start->mu[j] : 0.0, res[j] = 1.0;
     it = 0, cg = 0, conv = false;
     while (it < max_iter && !conv) {
         ++it;
         // Z = B X; Y = K^-1 Z, warm-started from X mu (K^-1 B x = mu x for an eigenpair)
         AFD_TRY(applyB(X, sp.Z));
-        if (it > 1) {
+        if (it > 1 || warm) {
             double D[BLK][BLK] = {};
             for (int j = 0; j < BLK; ++j) D[j][j] = mu[j];
             AFD_TRY(sp.lincomb(X, D, sp.Y));
@@ -570,7 +575,7 @@ int subspace_largest(Subspace& sp, const Grid& g, const uint8_t* nmask, ApplyB a
 
 int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const double* rho, const uint8_t* nmask,
                    const afd_solve_opts* inner, int nev, double tol, int max_iter, double* lam_out, double* Phi,
-                   double* S, afd_modal_stats* st, hipStream_t s) {
+                   double* S, afd_modal_stats* st, hipStream_t s, EigenBlock* block) {
     if (nev < 1 || nev > BLK - 1 || !(tol > 0) || max_iter < 1 || !lam_out || !Phi || !inner) {
         set_error("modal: nev 1..3, tol > 0, max_iter >= 1, non-null lambda, Phi, solve options");
         return AFD_E_INVALID_ARG;
@@ -598,8 +603,16 @@ int modal_subspace(afd_mesh* mesh, const Grid& g, const double h[3], const doubl
     int it = 0, cg = 0;
     bool conv = false;
     auto applyM = [&](const double* in, double* out) { return mass_apply(g, h, rho, nmask, BLK, in, out, s); };
-    if ((rc = subspace_largest(sp, g, nmask, applyM, inner, nev, tol, max_iter, X, mu, res, it, cg, conv)))
+    if ((rc = subspace_largest(sp, g, nmask, applyM, inner, nev, tol, max_iter, X, mu, res, it, cg, conv, block)))
         return done(rc);
+    if (block && block->X) {  // the K-orthonormal Ritz block and its values, for a later start
+        if (hipMemcpyAsync(block->X, X, (size_t)BLK * g.ndof * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            set_error("modal: copy of the Ritz block failed");
+            return done(AFD_E_HIP);
+        }
+        for (int j = 0; j < BLK; ++j) block->mu[j] = mu[j];
+        block->valid = true;
+    }
     // lambda = 1 / mu; phi = x / sqrt(mu) (M-normalised: x^T M x = mu x^T K x = mu)
     double D[BLK][BLK] = {};
     for (int j = 0; j < BLK; ++j) {
@@ -752,7 +765,8 @@ int buckling_subspace(afd_mesh* mesh, const Grid& g, const double h[3], double E
     double mu[BLK], res[BLK];
     int it = 0, cg = 0;
     bool conv = false;
-    if ((rc = subspace_largest(sp, g, nmask, applyNegKg, inner, nev, tol, max_iter, X, mu, res, it, cg, conv)))
+    if ((rc = subspace_largest(sp, g, nmask, applyNegKg, inner, nev, tol, max_iter, X, mu, res, it, cg, conv,
+                               nullptr)))
         return done(rc);
     double lam[BLK] = {0, 0, 0, 0};
     for (int j = 0; j < nev; ++j) {
