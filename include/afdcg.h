@@ -428,7 +428,8 @@ int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
  * (alpha_lambda lambda_10), its own mu_l, gamma_l by the same rules, and the
  * term w_l T_lambda / (alpha_lambda lambda_10) of the level set, T_lambda the
  * eigenvalue field of afd_modal (Eq. 3.4: the drop of lambda_1 when an
- * element loses stiffness and mass).
+ * element loses stiffness and mass); with lambda_soft it is a soft
+ * constraint (Sec. 3.6, Eq. 3.20-3.21): its violation does not count as one.
  * With damping the topology is extracted from the mean of the solve's level
  * set and the level set its topology was extracted from (a fixed point that
  * would alternate between two topologies settles).
@@ -467,6 +468,9 @@ typedef struct {
                                   lambda_10, 0 < alpha_lambda <= 1; <= 0: none   */
     double modal_tol;          /* Ritz residual of the eigenpair (e.g. 1e-9); its
                                   inner solves take the rtol of `solve`          */
+    int32_t lambda_soft;       /* 1: the eigenvalue constraint is soft (Sec. 3.6):
+                                  its term shapes the level set, its violation
+                                  neither steps back nor ends the loop          */
 } afd_levelset_opts;
 typedef struct {
     int32_t fea;               /* solve index                                    */

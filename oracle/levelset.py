@@ -51,6 +51,10 @@ Readings of the paper used here (it leaves these open):
   compliance and stress fields, the increase of g when e is removed.  A
   violated eigenvalue constraint is a hard violation; step 7's convergence
   test stays on the compliance.
+* Hard and soft constraints (Sec. 3.6, Eq. 3.20-3.21): a soft constraint
+  (here the eigenvalue one, lambda_soft) keeps its multiplier, penalty and
+  level-set term, but its violation neither sends the loop back nor ends it:
+  it shapes the topology without bounding the feasible space.
 * Topology at v (Eq. 3.6): the ceil(v nE) elements of highest T_L (ties by
   index; with the casting constraint of Sec. 3.7 the projected field, ties by
   the distance to the parting plane, then index); void elements get the
@@ -120,6 +124,7 @@ class Params:
     pnorm_p: float = 8.0
     damping: bool = False      # extract from the mean of this level set and the one the topology came from
     alpha_lambda: float = 0.0  # lambda_1 >= alpha_lambda lambda_10 (Eq. 3.21); <= 0: no eigenvalue constraint
+    lambda_soft: bool = False  # the eigenvalue constraint as a soft one (Sec. 3.6)
 
 
 @dataclasses.dataclass
@@ -243,7 +248,7 @@ class Loop:
             self.mu_l, self.gamma_l = al_update(self.mu_l, self.gamma_l, g_l, self.gl_prev, k, p.varsigma, p.eta)
             self.gl_prev = g_l
         self.fp += 1
-        if g > 0.0 or g_s > 0.0 or g_l > 0.0:
+        if g > 0.0 or g_s > 0.0 or (g_l > 0.0 and not p.lambda_soft):
             event = FEA_VIOLATED
         elif k == 0 or self._converged(J):
             event = FEA_CONVERGED

@@ -243,7 +243,7 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         ++fp;
         const bool converged = J_prev_same >= 0.0 && std::fabs(J - J_prev_same) < o->conv_tol * J_prev_same;
         int event;
-        if (g > 0.0 || g_s > 0.0 || g_l > 0.0) event = AFD_LS_VIOLATED;  // step 4
+        if (g > 0.0 || g_s > 0.0 || (g_l > 0.0 && !o->lambda_soft)) event = AFD_LS_VIOLATED;  // step 4 (hard)
         else if (k == 0 || converged) event = AFD_LS_CONVERGED;  // step 7
         else if (fp >= o->max_fp) event = AFD_LS_DIVERGED;
         else event = AFD_LS_FIXED_POINT;

@@ -752,6 +752,16 @@ def test_levelset_loop_with_eigen_invariants():
         g_old = r.g_l
         assert abs(mu - r.mu_l) <= 1e-12 * max(1.0, mu) and gamma == r.gamma_l, k
     assert conv[-1].v < 0.85 and h[-1].event == ls.FEA_TERMINATED
+    # the same bound as a soft constraint (Sec. 3.6): it still shapes the
+    # topology (the first steps are those of the hard run) but never stops a
+    # step (only the compliance bound does), so the run goes deeper
+    ps = ls.Params(alpha_J=3.0, alpha_lambda=1.0, lambda_soft=True, damping=True, dv_min=0.025 / 4)
+    (best_s, v_s, J_s), hs = ls.Loop(dims, ps).run(wl.clamp_x0(dims), _mid_span_load(dims)[None])
+    assert not any(r.event == ls.FEA_VIOLATED and r.g <= 0 for r in hs)
+    assert any(r.g_l > 0 and r.g <= 0 and r.event != ls.FEA_VIOLATED for r in hs)
+    conv_s = [r for r in hs if r.event == ls.FEA_CONVERGED]
+    assert [r.nsolid for r in conv_s[:4]] == [r.nsolid for r in conv[:4]]
+    assert conv_s[-1].v < conv[-1].v
 
 
 # ------------------------------------------------------------- modal analysis (Eq. 3.4, 3.21)
