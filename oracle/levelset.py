@@ -51,8 +51,15 @@ Readings of the paper used here (it leaves these open):
   compliance and stress fields, the increase of g when e is removed.  A
   violated eigenvalue constraint is a hard violation; step 7's convergence
   test stays on the compliance.
+* With the buckling constraint P >= alpha_P P_0 (Eq. 3.21) a further term
+  joins in the same way: P the smallest positive load factor of the stress
+  state of load case 0 (buckling.py: the ersatz void carries no stress
+  stiffness), g_p = 1 - P / (alpha_P P_0), its own mu_p and gamma_p, the
+  field T_P / (alpha_P P_0) with T_P the load-factor field of buckling.py
+  (the drop of P when an element loses stiffness, its prebuckling stress
+  scaled with it).
 * Hard and soft constraints (Sec. 3.6, Eq. 3.20-3.21): a soft constraint
-  (here the eigenvalue one, lambda_soft) keeps its multiplier, penalty and
+  (the eigenvalue one with lambda_soft, the buckling one with P_soft) keeps its multiplier, penalty and
   level-set term, but its violation neither sends the loop back nor ends it:
   it shapes the topology without bounding the feasible space.
 * Topology at v (Eq. 3.6): the ceil(v nE) elements of highest T_L (ties by
@@ -67,7 +74,7 @@ import math
 
 import numpy as np
 
-from . import fem, modal, post, solvers, stress
+from . import buckling, fem, modal, post, solvers, stress
 from .casting import cast_project, parting_distance
 
 FEA_FIXED_POINT = 0   # a fixed-point solve at the current target
@@ -125,6 +132,8 @@ class Params:
     damping: bool = False      # extract from the mean of this level set and the one the topology came from
     alpha_lambda: float = 0.0  # lambda_1 >= alpha_lambda lambda_10 (Eq. 3.21); <= 0: no eigenvalue constraint
     lambda_soft: bool = False  # the eigenvalue constraint as a soft one (Sec. 3.6)
+    alpha_P: float = 0.0       # P >= alpha_P P_0 (Eq. 3.21), load case 0; <= 0: no buckling constraint
+    P_soft: bool = False       # the buckling constraint as a soft one
 
 
 @dataclasses.dataclass
@@ -146,6 +155,10 @@ class Record:
     g_l: float = 0.0
     mu_l: float = 0.0
     gamma_l: float = 0.0
+    P: float = 0.0    # smallest buckling load factor (0 without the buckling constraint)
+    g_p: float = 0.0
+    mu_p: float = 0.0
+    gamma_p: float = 0.0
 
 
 def extract(field, vol, dims, p: Params):
@@ -193,6 +206,15 @@ def eigen_quantities(dims, solid, fixed, Ke, Me, p: Params):
     return float(lam[0]), modal.eigen_sensitivity(dims, rho, Ke, Me, lam[0], Phi[0])
 
 
+def buckling_quantities(dims, solid, fixed, Ke, U, p: Params):
+    """The smallest buckling load factor of load case 0 and its field."""
+    rho = density(solid, p)
+    sig = buckling.prebuckling_stress(dims, rho, U[0])
+    K = fem.assemble(dims, rho, Ke)
+    lam, Phi = buckling.buckling_modes(K, buckling.assemble_kg(dims, sig), fixed, 1)
+    return float(lam[0]), buckling.buckling_sensitivity(dims, rho, Ke, sig, lam[0], Phi[0])
+
+
 class Loop:
     """The loop as a state machine: ``first()`` gives the full domain; after
     each solve, ``after_solve(solid, J, field)`` records it and returns the
@@ -208,6 +230,9 @@ class Loop:
         self.mu_l, self.gamma_l = p.mu0, p.gamma0
         self.L0 = None
         self.gl_prev = None
+        self.mu_p, self.gamma_p = p.mu0, p.gamma0
+        self.P0 = None
+        self.gp_prev = None
         self.dv = p.dv0
         self.k = 0
         self.J0 = None
@@ -225,15 +250,17 @@ class Loop:
     def first(self):
         return np.ones(self.n, dtype=np.uint8)
 
-    def after_solve(self, solid, J, field_J, S=None, field_S=None, lam=None, field_lam=None):
+    def after_solve(self, solid, J, field_J, S=None, field_S=None, lam=None, field_lam=None, P=None, field_P=None):
         p = self.p
         k, v = self.k, self.v
         stress = p.alpha_sigma > 0
         eigen = p.alpha_lambda > 0
+        buck = p.alpha_P > 0
         if k == 0:
             self.J0 = J
             self.S0 = S
             self.L0 = lam
+            self.P0 = P
         g = J / (p.alpha_J * self.J0) - 1.0
         mu, gamma = al_update(self.mu, self.gamma, g, self.g_prev, k, p.varsigma, p.eta)
         self.mu, self.gamma, self.g_prev = mu, gamma, g
@@ -247,8 +274,13 @@ class Loop:
             g_l = 1.0 - lam / (p.alpha_lambda * self.L0)
             self.mu_l, self.gamma_l = al_update(self.mu_l, self.gamma_l, g_l, self.gl_prev, k, p.varsigma, p.eta)
             self.gl_prev = g_l
+        g_p = 0.0
+        if buck:
+            g_p = 1.0 - P / (p.alpha_P * self.P0)
+            self.mu_p, self.gamma_p = al_update(self.mu_p, self.gamma_p, g_p, self.gp_prev, k, p.varsigma, p.eta)
+            self.gp_prev = g_p
         self.fp += 1
-        if g > 0.0 or g_s > 0.0 or (g_l > 0.0 and not p.lambda_soft):
+        if g > 0.0 or g_s > 0.0 or (g_l > 0.0 and not p.lambda_soft) or (g_p > 0.0 and not p.P_soft):
             event = FEA_VIOLATED
         elif k == 0 or self._converged(J):
             event = FEA_CONVERGED
@@ -269,7 +301,7 @@ class Loop:
                 nxt = extract(self.best[3], self.v, self.dims, p)
         else:
             # steps 5-6: the augmented level set and the topology extracted from it
-            # the active constraints in the order J, stress, eigenvalue
+            # the active constraints in the order J, stress, eigenvalue, buckling
             mus, gammas, gs, fields, scales = [mu], [gamma], [g], [field_J], [p.alpha_J * self.J0]
             if stress:
                 mus.append(self.mu_s), gammas.append(self.gamma_s), gs.append(g_s)
@@ -277,6 +309,9 @@ class Loop:
             if eigen:
                 mus.append(self.mu_l), gammas.append(self.gamma_l), gs.append(g_l)
                 fields.append(field_lam), scales.append(p.alpha_lambda * self.L0)
+            if buck:
+                mus.append(self.mu_p), gammas.append(self.gamma_p), gs.append(g_p)
+                fields.append(field_P), scales.append(p.alpha_P * self.P0)
             w = weights(mus, gammas, gs)
             field = combined_field(fields, [wi / sc for wi, sc in zip(w, scales)])
             if p.damping and self.src is not None:
@@ -298,7 +333,9 @@ class Loop:
         self.history.append(Record(k, event, v, int(solid.sum()), J, g, mu, gamma, self.dv,
                                    S if stress else 0.0, g_s, self.mu_s if stress else 0.0,
                                    self.gamma_s if stress else 0.0, lam if eigen else 0.0, g_l,
-                                   self.mu_l if eigen else 0.0, self.gamma_l if eigen else 0.0))
+                                   self.mu_l if eigen else 0.0, self.gamma_l if eigen else 0.0,
+                                   P if buck else 0.0, g_p, self.mu_p if buck else 0.0,
+                                   self.gamma_p if buck else 0.0))
         self.k += 1
         if self.k >= p.max_fea:
             nxt = None
@@ -322,11 +359,13 @@ class Loop:
             U = fea(self.dims, solid, fixed, F, Ke, self.p)
             J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
             fJ = compliance_field(self.dims, solid, Ke, U, self.p)
-            S = fS = lam = fL = None
+            S = fS = lam = fL = P = fP = None
             if self.p.alpha_sigma > 0:
                 S, fS = stress_quantities(self.dims, solid, fixed, Ke, U, self.p)
             if self.p.alpha_lambda > 0:
                 lam, fL = eigen_quantities(self.dims, solid, fixed, Ke, Me, self.p)
-            solid = self.after_solve(solid, J, fJ, S, fS, lam, fL)
+            if self.p.alpha_P > 0:
+                P, fP = buckling_quantities(self.dims, solid, fixed, Ke, U, self.p)
+            solid = self.after_solve(solid, J, fJ, S, fS, lam, fL, P, fP)
         b = self.best
         return (b[0], b[1], b[2]), self.history

@@ -764,6 +764,42 @@ def test_levelset_loop_with_eigen_invariants():
     assert conv_s[-1].v < conv[-1].v
 
 
+def test_levelset_loop_with_buckling_invariants():
+    # J <= 3 J0 and P >= 0.8 P0 with damping on an axially compressed 12x6x4
+    # cantilever (plus a mid-edge load): every removal lowers the load
+    # factor; the first volume step takes elements of small T_P (a field of
+    # the wrong sign would take the critical ones and lose far more); the
+    # buckling bound stops a step; mu_p / gamma_p follow Eq. 3.11-3.12; as a
+    # soft bound it is exceeded without a step back and the run goes deeper
+    from oracle import levelset as ls
+    dims = (12, 6, 4)
+    F = wl.edge_load(dims, "mid")
+    for j in range(dims[1] + 1):
+        for k in range(dims[2] + 1):
+            F[3 * wl.node_id(dims, dims[0], j, k)] -= 1.0 / ((dims[1] + 1) * (dims[2] + 1))
+    runs = {}
+    for soft in (False, True):
+        p = ls.Params(alpha_J=3.0, alpha_P=0.8, P_soft=soft, damping=True, dv_min=0.025 / 4)
+        runs[soft] = (p, ls.Loop(dims, p).run(wl.clamp_x0(dims), F[None])[1])
+    p, h = runs[False]
+    P0 = h[0].P
+    assert P0 > 0 and abs(h[0].g_p - (1 - 1 / 0.8)) < 1e-15
+    conv = [r for r in h if r.event == ls.FEA_CONVERGED]
+    assert all(r.g <= 0 and r.g_p <= 0 and r.P >= 0.8 * P0 for r in conv)
+    assert 0.9 * P0 < conv[1].P < P0
+    assert any(r.event == ls.FEA_VIOLATED and r.g_p > 0 and r.g <= 0 for r in h)
+    mu, gamma, g_old = p.mu0, p.gamma0, None
+    for k, r in enumerate(h):
+        mu, gamma = ls.al_update(mu, gamma, r.g_p, g_old, k, p.varsigma, p.eta)
+        g_old = r.g_p
+        assert abs(mu - r.mu_p) <= 1e-12 * max(1.0, mu) and gamma == r.gamma_p, k
+    ps, hs = runs[True]
+    assert not any(r.event == ls.FEA_VIOLATED and r.g <= 0 for r in hs)
+    assert any(r.g_p > 0 and r.g <= 0 and r.event != ls.FEA_VIOLATED for r in hs)
+    conv_s = [r for r in hs if r.event == ls.FEA_CONVERGED]
+    assert conv_s[-1].v < conv[-1].v
+
+
 # ------------------------------------------------------------- modal analysis (Eq. 3.4, 3.21)
 def test_mass_matrix_exact_and_quadrature():
     from oracle.modal import me_exact, me_gauss
