@@ -430,6 +430,12 @@ int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
  * eigenvalue field of afd_modal (Eq. 3.4: the drop of lambda_1 when an
  * element loses stiffness and mass); with lambda_soft it is a soft
  * constraint (Sec. 3.6, Eq. 3.20-3.21): its violation does not count as one.
+ * With alpha_P > 0 the smallest buckling load factor P of load case 0's
+ * stress state joins the same way (afd_buckling on each topology):
+ * P >= alpha_P P_0, g_p = 1 - P / (alpha_P P_0), mu_p, gamma_p, the term
+ * w_p T_P / (alpha_P P_0) with T_P the load-factor field of afd_buckling;
+ * P_soft makes it soft.  The eigen-solves of each step start from the Ritz
+ * block of the previous step.
  * With damping the topology is extracted from the mean of the solve's level
  * set and the level set its topology was extracted from (a fixed point that
  * would alternate between two topologies settles).
@@ -471,6 +477,9 @@ typedef struct {
     int32_t lambda_soft;       /* 1: the eigenvalue constraint is soft (Sec. 3.6):
                                   its term shapes the level set, its violation
                                   neither steps back nor ends the loop          */
+    double alpha_P;            /* buckling constraint P >= alpha_P P_0 (load case
+                                  0), 0 < alpha_P <= 1; <= 0: none              */
+    int32_t P_soft;            /* 1: the buckling constraint is soft            */
 } afd_levelset_opts;
 typedef struct {
     int32_t fea;               /* solve index                                    */
@@ -488,6 +497,8 @@ typedef struct {
                                   multiplier and penalty (0 without it)         */
     double lam, g_l, mu_l, gamma_l; /* lowest eigenvalue, its constraint value,
                                   multiplier and penalty (0 without it)         */
+    double P, g_p, mu_p, gamma_p; /* smallest buckling load factor, its
+                                  constraint value, multiplier and penalty     */
 } afd_levelset_record;
 int afd_levelset_run(afd_mesh* mesh, const afd_levelset_opts* opts, int32_t nload, const double* F,
                      uint8_t* solid, afd_levelset_record* hist, int32_t hist_cap, int32_t* n_hist,

@@ -81,7 +81,8 @@ class afd_levelset_opts(C.Structure):
                 ("max_fp", C.c_int32), ("max_fea", C.c_int32), ("void_scale", C.c_double),
                 ("cast_axis", C.c_int32), ("cast_parting", C.c_int32), ("alpha_sigma", C.c_double),
                 ("pnorm_p", C.c_double), ("damping", C.c_int32), ("solve", afd_solve_opts),
-                ("alpha_lambda", C.c_double), ("modal_tol", C.c_double), ("lambda_soft", C.c_int32)]
+                ("alpha_lambda", C.c_double), ("modal_tol", C.c_double), ("lambda_soft", C.c_int32),
+                ("alpha_P", C.c_double), ("P_soft", C.c_int32)]
 
 
 class afd_levelset_record(C.Structure):
@@ -89,7 +90,8 @@ class afd_levelset_record(C.Structure):
                 ("v", C.c_double), ("J", C.c_double), ("g", C.c_double), ("mu", C.c_double),
                 ("gamma", C.c_double), ("dv", C.c_double), ("t_fea", C.c_double), ("t_total", C.c_double),
                 ("S", C.c_double), ("g_s", C.c_double), ("mu_s", C.c_double), ("gamma_s", C.c_double),
-                ("lam", C.c_double), ("g_l", C.c_double), ("mu_l", C.c_double), ("gamma_l", C.c_double)]
+                ("lam", C.c_double), ("g_l", C.c_double), ("mu_l", C.c_double), ("gamma_l", C.c_double),
+                ("P", C.c_double), ("g_p", C.c_double), ("mu_p", C.c_double), ("gamma_p", C.c_double)]
 
 
 AFD_LS_FIXED_POINT, AFD_LS_CONVERGED, AFD_LS_VIOLATED, AFD_LS_DIVERGED, AFD_LS_TERMINATED = 0, 1, 2, 3, 4
@@ -421,12 +423,13 @@ def afd_combine_fields(ctx, n, groups, coef, out):
 def make_levelset_opts(alpha_J=3.0, dv0=0.025, dv_min=0.025 / 16, mu0=100.0, gamma0=10.0, varsigma=0.25, eta=10.0,
                        conv_tol=0.01, max_fp=8, max_fea=400, void_scale=1e-3, cast_axis=-1, cast_parting=0,
                        alpha_sigma=0.0, pnorm_p=8.0, damping=False, alpha_lambda=0.0, modal_tol=1e-9,
-                       lambda_soft=False, **solvekw):
+                       lambda_soft=False, alpha_P=0.0, P_soft=False, **solvekw):
     so = make_opts(**solvekw)
     o = afd_levelset_opts(float(alpha_J), float(dv0), float(dv_min), float(mu0), float(gamma0), float(varsigma),
                           float(eta), float(conv_tol), int(max_fp), int(max_fea), float(void_scale), int(cast_axis),
                           int(cast_parting), float(alpha_sigma), float(pnorm_p), 1 if damping else 0, so,
-                          float(alpha_lambda), float(modal_tol), 1 if lambda_soft else 0)
+                          float(alpha_lambda), float(modal_tol), 1 if lambda_soft else 0, float(alpha_P),
+                          1 if P_soft else 0)
     o._keep = so._keep
     return o
 

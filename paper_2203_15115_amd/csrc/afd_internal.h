@@ -351,7 +351,11 @@ int geo_apply(const Grid& g, const double h[3], double E, double nu, const doubl
               const double* U0, int nrhs, const double* X, double* Y, hipStream_t s);
 int buckling_subspace(afd_mesh* mesh, const Grid& g, const double h[3], double E, double nu, const double* rho,
                       const uint8_t* nmask, const double* U, const afd_solve_opts* inner, int nev, double tol,
-                      int max_iter, double* lam_out, double* Phi, double* S, afd_modal_stats* st, hipStream_t s);
+                      int max_iter, double* lam_out, double* Phi, double* S, afd_modal_stats* st, hipStream_t s,
+                      EigenBlock* block = nullptr);
+// afd_buckling with a start block (see EigenBlock), for the optimisation loop
+int buckling_with_block(afd_mesh* m, const double* U, const afd_solve_opts* inner, int nev, double tol, int max_iter,
+                        double* lam, double* Phi, double* S, afd_modal_stats* st, EigenBlock* block);
 // rho[e] = solid[e] ? 1 : void_scale
 int launch_density(int64_t n, const uint8_t* solid, double void_scale, double* rho, hipStream_t s);
 // ranking and threshold (see afd_threshold): threshold_run on a caller-given

@@ -528,6 +528,19 @@ int modal_with_block(afd_mesh* m, const afd_solve_opts* inner, int nev, double t
     return modal_subspace(m, m->g, h, m->rho, m->nmask, inner, nev, tol, max_iter, lam, Phi, S, st, m->ctx->stream,
                           block);
 }
+// afd_buckling, optionally starting from (and handing back) a subspace block
+int buckling_with_block(afd_mesh* m, const double* U, const afd_solve_opts* inner, int nev, double tol, int max_iter,
+                        double* lam, double* Phi, double* S, afd_modal_stats* st, EigenBlock* block) {
+    if (!m) {
+        set_error("buckling: null mesh");
+        return AFD_E_INVALID_ARG;
+    }
+    AFD_TRY(check_ctx(m->ctx));
+    if (st) memset(st, 0, sizeof(*st));
+    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
+    return buckling_subspace(m, m->g, h, m->desc.E, m->desc.nu, m->rho, m->nmask, U, inner, nev, tol, max_iter, lam,
+                             Phi, S, st, m->ctx->stream, block);
+}
 }  // namespace afd
 
 extern "C" {
@@ -1062,15 +1075,7 @@ int afd_apply_Kg(afd_mesh* m, const double* U0, int32_t nrhs, const double* X, d
 
 int afd_buckling(afd_mesh* m, const double* U, const afd_solve_opts* inner, int32_t nev, double tol,
                  int32_t max_iter, double* lam, double* Phi, double* S, afd_modal_stats* st) {
-    if (!m) {
-        set_error("buckling: null mesh");
-        return AFD_E_INVALID_ARG;
-    }
-    AFD_TRY(check_ctx(m->ctx));
-    if (st) memset(st, 0, sizeof(*st));
-    const double h[3] = {m->desc.hx, m->desc.hy, m->desc.hz};
-    return buckling_subspace(m, m->g, h, m->desc.E, m->desc.nu, m->rho, m->nmask, U, inner, nev, tol, max_iter, lam,
-                             Phi, S, st, m->ctx->stream);
+    return afd::buckling_with_block(m, U, inner, nev, tol, max_iter, lam, Phi, S, st, nullptr);
 }
 
 int afd_stress_pnorm(afd_mesh* m, int32_t nrhs, const double* U, double p, double* vm, double* pn, double* B) {

@@ -33,10 +33,13 @@ struct Dev {
     double* Phi = nullptr;      // n_dof, lowest mode (eigenvalue constraint)
     double* SL = nullptr;       // n_elem, its eigenvalue field
     double* XB = nullptr;       // 4 x n_dof, the eigen-solver's last Ritz block (start of the next one)
+    double* PhiB = nullptr;     // n_dof, buckling mode (buckling constraint)
+    double* SP = nullptr;       // n_elem, its load-factor field
+    double* XBB = nullptr;      // 4 x n_dof, the buckling solver's last Ritz block
     void release() {
         for (void* p : {(void*)rho, (void*)solid, (void*)S, (void*)raw, (void*)cur, (void*)src, (void*)best,
                         (void*)cast, (void*)dist, (void*)F, (void*)UL, (void*)B, (void*)J, (void*)Phi, (void*)SL,
-                        (void*)XB})
+                        (void*)XB, (void*)PhiB, (void*)SP, (void*)XBB})
             if (p) (void)afd::dev_free(p);
     }
 };
@@ -117,6 +120,11 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         set_error("levelset: the eigenvalue constraint needs 0 < alpha_lambda <= 1 and modal_tol > 0");
         return AFD_E_INVALID_ARG;
     }
+    const bool buck = o->alpha_P > 0.0;
+    if (buck && !(o->alpha_P <= 1.0 && o->modal_tol > 0.0)) {
+        set_error("levelset: the buckling constraint needs 0 < alpha_P <= 1 and modal_tol > 0");
+        return AFD_E_INVALID_ARG;
+    }
     // energy fields: without the stress constraint the nload strain-energy
     // fields; with it the afd_sensitivity layout of [U_0..U_n-1, L_0..L_n-1]
     // with the pairs (r, n + r): n strain energies, n adjoint self energies
@@ -134,7 +142,8 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         (rc = alloc(&dv.best, ne)) || (rc = alloc(&dv.cast, ne)) || (rc = alloc(&dv.dist, ne)) ||
         (rc = alloc(&dv.F, (size_t)nload * nd)) || (rc = alloc(&dv.UL, (size_t)(stress ? 2 : 1) * nload * nd)) ||
         (stress && (rc = alloc(&dv.B, (size_t)nload * nd))) || (rc = alloc(&dv.J, nload)) ||
-        (eigen && ((rc = alloc(&dv.Phi, nd)) || (rc = alloc(&dv.SL, ne)) || (rc = alloc(&dv.XB, 4 * nd)))))
+        (eigen && ((rc = alloc(&dv.Phi, nd)) || (rc = alloc(&dv.SL, ne)) || (rc = alloc(&dv.XB, 4 * nd)))) ||
+        (buck && ((rc = alloc(&dv.PhiB, nd)) || (rc = alloc(&dv.SP, ne)) || (rc = alloc(&dv.XBB, 4 * nd)))))
         return fail(rc);
     auto copy = [&](void* dst, const void* src_, size_t bytes, hipMemcpyKind kind) -> int {
         if (hipMemcpyAsync(dst, src_, bytes, kind, s) != hipSuccess) {
@@ -159,14 +168,15 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
     std::vector<uint8_t> solid_h(ne, 1), best_h(ne, 1);
     if ((rc = copy(dv.solid, solid_h.data(), ne, hipMemcpyHostToDevice))) return fail(rc);
     double mu = o->mu0, gamma = o->gamma0, mu_s = o->mu0, gamma_s = o->gamma0, step = o->dv0, v = 1.0;
-    double mu_l = o->mu0, gamma_l = o->gamma0;
-    double J0 = 0.0, S0 = 0.0, L0 = 0.0, g_prev = 0.0, gs_prev = 0.0, gl_prev = 0.0;
+    double mu_l = o->mu0, gamma_l = o->gamma0, mu_p = o->mu0, gamma_p = o->gamma0;
+    double J0 = 0.0, S0 = 0.0, L0 = 0.0, P0 = 0.0, g_prev = 0.0, gs_prev = 0.0, gl_prev = 0.0, gp_prev = 0.0;
     double J_prev_same = -1.0, v_best = 1.0;  // -1: no previous solve at this target
     int fp = 0;
     bool have_src = false;
     std::vector<afd_solve_stats> st(nload), st2(nload);
-    EigenBlock eig_block;  // each eigen-solve starts from the previous topology's Ritz block
+    EigenBlock eig_block, buck_block;  // each eigen-solve starts from the previous topology's Ritz block
     eig_block.X = dv.XB;
+    buck_block.X = dv.XBB;
     std::vector<double> Jh(nload);
     std::vector<int32_t> pairs(2 * nload);
     for (int r = 0; r < nload; ++r) pairs[2 * r] = r, pairs[2 * r + 1] = nload + r;
@@ -205,6 +215,20 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
                 return fail(rc);
             modal_cg = ms.cg_iterations;
         }
+        double Pb = 0.0;
+        if (buck) {
+            // the smallest buckling load factor of load case 0 and its field (Eq. 3.5)
+            afd_solve_opts bo = o->solve;
+            bo.mem_kind = AFD_MEM_DEVICE;
+            bo.pairs = nullptr;
+            bo.npairs = 0;
+            bo.x0 = nullptr;
+            afd_modal_stats bs{};
+            if ((rc = buckling_with_block(m, dv.UL, &bo, 1, o->modal_tol, 200, &Pb, dv.PhiB, dv.SP, &bs,
+                                          &buck_block)))
+                return fail(rc);
+            modal_cg += bs.cg_iterations;
+        }
         if ((rc = copy(Jh.data(), dv.J, nload * sizeof(double), hipMemcpyDeviceToHost)) ||
             (rc = copy(solid_h.data(), dv.solid, ne, hipMemcpyDeviceToHost)))
             return fail(rc);
@@ -224,7 +248,7 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         for (int64_t e = 0; e < ne; ++e) nsolid += solid_h[e];
         if (topo_hist) memcpy(topo_hist + (size_t)k * ne, solid_h.data(), ne);
         // step 3: constraint values and the multiplier / penalty updates
-        if (k == 0) J0 = J, S0 = Sp, L0 = lam;
+        if (k == 0) J0 = J, S0 = Sp, L0 = lam, P0 = Pb;
         const double g = J / (o->alpha_J * J0) - 1.0;
         al_update(mu, gamma, g, g_prev, k, o->varsigma, o->eta);
         g_prev = g;
@@ -240,10 +264,17 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
             al_update(mu_l, gamma_l, g_l, gl_prev, k, o->varsigma, o->eta);
             gl_prev = g_l;
         }
+        double g_p = 0.0;
+        if (buck) {
+            g_p = 1.0 - Pb / (o->alpha_P * P0);
+            al_update(mu_p, gamma_p, g_p, gp_prev, k, o->varsigma, o->eta);
+            gp_prev = g_p;
+        }
         ++fp;
         const bool converged = J_prev_same >= 0.0 && std::fabs(J - J_prev_same) < o->conv_tol * J_prev_same;
         int event;
-        if (g > 0.0 || g_s > 0.0 || (g_l > 0.0 && !o->lambda_soft)) event = AFD_LS_VIOLATED;  // step 4 (hard)
+        if (g > 0.0 || g_s > 0.0 || (g_l > 0.0 && !o->lambda_soft) || (g_p > 0.0 && !o->P_soft))
+            event = AFD_LS_VIOLATED;  // step 4: a hard constraint violated
         else if (k == 0 || converged) event = AFD_LS_CONVERGED;  // step 7
         else if (fp >= o->max_fp) event = AFD_LS_DIVERGED;
         else event = AFD_LS_FIXED_POINT;
@@ -264,10 +295,10 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
             }
         } else {
             // steps 5-6: the augmented level set and the topology at the target
-            // the active constraints in the order compliance, stress, eigenvalue
-            const double* grp[3];
-            int32_t rows[3];
-            double wgt[3], scale[3];
+            // the active constraints in the order compliance, stress, eigenvalue, buckling
+            const double* grp[4];
+            int32_t rows[4];
+            double wgt[4], scale[4];
             int nt = 0;
             grp[nt] = dv.S, rows[nt] = nload, wgt[nt] = std::max(mu + gamma * g, 0.0), scale[nt++] = o->alpha_J * J0;
             if (stress)
@@ -276,9 +307,12 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
             if (eigen)
                 grp[nt] = dv.SL, rows[nt] = 1, wgt[nt] = std::max(mu_l + gamma_l * g_l, 0.0),
                 scale[nt++] = o->alpha_lambda * L0;
+            if (buck)
+                grp[nt] = dv.SP, rows[nt] = 1, wgt[nt] = std::max(mu_p + gamma_p * g_p, 0.0),
+                scale[nt++] = o->alpha_P * P0;
             bool all_zero = true;
             for (int i = 0; i < nt; ++i) all_zero = all_zero && wgt[i] == 0.0;
-            double coef[3];
+            double coef[4];
             for (int i = 0; i < nt; ++i) coef[i] = (all_zero ? 1.0 : wgt[i]) / scale[i];
             if ((rc = afd_combine_fields(ctx, ne, nt, grp, rows, coef, dv.raw))) return fail(rc);
             double* cur = dv.raw;
@@ -328,6 +362,10 @@ extern "C" int afd_levelset_run(afd_mesh* m, const afd_levelset_opts* o, int32_t
         h.g_l = g_l;
         h.mu_l = eigen ? mu_l : 0.0;
         h.gamma_l = eigen ? gamma_l : 0.0;
+        h.P = Pb;
+        h.g_p = g_p;
+        h.mu_p = buck ? mu_p : 0.0;
+        h.gamma_p = buck ? gamma_p : 0.0;
         if (hipStreamSynchronize(s) != hipSuccess) {
             set_error("levelset: stream sync failed");
             return fail(AFD_E_HIP);

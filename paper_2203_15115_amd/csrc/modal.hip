@@ -713,7 +713,8 @@ int geo_apply(const Grid& g, const double h[3], double E, double nu, const doubl
 
 int buckling_subspace(afd_mesh* mesh, const Grid& g, const double h[3], double E, double nu, const double* rho,
                       const uint8_t* nmask, const double* U, const afd_solve_opts* inner, int nev, double tol,
-                      int max_iter, double* lam_out, double* Phi, double* S, afd_modal_stats* st, hipStream_t s) {
+                      int max_iter, double* lam_out, double* Phi, double* S, afd_modal_stats* st, hipStream_t s,
+                      EigenBlock* block) {
     if (nev < 1 || nev > BLK - 1 || !(tol > 0) || max_iter < 1 || !lam_out || !Phi || !inner || !U) {
         set_error("buckling: nev 1..3, tol > 0, max_iter >= 1, non-null U, lambda, Phi, solve options");
         return AFD_E_INVALID_ARG;
@@ -766,8 +767,16 @@ int buckling_subspace(afd_mesh* mesh, const Grid& g, const double h[3], double E
     int it = 0, cg = 0;
     bool conv = false;
     if ((rc = subspace_largest(sp, g, nmask, applyNegKg, inner, nev, tol, max_iter, X, mu, res, it, cg, conv,
-                               nullptr)))
+                               block)))
         return done(rc);
+    if (block && block->X) {  // the K-orthonormal Ritz block and its values, for a later start
+        if (hipMemcpyAsync(block->X, X, (size_t)BLK * g.ndof * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            set_error("buckling: copy of the Ritz block failed");
+            return done(AFD_E_HIP);
+        }
+        for (int j = 0; j < BLK; ++j) block->mu[j] = mu[j];
+        block->valid = true;
+    }
     double lam[BLK] = {0, 0, 0, 0};
     for (int j = 0; j < nev; ++j) {
         if (!(mu[j] > 0)) {

@@ -995,15 +995,19 @@ def _levelset_lockstep(ctx, dims, loads, block, params, cast=(-1, 0)):
             mismatched += diff.size
         U = ls.fea(dims, s_k, fixed, F, Ke, p)
         J = float(sum(post.compliance(F[r], U[r]) for r in range(F.shape[0])))
-        S = fS = lam = fL = None
+        S = fS = lam = fL = Pb = fP = None
         if p.alpha_sigma > 0:
             S, fS = ls.stress_quantities(dims, s_k, fixed, Ke, U, p)
             assert abs(rec.S - S) <= 1e-8 * S, (k, rec.S, S)
         if p.alpha_lambda > 0:
             lam, fL = ls.eigen_quantities(dims, s_k, fixed, Ke, Me, p)
             assert abs(rec.lam - lam) <= 1e-8 * lam, (k, rec.lam, lam)
-        nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p), S, fS, lam, fL)
+        if p.alpha_P > 0:
+            Pb, fP = ls.buckling_quantities(dims, s_k, fixed, Ke, U, p)
+            assert abs(rec.P - Pb) <= 1e-8 * Pb, (k, rec.P, Pb)
+        nxt = loop.after_solve(s_k, J, ls.compliance_field(dims, s_k, Ke, U, p), S, fS, lam, fL, Pb, fP)
         o_rec = loop.history[-1]
+        assert abs(rec.mu_p - o_rec.mu_p) <= 1e-8 * max(1.0, o_rec.mu_p) and rec.gamma_p == o_rec.gamma_p, k
         assert abs(rec.mu_l - o_rec.mu_l) <= 1e-8 * max(1.0, o_rec.mu_l) and rec.gamma_l == o_rec.gamma_l, k
         assert abs(rec.J - J) <= 1e-8 * J, (k, rec.J, J)
         assert abs(rec.mu_s - o_rec.mu_s) <= 1e-8 * max(1.0, o_rec.mu_s) and rec.gamma_s == o_rec.gamma_s, k
@@ -1036,6 +1040,30 @@ def test_levelset_loop_with_eigen_constraint_matches_oracle(ctx, soft):
     assert mism <= 2 * len(hist)
     print(f"level-set loop with the {'soft' if soft else 'hard'} eigenvalue bound 12x6x4: {len(hist)} solves, final volume {conv[-1].v:.4f}, "
           f"lambda/lambda0 {conv[-1].lam / hist[0].lam:.3f}, {mism} elements inside tie bands")
+
+
+@pytest.mark.parametrize("soft", [False, True])
+def test_levelset_loop_with_buckling_constraint_matches_oracle(ctx, soft):
+    # J <= 3 J0 and P >= 0.8 P0 with damping, an axially compressed 12x6x4
+    # cantilever with a mid-edge load: the buckling load factor of every
+    # topology by subspace iteration on the GPU, by a dense solve of the
+    # pencil in the oracle
+    dims = (12, 6, 4)
+    f = wl.edge_load(dims, "mid")
+    for j in range(dims[1] + 1):
+        for k in range(dims[2] + 1):
+            f[3 * wl.node_id(dims, dims[0], j, k)] -= 1.0 / ((dims[1] + 1) * (dims[2] + 1))
+    params = dict(alpha_J=3.0, alpha_P=0.8, P_soft=soft, damping=True, dv_min=0.025 / 4)
+    hist, solid, b_solid, mism = _levelset_lockstep(ctx, dims, [f], (4, 3, 2), params)
+    conv = [r for r in hist if r.event == afdcg.AFD_LS_CONVERGED]
+    if soft:
+        assert any(r.g_p > 0 and r.g <= 0 and r.event != afdcg.AFD_LS_VIOLATED for r in hist)
+    else:
+        assert all(r.g <= 0 and r.g_p <= 0 for r in conv)
+        assert any(r.event == afdcg.AFD_LS_VIOLATED and r.g_p > 0 and r.g <= 0 for r in hist)
+    assert mism <= 2 * len(hist)
+    print(f"level-set loop with the {'soft' if soft else 'hard'} buckling bound 12x6x4: {len(hist)} solves, "
+          f"final volume {conv[-1].v:.4f}, P/P0 {conv[-1].P / hist[0].P:.3f}, {mism} elements inside tie bands")
 
 
 def test_levelset_loop_matches_oracle(ctx):
