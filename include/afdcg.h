@@ -435,7 +435,8 @@ int afd_solve(afd_mesh* mesh, const afd_solve_opts* opts, int32_t nrhs,
  * P >= alpha_P P_0, g_p = 1 - P / (alpha_P P_0), mu_p, gamma_p, the term
  * w_p T_P / (alpha_P P_0) with T_P the load-factor field of afd_buckling;
  * P_soft makes it soft.  The eigen-solves of each step start from the Ritz
- * block of the previous step.
+ * block of the previous step and run at most 200 subspace iterations; one
+ * that does not meet modal_tol ends the loop with its status.
  * With damping the topology is extracted from the mean of the solve's level
  * set and the level set its topology was extracted from (a fixed point that
  * would alternate between two topologies settles).
@@ -485,7 +486,8 @@ typedef struct {
     int32_t fea;               /* solve index                                    */
     int32_t event;             /* AFD_LS_*                                       */
     int32_t nsolid;            /* solid elements of the solved topology          */
-    int32_t iterations;        /* CG iterations of the solve (summed over loads) */
+    int32_t iterations;        /* CG iterations of the solves (summed over loads,
+                                  adjoint solves and eigen-solves)              */
     double v;                  /* target volume fraction of the solved topology  */
     double J, g;               /* compliance and constraint value               */
     double mu, gamma;          /* after this solve's update                      */
