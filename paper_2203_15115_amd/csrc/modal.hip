@@ -491,6 +491,13 @@ int subspace_largest(Subspace& sp, const Grid& g, const uint8_t* nmask, ApplyB a
         ++it;
         // Z = B X; Y = K^-1 Z, warm-started from X mu (K^-1 B x = mu x for an eigenpair)
         AFD_TRY(applyB(X, sp.Z));
+        // inexact inner solves: to 1e-2 of the smallest Ritz residual of the
+        // wanted pairs so far, never looser than 1e-2 nor tighter than the
+        // caller's rtol (the residuals are measured with the operators, so
+        // the stopping test stays exact)
+        double rmin = 1.0;
+        for (int j = 0; j < nev; ++j) rmin = std::min(rmin, res[j]);
+        so.rtol = std::max(inner->rtol, 1e-2 * rmin);
         if (it > 1 || warm) {
             double D[BLK][BLK] = {};
             for (int j = 0; j < BLK; ++j) D[j][j] = mu[j];
