@@ -178,6 +178,10 @@ def bench_multi(ctx, stream, args):
     U = torch.randn((4, p.ndof), dtype=torch.float64, device=dev)
     Y = torch.empty_like(U)
     t_valu = _events_time(stream, lambda: afdcg.afd_apply_K(m, afdcg.AFD_FP64, 4, U, Y), 50)
+    t_one = _events_time(stream, lambda: afdcg.afd_apply_K(m, afdcg.AFD_FP64, 1, U[0], Y[0]), 50)
+    # algorithmic bytes of the 4-column apply: u and y of every column, densities and fixity once
+    nn = (p.dims[0] + 1) * (p.dims[1] + 1) * (p.dims[2] + 1)
+    alg4 = matvec_algorithmic_bytes(p.dims) + 3 * nn * 6 * 8
     t_mfma = _events_time(stream, lambda: afdcg.afd_apply_K_mfma(m, 4, U, Y), 50)
     nx, ny, nz = p.dims
     # dense contraction flops actually issued: 32 (padded) x 24 x 2 per element per RHS,
@@ -203,6 +207,8 @@ def bench_multi(ctx, stream, args):
     afdcg.afd_mesh_destroy(m)
     return {"workload": "cantilever 128x64x64, 40% void, 4 RHS (3 edge loads + point load), 8x8x8 blocks",
             "apply_valu_us": round(t_valu * 1e6, 2), "apply_mfma_us": round(t_mfma * 1e6, 2),
+            "apply_valu_1rhs_us": round(t_one * 1e6, 2), "apply_4rhs_over_4x1rhs": round(t_valu / (4 * t_one), 3),
+            "apply_4rhs_alg_bytes": alg4, "apply_4rhs_hbm_frac": round(alg4 / t_valu / 1e9 / HBM_PEAK_GBS, 4),
             "gdofs_valu_total": round(4 * p.ndof / t_valu / 1e9, 2),
             "gdofs_mfma_total": round(4 * p.ndof / t_mfma / 1e9, 2),
             "mfma_tflops": round(alg_flops / t_mfma / 1e12, 3), "mfma_peak_tflops": 78.6,
