@@ -805,8 +805,12 @@ constexpr uint32_t OOB = 0x80000000u;  // beyond every buffer range used below
 template <typename T, bool CUB, int DIST, bool DOT = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_apply_bl(MvParams<T> P, KH<T> kh) {
     using S = DmaShape<T>;
-    constexpr int R = DIST + 2;        // plane ring slots: planes k and k + 1 being read, DIST in flight
-    constexpr int RR = DIST + 1;       // density ring slots: layer k being read, DIST in flight
+    // plane ring: planes k and k + 1 being read, DIST in flight; density ring:
+    // layer k being read, DIST in flight.  Both are rounded up to 4 slots, so
+    // that with the loop below unrolled by 4 every slot is a constant offset.
+    constexpr int R = 4;
+    constexpr int RR = DIST + 1 <= 2 ? 2 : 4;
+    static_assert(DIST + 2 <= R && DIST + 1 <= RR, "ring too small for the prefetch distance");
     constexpr int SLOT = S::J * NT;    // dwords per plane slot (whole-wave DMA, pad included)
     constexpr int NB = S::J + S::DW;   // loads per wave and layer (waves 0 and 1 issue one more)
     __shared__ __attribute__((aligned(16))) uint32_t ring[R][SLOT];
@@ -855,8 +859,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
         }
     }
     const int kfirst = Z0 - 1;
-    auto slot = [&](int g) { return (g - kfirst) % R; };
-    auto rslot = [&](int k) { return (k - kfirst) % RR; };
+    auto slot = [&](int g) { return (g - kfirst) & (R - 1); };  // g >= kfirst
+    auto rslot = [&](int k) { return (k - kfirst) & (RR - 1); };
     // node plane g with its fixity words (zeros outside 0..min(nz, Z1))
     auto issue_plane = [&](int g) {
         const bool in = g >= 0 && g <= Z1 && g <= nz;
@@ -984,11 +988,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
             for (int c = 0; c < 3; ++c) pin[c] = ((mbc >> c) & 1) ? T(0) : rbc[c];
         }
     };
-    for (int k = kfirst;; k += 2) {
+    for (int k = kfirst;; k += 4) {
         layer(k, bfA, ctA, bfB, ctB);
         if (k + 1 >= Z1) break;
         layer(k + 1, bfB, ctB, bfA, ctA);
         if (k + 2 >= Z1) break;
+        layer(k + 2, bfA, ctA, bfB, ctB);
+        if (k + 3 >= Z1) break;
+        layer(k + 3, bfB, ctB, bfA, ctA);
+        if (k + 4 >= Z1) break;
     }
     wait_vm_and_barrier<0>();  // the trailing out-of-range batches too, before the LDS is released
     if (own && Z1 - 1 >= Z0) finish(Z1 - 1);
