@@ -5,7 +5,9 @@ independent exact-rational construction, a closed form, an invariant, a
 textbook special case (the patch test), or brute force on a tiny input.
 """
 from fractions import Fraction
+import json
 import math
+import os
 
 import numpy as np
 import scipy.linalg as sla
@@ -15,6 +17,15 @@ from oracle import fem, solvers, post
 from paper_2203_15115_amd import workloads as wl
 
 pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    """A hand-worked fixture under tests/golden (each states what it pins)."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
 
 
 def lame(E, nu):
@@ -32,12 +43,13 @@ def test_ke_gauss_equals_exact_rationals(h):
 def test_ke_unit_cube_closed_forms():
     # Unit cube, E=1, nu=3/10: lambda=15/26, mu=5/13.  Every diagonal entry is
     # (lambda+2mu)/9 + 2*mu/9 = (lambda+4mu)/9 = 55/234 and the trace is 24x that.
+    g = golden("ke_unit_cube.json")
     K = fem.ke_exact()
     lam, mu = lame(Fraction(1), Fraction(3, 10))
-    assert (lam, mu) == (Fraction(15, 26), Fraction(5, 13))
+    assert (lam, mu) == tuple(Fraction(v) for v in g["lame"])
     for i in range(24):
-        assert K[i][i] == (lam + 4 * mu) / 9 == Fraction(55, 234)
-    assert sum(K[i][i] for i in range(24)) == Fraction(220, 39)
+        assert K[i][i] == (lam + 4 * mu) / 9 == Fraction(g["diagonal"])
+    assert sum(K[i][i] for i in range(24)) == Fraction(g["trace"])
     for i in range(24):
         for j in range(24):
             assert K[i][j] == K[j][i]
@@ -69,9 +81,9 @@ def test_ke_unit_cube_spectrum():
     # Eigenvalues of the unit-cube matrix (E=1, nu=3/10), derived from the
     # rational matrix: 0 (x6), 5/78 (x2), 55/468 (x3), 5/26 (x3), 10/39 (x1),
     # 5/13 (x8), 5/4 (x1).  They sum to the trace 220/39.
-    spec = ([0] * 6 + [Fraction(5, 78)] * 2 + [Fraction(55, 468)] * 3 + [Fraction(5, 26)] * 3
-            + [Fraction(10, 39)] + [Fraction(5, 13)] * 8 + [Fraction(5, 4)])
-    assert sum(spec) == Fraction(220, 39)
+    g = golden("ke_unit_cube.json")
+    spec = [Fraction(v) for v, m in g["spectrum"] for _ in range(m)]
+    assert len(spec) == 24 and sum(spec) == Fraction(g["trace"])
     ev = np.sort(np.linalg.eigvalsh(fem.ke_gauss()))
     assert np.allclose(ev, np.sort([float(v) for v in spec]), atol=1e-14)
 
@@ -314,19 +326,14 @@ def test_coarse_matrix_structure():
 
 # ------------------------------------------------------------- casting (Sec. 3.7)
 def test_casting_projection_worked_line():
-    # a line of 8 elements along x, parting plane before element 3, worked by hand:
-    # j < 3 takes the running maximum from j = 0: 3, max(3,1) = 3, max(3,4) = 4;
-    # j >= 3 takes it from the far end: 6, max(6,2) = 6, 9, 9, 9
+    # a line of 8 elements, worked by hand for a parting plane inside it and
+    # for one-sided castings, laid along each axis in turn
     from oracle.casting import cast_project
-    phi = [3, 1, 4, 1, 5, 9, 2, 6]
-    want = [3, 3, 4, 9, 9, 9, 6, 6]
-    assert list(cast_project(phi, (8, 1, 1), 0, 3)) == want
-    # the same line laid along y and along z
-    assert list(cast_project(phi, (1, 8, 1), 1, 3)) == want
-    assert list(cast_project(phi, (1, 1, 8), 2, 3)) == want
-    # one-sided castings: the whole line on one side of the plane
-    assert list(cast_project(phi, (8, 1, 1), 0, 0)) == [9, 9, 9, 9, 9, 9, 6, 6]
-    assert list(cast_project(phi, (8, 1, 1), 0, 8)) == [3, 3, 4, 4, 5, 9, 9, 9]
+    g = golden("casting_worked_line.json")
+    phi = g["phi"]
+    for case in g["cases"]:
+        for axis, dims in ((0, (8, 1, 1)), (1, (1, 8, 1)), (2, (1, 1, 8))):
+            assert list(cast_project(phi, dims, axis, case["parting"])) == case["want"], (case, axis)
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
@@ -527,23 +534,21 @@ def test_coarse_matrix_order_from_hand_built_motions():
 # ------------------------------------------------------------- level-set loop (Sec. 3.3-3.4, 3.8)
 def test_al_update_hand_checked_sequence():
     # mu <- max(mu + gamma g, 0); gamma kept when min(g_k, 0) <= 0.25 min(g_{k-1}, 0),
-    # else max(10 gamma, k^2) (Eq. 3.11-3.12 as printed), both from the old values.
-    # Worked by hand from mu = 100, gamma = 10:
-    #   k=0 g=-2/3 : mu 100 - 20/3 = 280/3, gamma 10 (no previous g)
-    #   k=1 g=-1/2 : -1/2 <= -1/6 keeps gamma; mu 280/3 - 5 = 265/3
-    #   k=2 g=-1/10: -1/10 > -1/8 -> gamma max(100, 4) = 100; mu 265/3 - 1 = 262/3
-    #   k=3 g=1/20 : 0 > -1/40 -> gamma max(1000, 9) = 1000; mu 262/3 + 100/20 = 277/3
-    #   k=4 g=1/50 : 0 <= 0 keeps gamma; mu 277/3 + 20 = 337/3
-    #   k=5 g=-9/10: -9/10 <= 0 keeps gamma; mu max(337/3 - 900, 0) = 0
+    # else max(10 gamma, k^2) (Eq. 3.11-3.12 as printed), both from the old values;
+    # the sequence from mu = 100, gamma = 10 is worked by hand in the fixture
     from oracle.levelset import al_update
-    mu, gamma, prev = 100.0, 10.0, None
-    want = [(280 / 3, 10.0), (265 / 3, 10.0), (262 / 3, 100.0), (277 / 3, 1000.0), (337 / 3, 1000.0), (0.0, 1000.0)]
-    for k, g in enumerate([-2 / 3, -1 / 2, -1 / 10, 1 / 20, 1 / 50, -9 / 10]):
-        mu, gamma = al_update(mu, gamma, g, prev, k)
-        prev = g
-        assert abs(mu - want[k][0]) <= 1e-12 * max(1.0, want[k][0]) and gamma == want[k][1], (k, mu, gamma)
+    g = golden("al_update_sequence.json")
+    mu, gamma, prev = float(g["mu0"]), float(g["gamma0"]), None
+    for st in g["steps"]:
+        gk = float(Fraction(st["g"]))
+        mu, gamma = al_update(mu, gamma, gk, prev, st["k"])
+        prev = gk
+        want_mu = float(Fraction(st["mu"]))
+        assert abs(mu - want_mu) <= 1e-12 * max(1.0, want_mu) and gamma == st["gamma"], (st, mu, gamma)
     # the k^2 branch: a small penalty late in the run
-    assert al_update(5.0, 1.0, -0.01, -0.5, 20) == (4.99, 400.0)
+    L = g["late_step"]
+    got = al_update(float(L["mu"]), float(L["gamma"]), float(Fraction(L["g"])), float(Fraction(L["g_prev"])), L["k"])
+    assert got == (float(Fraction(L["want_mu"])), float(L["want_gamma"]))
 
 
 def test_augmented_weights():
