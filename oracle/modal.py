@@ -82,14 +82,6 @@ def lowest_modes(K, M, fixed, nev=1):
     return lam, Phi
 
 
-def element_mass_energy(dims, rho, Me, u, v=None):
-    """rho_e u_e^T Me v_e per element."""
-    dm = fem.dofmap(dims)
-    ue = u[dm]
-    ve = ue if v is None else v[dm]
-    return rho * np.einsum("ei,ij,ej->e", ue, Me, ve)
-
-
 def eigen_sensitivity(dims, rho, Ke, Me, lam, phi):
     """T_lambda(e) = rho_e phi_e^T (Ke - lambda Me) phi_e."""
     dm = fem.dofmap(dims)
