@@ -412,36 +412,57 @@ __global__ void k_prolong_add(BlkP p, const uint8_t* nm, int64_t nnode, const do
 }
 
 // p' = beta p + M^-1 r - W mu (zero on fixed DOFs), the direction update of
-// the deflated PCG; one thread per node, skipped for converged right-hand sides
+// the deflated PCG, skipped for converged right-hand sides.  A workgroup
+// takes WG consecutive nodes: their 3 WG components of p and r are staged
+// through LDS with unit-stride global accesses (a node's three components
+// sit 24 bytes apart, so node-per-thread global loads would touch every
+// line three times), each thread then updates one node (its block and its
+// position in it computed once), and the result leaves through LDS the same
+// way.  In place (Pnew == Pold) is allowed.
 template <typename T>
-__global__ void k_form_dir(BlkP p, const uint8_t* nm, int64_t nnode, const CgScalars* sc, const double* MU,
-                           const T* Pold, const T* R, const double* rinv, const float* rinv32, double kd0, double kd1,
-                           double kd2, T* Pnew) {
+__global__ __launch_bounds__(WG) void k_form_dir(BlkP p, const uint8_t* nm, int64_t nnode, const CgScalars* sc,
+                                                 const double* MU, const T* Pold, const T* R, const double* rinv,
+                                                 const float* rinv32, double ikd0, double ikd1, double ikd2,
+                                                 T* Pnew) {
+    __shared__ T sp[3 * WG], sr[3 * WG];
     const int r = blockIdx.y;
     if (sc[r].done) return;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;  // 3 nnode < 2^31 (checked at mesh creation)
-    if (n >= nnode) return;
-    const double beta = sc[r].beta;
-    double w[3] = {0.0, 0.0, 0.0};
-    if (MU) {
-        int bb[3];
-        double x[3];
-        node_block(p, n, bb, x);
-        const double* m = MU + (int64_t)r * p.ncoarse + 6 * (bb[0] + p.nb[0] * (bb[1] + p.nb[1] * bb[2]));
-        w[0] = m[0] + m[4] * x[2] - m[5] * x[1];
-        w[1] = m[1] - m[3] * x[2] + m[5] * x[0];
-        w[2] = m[2] + m[3] * x[1] - m[4] * x[0];
+    const int t = threadIdx.x;
+    const int64_t n0 = (int64_t)blockIdx.x * WG;  // 3 nnode < 2^31 (checked at mesh creation)
+    const int cnt = (int)min((int64_t)WG, nnode - n0);
+    const int nv = 3 * cnt;
+    const int64_t base = (int64_t)r * 3 * nnode + 3 * n0;
+    for (int e = t; e < nv; e += WG) {
+        sp[e] = Pold[base + e];
+        sr[e] = R[base + e];
     }
-    const double ri = rinv ? rinv[n] : (double)rinv32[n];
-    // M^-1 r formed exactly as in k_cg_update and k_precond
-    const double ikd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
-    const uint8_t mk = nm[n];
-    const int64_t o = (int64_t)r * 3 * nnode + 3 * (int64_t)n;
+    __syncthreads();
+    if (t < cnt) {
+        const int n = (int)(n0 + t);
+        const double beta = sc[r].beta;
+        double w[3] = {0.0, 0.0, 0.0};
+        if (MU) {
+            int bb[3];
+            double x[3];
+            node_block(p, n, bb, x);
+            const double* m = MU + (int64_t)r * p.ncoarse + 6 * (bb[0] + p.nb[0] * (bb[1] + p.nb[1] * bb[2]));
+            w[0] = m[0] + m[4] * x[2] - m[5] * x[1];
+            w[1] = m[1] - m[3] * x[2] + m[5] * x[0];
+            w[2] = m[2] + m[3] * x[1] - m[4] * x[0];
+        }
+        const double ri = rinv ? rinv[n] : (double)rinv32[n];
+        // M^-1 r formed exactly as in k_cg_update and k_precond (the host's
+        // 1 / kd is the same correctly rounded quotient they form)
+        const double ikd[3] = {ikd0, ikd1, ikd2};
+        const uint8_t mk = nm[n];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const double v = beta * (double)Pold[o + c] + ri * ikd[c] * (double)R[o + c] - w[c];
-        Pnew[o + c] = ((mk >> c) & 1) ? T(0) : (T)v;
+        for (int c = 0; c < 3; ++c) {
+            const double v = beta * (double)sp[3 * t + c] + ri * ikd[c] * (double)sr[3 * t + c] - w[c];
+            sp[3 * t + c] = ((mk >> c) & 1) ? T(0) : (T)v;
+        }
     }
+    __syncthreads();
+    for (int e = t; e < nv; e += WG) Pnew[base + e] = sp[e];
 }
 
 __global__ void k_copy(int64_t n, const double* a, double* b) {
@@ -641,7 +662,8 @@ int launch_form_dir(const Grid& g, const Blocks& b, const uint8_t* nmask, const 
                     int nrhs, const double* MU, const double* rinv, const double* Pold, const double* R,
                     double* Pnew, hipStream_t s) {
     hipLaunchKernelGGL((k_form_dir<double>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, g.nnode,
-                       sc, MU, Pold, R, rinv, (const float*)nullptr, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], Pnew);
+                       sc, MU, Pold, R, rinv, (const float*)nullptr, 1.0 / kh.kdiag[0], 1.0 / kh.kdiag[1],
+                       1.0 / kh.kdiag[2], Pnew);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
@@ -650,7 +672,8 @@ int launch_form_dir_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, co
                         const CgScalars* sc, int nrhs, const double* MU, const float* rinv32, const float* Pold,
                         const float* R, float* Pnew, hipStream_t s) {
     hipLaunchKernelGGL((k_form_dir<float>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, g.nnode,
-                       sc, MU, Pold, R, (const double*)nullptr, rinv32, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], Pnew);
+                       sc, MU, Pold, R, (const double*)nullptr, rinv32, 1.0 / kh.kdiag[0], 1.0 / kh.kdiag[1],
+                       1.0 / kh.kdiag[2], Pnew);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
