@@ -151,7 +151,7 @@ struct CgScalars {
     int32_t done;            // 0 running, 1 converged, 2 breakdown, 3 max_iter
     int32_t iters;
     int32_t max_iter;
-    int32_t pad;
+    int32_t xdone;           // the direction kernel has applied the x update of the iteration that set done
 };
 
 // persist.hip: the FP64 deflated PCG as one launch, one workgroup per
@@ -193,12 +193,14 @@ void apply_tiling(const Grid& g, int fp32, int variant, int zc_req, int nrhs, in
 int launch_tile_rho(const Grid& g, const double* rho, double* rho_t, float* rho32_t, hipStream_t s);
 int launch_tile_fmask(const Grid& g, const uint8_t* nmask, uint16_t* fm_t, hipStream_t s);
 // p' = beta p + M^-1 r - W mu (MU null: no deflation), zero on fixed DOFs
+// X (may be null): also x += alpha p_old, the x update of the iteration
+// (k_cg_update then runs without X)
 int launch_form_dir(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh, const CgScalars* sc,
                     int nrhs, const double* MU, const double* rinv, const double* Pold, const double* R,
-                    double* Pnew, hipStream_t s);
+                    double* Pnew, double* X, hipStream_t s);
 int launch_form_dir_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh,
                         const CgScalars* sc, int nrhs, const double* MU, const float* rinv32, const float* Pold,
-                        const float* R, float* Pnew, hipStream_t s);
+                        const float* R, float* Pnew, float* X, hipStream_t s);
 // Q = A P with the per-workgroup partial sums of P.Q (d.partial, slot 0 of
 // each right-hand side), skipping converged right-hand sides (d.sc)
 int launch_apply_dot(const MatvecArgs& a, const KeHaar& kh, const DcgArgs& d, int fp32, int nrhs, const void* P,

@@ -419,13 +419,15 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
         }
         return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32, true);
     };
-    // p' = beta p + M^-1 r - W mu (Pnew), then q = A p' with the p'.q partials
-    auto direction = [&](T* Pold, T* Pnew) -> int {
+    // p' = beta p + M^-1 r - W mu (Pnew), then q = A p' with the p'.q partials;
+    // with Xu the same launch applies the iteration's x += alpha p (p = Pold)
+    auto direction = [&](T* Pold, T* Pnew, T* Xu) -> int {
         const double* mu = m->deflate ? w.MU : nullptr;
         if constexpr (sizeof(T) == 8)
-            AFD_TRY(launch_form_dir(m->g, m->blk, m->nmask, m->kh, sc, nrhs, mu, m->rinv, Pold, R, Pnew, s));
+            AFD_TRY(launch_form_dir(m->g, m->blk, m->nmask, m->kh, sc, nrhs, mu, m->rinv, Pold, R, Pnew, Xu, s));
         else
-            AFD_TRY(launch_form_dir_f32(m->g, m->blk, m->nmask, m->kh, sc, nrhs, mu, m->rinv32, Pold, R, Pnew, s));
+            AFD_TRY(
+                launch_form_dir_f32(m->g, m->blk, m->nmask, m->kh, sc, nrhs, mu, m->rinv32, Pold, R, Pnew, Xu, s));
         return launch_apply_dot(a, m->kh, dm, sizeof(T) == 4 ? 1 : 0, nrhs, Pnew, Q, s);
     };
     if (m->deflate) {
@@ -435,22 +437,23 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     }
     if constexpr (sizeof(T) == 8) AFD_TRY(launch_fill_f64(nrhs * ndof, 0.0, (double*)P0, s));
     else AFD_TRY(launch_fill_f32(nrhs * ndof, 0.0f, (float*)P0, s));
-    AFD_TRY(direction(P0, P1));
+    AFD_TRY(direction(P0, P1, nullptr));
     std::swap(P0, P1);
     std::vector<CgScalars> hsc(nrhs);
     const int ce = std::max(1, check_every);
     auto iterate = [&](int n) -> int {
         for (int j = 0; j < n; ++j) {
             AFD_TRY(launch_scalar_alpha(sc, nrhs, w.partM, m->npartM, s));
+            // r -= alpha q, z, r.z and r.r here; x += alpha p in the direction launch below
             if constexpr (sizeof(T) == 8)
-                AFD_TRY(launch_cg_update(m->g, m->kh, m->rinv, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr,
-                                         w.partV, VEC_NPART, s));
+                AFD_TRY(launch_cg_update(m->g, m->kh, m->rinv, sc, nrhs, nullptr, nullptr, R, Q,
+                                         m->deflate ? Z : nullptr, w.partV, VEC_NPART, s));
             else
-                AFD_TRY(launch_cg_update_f32(m->g, m->kh, m->rinv32, sc, nrhs, X, P0, R, Q, m->deflate ? Z : nullptr,
-                                             w.partV, VEC_NPART, s));
+                AFD_TRY(launch_cg_update_f32(m->g, m->kh, m->rinv32, sc, nrhs, nullptr, nullptr, R, Q,
+                                             m->deflate ? Z : nullptr, w.partV, VEC_NPART, s));
             if (!m->deflate || m->blk.nblk < nrhs) AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
             AFD_TRY(coarse_of_z(m->deflate && m->blk.nblk >= nrhs));
-            AFD_TRY(direction(P0, P1));
+            AFD_TRY(direction(P0, P1, X));
             std::swap(P0, P1);
         }
         return AFD_OK;

@@ -120,7 +120,11 @@ __global__ void k_cg_start(CgScalars* sc, const double* part, int npart) {
 __global__ void k_scalar_alpha(CgScalars* sc, const double* part, int npart) {
     __shared__ double sh[WG / 64];
     const int r = blockIdx.x;
-    if (sc[r].done) return;
+    if (sc[r].done) {
+        // the direction kernel of the iteration that set done has run since
+        if (threadIdx.x == 0) sc[r].xdone = 1;
+        return;
+    }
     double pq = sum_partials(part + (int64_t)(r * 2 + 0) * npart, npart, sh);
     if (threadIdx.x == 0) {
         sc[r].pq = pq;
@@ -163,8 +167,10 @@ __global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, con
     const int r = blockIdx.y;
     if (sc[r].done) return;
     const T a = (T)sc[r].alpha;
-    X += r * ndof;
-    Pv += r * ndof;
+    if (X) {  // else x += alpha p is done by k_form_dir
+        X += r * ndof;
+        Pv += r * ndof;
+    }
     R += r * ndof;
     Q += r * ndof;
     if (Z) Z += r * ndof;
@@ -174,7 +180,7 @@ __global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, con
         const int64_t n = i / 3;
         const int c = (int)(i - 3 * n);
         const double ri = (sizeof(T) == 8) ? rinv[n] : (double)rinv32[n];
-        X[i] = X[i] + a * Pv[i];
+        if (X) X[i] = X[i] + a * Pv[i];  // else in k_form_dir
         const T rv = R[i] - a * Q[i];
         R[i] = rv;
         const double z = ri * ikd[c] * (double)rv;
@@ -418,24 +424,34 @@ __global__ void k_prolong_add(BlkP p, const uint8_t* nm, int64_t nnode, const do
 // sit 24 bytes apart, so node-per-thread global loads would touch every
 // line three times), each thread then updates one node (its block and its
 // position in it computed once), and the result leaves through LDS the same
-// way.  In place (Pnew == Pold) is allowed.
+// way.  In place (Pnew == Pold) is allowed.  With X it also applies the
+// iteration's x += alpha p (p the old direction, read here anyway), which
+// saves k_cg_update a read of p and a read and write of x.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_form_dir(BlkP p, const uint8_t* nm, int64_t nnode, const CgScalars* sc,
                                                  const double* MU, const T* Pold, const T* R, const double* rinv,
                                                  const float* rinv32, double ikd0, double ikd1, double ikd2,
-                                                 T* Pnew) {
+                                                 T* Pnew, T* X) {
     __shared__ T sp[3 * WG], sr[3 * WG];
     const int r = blockIdx.y;
-    if (sc[r].done) return;
+    // X: x += alpha p_old, also in the iteration whose restriction set done
+    // (once: the next alpha kernel sets xdone); p' only while running
+    const bool dn = sc[r].done != 0;
+    const bool doX = X != nullptr && !(dn && sc[r].xdone);
+    if (dn && !doX) return;
     const int t = threadIdx.x;
     const int64_t n0 = (int64_t)blockIdx.x * WG;  // 3 nnode < 2^31 (checked at mesh creation)
     const int cnt = (int)min((int64_t)WG, nnode - n0);
     const int nv = 3 * cnt;
     const int64_t base = (int64_t)r * 3 * nnode + 3 * n0;
+    const T a = (T)sc[r].alpha;
     for (int e = t; e < nv; e += WG) {
-        sp[e] = Pold[base + e];
-        sr[e] = R[base + e];
+        const T pv = Pold[base + e];
+        if (doX) X[base + e] = X[base + e] + a * pv;
+        sp[e] = pv;
+        if (!dn) sr[e] = R[base + e];
     }
+    if (dn) return;  // the same for the whole workgroup
     __syncthreads();
     if (t < cnt) {
         const int n = (int)(n0 + t);
@@ -660,20 +676,20 @@ int launch_prolong_add(const Grid& g, const Blocks& b, const uint8_t* nmask, int
 
 int launch_form_dir(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh, const CgScalars* sc,
                     int nrhs, const double* MU, const double* rinv, const double* Pold, const double* R,
-                    double* Pnew, hipStream_t s) {
+                    double* Pnew, double* X, hipStream_t s) {
     hipLaunchKernelGGL((k_form_dir<double>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, g.nnode,
                        sc, MU, Pold, R, rinv, (const float*)nullptr, 1.0 / kh.kdiag[0], 1.0 / kh.kdiag[1],
-                       1.0 / kh.kdiag[2], Pnew);
+                       1.0 / kh.kdiag[2], Pnew, X);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
 
 int launch_form_dir_f32(const Grid& g, const Blocks& b, const uint8_t* nmask, const KeHaar& kh,
                         const CgScalars* sc, int nrhs, const double* MU, const float* rinv32, const float* Pold,
-                        const float* R, float* Pnew, hipStream_t s) {
+                        const float* R, float* Pnew, float* X, hipStream_t s) {
     hipLaunchKernelGGL((k_form_dir<float>), dim3(nblocks(g.nnode), nrhs), dim3(WG), 0, s, blkp(g, b), nmask, g.nnode,
                        sc, MU, Pold, R, (const double*)nullptr, rinv32, 1.0 / kh.kdiag[0], 1.0 / kh.kdiag[1],
-                       1.0 / kh.kdiag[2], Pnew);
+                       1.0 / kh.kdiag[2], Pnew, X);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
