@@ -176,18 +176,37 @@ __global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, con
     if (Z) Z += r * ndof;
     const double ikd[3] = {1.0 / kd0, 1.0 / kd1, 1.0 / kd2};
     double rz = 0.0, rr = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < ndof; i += (int64_t)gridDim.x * WG) {
-        const int64_t n = i / 3;
-        const int c = (int)(i - 3 * n);
-        const double ri = (sizeof(T) == 8) ? rinv[n] : (double)rinv32[n];
+    // one element (i < 3 nnode < 2^31, checked at mesh creation)
+    auto elem = [&](int i, T rold, T q, double ri) {
+        const int c = i - 3 * (i / 3);
         if (X) X[i] = X[i] + a * Pv[i];  // else in k_form_dir
-        const T rv = R[i] - a * Q[i];
+        const T rv = rold - a * q;
         R[i] = rv;
         const double z = ri * ikd[c] * (double)rv;
         if (Z) Z[i] = (T)z;
         rz += (double)rv * z;
         rr += (double)rv * (double)rv;
+    };
+    auto rinv_of = [&](int i) { return (sizeof(T) == 8) ? rinv[i / 3] : (double)rinv32[i / 3]; };
+    const int64_t n = ndof, stride = (int64_t)gridDim.x * WG;  // indices stay 64-bit: i + 4 stride may pass 2^31
+    int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    // four elements per step, their loads issued together (one element per
+    // step leaves too few loads in flight to cover the memory latency); the
+    // elements are still taken in ascending order, so the sums are unchanged
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        T rv[4], qv[4];
+        double ri[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = (int)(i + u * stride);
+            rv[u] = R[j];
+            qv[u] = Q[j];
+            ri[u] = rinv_of(j);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) elem((int)(i + u * stride), rv[u], qv[u], ri[u]);
     }
+    for (; i < n; i += stride) elem((int)i, R[i], Q[i], rinv_of((int)i));
     double s0 = wg_reduce(rz, sh);
     double s1 = wg_reduce(rr, sh);
     if (threadIdx.x == 0) {
@@ -445,11 +464,16 @@ __global__ __launch_bounds__(WG) void k_form_dir(BlkP p, const uint8_t* nm, int6
     const int nv = 3 * cnt;
     const int64_t base = (int64_t)r * 3 * nnode + 3 * n0;
     const T a = (T)sc[r].alpha;
-    for (int e = t; e < nv; e += WG) {
-        const T pv = Pold[base + e];
-        if (doX) X[base + e] = X[base + e] + a * pv;
-        sp[e] = pv;
-        if (!dn) sr[e] = R[base + e];
+    // nv <= 3 WG: three unrolled steps, so that their loads are in flight together
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int e = t + k * WG;
+        if (e < nv) {
+            const T pv = Pold[base + e];
+            if (doX) X[base + e] = X[base + e] + a * pv;
+            sp[e] = pv;
+            if (!dn) sr[e] = R[base + e];
+        }
     }
     if (dn) return;  // the same for the whole workgroup
     __syncthreads();
@@ -478,7 +502,11 @@ __global__ __launch_bounds__(WG) void k_form_dir(BlkP p, const uint8_t* nm, int6
         }
     }
     __syncthreads();
-    for (int e = t; e < nv; e += WG) Pnew[base + e] = sp[e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int e = t + k * WG;
+        if (e < nv) Pnew[base + e] = sp[e];
+    }
 }
 
 __global__ void k_copy(int64_t n, const double* a, double* b) {
