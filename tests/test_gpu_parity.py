@@ -281,7 +281,8 @@ def test_dot(ctx, n):
 DEFL = [((8, 4, 4), (4, 2, 2)), ((24, 12, 12), (4, 4, 4)), ((9, 5, 7), (4, 4, 3)), ((16, 8, 8), (8, 8, 8))]
 
 
-@pytest.mark.parametrize("dims,block", DEFL)
+# the restriction also on a long (64-element) block edge and on ragged blocks
+@pytest.mark.parametrize("dims,block", DEFL + [((70, 5, 6), (64, 8, 3)), ((20, 11, 7), (6, 5, 7))])
 def test_restrict_prolong_match_oracle_W(ctx, dims, block):
     rho, _ = rand_problem(dims, 6)
     fixed = wl.clamp_x0(dims)
