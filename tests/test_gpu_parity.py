@@ -753,6 +753,29 @@ def test_max_iter_reports_not_converged(ctx):
     assert np.all(np.isfinite(U))
 
 
+def test_iterates_after_k_iterations(ctx, c0_direct):
+    # x_k after exactly k iterations (the x update of every iteration applied,
+    # the last one included): its energy-norm error decreases strictly with k,
+    # and replayed iteration chunks (check_every 2) give the eager iterate bitwise
+    p, K, ud = c0_direct
+    Kff, free = fem.constrained_operator(K, p.fixed)
+    m = make_mesh(ctx, p.dims, p.rho, p.fixed, block=p.block)
+    F = np.ascontiguousarray(p.F[:1])
+    errs, its = [], {}
+    for k in (2, 3, 6, 12):
+        for ce in (1, 2):
+            U = np.zeros_like(F)
+            code, st = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-14, max_iter=k, check_every=ce), 1, F, U,
+                                       raise_on_error=False)
+            assert code == afdcg.AFD_E_NOT_CONVERGED and st[0].iterations == k, (k, ce, code)
+            its[(k, ce)] = U[0].copy()
+        assert np.array_equal(its[(k, 1)], its[(k, 2)]), k
+        e = its[(k, 1)][free] - ud[free]
+        errs.append(float(e @ (Kff @ e)))
+    afdcg.afd_mesh_destroy(m)
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+
+
 def test_invalid_inputs_rejected(ctx):
     with pytest.raises(afdcg.AfdError):
         afdcg.afd_mesh_create(ctx, (0, 1, 1))
