@@ -955,6 +955,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
         if (own && k - 1 >= Z0) finish(k - 1);  // plane k - 1, with the row below's exchange
         issue_plane(k + 1 + DIST);  // into the slot of plane k - 1, done with before the barrier
         issue_rho(k + DIST);        // into the slot of densities k - 1
+        __builtin_amdgcn_s_setprio(0);
         T rho_k, rbc[3];
         int fmt, mbc;
         lds_face_own(ring_base + slot(k + 1) * PLANE_B, rring_base + rslot(k) * RL_B, mring_base + slot(k + 1) * ML_B,
@@ -977,6 +978,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
             up[c] = yb[2][c] + dpp_shr1(yb[3][c]);
         }
         lds_xch_put(xch_put + xb * XB_B, up[0], up[1], up[2]);
+        // from here through the barrier to the next plane's loads this wave
+        // goes ahead of the other resident workgroups' arithmetic (measured:
+        // 29.4 -> 28.3 us at 192x96x96, 38 -> 34.5 us for 4 right-hand sides
+        // at 128x64x64); the priority drops again once the loads are out
+        __builtin_amdgcn_s_setprio(1);
         if (__builtin_amdgcn_ballot_w64(mbc != 0)) {  // identity rows of fixed DOFs: the input value
 #pragma unroll
             for (int c = 0; c < 3; ++c)
