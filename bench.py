@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per FP64 apply launch at 192x96x96 from rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by the
 # same counter on a 512 MiB copy (kernel as of the committed counter summary
 # profiles/apply_fp64_192x96x96_counters.md); None when not measured
-TRAFFIC_BYTES = 74_730_894 + 43_951_434
+TRAFFIC_BYTES = 74_861_517 + 43_919_251
 
 
 # plain-apply kernel of each autotuner variant
