@@ -229,6 +229,7 @@ int launch_cg_init(CgScalars* sc, int nrhs, const double* part, int npart, doubl
 int launch_cg_start(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
 int launch_scalar_alpha(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
 int launch_scalar_beta(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
+// X, Pv may be null: no x update (the deflated PCG does it in launch_form_dir)
 int launch_cg_update(const Grid& g, const KeHaar& kh, const double* rinv, CgScalars* sc, int nrhs, double* X,
                      const double* Pv, double* R, const double* Q, double* Z, double* partial, int npart,
                      hipStream_t s);

@@ -157,8 +157,9 @@ __global__ void k_scalar_beta(CgScalars* sc, const double* part, int npart) {
     }
 }
 
-// x += alpha p, r -= alpha q, z = M^-1 r (optional), partials of r.z and r.r;
-// flat over DOFs so that every array access is a unit-stride stream
+// r -= alpha q, z = M^-1 r (optional), partials of r.z and r.r, and x += alpha p
+// when X is given (the deflated PCG leaves that to k_form_dir, which reads p
+// anyway); flat over DOFs so that every array access is a unit-stride stream
 template <typename T>
 __global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, const float* rinv32,
                             double kd0, double kd1, double kd2, CgScalars* sc, T* X, const T* Pv, T* R,
