@@ -297,7 +297,9 @@ __global__ __launch_bounds__(256) void k_potrf_tile(double* A, double* Linv, int
             const double edc = ed[c];
             const bool dr = !(edc > 0.0) || !(d > DROP_TOL * edc);
             // 1/sqrt(d) once; 1/d and sqrt(d) follow from it by one product each
-            const double pi = dr ? 1.0 : rsqrt_newton(d);
+            // (the estimate needs a normal argument well inside the range; a
+            // pivot as small as 2^-900 only arises for E near the denormals)
+            const double pi = dr ? 1.0 : (d > 0x1p-900 ? rsqrt_newton(d) : 1.0 / sqrt(d));
             const double id = dr ? 0.0 : pi * pi;
             const double f = r > c ? ucol[b][r] * id : 0.0;
             const double* uc = &ucol[b][cb];

@@ -776,6 +776,22 @@ def test_iterates_after_k_iterations(ctx, c0_direct):
     assert all(b < a for a, b in zip(errs, errs[1:])), errs
 
 
+def test_tiny_modulus_scales_the_solution(ctx):
+    # K is linear in E: with E = 1e-290 the coarse pivots (~E) fall below the
+    # range of the factor's reciprocal-square-root estimate and take the
+    # plain square root; the displacements are those of E = 1 divided by E
+    p = wl.cantilever((12, 6, 6), 30, seed=5, block=(4, 4, 4))
+    out = []
+    for E in (1.0, 1e-290):
+        m = make_mesh(ctx, p.dims, p.rho, p.fixed, block=p.block, E=E)
+        U = np.zeros_like(p.F[:1])
+        _, st = afdcg.afd_solve(m, afdcg.make_opts(rtol=1e-10), 1, np.ascontiguousarray(p.F[:1]), U)
+        afdcg.afd_mesh_destroy(m)
+        assert st[0].rel_residual_true <= 1e-10
+        out.append(U[0] * E)
+    assert np.linalg.norm(out[1] - out[0]) <= 1e-8 * np.linalg.norm(out[0])
+
+
 def test_invalid_inputs_rejected(ctx):
     with pytest.raises(afdcg.AfdError):
         afdcg.afd_mesh_create(ctx, (0, 1, 1))
