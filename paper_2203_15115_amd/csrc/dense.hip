@@ -109,14 +109,21 @@ typedef double dacc4 __attribute__((ext_vector_type(4)));
 // writes its partial product to C + z czs (beta must then be 0).
 __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double alpha, const double* A, int lda,
                                                    int ta, const double* B, int ldb, int tb, double beta, double* C,
-                                                   int ldc, int kchunk, int64_t czs) {
+                                                   int ldc, int kchunk, int64_t czs, int64_t azs = 0, int64_t bzs = 0,
+                                                   int batched = 0) {
     __shared__ double As[GK][GT + 2];
     __shared__ double Bs[GK][GT + 2];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wr = wv >> 1, wc = wv & 1;
     const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
-    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    // blockIdx.z: a slice of K (partial products at C + z czs), or with
+    // batched a separate product A + z azs, B + z bzs -> C + z czs
+    const int kbeg = batched ? 0 : blockIdx.z * kchunk, kend = batched ? K : min(K, kbeg + kchunk);
     C += blockIdx.z * czs;
+    if (batched) {
+        A += blockIdx.z * azs;
+        B += blockIdx.z * bzs;
+    }
     // loader: element e = t + 256 q (q < 4) of the 64 x 16 A tile and the 16 x 64 B tile
     double ra[4], rb[4];
     auto load = [&](int k0) {
@@ -207,6 +214,17 @@ __global__ void k_sum_split(int M, int N, int S, const double* src, int ld, int6
     double v = 0.0;
     for (int z = 0; z < S; ++z) v += src[z * zs + (int64_t)i * ld + j];
     dst[(int64_t)i * ldd + j] = v;
+}
+
+// nbatch products C_z = alpha A_z B_z + beta C_z (no transposes), X_z = X + z xzs
+int gemm_batched(int nbatch, int M, int N, int K, double alpha, const double* A, int lda, int64_t azs,
+                 const double* B, int ldb, int64_t bzs, double beta, double* C, int ldc, int64_t czs, hipStream_t s) {
+    if (nbatch <= 0 || M <= 0 || N <= 0 || K <= 0) return AFD_OK;
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, nbatch);
+    hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, K, czs,
+                       azs, bzs, 1);
+    AFD_HIP_TRY(hipGetLastError());
+    return AFD_OK;
 }
 
 // C = alpha op(A) op(B) with K split over S workgroup slices whose partial
@@ -992,17 +1010,30 @@ int coarse_factor(Coarse& c, hipStream_t s) {
             }
         }
         AFD_HIP_TRY(hipGetLastError());
-        // Linv: row tile i: X[i, 0:i] = -X_ii (L[i, 0:i] X[0:i, 0:i]); the first
-        // product is nb x i0 x i0, too few output tiles for the GPU, so K is
-        // split (partials in work rows nb.., the sum in work rows 0..nb-1)
-        for (int i0 = NB; i0 < P; i0 += NB) {
-            const int nb = std::min(NB, P - i0);
-            const int tiles = (i0 + GT - 1) / GT;
-            const int S = std::max(1, std::min({(P - nb) / nb, 256 / tiles, i0 / 128}));
-            AFD_TRY(gemm_split(nb, i0, i0, 1.0, Dk + (int64_t)i0 * P, P, 0, Li, P, 0, work, P, work + (int64_t)nb * P,
-                               P, S, st));
-            AFD_TRY(gemm(nb, i0, nb, -1.0, Li + (int64_t)i0 * P + i0, P, 0, work, P, 0, 0.0, Li + (int64_t)i0 * P,
-                         P, st));
+        // Linv by recursive doubling: the diagonal tiles hold the tile
+        // inverses; at block size sz every pair of neighbouring blocks A =
+        // [a, a + sz), C = [a + sz, a + 2 sz) (the last one possibly shorter)
+        // gets its off-diagonal block of the inverse, -C^-1 (L_CA A^-1), so
+        // the pairs become the inverted blocks of size 2 sz.  The pairs of a
+        // level are independent: two batched products per level (plus two
+        // for a short last pair) instead of a chain of tile rows
+        for (int sz = NB; sz < P; sz *= 2) {
+            const int full = P / (2 * sz);                      // pairs with C of full size
+            const int64_t step = (int64_t)2 * sz * P + 2 * sz;  // from one pair's blocks to the next
+            // T_p = L[a+sz : a+2sz, a : a+sz] A^-1 into work (sz x sz each)
+            AFD_TRY(gemm_batched(full, sz, sz, sz, 1.0, Dk + (int64_t)sz * P, P, step, Li, P, step, 0.0, work, sz,
+                                 (int64_t)sz * sz, st));
+            // X_CA = -C^-1 T_p
+            AFD_TRY(gemm_batched(full, sz, sz, sz, -1.0, Li + (int64_t)sz * P + sz, P, step, work, sz,
+                                 (int64_t)sz * sz, 0.0, Li + (int64_t)sz * P, P, step, st));
+            const int a = full * 2 * sz, sc = P - a - sz;  // a shorter last pair
+            if (sc > 0) {
+                double* Tl = work + (int64_t)full * sz * sz;
+                AFD_TRY(gemm(sc, sz, sz, 1.0, Dk + (int64_t)(a + sz) * P + a, P, 0, Li + (int64_t)a * P + a, P, 0, 0.0,
+                             Tl, sz, st));
+                AFD_TRY(gemm(sc, sz, sc, -1.0, Li + (int64_t)(a + sz) * P + a + sz, P, 0, Tl, sz, 0, 0.0,
+                             Li + (int64_t)(a + sz) * P + a, P, st));
+            }
         }
         hipLaunchKernelGGL(k_zero_dropped, dim3((P + 255) / 256, P), dim3(256), 0, st, Li, P,
                            c.dropped_dev + (int64_t)k * P);
