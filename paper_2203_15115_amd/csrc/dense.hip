@@ -695,11 +695,15 @@ __global__ __launch_bounds__(256) void k_gemv(int P, const TM* M, int64_t mstrid
     auto window = [&](const TM* m, const double* xv, int j0, int j1) {
         // aligned groups of N (P, the block offsets and the vector strides are
         // multiples of 4); group members outside [j0, j1) count zero.  A chunk
-        // is GU 16-byte loads per lane of the matrix and of the first
-        // right-hand side, all issued before the first is used, so that a row
-        // window of up to 64 * N * GU columns (1024 in FP64: every chain step's
-        // window) costs one memory latency instead of one per four loads
-        constexpr int GU = 8;
+        // is GU 16-byte loads per lane of the matrix (and the matching FP64
+        // loads of the first right-hand side), all issued before the first is
+        // used, so that a row window of up to 64 * N * GU = 1024 columns (every
+        // chain step's window) costs one memory latency instead of one per
+        // four loads.  The FP32 copies take half the matrix loads per chunk:
+        // with eight, their widened values and the twice as many x loads held
+        // 164 registers (three wavefronts per SIMD), and the copies streamed no
+        // faster than FP64
+        constexpr int GU = 1024 / (64 * N);
         for (int jj = (j0 & ~(N - 1)) + N * lane; jj < j1; jj += 64 * N * GU) {
             double mv[GU][N], xv0[GU][N];
 #pragma unroll
