@@ -187,12 +187,14 @@ int afd_mesh_autotune(afd_mesh* mesh, int32_t precision, int32_t nrhs, afd_tune_
 int afd_mesh_apply_config(afd_mesh* mesh, int32_t precision, int32_t variant, int32_t zc);
 /* Element type of the coarse solve matrices the deflated iterations of
  * afd_solve stream (Sec. 3.5's coarse problem W^T K W, always factored in
- * FP64): AFD_FP64 (the default unless the environment sets AFD_COARSE_F32=1)
- * streams the FP64 factor; AFD_FP32 (opt-in) uses FP32 copies made once per
- * factorisation, with FP64 vectors and accumulation (half the bytes per
- * coarse solve; the coarse correction is then exact to ~1e-7 relative, the
- * stopping test and the true residual stay FP64).  AFD_E_INVALID_ARG
- * otherwise. */
+ * FP64): AFD_FP64 streams the FP64 factor; AFD_FP32 uses FP32 copies made
+ * once per factorisation, with FP64 vectors and accumulation (half the bytes
+ * per coarse solve; the coarse correction is then exact to ~1e-7 relative,
+ * the stopping test and the true residual stay FP64).  By default (no call)
+ * the FP64 iterations stream the FP64 factor (the copies if the environment
+ * sets AFD_COARSE_F32=1) and the FP32 inner solves of AFD_MIXED stream the
+ * copies; AFD_FP64 set here makes both stream the factor, AFD_FP32 both the
+ * copies.  AFD_E_INVALID_ARG otherwise. */
 int afd_mesh_coarse_precision(afd_mesh* mesh, int32_t precision);
 /* Execution form of the FP64 deflated PCG of afd_solve on this mesh (the
  * iteration of Sec. 3.5 is the same in both forms, only its execution
@@ -381,8 +383,9 @@ int afd_combine_fields(afd_context* ctx, int64_t n, int32_t nterms, const double
 /* ---- the whole solve ---------------------------------------------------- */
 /* Solves A U[r] = F[r] for r < nrhs (1..4) by deflated Jacobi-PCG (Sec. 3.5),
  * FP64 or FP32-inner/FP64-refined per opts->precision (the coarse factor is
- * computed and applied in FP64 unless afd_mesh_coarse_precision opts in to
- * FP32 copies; the stopping test and the reported true residual are FP64),
+ * computed in FP64 and applied through FP32 copies where
+ * afd_mesh_coarse_precision says so; the stopping test and the reported true
+ * residual are FP64),
  * then writes the compliances J[r] = F[r].U[r] (Eq. 1.3) and, if S != NULL,
  * the energy fields of afd_sensitivity (opts->pairs).  F, U, J, S are host or device per
  * opts->mem_kind.  F must be zero on fixed DOFs (AFD_E_INVALID_ARG

@@ -160,6 +160,10 @@ bool coarse_f32_enabled() {
 }
 void clear_error() { g_err.clear(); }
 bool use_coarse_f32(const afd_mesh* m) { return m->coarse_f32 < 0 ? coarse_f32_enabled() : m->coarse_f32 == 1; }
+// The FP32 inner solves of the mixed form stream the FP32 copies unless the
+// mesh asks for the FP64 factor: their vectors and products are FP32 already,
+// and the FP64 refinement around them sets the accuracy.
+bool use_coarse_f32_inner(const afd_mesh* m) { return m->coarse_f32 != 0; }
 
 int check_ctx(afd_context* c) {
     if (!c) {
@@ -361,6 +365,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     Work& w = m->w;
     MatvecArgs a = mv_args(m);
     const bool f32 = sizeof(T) == 4;
+    const bool c32 = (f32 ? use_coarse_f32_inner(m) : use_coarse_f32(m)) && m->coarse.valid32;
     const int64_t ndof = m->g.ndof;
     // ||b||
     if constexpr (sizeof(T) == 8) AFD_TRY(launch_dot_rhs(ndof, nrhs, (const double*)Bv, w.partV, VEC_NPART, s));
@@ -375,7 +380,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
                 DcgArgs d0 = dcg_args(m, sc, w.partM, m->npartM);
                 AFD_TRY(launch_residual(a, m->kh, d0, nrhs, Bv, X, R, s));
                 AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, nrhs, R, w.G, s));
-                AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32));
+                AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, c32));
                 AFD_TRY(launch_prolong_add(m->g, m->blk, m->nmask, nrhs, w.MU, sc, X, s));
             }
         } else {
@@ -386,7 +391,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
         // deflated start
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_restrict(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
         else AFD_TRY(launch_restrict_f32(m->g, m->blk, m->nmask, nrhs, Bv, w.G, s));
-        AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32));
+        AFD_TRY(coarse_solve(m->coarse, nrhs, w.G, w.MU, s, c32));
         if constexpr (sizeof(T) == 8) AFD_TRY(launch_prolong(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
         else AFD_TRY(launch_prolong_f32(m->g, m->blk, m->nmask, nrhs, w.MU, X, s));
     } else {
@@ -417,7 +422,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             AFD_TRY(launch_restrict_diff_f32(m->g, m->blk, m->nmask, nrhs, AZ, R, w.G, s, m->coarse.perm,
                                              m->coarse.gperm, npad, bsc, w.partV, VEC_NPART));
         }
-        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, use_coarse_f32(m) && m->coarse.valid32, true);
+        return coarse_solve(m->coarse, nrhs, w.G, w.MU, s, c32, true);
     };
     // p' = beta p + M^-1 r - W mu (Pnew), then q = A p' with the p'.q partials;
     // with Xu the same launch applies the iteration's x += alpha p (p = Pold)
@@ -475,7 +480,7 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
             (uintptr_t)c.LinvT, (uintptr_t)c.T, (uintptr_t)c.U, (uintptr_t)c.perm, (uintptr_t)c.iperm,
             (uintptr_t)c.gperm, (uintptr_t)c.xperm, (uintptr_t)c.blk.P, (uintptr_t)c.blk.K,
             (uintptr_t)c.Linv32, (uintptr_t)c.LinvT32, (uintptr_t)c.T32, (uintptr_t)c.U32,
-            (uintptr_t)(use_coarse_f32(m) && c.valid32),
+            (uintptr_t)c32,
             (uintptr_t)(m->tune_variant[0] + 8), (uintptr_t)(m->tune_variant[1] + 8), (uintptr_t)m->tune_zc[0],
             (uintptr_t)m->tune_zc[1]};
         if (!gr.exec || gr.key != key) {
@@ -1166,9 +1171,11 @@ int afd_solve(afd_mesh* m, const afd_solve_opts* o, int32_t nrhs, const double* 
     const int ce = o->check_every > 0 ? o->check_every : 16;
     std::vector<CgScalars> hsc(nrhs), hout(nrhs);
     int refinements = 0;
-    // FP32 copies of the coarse solve matrices for the iterations (made once per
-    // factorisation; without memory for them the FP64 factor is used)
-    if (m->deflate && use_coarse_f32(m) && coarse_make_f32(m->coarse, s) != AFD_OK) clear_error();
+    // FP32 copies of the coarse solve matrices for the iterations that stream
+    // them (made once per factorisation; without memory for them the FP64
+    // factor is used)
+    if (m->deflate && (use_coarse_f32(m) || (mixed && use_coarse_f32_inner(m))) && coarse_make_f32(m->coarse, s) != AFD_OK)
+        clear_error();
     // warm start: the caller's x0 (host or device per mem_kind; its values on
     // fixed DOFs are ignored)
     const bool warm = o->x0 != nullptr;
