@@ -436,6 +436,31 @@ def test_coarse_precision_fp32_and_fp64_agree(ctx, c0_direct):
     assert it32 <= 1.1 * it64 + 2, (it64, it32)
 
 
+def test_mixed_inner_solves_stream_the_coarse_copies(ctx, c0_direct):
+    # the FP32 inner solves of the mixed form stream the FP32 copies of the
+    # coarse solve matrices unless the mesh asks for the FP64 factor: by default
+    # the solve is bitwise the one with the copies requested, with the factor it
+    # differs, and all three reach the direct solution
+    p, K, ud = c0_direct
+    p2 = wl.Problem(p.dims, p.rho, p.fixed, p.F, (2, 2, 2))
+    res = {}
+    for cp in (None, afdcg.AFD_FP32, afdcg.AFD_FP64):
+        m = make_mesh(ctx, p2.dims, p2.rho, p2.fixed, block=p2.block)
+        if cp is not None:
+            afdcg.afd_mesh_coarse_precision(m, cp)
+        U = np.zeros((1, p2.ndof))
+        J = np.zeros(1)
+        opts = afdcg.make_opts(rtol=1e-11, max_iter=20000, precision=afdcg.AFD_MIXED)
+        code, st = afdcg.afd_solve(m, opts, 1, np.ascontiguousarray(p2.F[:1]), U, J, None)
+        afdcg.afd_mesh_destroy(m)
+        assert code == afdcg.AFD_OK and st[0].rel_residual_true <= 1e-11, (cp, st[0].rel_residual_true)
+        assert np.linalg.norm(U[0] - ud) / np.linalg.norm(ud) <= 1e-6, cp
+        res[cp] = (U[0].copy(), st[0].iterations)
+    assert np.array_equal(res[None][0], res[afdcg.AFD_FP32][0])
+    assert res[None][1] == res[afdcg.AFD_FP32][1]
+    assert not np.array_equal(res[None][0], res[afdcg.AFD_FP64][0])
+
+
 def test_box_voxels_apply_and_solve(ctx):
     # non-cubic voxels take the general Haar coefficients (51 values)
     dims, h, E, nu = (19, 9, 8), (1.0, 2.0, 0.5), 2.5, 0.27
