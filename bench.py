@@ -748,7 +748,7 @@ def main():
         cast[f"axis{axis}"] = {"parting": parting, "us": round(t_c * 1e6, 2),
                                "gbs": round(2 * 8 * p.nelem / t_c / 1e9, 1)}
     out["casting"] = cast
-    # the opt-in coarse solve over FP32 copies of the FP64 factor's solve
+    # the FP64 iterations' opt-in coarse solve over FP32 copies of the FP64 factor's solve
     # matrices (FP64 vectors and accumulation), same steps
     afdcg.afd_mesh_coarse_precision(mesh, afdcg.AFD_FP32)
     step()

@@ -144,13 +144,11 @@ int mesh_dof_mask(const afd_mesh* m, uint8_t* host) {
 
 namespace {
 
-// The deflated iterations (FP64 and the FP32 inner solves of the mixed form)
-// stream FP32 copies of the coarse solve matrices, with FP64 vectors and
-// accumulation (AFD_COARSE_F32=0: the FP64 factor)
+// AFD_COARSE_F32 as read once for the process (-1: not read yet)
 int g_coarse_f32 = -1;
-// FP32 copies of the coarse solve matrices are opt-in (AFD_COARSE_F32=1 for the
-// process, afd_mesh_coarse_precision per mesh): by default the coarse solve
-// streams the FP64 factor
+// For the FP64 iterations the FP32 copies of the coarse solve matrices are
+// opt-in (AFD_COARSE_F32=1 for the process, afd_mesh_coarse_precision per
+// mesh): by default they stream the FP64 factor
 bool coarse_f32_enabled() {
     if (g_coarse_f32 < 0) {
         const char* e = getenv("AFD_COARSE_F32");
