@@ -227,15 +227,17 @@ int launch_dot_rhs_f32(int64_t ndof, int nrhs, const float* F, double* partial, 
 int launch_cg_init(CgScalars* sc, int nrhs, const double* part, int npart, double rtol, int max_iter,
                    hipStream_t s);
 int launch_cg_start(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
-int launch_scalar_alpha(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
 int launch_scalar_beta(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s);
-// X, Pv may be null: no x update (the deflated PCG does it in launch_form_dir)
+// alpha from the p.q partials (pqpart, npq per right-hand side, as the
+// direction apply writes them), then the r/z update with its r.z and r.r
+// partials; X, Pv may be null: no x update (the deflated PCG does it in
+// launch_form_dir)
 int launch_cg_update(const Grid& g, const KeHaar& kh, const double* rinv, CgScalars* sc, int nrhs, double* X,
                      const double* Pv, double* R, const double* Q, double* Z, double* partial, int npart,
-                     hipStream_t s);
+                     const double* pqpart, int npq, hipStream_t s);
 int launch_cg_update_f32(const Grid& g, const KeHaar& kh, const float* rinv32, CgScalars* sc, int nrhs, float* X,
                          const float* Pv, float* R, const float* Q, float* Z, double* partial, int npart,
-                         hipStream_t s);
+                         const double* pqpart, int npq, hipStream_t s);
 int launch_precond(const Grid& g, const KeHaar& kh, const double* rinv, int nrhs, const double* R, double* Z,
                    hipStream_t s);
 int launch_precond_f32(const Grid& g, const KeHaar& kh, const float* rinv32, int nrhs, const float* R, float* Z,

@@ -446,14 +446,13 @@ int dcg_run(afd_mesh* m, int nrhs, const T* Bv, T* X, T* R, T* P0, T* P1, T* Q, 
     const int ce = std::max(1, check_every);
     auto iterate = [&](int n) -> int {
         for (int j = 0; j < n; ++j) {
-            AFD_TRY(launch_scalar_alpha(sc, nrhs, w.partM, m->npartM, s));
-            // r -= alpha q, z, r.z and r.r here; x += alpha p in the direction launch below
+            // alpha, r -= alpha q, z, r.z and r.r here; x += alpha p in the direction launch below
             if constexpr (sizeof(T) == 8)
                 AFD_TRY(launch_cg_update(m->g, m->kh, m->rinv, sc, nrhs, nullptr, nullptr, R, Q,
-                                         m->deflate ? Z : nullptr, w.partV, VEC_NPART, s));
+                                         m->deflate ? Z : nullptr, w.partV, VEC_NPART, w.partM, m->npartM, s));
             else
                 AFD_TRY(launch_cg_update_f32(m->g, m->kh, m->rinv32, sc, nrhs, nullptr, nullptr, R, Q,
-                                             m->deflate ? Z : nullptr, w.partV, VEC_NPART, s));
+                                             m->deflate ? Z : nullptr, w.partV, VEC_NPART, w.partM, m->npartM, s));
             if (!m->deflate || m->blk.nblk < nrhs) AFD_TRY(launch_scalar_beta(sc, nrhs, w.partV, VEC_NPART, s));
             AFD_TRY(coarse_of_z(m->deflate && m->blk.nblk >= nrhs));
             AFD_TRY(direction(P0, P1, X));

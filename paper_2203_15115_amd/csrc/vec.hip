@@ -117,26 +117,6 @@ __global__ void k_cg_start(CgScalars* sc, const double* part, int npart) {
     }
 }
 
-__global__ void k_scalar_alpha(CgScalars* sc, const double* part, int npart) {
-    __shared__ double sh[WG / 64];
-    const int r = blockIdx.x;
-    if (sc[r].done) {
-        // the direction kernel of the iteration that set done has run since
-        if (threadIdx.x == 0) sc[r].xdone = 1;
-        return;
-    }
-    double pq = sum_partials(part + (int64_t)(r * 2 + 0) * npart, npart, sh);
-    if (threadIdx.x == 0) {
-        sc[r].pq = pq;
-        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(sc[r].rz)) {
-            sc[r].done = 2;  // breakdown: A not SPD on the Krylov space (e.g. no fixed DOFs)
-            sc[r].alpha = 0.0;
-        } else {
-            sc[r].alpha = sc[r].rz / pq;
-        }
-    }
-}
-
 __global__ void k_scalar_beta(CgScalars* sc, const double* part, int npart) {
     __shared__ double sh[WG / 64];
     const int r = blockIdx.x;
@@ -157,17 +137,43 @@ __global__ void k_scalar_beta(CgScalars* sc, const double* part, int npart) {
     }
 }
 
-// r -= alpha q, z = M^-1 r (optional), partials of r.z and r.r, and x += alpha p
-// when X is given (the deflated PCG leaves that to k_form_dir, which reads p
-// anyway); flat over DOFs so that every array access is a unit-stride stream
+// alpha = r.z / p.q from the p.q partials, then r -= alpha q, z = M^-1 r
+// (optional), partials of r.z and r.r, and x += alpha p when X is given (the
+// deflated PCG leaves that to k_form_dir, which reads p anyway); flat over
+// DOFs so that every array access is a unit-stride stream.  Every workgroup
+// sums the p.q partials in the same order and so takes the same alpha;
+// workgroup 0 records it (and a breakdown, which every workgroup sees alike).
 template <typename T>
 __global__ void k_cg_update(int64_t nnode, int64_t ndof, const double* rinv, const float* rinv32,
                             double kd0, double kd1, double kd2, CgScalars* sc, T* X, const T* Pv, T* R,
-                            const T* Q, T* Z, double* part, int npart) {
+                            const T* Q, T* Z, double* part, int npart, const double* pqpart, int npq) {
     __shared__ double sh[WG / 64];
     const int r = blockIdx.y;
-    if (sc[r].done) return;
-    const T a = (T)sc[r].alpha;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // one read of the flag per workgroup: workgroup 0 may set it (breakdown)
+    // while others run, and the waves of a workgroup must agree
+    __shared__ int done_all;
+    if (threadIdx.x == 0) done_all = sc[r].done;
+    __syncthreads();
+    if (done_all) {
+        // the direction kernel of the iteration that set done has run since
+        if (lead) sc[r].xdone = 1;
+        return;
+    }
+    __shared__ double pq_all;  // the sum is formed in thread 0; every thread needs it
+    const double pq0 = sum_partials(pqpart + (int64_t)(r * 2 + 0) * npq, npq, sh);
+    if (threadIdx.x == 0) pq_all = pq0;
+    __syncthreads();
+    const double pq = pq_all;
+    const double rzv = sc[r].rz;
+    const bool brk = !(pq > 0.0) || !isfinite(pq) || !isfinite(rzv);
+    if (lead) {
+        sc[r].pq = pq;
+        sc[r].alpha = brk ? 0.0 : rzv / pq;
+        if (brk) sc[r].done = 2;  // breakdown: A not SPD on the Krylov space (e.g. no fixed DOFs)
+    }
+    if (brk) return;
+    const T a = (T)(rzv / pq);
     if (X) {  // else x += alpha p is done by k_form_dir
         X += r * ndof;
         Pv += r * ndof;
@@ -648,11 +654,6 @@ int launch_cg_start(CgScalars* sc, int nrhs, const double* part, int npart, hipS
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
-int launch_scalar_alpha(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s) {
-    hipLaunchKernelGGL(k_scalar_alpha, dim3(nrhs), dim3(WG), 0, s, sc, part, npart);
-    AFD_HIP_TRY(hipGetLastError());
-    return AFD_OK;
-}
 int launch_scalar_beta(CgScalars* sc, int nrhs, const double* part, int npart, hipStream_t s) {
     hipLaunchKernelGGL(k_scalar_beta, dim3(nrhs), dim3(WG), 0, s, sc, part, npart);
     AFD_HIP_TRY(hipGetLastError());
@@ -661,20 +662,20 @@ int launch_scalar_beta(CgScalars* sc, int nrhs, const double* part, int npart, h
 
 int launch_cg_update(const Grid& g, const KeHaar& kh, const double* rinv, CgScalars* sc, int nrhs, double* X,
                      const double* Pv, double* R, const double* Q, double* Z, double* partial, int npart,
-                     hipStream_t s) {
+                     const double* pqpart, int npq, hipStream_t s) {
     hipLaunchKernelGGL((k_cg_update<double>), dim3(npart, nrhs), dim3(WG), 0, s, g.nnode, g.ndof, rinv,
                        (const float*)nullptr, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], sc, X, Pv, R, Q, Z, partial,
-                       npart);
+                       npart, pqpart, npq);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
 
 int launch_cg_update_f32(const Grid& g, const KeHaar& kh, const float* rinv32, CgScalars* sc, int nrhs, float* X,
                          const float* Pv, float* R, const float* Q, float* Z, double* partial, int npart,
-                         hipStream_t s) {
+                         const double* pqpart, int npq, hipStream_t s) {
     hipLaunchKernelGGL((k_cg_update<float>), dim3(npart, nrhs), dim3(WG), 0, s, g.nnode, g.ndof,
                        (const double*)nullptr, rinv32, kh.kdiag[0], kh.kdiag[1], kh.kdiag[2], sc, X, Pv, R, Q, Z,
-                       partial, npart);
+                       partial, npart, pqpart, npq);
     AFD_HIP_TRY(hipGetLastError());
     return AFD_OK;
 }
